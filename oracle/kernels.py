@@ -1,0 +1,219 @@
+"""SPH kernel functions and the kernel constants used by the error analysis.
+
+Follows the paper's introduction (Eq. cubic-kernel: the cubic B-spline with
+support bound q = 2), Sec. 3.1 (the normalized ray-restricted kernel
+B_Lambda(t) = w(sqrt(Lambda^2 + t^2))) and Sec. 4.4 / App. A.4 (the constants
+kappa and kappa').  The Wendland C2 kernel is not in the paper; it is the
+standard 3-D normalisation (21/16pi)(1 - r/2)^4 (1 + 2r) on [0, 2).
+
+Every kernel here is a piecewise polynomial in r, stored as
+(r_lo, r_hi, ascending coefficients) times a constant factor, so that the
+integrals below can be written out in closed form.
+
+Pinned by tests/test_oracle_kernels.py: kappa and kappa' against the values
+printed in App. A.4, unit volume integral, the column integral against an
+independent high-precision quadrature and against 2*int_0^q w and the
+normalisation 2*pi*int Lambda*Sigma(Lambda) dLambda = 1.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+from numpy.polynomial import polynomial as P
+
+CUBIC = "cubic"
+WENDLAND = "wendland"
+KINDS = (CUBIC, WENDLAND)
+
+Q_SUPPORT = 2.0  # both kernels vanish for r >= 2
+
+
+def support(kind: str) -> float:
+    """Upper bound q of the kernel's support (Fig. 1 caption)."""
+    if kind not in KINDS:
+        raise ValueError(kind)
+    return Q_SUPPORT
+
+
+def pieces(kind: str):
+    """Kernel as [(r_lo, r_hi, coeffs ascending in r)], and its constant factor.
+
+    cubic (Eq. cubic-kernel):  (1/4pi)[(2-r)^3 - 4(1-r)^3] on [0,1) which expands
+    to (1/4pi)(4 - 6r^2 + 3r^3), and (1/4pi)(2-r)^3 on [1,2).
+    wendland C2: (21/16pi)(1-r/2)^4 (1+2r) on [0,2).
+    """
+    if kind == CUBIC:
+        inner = P.polysub(P.polypow([2.0, -1.0], 3), 4.0 * P.polypow([1.0, -1.0], 3))
+        outer = P.polypow([2.0, -1.0], 3)
+        return [(0.0, 1.0, inner), (1.0, 2.0, outer)], 1.0 / (4.0 * math.pi)
+    if kind == WENDLAND:
+        poly = P.polymul(P.polypow([1.0, -0.5], 4), [1.0, 2.0])
+        return [(0.0, 2.0, poly)], 21.0 / (16.0 * math.pi)
+    raise ValueError(kind)
+
+
+def w(kind: str, r):
+    """Kernel value w(r) for r >= 0 (zero outside the support)."""
+    r = np.asarray(r, dtype=np.float64)
+    out = np.zeros_like(r)
+    pcs, fac = pieces(kind)
+    for lo, hi, c in pcs:
+        m = (r >= lo) & (r < hi)
+        out[m] = P.polyval(r[m], c)
+    return fac * out
+
+
+def w_near_edge(kind: str, r, two_minus_r):
+    """w(r) evaluated with 2 - r supplied separately (accurate near r -> 2).
+
+    Only the outermost piece uses the supplied 2 - r; both kernels are written as
+    a polynomial in (2 - r) there: cubic (2-r)^3, Wendland ((2-r)/2)^4 (1+2r).
+    """
+    r = np.asarray(r, dtype=np.float64)
+    e = np.asarray(two_minus_r, dtype=np.float64)
+    out = np.zeros_like(r)
+    if kind == CUBIC:
+        m_in = r < 1.0
+        m_out = (r >= 1.0) & (e > 0.0)
+        out[m_in] = (4.0 - 6.0 * r[m_in] ** 2 + 3.0 * r[m_in] ** 3) / (4.0 * math.pi)
+        out[m_out] = e[m_out] ** 3 / (4.0 * math.pi)
+        return out
+    if kind == WENDLAND:
+        m = e > 0.0
+        out[m] = 21.0 / (16.0 * math.pi) * (0.5 * e[m]) ** 4 * (1.0 + 2.0 * r[m])
+        return out
+    raise ValueError(kind)
+
+
+def breakpoints(kind: str):
+    """Interior radii where the kernel's polynomial changes (excluding 0 and q)."""
+    return [1.0] if kind == CUBIC else []
+
+
+def w0(kind: str) -> float:
+    """Kernel peak w(0): the cubic kernel gives 1/pi, Wendland C2 21/(16 pi)."""
+    return float(w(kind, np.array([0.0]))[0])
+
+
+def volume_integral(kind: str) -> float:
+    """4 pi int_0^q r^2 w(r) dr (must be 1 for a normalised SPH kernel)."""
+    pcs, fac = pieces(kind)
+    tot = 0.0
+    for lo, hi, c in pcs:
+        ci = P.polyint(P.polymul(c, [0.0, 0.0, 1.0]))
+        tot += P.polyval(hi, ci) - P.polyval(lo, ci)
+    return 4.0 * math.pi * fac * tot
+
+
+def kappa(kind: str) -> float:
+    """kappa = (4 pi int_0^inf [t w(t)]^2 dt)^(1/2)  (Sec. 4.4; App. A.4).
+
+    The L2 norm of a normalized particle's contribution; the paper prints
+    roughly 0.352 for the cubic kernel.
+    """
+    pcs, fac = pieces(kind)
+    tot = 0.0
+    for lo, hi, c in pcs:
+        integrand = P.polymul(P.polymul(c, c), [0.0, 0.0, 1.0])
+        ci = P.polyint(integrand)
+        tot += P.polyval(hi, ci) - P.polyval(lo, ci)
+    return math.sqrt(4.0 * math.pi * fac * fac * tot)
+
+
+def dB_dt(kind: str, lam: float, t):
+    """d/dt of B_Lambda(t) = w(sqrt(Lambda^2 + t^2)) (Sec. 3.1): w'(r) t / r."""
+    t = np.asarray(t, dtype=np.float64)
+    r = np.sqrt(lam * lam + t * t)
+    pcs, fac = pieces(kind)
+    out = np.zeros_like(t)
+    for lo, hi, c in pcs:
+        m = (r >= lo) & (r < hi) & (r > 0)
+        out[m] = P.polyval(r[m], P.polyder(c)) * t[m] / r[m]
+    return fac * out
+
+
+def kappa_prime(kind: str) -> float:
+    """kappa' = (int_0^q Lambda int_R [d/dt B_Lambda(t)]^2 dt dLambda)^(1/2).
+
+    Evaluated from this definition (App. A.4) by nested adaptive quadrature that
+    splits at the kernel's breakpoints.  The paper prints sqrt(14)/(7 pi) ~ 0.170
+    for the cubic kernel.
+    """
+    from scipy import integrate
+
+    q = support(kind)
+    bps = breakpoints(kind)
+
+    def inner(lam):
+        s = math.sqrt(max(q * q - lam * lam, 0.0))
+        pts = [math.sqrt(b * b - lam * lam) for b in bps if b > lam]
+        edges = [0.0] + sorted(pts) + [s]
+        tot = 0.0
+        for a, b in zip(edges[:-1], edges[1:]):
+            if b > a:
+                v, _ = integrate.quad(lambda t: dB_dt(kind, lam, np.array([t]))[0] ** 2, a, b,
+                                      epsabs=0.0, epsrel=1e-12, limit=200)
+                tot += v
+        return 2.0 * tot  # the integrand is even in t
+
+    outer_pts = sorted(set(bps))
+    edges = [0.0] + outer_pts + [q]
+    tot = 0.0
+    for a, b in zip(edges[:-1], edges[1:]):
+        v, _ = integrate.quad(lambda lam: lam * inner(lam), a, b, epsabs=0.0, epsrel=1e-12, limit=200)
+        tot += v
+    return math.sqrt(tot)
+
+
+def _power_antiderivative(n: int, lam, t):
+    """Antiderivative in t of r^n with r = sqrt(lam^2 + t^2), lam > 0 (mpmath numbers).
+
+    Even n: expand (lam^2 + t^2)^(n/2) binomially.  Odd n: the reduction
+    K_n = (t r^n + n lam^2 K_{n-2}) / (n + 1) with K_{-1} = asinh(t / lam).
+    """
+    import mpmath
+
+    if n % 2 == 0:
+        m = n // 2
+        return sum(math.comb(m, j) * lam ** (2 * (m - j)) * t ** (2 * j + 1) / (2 * j + 1)
+                   for j in range(m + 1))
+    r = mpmath.sqrt(lam * lam + t * t)
+    k = mpmath.asinh(t / lam)  # K_{-1}
+    for p in range(1, n + 1, 2):
+        k = (t * r ** p + p * lam * lam * k) / (p + 1)
+    return k
+
+
+def column_integral(kind: str, lam: float, digits: int = 60) -> float:
+    """Sigma(Lambda) = int_R B_Lambda(t) dt, the line integral of the kernel.
+
+    Closed form: on each kernel piece r in [r_lo, r_hi) the integrand is a
+    polynomial in r, and each power r^n has the antiderivative above; the
+    t-range of a piece is sqrt(max(r_lo^2 - Lambda^2, 0)) .. sqrt(r_hi^2 - Lambda^2).
+    The antiderivatives cancel heavily for grazing rays (Lambda -> q), so they
+    are evaluated with ``digits`` significant digits (mpmath) and rounded once.
+    """
+    import mpmath
+
+    q = support(kind)
+    if lam >= q:
+        return 0.0
+    pcs, fac = pieces(kind)
+    with mpmath.workdps(digits):
+        L = mpmath.mpf(lam)
+        tot = mpmath.mpf(0)
+        for lo, hi, c in pcs:
+            if hi <= lam:
+                continue
+            ta = mpmath.sqrt(max(mpmath.mpf(lo) ** 2 - L * L, 0))
+            tb = mpmath.sqrt(mpmath.mpf(hi) ** 2 - L * L)
+            for n, cn in enumerate(c):
+                if cn == 0.0:
+                    continue
+                cm = mpmath.mpf(cn)
+                if lam == 0.0:
+                    tot += cm * (tb ** (n + 1) - ta ** (n + 1)) / (n + 1)
+                else:
+                    tot += cm * (_power_antiderivative(n, L, tb) - _power_antiderivative(n, L, ta))
+        return float(2 * mpmath.mpf(fac) * tot)

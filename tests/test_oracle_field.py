@@ -1,0 +1,307 @@
+"""Pins of oracle.field (exact accumulation, pieces, merge), oracle.render and
+oracle.geometry / oracle.grid."""
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import field, geometry, grid, kernels, knots, lut, quanta, render
+
+
+@pytest.fixture(scope="module")
+def setup():
+    kind, K, D, n = "cubic", 4, 2, 32
+    _, th, _ = lut.knot_table(kind, K, D, n)
+    sh, _ = lut.lut_entries(kind, K, D, th)
+    xyz, h, val = synth.random_scene(5, 400, h_lo=0.04, h_hi=0.12)
+    amax = grid.a_max(kind, xyz, h, val)
+    hr, phr = grid.representatives(h, val)
+    tau, sigma = quanta.choose_quanta(kind, D, amax, hr, phr)
+    return dict(kind=kind, K=K, D=D, table={"theta": th, "shat": sh}, xyz=xyz, h=h, val=val, q=(tau, sigma))
+
+
+def _ray(seed):
+    o, v = synth.random_rays(seed, 1)
+    return o[0].astype(np.float64), v[0].astype(np.float64)
+
+
+def test_accumulation_equals_sum_of_particles(setup):
+    """Eq. accumulation-rule on the merged knot list gives, at every integer position,
+    exactly the sum of the particles' own encoded polynomials (Sec. 2)."""
+    s = setup
+    o, v = _ray(11)
+    hits, sk = field.ray_knots(o, v, -10.0, 10.0, s["xyz"], s["h"], s["val"], s["table"], s["q"], s["K"], s["D"], s["kind"])
+    assert len(hits) > 5
+    pieces, tail = field.exact_pieces(sk)
+    assert tail == [0] * (s["D"] + 1)
+    per = {}
+    for (t, pid, kidx, a) in sk:
+        per.setdefault(pid, []).append((t, kidx, a))
+
+    def own(pid, x):
+        return sum(sum(a[d] * (x - t) ** d for d in range(len(a))) for t, _, a in per[pid] if t <= x)
+
+    rng = np.random.default_rng(0)
+    for (ta, tb, coefs, _) in pieces[:: max(1, len(pieces) // 25)]:
+        for x in {ta, int(rng.integers(ta, tb)), tb - 1}:
+            ray_val = sum(coefs[d] * (x - ta) ** d for d in range(len(coefs)))
+            assert ray_val == sum(own(p, x) for p in per)
+
+
+def test_knot_order_and_pieces(setup):
+    s = setup
+    o, v = _ray(12)
+    hits, sk = field.ray_knots(o, v, -10.0, 10.0, s["xyz"], s["h"], s["val"], s["table"], s["q"], s["K"], s["D"], s["kind"])
+    keys = [(t, p, k) for (t, p, k, _) in sk]
+    assert keys == sorted(keys) and len(set(keys)) == len(keys)
+    assert len(sk) == (s["K"] + 1) * len(hits)
+    pieces, _ = field.exact_pieces(sk)
+    distinct = sorted({t for t, _, _, _ in sk})
+    assert [p[0] for p in pieces] == distinct[:-1] and [p[1] for p in pieces] == distinct[1:]
+
+
+def test_empty_ray(setup):
+    s = setup
+    f = field.ray_field(np.array([5.0, 5.0, 5.0]), np.array([0.0, 0.0, 1.0]), 0.0, 1.0, s["xyz"], s["h"], s["val"],
+                        s["table"], s["q"], s["K"], s["D"], s["kind"], 1e-3)
+    assert len(f["hits"]) == 0 and f["pieces"] == [] and f["peak"] == 0.0 and f["nodes"] == []
+
+
+def _exact_poly(coefs, ta, tb, sigma):
+    """Exact field on a piece as rational polynomial coefficients in u in [0, 1]."""
+    L = tb - ta
+    return [Fraction(sigma) * coefs[d] * L ** d for d in range(len(coefs))]
+
+
+def _legendre_exact(D):
+    from numpy.polynomial import legendre as Lg
+    rows = []
+    for j in range(D + 1):
+        c = [0] * j + [1]
+        pw = [Fraction(x).limit_denominator(10 ** 6) for x in Lg.leg2poly(c)]
+        # substitute x = 2u - 1
+        acc = [Fraction(0)] * (D + 1)
+        for m, cm in enumerate(pw):
+            term = [Fraction(1)]
+            for _ in range(m):
+                term = [a * -1 for a in term] + [Fraction(0)]
+                term = [term[i] + (2 * (term[i - 1] if i > 0 else 0) if False else 0) for i in range(len(term))]
+            # expand (2u - 1)^m exactly
+            poly = [Fraction(math.comb(m, i)) * Fraction(2) ** i * Fraction(-1) ** (m - i) for i in range(m + 1)]
+            for i, pc in enumerate(poly):
+                acc[i] += cm * pc
+        rows.append(acc)
+    return rows
+
+
+def _int_poly(p, lo, hi):
+    """int_lo^hi of a rational polynomial in u."""
+    return sum(c * (Fraction(hi) ** (i + 1) - Fraction(lo) ** (i + 1)) / (i + 1) for i, c in enumerate(p))
+
+
+def _pmul(a, b):
+    out = [Fraction(0)] * (len(a) + len(b) - 1)
+    for i, x in enumerate(a):
+        for j, y in enumerate(b):
+            out[i + j] += x * y
+    return out
+
+
+def _compose_affine(p, s0, s1):
+    """p(s0 + s1 u) as coefficients in u (exact)."""
+    out = [Fraction(0)]
+    for i, c in enumerate(p):
+        term = [Fraction(1)]
+        for _ in range(i):
+            term = _pmul(term, [Fraction(s0), Fraction(s1)])
+        out = [x + y for x, y in zip(out + [Fraction(0)] * (len(term) - len(out)), [c * t for t in term] + [Fraction(0)] * (len(out) - len(term)))]
+    return out
+
+
+@pytest.mark.parametrize("tol", [1e-2, 1e-3])
+def test_merge_invariants_exact(setup, tol):
+    """Merged nodes partition the exact pieces; each node's residual, recomputed in exact
+    rational arithmetic from the integer pieces, is within tol * peak in the RMS sense, and
+    the node polynomial reproduces the field's moments 0..D (it is the L2 projection)."""
+    s = setup
+    D = s["D"]
+    tau, sigma = s["q"]
+    o, v = _ray(13)
+    f = field.ray_field(o, v, -10.0, 10.0, s["xyz"], s["h"], s["val"], s["table"], s["q"], s["K"], D, s["kind"], tol)
+    pieces, nodes, M = f["pieces"], f["nodes"], f["merger"]
+    assert pieces and nodes
+    assert nodes[0]["a"] == pieces[0][0] and nodes[-1]["b"] == pieces[-1][1]
+    starts = {p[0] for p in pieces}
+    for A, B in zip(nodes[:-1], nodes[1:]):
+        assert A["b"] == B["a"] and B["a"] in starts
+    assert len(nodes) < len(pieces)
+    pk = Fraction(f["peak"])
+    for node in nodes[:: max(1, len(nodes) // 6)]:
+        a, b = node["a"], node["b"]
+        inside = [p for p in pieces if a <= p[0] and p[1] <= b]
+        Lw = Fraction(b - a)
+        # exact field pieces in the node's u-coordinate
+        segs = []
+        for (ta, tb, coefs, _) in inside:
+            p = _exact_poly(coefs, ta, tb, sigma)            # in u_p on [0,1]
+            lo, hi = Fraction(ta - a) / Lw, Fraction(tb - a) / Lw
+            # u_p = (u - lo) / (hi - lo)
+            segs.append((lo, hi, _compose_affine(p, -lo / (hi - lo), 1 / (hi - lo))))
+        Pn = [Fraction(x) for x in M.to_power(node)]
+        # moments: int F u^j = int P u^j, j <= D
+        for j in range(D + 1):
+            mono = [Fraction(0)] * j + [Fraction(1)]
+            mf = sum(_int_poly(_pmul(pp, mono), lo, hi) for lo, hi, pp in segs)
+            mp = _int_poly(_pmul(Pn, mono), 0, 1)
+            scale = sum(_int_poly(_pmul(pp, pp), lo, hi) for lo, hi, pp in segs)
+            assert abs(float(mf - mp)) <= 1e-9 * math.sqrt(float(scale)) + 1e-300
+        resid = Fraction(0)
+        for lo, hi, pp in segs:
+            diff = [x - y for x, y in zip(pp + [Fraction(0)] * (len(Pn) - len(pp)), Pn + [Fraction(0)] * (len(pp) - len(Pn)))]
+            resid += _int_poly(_pmul(diff, diff), lo, hi)
+        resid_world = resid * Lw * Fraction(tau)
+        assert float(resid_world) <= float((Fraction(tol) * pk) ** 2 * Lw * Fraction(tau)) * (1 + 1e-9)
+        assert abs(float(resid_world) - node["r"]) <= 1e-6 * float((Fraction(tol) * pk) ** 2 * Lw * Fraction(tau))
+
+
+def test_merge_greedy_maximal_within_chunks(setup):
+    """Within a chunk, a node was closed only because adding the next piece failed the test."""
+    s = setup
+    o, v = _ray(14)
+    tol = 1e-3
+    hits, sk = field.ray_knots(o, v, -10.0, 10.0, s["xyz"], s["h"], s["val"], s["table"], s["q"], s["K"], s["D"], s["kind"])
+    pieces, _ = field.exact_pieces(sk)
+    tau, sigma = s["q"]
+    M = field.Merger(s["D"], tau, sigma)
+    pk = field.peak(pieces, sigma)
+    chunk_of = {p[0]: p[3] // field.MERGE_CHUNK for p in pieces}
+    nodes, _ = field.merge(sk, pieces, tol, tau, sigma, s["D"])
+    by_start = {p[0]: p for p in pieces}
+    for A, B in zip(nodes[:-1], nodes[1:]):
+        if chunk_of[A["a"]] == chunk_of[B["a"]]:
+            nxt = by_start[B["a"]]
+            # greedy state of A: rebuild by merging A's pieces from the left
+            cur = None
+            for p in pieces:
+                if A["a"] <= p[0] < A["b"]:
+                    leaf = M.leaf(p[0], p[1], p[2])
+                    cur = leaf if cur is None else M.combine(cur, leaf)
+            cand = M.combine(cur, M.leaf(nxt[0], nxt[1], nxt[2]))
+            assert not M.passes(cand, tol, pk)
+
+
+def test_field_close_to_sph_truth(setup):
+    """The exact quantized field approximates the true SPH sum along the ray
+    (relative L2 error of the order of E_{4,2} ~ 0.8 %, plus the nearest-entry error of a
+    32-entry table: 2.2 % measured; 16 % with 8 entries, 1.4 % with 128)."""
+    s = setup
+    o, v = _ray(15)
+    tau, sigma = s["q"]
+    f = field.ray_field(o, v, -10.0, 10.0, s["xyz"], s["h"], s["val"], s["table"], s["q"], s["K"], s["D"], s["kind"], 0.0)
+    ts = np.linspace(f["pieces"][0][0] * tau, f["pieces"][-1][1] * tau, 4001)
+    chi = geometry.widen(s["xyz"])
+    z = geometry.widen(s["h"])
+    val = geometry.widen(s["val"])
+    truth = np.zeros_like(ts)
+    for i, t in enumerate(ts):
+        r = np.linalg.norm(chi - (o + t * v), axis=1) / z
+        truth[i] = np.sum(val / z ** 3 * kernels.w("cubic", r))
+    approx = np.zeros_like(ts)
+    for (ta, tb, c, _) in f["pieces"]:
+        m = (ts >= ta * tau) & (ts < tb * tau)
+        x = ts[m] / tau - ta
+        approx[m] = sigma * sum(float(c[d]) * x ** d for d in range(len(c)))
+    rel = np.sqrt(np.sum((approx - truth) ** 2) / np.sum(truth ** 2))
+    assert rel < 0.03
+
+
+def test_render_special_cases(setup):
+    s = setup
+    o, v = _ray(16)
+    tau, sigma = s["q"]
+    f = field.ray_field(o, v, -10.0, 10.0, s["xyz"], s["h"], s["val"], s["table"], s["q"], s["K"], s["D"], s["kind"], 0.0)
+    out = [field.node_output(n, f["merger"]) for n in f["nodes"]]
+    t0, t1 = out[0][0], out[-1][1]
+    # zero emission, constant extinction: alpha = 1 - exp(-sigma * covered length)
+    tf = np.zeros((4, 4))
+    tf[:, 3] = 0.7
+    px = render.composite(out, t0 - 1, t1 + 1, tf, 0.0, 1.0, 1e9)
+    assert abs(px[3] - (1 - math.exp(-0.7 * (t1 - t0)))) < 1e-12 and np.all(px[:3] == 0)
+    # emission linear in v, no extinction: pixel -> k * integral of F as the step shrinks
+    vmax = 2 * f["peak"]
+    tf = np.zeros((2, 4))
+    tf[1, 0] = 1.0  # red emission = v / vmax
+    exact = Fraction(0)
+    for (ta, tb, c, _) in f["pieces"]:
+        L = tb - ta
+        exact += Fraction(sigma) * sum(Fraction(int(c[d])) * Fraction(L) ** (d + 1) / (d + 1) for d in range(len(c))) * Fraction(tau)
+    px = render.composite(out, t0 - 1, t1 + 1, tf, 0.0, vmax, (t1 - t0) / 20000)
+    assert abs(px[0] - float(exact) / vmax) < 1e-6 * abs(float(exact) / vmax)
+    # empty ray
+    assert np.all(render.composite([], 0.0, 1.0, tf, 0.0, 1.0, 0.01) == 0)
+
+
+def test_geometry_against_direct_formula():
+    rng = np.random.default_rng(3)
+    o, v = synth.random_rays(4, 50)
+    xyz, h, _ = synth.random_scene(6, 50)
+    for i in range(50):
+        oo, vv = o[i].astype(np.float64), v[i].astype(np.float64)
+        lam2, tchi = geometry.pair_terms(oo[None], vv[None], geometry.widen(xyz), geometry.widen(h))
+        dx = geometry.widen(xyz) - oo
+        t_ref = dx @ vv
+        perp = dx - np.outer(t_ref, vv)
+        lam_ref = np.linalg.norm(perp, axis=1) / geometry.widen(h)
+        assert np.allclose(tchi, t_ref, rtol=0, atol=1e-12)
+        # float32 directions are unit only to ~1e-7, which both formulas see differently
+        assert np.allclose(np.sqrt(lam2), lam_ref, rtol=1e-6, atol=1e-9)
+
+
+def test_camera_rays_are_unit_and_centered():
+    cam = synth.plain_camera(8, 6)
+    o, v = geometry.camera_rays(cam)
+    assert np.allclose(np.linalg.norm(v, axis=1), 1.0, atol=1e-15)
+    c = v.reshape(6, 8, 3)
+    mid = 0.25 * (c[2, 3] + c[2, 4] + c[3, 3] + c[3, 4])
+    f = np.array([0.0, 0.0, 2.0]) / 2.0
+    assert np.allclose(mid / np.linalg.norm(mid), f, atol=1e-12)
+    # top row looks up (+y), left column looks towards -x for this right-handed frame
+    assert c[0, 3, 1] > 0 and c[5, 3, 1] < 0
+    cam2 = synth.tiny_camera(4, 4)
+    o2, v2 = geometry.camera_rays(cam2)
+    assert np.allclose(v2, [0.0, 0.0, 1.0]) and np.allclose(o2[:, 2], -0.2)
+
+
+def test_grid_levels_and_morton():
+    xyz, h, val = synth.random_scene(7, 500, h_lo=0.005, h_hi=0.08)
+    g, codes, perm = grid.morton_order(xyz, h)
+    qz = 2.0 * geometry.widen(h)
+    c = g["c0"] * 2.0 ** g["level"]
+    assert np.all(qz <= c) and np.all((g["level"] == 0) | (qz > c / 2))
+    assert math.frexp(g["c0"])[0] == 0.5  # power of two
+    # Morton code against a bitwise interleave written differently
+    for i in range(0, 500, 37):
+        ix, iy, iz = (int(x) for x in g["cell"][i])
+        ref = 0
+        for b in range(21):
+            ref |= ((ix >> b) & 1) << (3 * b) | ((iy >> b) & 1) << (3 * b + 1) | ((iz >> b) & 1) << (3 * b + 2)
+        assert int(codes[i]) == ref
+    keys = list(zip(g["level"][perm], codes[perm], perm))
+    assert keys == sorted(keys)
+
+
+def test_amax_bounds_the_field():
+    kind = "cubic"
+    xyz, h, val = synth.random_scene(8, 300, h_lo=0.02, h_hi=0.15, signed=True)
+    am = grid.a_max(kind, xyz, h, val)
+    chi = geometry.widen(xyz)
+    z = geometry.widen(h)
+    v = geometry.widen(val)
+    rng = np.random.default_rng(0)
+    pts = np.concatenate([chi[rng.integers(0, 300, 200)], rng.uniform(-0.1, 1.1, (200, 3))])
+    for x in pts:
+        r = np.linalg.norm(chi - x, axis=1) / z
+        fld = np.sum(np.abs(v) / z ** 3 * kernels.w(kind, r))
+        assert fld <= am / grid.AMAX_MARGIN
