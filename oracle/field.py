@@ -172,7 +172,12 @@ class Merger:
         return U
 
     def passes(self, node, tol, pk):
-        return node["r"] <= (tol * pk) ** 2 * (float(node["b"] - node["a"]) * self.tau)
+        thr = (tol * pk) ** 2 * (float(node["b"] - node["a"]) * self.tau)
+        if thr > 0.0:
+            self.margin = min(self.margin, abs(node["r"] - thr) / thr)
+        return node["r"] <= thr
+
+    margin = float("inf")  # smallest relative distance of a merge decision from its threshold
 
     def to_power(self, node):
         """Coefficients c_d of the node's polynomial in powers of u = (t - t_a) / (t_b - t_a)."""
@@ -236,7 +241,7 @@ def ray_field(o, v, t_min, t_max, xyz, zeta, value, table, quanta, K, D, kind, t
     tau, sigma = quanta
     nodes, M = merge(sk, pieces, tol, tau, sigma, D)
     return {"hits": hits, "knots": sk, "pieces": pieces, "tail": tail, "peak": peak(pieces, sigma),
-            "nodes": nodes, "merger": M}
+            "nodes": nodes, "merger": M, "margin": M.margin}
 
 
 def node_output(node, M):

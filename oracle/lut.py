@@ -245,12 +245,15 @@ def _local_opt(kind, lam, K, D, y0, s):
 
 
 def default_starts(P: int):
+    """Fixed grid of starting shapes y = theta / s for the multistart (Sec. 3.4 asks for a
+    global optimum; neighbouring local optima can differ by ~1 % in E^2, so the
+    starts cover the plausible region rather than a few guesses)."""
     if P == 1:
-        return [[0.5], [0.7], [0.9]]
+        return [[0.3 + 0.1 * i] for i in range(9)]
     if P == 2:
-        return [[0.3, 0.8], [0.5, 0.9], [0.6, 0.95], [0.2, 0.6], [0.4, 0.7]]
+        return [[y1, y2] for y1 in (0.2, 0.3, 0.4, 0.5, 0.6) for y2 in (0.7, 0.8, 0.9, 1.0, 1.1)]
     if P == 3:
-        return [[0.2, 0.5, 0.9], [0.3, 0.6, 0.95], [0.35, 0.7, 0.97], [0.15, 0.4, 0.75]]
+        return [[y1, y2, y3] for y1 in (0.15, 0.3, 0.45) for y2 in (0.5, 0.65, 0.8) for y3 in (0.9, 1.0, 1.1)]
     raise ValueError("K <= 6 supported")
 
 
