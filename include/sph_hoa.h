@@ -1,0 +1,213 @@
+/*
+ * sph_hoa.h - C ABI of the MI355X library for particle-wise higher-order SPH
+ * field approximation on viewing rays (arXiv 2401.02896, "Particle-Wise
+ * Higher-Order SPH Field Approximation for DVR").
+ *
+ * Pipeline (Sec. 2, three passes): for every ray, each SPH particle whose
+ * kernel support the ray crosses contributes an L2-optimal even piecewise
+ * polynomial of degree D with K pieces (Sec. 3), quantized to integer knots
+ * (Sec. 4.2-4.3); per ray the knots are sorted and accumulated exactly with
+ * the integer update rule (Eq. accumulation-rule); the resulting exact field
+ * is merged under an error bound and classified / composited front to back.
+ *
+ * Conventions for every call:
+ *  - All array arguments are DEVICE pointers (hipMalloc'd or torch tensors on
+ *    the current ROCm device) unless stated otherwise; the caller owns them.
+ *  - `stream` is a hipStream_t (NULL = default stream).  Work is enqueued on
+ *    it; calls that must report counts synchronise it (stated per call).
+ *  - No call throws across the ABI.  Every call returns a status; on failure
+ *    sph_hoa_last_error() (thread-local) holds a detail message and outputs
+ *    are unspecified except where stated.
+ *  - Host-detectable argument errors are reported before anything is launched.
+ */
+#ifndef SPH_HOA_H
+#define SPH_HOA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SPH_HOA_OK = 0,
+  SPH_HOA_E_INVALID_ARG = 1,   /* bad argument: NULL, NaN, h <= 0, non-unit direction, bad K/D ... */
+  SPH_HOA_E_OUT_OF_MEMORY = 2, /* device allocation failed, or a caller capacity is too small */
+  SPH_HOA_E_OVERFLOW = 3,      /* a quantized position or coefficient leaves its integer range */
+  SPH_HOA_E_DEVICE = 4,        /* HIP runtime error */
+  SPH_HOA_E_UNSUPPORTED = 5,   /* configuration outside the implemented range */
+  SPH_HOA_E_INTERNAL = 6       /* an internal invariant failed (e.g. a ray's knots did not cancel) */
+} sph_hoa_status;
+
+typedef enum {
+  SPH_HOA_KERNEL_CUBIC = 0,       /* cubic B-spline, Eq. cubic-kernel, support q = 2 */
+  SPH_HOA_KERNEL_WENDLAND_C2 = 1  /* (21/16pi)(1-r/2)^4(1+2r), support q = 2 */
+} sph_hoa_kernel;
+
+/* approx_rays: also return the sorted knots and the pre-merge exact integer pieces */
+#define SPH_HOA_FLAG_EXACT 1u
+
+/* Method parameters (Sec. 3.2 K and D, Sec. 4.4 quanta, Sec. 5 bit length). */
+typedef struct {
+  int32_t degree;       /* D: polynomial degree, 1..6 */
+  int32_t pieces;       /* K: non-trivial pieces per particle, 1..6, with K*D >= 2 */
+  int32_t lut_entries;  /* number of equidistant Lambda table entries (Sec. 3.1); 0 -> 4096; 2..65536 */
+  int32_t int_bits;     /* integer bit length (Sec. 5.1); only 64 is implemented; 0 -> 64 */
+  double merge_tol;     /* merge tolerance relative to the ray's peak; 0 disables merging */
+  double a_max;         /* > 0: bound on |field| used for sigma = a_max / INT_MAX (Sec. 4.4); else derived */
+  double h_repr;        /* > 0: representative smoothing length (Sec. 4.4); else lower median of h */
+  double phi_repr;      /* > 0: representative amplitude / h^3; else lower median of |value| / h^3 */
+  double tau;           /* > 0: length quantum to use instead of the minimiser of Q_D */
+  const double* knot_table; /* optional HOST array [lut_entries][ceil(K/2)] of optimal knots theta_k
+                               (units of h) replacing the library's own optimisation (Sec. 3.4); copied */
+  uint32_t flags;       /* reserved, 0 */
+} sph_hoa_params;
+
+typedef struct sph_hoa_index_s* sph_hoa_index; /* opaque; owns its device memory */
+
+/* Read-back of the quantities an index was built with (host struct). */
+typedef struct {
+  int64_t n_particles;
+  int32_t kernel, degree, pieces, lut_entries;
+  double tau, sigma, a_max, h_repr, phi_repr;
+  double grid_lo[3];
+  double cell0;         /* finest cell size c_0 (a power of two) */
+  int32_t n_levels;
+  int32_t level_dims[32][3];
+} sph_hoa_index_info;
+
+/* Rays x(t) = origin + t * dir, t in [t_min, t_max] (Fig. 1). */
+typedef struct {
+  int64_t n;
+  const float* origin;  /* device [n][3] */
+  const float* dir;     /* device [n][3], unit length (|dir|^2 within 1e-5 of 1) */
+  float t_min, t_max;   /* t_min < t_max, |t| < 2^30 * tau */
+} sph_hoa_rays;
+
+/* Output of approx_rays.  Merged piece i of ray r is index ray_offsets[r] + j:
+ * F(t) = sum_d coef[i][d] * u^d with u = (t - t_start[i]) / (t_end[i] - t_start[i]),
+ * valid on [t_start[i], t_end[i]]; the field is zero outside a ray's pieces. */
+typedef struct {
+  int64_t capacity;      /* pieces allocated by the caller */
+  int64_t* ray_offsets;  /* device [n + 1] */
+  float* t_start;        /* device [capacity] */
+  float* t_end;          /* device [capacity] */
+  float* coef;           /* device [capacity][D + 1] */
+  float* ray_peak;       /* device [n]: sigma * max |a_0| over the ray's exact pieces */
+  /* outputs written by the call (host fields): */
+  int64_t n_pieces;      /* merged pieces written (or needed, on E_OUT_OF_MEMORY) */
+  int64_t n_pairs;       /* (particle, ray) contributions */
+  int64_t n_knots;
+  int64_t n_exact_pieces;
+  /* exact mode (params flags of the call = SPH_HOA_FLAG_EXACT); all device, may be NULL otherwise */
+  int64_t exact_capacity;  /* capacity of exact_t / exact_coef (pieces) */
+  int64_t* exact_offsets;  /* [n + 1] */
+  int64_t* exact_t;        /* [exact_capacity] start of the piece in quanta (end = next start) */
+  int64_t* exact_end;      /* [exact_capacity] end of the piece in quanta */
+  int64_t* exact_coef;     /* [exact_capacity][D + 1] integer localized coefficients a_d */
+  int64_t knot_capacity;   /* capacity of the knot arrays */
+  int64_t* knot_offsets;   /* [n + 1] */
+  int64_t* knot_t;         /* [knot_capacity] knot position in quanta, sorted per ray */
+  int32_t* knot_pid;       /* [knot_capacity] particle input index (ties broken by pid, then kidx) */
+  int32_t* knot_kidx;      /* [knot_capacity] k + ceil(K/2) for the knot at t0 + sign(k) o_|k| */
+} sph_hoa_field;
+
+typedef struct {
+  float eye[3], look_at[3], up[3];
+  float fov_y_deg;          /* perspective vertical field of view */
+  int32_t ortho;            /* 1: orthographic, rays parallel to look_at - eye */
+  float ortho_half_extent;  /* orthographic half height of the view */
+  int32_t width, height;    /* pixels; ray index = row * width + col, row 0 at the top */
+  float t_min, t_max;       /* ray segment */
+} sph_hoa_camera;
+
+/* 1-D transfer function: n RGBA control points equally spaced on [v_min, v_max],
+ * linearly interpolated and clamped; rgb = emission density, a = extinction. */
+typedef struct {
+  const float* rgba;  /* device [n][4] */
+  int32_t n;          /* >= 2 */
+  float v_min, v_max; /* v_max > v_min */
+  float step;         /* sampling step along the ray (world units), > 0 */
+} sph_hoa_tf;
+
+/* Counters of the last approx_rays / render on an index (host struct). */
+typedef struct {
+  int64_t n_rays;
+  int64_t n_pairs;
+  int64_t n_knots;
+  int64_t n_pieces;       /* merged pieces (render: pieces composited) */
+  int64_t max_hits;       /* largest number of contributions on one ray */
+  int64_t rays_global;    /* rays processed from device memory instead of LDS */
+} sph_hoa_stats;
+
+/*
+ * Build the particle index and the per-configuration tables.
+ *  xyz [n][3], h [n] (> 0), value [n] (amplitude m*alpha/rho, Sec. 1): device float32, copied.
+ *  Computes the optimal-knot table and projection coefficients (Sec. 3.1-3.4) for
+ *  (kernel, K, D, lut_entries), the quanta tau and sigma (Sec. 4.4), and a
+ *  multi-level Morton grid of the particles.  Synchronises `stream`.
+ *  On success *out receives a handle to free with sph_hoa_index_free.
+ */
+sph_hoa_status sph_hoa_build_index(const float* xyz, const float* h, const float* value, int64_t n,
+                                   sph_hoa_kernel kernel, const sph_hoa_params* params, void* stream,
+                                   sph_hoa_index* out);
+
+/*
+ * Per-ray higher-order field for arbitrary rays (Sec. 2 passes 1-3 without
+ * classification).  Writes out->ray_offsets, pieces and ray_peak; fills the
+ * host counters of *out.  flags: 0 or SPH_HOA_FLAG_EXACT.  Synchronises `stream`.
+ * If out->capacity (or an exact-mode capacity) is too small, returns
+ * SPH_HOA_E_OUT_OF_MEMORY with the required count in n_pieces (and
+ * n_exact_pieces / n_knots); nothing else is guaranteed then.
+ */
+sph_hoa_status sph_hoa_approx_rays(sph_hoa_index idx, const sph_hoa_rays* rays, sph_hoa_field* out,
+                                   uint32_t flags, void* stream);
+
+/*
+ * Render: camera rays, per-ray field, merge with the index's merge_tol,
+ * classification with `tf` and front-to-back emission-absorption compositing.
+ * rgba_out: device float32 [height][width][4] (premultiplied colour, alpha = 1 - T).
+ * Asynchronous on `stream` except for one read of the per-frame hit counts.
+ */
+sph_hoa_status sph_hoa_render(sph_hoa_index idx, const sph_hoa_camera* cam, const sph_hoa_tf* tf,
+                              float* rgba_out, void* stream);
+
+sph_hoa_status sph_hoa_index_free(sph_hoa_index idx);
+
+/* Host copy of the index parameters. */
+sph_hoa_status sph_hoa_index_get_info(sph_hoa_index idx, sph_hoa_index_info* info);
+
+/* Host copies of the table: theta [lut_entries][P], shat [lut_entries][P][D+1] (jump
+ * coefficients at +theta_k), smid [lut_entries][D+1] (jump at 0, even K); any may be NULL. */
+sph_hoa_status sph_hoa_index_get_lut(sph_hoa_index idx, double* theta, double* shat, double* smid);
+
+/* Device copies of the grid keys: morton [n] (Morton code of the particle's cell), level [n],
+ * order [n] (input index of the i-th particle in (level, Morton, index) order); any may be NULL. */
+sph_hoa_status sph_hoa_index_get_grid(sph_hoa_index idx, uint64_t* morton, int32_t* level, int32_t* order,
+                                      void* stream);
+
+/* Counters of the last call on this index; synchronises the stream of that call. */
+sph_hoa_status sph_hoa_index_get_stats(sph_hoa_index idx, sph_hoa_stats* stats);
+
+/* Host-only: the library's optimal knots for one Lambda (Sec. 3.4), theta_out[ceil(K/2)],
+ * and the squared L2 error of the optimum.  No GPU work. */
+sph_hoa_status sph_hoa_optimal_knots(sph_hoa_kernel kernel, int32_t pieces, int32_t degree, double lambda,
+                                     double* theta_out, double* err2_out);
+
+/* Host-only: the library's optimal-knot table (Sec. 3.1, 3.4) for n equidistant Lambda_i = (i + 1/2) q / n,
+ * theta_out[n][ceil(K/2)], and the squared L2 error of each entry err2_out[n] (may be NULL). */
+sph_hoa_status sph_hoa_knot_table(sph_hoa_kernel kernel, int32_t pieces, int32_t degree, int32_t n, double* theta_out,
+                                  double* err2_out);
+
+/* Host-only: the length quantum minimising Q_D(tau / h_repr, sigma / phi_repr) (Sec. 4.4, App. A.5). */
+sph_hoa_status sph_hoa_optimal_tau(sph_hoa_kernel kernel, int32_t degree, double sigma, double h_repr,
+                                   double phi_repr, double* tau_out);
+
+const char* sph_hoa_status_string(sph_hoa_status s);
+const char* sph_hoa_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPH_HOA_H */

@@ -1,0 +1,330 @@
+"""Python binding of libsph_hoa (include/sph_hoa.h): argument marshalling only.
+
+Every step of the path runs in the HIP library; this module converts torch
+tensors on the ROCm device into the pointers and structs of the C ABI and
+raises ``SphHoaError`` on any non-OK status.  If the library has not been
+built (``python -m paper_2401_02896_amd.build``), importing the binding
+functions raises immediately: there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsph_hoa.so")
+
+KERNEL_CUBIC = 0
+KERNEL_WENDLAND_C2 = 1
+FLAG_EXACT = 1
+
+STATUS = {0: "OK", 1: "E_INVALID_ARG", 2: "E_OUT_OF_MEMORY", 3: "E_OVERFLOW", 4: "E_DEVICE", 5: "E_UNSUPPORTED",
+          6: "E_INTERNAL"}
+
+
+class SphHoaError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("degree", ctypes.c_int32), ("pieces", ctypes.c_int32), ("lut_entries", ctypes.c_int32),
+                ("int_bits", ctypes.c_int32), ("merge_tol", ctypes.c_double), ("a_max", ctypes.c_double),
+                ("h_repr", ctypes.c_double), ("phi_repr", ctypes.c_double), ("tau", ctypes.c_double),
+                ("knot_table", ctypes.POINTER(ctypes.c_double)), ("flags", ctypes.c_uint32)]
+
+
+class IndexInfo(ctypes.Structure):
+    _fields_ = [("n_particles", ctypes.c_int64), ("kernel", ctypes.c_int32), ("degree", ctypes.c_int32),
+                ("pieces", ctypes.c_int32), ("lut_entries", ctypes.c_int32), ("tau", ctypes.c_double),
+                ("sigma", ctypes.c_double), ("a_max", ctypes.c_double), ("h_repr", ctypes.c_double),
+                ("phi_repr", ctypes.c_double), ("grid_lo", ctypes.c_double * 3), ("cell0", ctypes.c_double),
+                ("n_levels", ctypes.c_int32), ("level_dims", (ctypes.c_int32 * 3) * 32)]
+
+
+class Rays(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("origin", ctypes.c_void_p), ("dir", ctypes.c_void_p),
+                ("t_min", ctypes.c_float), ("t_max", ctypes.c_float)]
+
+
+class Field(ctypes.Structure):
+    _fields_ = [("capacity", ctypes.c_int64), ("ray_offsets", ctypes.c_void_p), ("t_start", ctypes.c_void_p),
+                ("t_end", ctypes.c_void_p), ("coef", ctypes.c_void_p), ("ray_peak", ctypes.c_void_p),
+                ("n_pieces", ctypes.c_int64), ("n_pairs", ctypes.c_int64), ("n_knots", ctypes.c_int64),
+                ("n_exact_pieces", ctypes.c_int64), ("exact_capacity", ctypes.c_int64),
+                ("exact_offsets", ctypes.c_void_p), ("exact_t", ctypes.c_void_p), ("exact_end", ctypes.c_void_p),
+                ("exact_coef", ctypes.c_void_p), ("knot_capacity", ctypes.c_int64), ("knot_offsets", ctypes.c_void_p),
+                ("knot_t", ctypes.c_void_p), ("knot_pid", ctypes.c_void_p), ("knot_kidx", ctypes.c_void_p)]
+
+
+class Camera(ctypes.Structure):
+    _fields_ = [("eye", ctypes.c_float * 3), ("look_at", ctypes.c_float * 3), ("up", ctypes.c_float * 3),
+                ("fov_y_deg", ctypes.c_float), ("ortho", ctypes.c_int32), ("ortho_half_extent", ctypes.c_float),
+                ("width", ctypes.c_int32), ("height", ctypes.c_int32), ("t_min", ctypes.c_float),
+                ("t_max", ctypes.c_float)]
+
+
+class TF(ctypes.Structure):
+    _fields_ = [("rgba", ctypes.c_void_p), ("n", ctypes.c_int32), ("v_min", ctypes.c_float), ("v_max", ctypes.c_float),
+                ("step", ctypes.c_float)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("n_rays", ctypes.c_int64), ("n_pairs", ctypes.c_int64), ("n_knots", ctypes.c_int64),
+                ("n_pieces", ctypes.c_int64), ("max_hits", ctypes.c_int64), ("rays_global", ctypes.c_int64)]
+
+
+EXPORTS = ["sph_hoa_build_index", "sph_hoa_approx_rays", "sph_hoa_render", "sph_hoa_index_free",
+           "sph_hoa_index_get_info", "sph_hoa_index_get_lut", "sph_hoa_index_get_grid", "sph_hoa_index_get_stats",
+           "sph_hoa_optimal_knots", "sph_hoa_knot_table", "sph_hoa_optimal_tau", "sph_hoa_status_string", "sph_hoa_last_error"]
+
+_lib = None
+
+
+def lib():
+    """The loaded library (loads it on first use; raises if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2401_02896_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i64, i32, u32, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32, ctypes.c_double
+    L.sph_hoa_build_index.argtypes = [vp, vp, vp, i64, ctypes.c_int, ctypes.POINTER(Params), vp, ctypes.POINTER(vp)]
+    L.sph_hoa_approx_rays.argtypes = [vp, ctypes.POINTER(Rays), ctypes.POINTER(Field), u32, vp]
+    L.sph_hoa_render.argtypes = [vp, ctypes.POINTER(Camera), ctypes.POINTER(TF), vp, vp]
+    L.sph_hoa_index_free.argtypes = [vp]
+    L.sph_hoa_index_get_info.argtypes = [vp, ctypes.POINTER(IndexInfo)]
+    L.sph_hoa_index_get_lut.argtypes = [vp, vp, vp, vp]
+    L.sph_hoa_index_get_grid.argtypes = [vp, vp, vp, vp, vp]
+    L.sph_hoa_index_get_stats.argtypes = [vp, ctypes.POINTER(Stats)]
+    L.sph_hoa_optimal_knots.argtypes = [ctypes.c_int, i32, i32, dbl, ctypes.POINTER(dbl), ctypes.POINTER(dbl)]
+    L.sph_hoa_knot_table.argtypes = [ctypes.c_int, i32, i32, i32, vp, vp]
+    L.sph_hoa_optimal_tau.argtypes = [ctypes.c_int, i32, dbl, dbl, dbl, ctypes.POINTER(dbl)]
+    L.sph_hoa_status_string.argtypes = [ctypes.c_int]
+    L.sph_hoa_status_string.restype = ctypes.c_char_p
+    L.sph_hoa_last_error.restype = ctypes.c_char_p
+    for name in EXPORTS[:-2]:
+        getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(status):
+    if status != 0:
+        raise SphHoaError(status, lib().sph_hoa_last_error().decode())
+
+
+def _stream():
+    import torch
+
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _dev_f32(a, shape_last=None):
+    import torch
+
+    t = a if isinstance(a, torch.Tensor) else torch.as_tensor(a)
+    t = t.to(device="cuda", dtype=torch.float32).contiguous()
+    return t
+
+
+class Index:
+    """Owns an sph_hoa_index handle (sph_hoa_build_index / sph_hoa_index_free)."""
+
+    def __init__(self, handle, K, D, n):
+        self.handle = handle
+        self.K, self.D, self.n = K, D, n
+
+    def free(self):
+        if self.handle:
+            _check(lib().sph_hoa_index_free(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def info(self):
+        inf = IndexInfo()
+        _check(lib().sph_hoa_index_get_info(self.handle, ctypes.byref(inf)))
+        return {"n_particles": inf.n_particles, "kernel": inf.kernel, "degree": inf.degree, "pieces": inf.pieces,
+                "lut_entries": inf.lut_entries, "tau": inf.tau, "sigma": inf.sigma, "a_max": inf.a_max,
+                "h_repr": inf.h_repr, "phi_repr": inf.phi_repr, "grid_lo": list(inf.grid_lo), "cell0": inf.cell0,
+                "n_levels": inf.n_levels,
+                "level_dims": [list(inf.level_dims[l]) for l in range(inf.n_levels)]}
+
+    def lut(self):
+        import numpy as np
+
+        inf = self.info()
+        n, P, D = inf["lut_entries"], (self.K + 1) // 2, self.D
+        theta = np.zeros((n, P))
+        shat = np.zeros((n, P, D + 1))
+        smid = np.zeros((n, D + 1))
+        _check(lib().sph_hoa_index_get_lut(self.handle, theta.ctypes.data_as(ctypes.c_void_p),
+                                           shat.ctypes.data_as(ctypes.c_void_p), smid.ctypes.data_as(ctypes.c_void_p)))
+        return theta, shat, smid
+
+    def grid(self):
+        import torch
+
+        morton = torch.empty(self.n, dtype=torch.int64, device="cuda")
+        level = torch.empty(self.n, dtype=torch.int32, device="cuda")
+        order = torch.empty(self.n, dtype=torch.int32, device="cuda")
+        _check(lib().sph_hoa_index_get_grid(self.handle, _ptr(morton), _ptr(level), _ptr(order), _stream()))
+        return morton, level, order
+
+    def stats(self):
+        s = Stats()
+        _check(lib().sph_hoa_index_get_stats(self.handle, ctypes.byref(s)))
+        return {f: getattr(s, f) for f, _ in Stats._fields_}
+
+
+def sph_hoa_build_index(xyz, h, value, kernel=KERNEL_CUBIC, degree=2, pieces=4, lut_entries=4096, merge_tol=1e-3,
+                        a_max=0.0, h_repr=0.0, phi_repr=0.0, tau=0.0, knot_table=None):
+    """Build an index (sph_hoa_build_index).  xyz [n,3], h [n], value [n]: tensors or arrays."""
+    import numpy as np
+
+    x = _dev_f32(xyz)
+    hh = _dev_f32(h)
+    v = _dev_f32(value)
+    n = int(hh.numel())
+    if x.numel() != 3 * n or v.numel() != n:
+        raise ValueError("xyz must be [n, 3], h and value [n]")
+    p = Params(degree, pieces, lut_entries, 64, merge_tol, a_max, h_repr, phi_repr, tau, None, 0)
+    kt = None
+    if knot_table is not None:
+        kt = np.ascontiguousarray(knot_table, dtype=np.float64)
+        p.knot_table = kt.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    handle = ctypes.c_void_p()
+    _check(lib().sph_hoa_build_index(_ptr(x), _ptr(hh), _ptr(v), n, kernel, ctypes.byref(p), _stream(),
+                                     ctypes.byref(handle)))
+    return Index(handle, pieces, degree, n)
+
+
+def sph_hoa_approx_rays(index, origin, direction, t_min, t_max, capacity=None, exact=False, exact_capacity=None):
+    """Per-ray merged fields (sph_hoa_approx_rays).  Returns a dict of device tensors and counts.
+
+    capacity: pieces to allocate (default: grows and retries once on E_OUT_OF_MEMORY).
+    """
+    import torch
+
+    o = _dev_f32(origin).reshape(-1, 3)
+    d = _dev_f32(direction).reshape(-1, 3)
+    n = o.shape[0]
+    D = index.D
+    cap = capacity if capacity is not None else max(1024, 64 * n)
+    ecap = exact_capacity if exact_capacity is not None else max(1024, 64 * n)
+    for attempt in range(2):
+        offs = torch.empty(n + 1, dtype=torch.int64, device="cuda")
+        t0 = torch.empty(max(cap, 1), dtype=torch.float32, device="cuda")
+        t1 = torch.empty(max(cap, 1), dtype=torch.float32, device="cuda")
+        coef = torch.empty(max(cap, 1) * (D + 1), dtype=torch.float32, device="cuda")
+        peak = torch.empty(max(n, 1), dtype=torch.float32, device="cuda")
+        f = Field()
+        f.capacity = cap
+        f.ray_offsets, f.t_start, f.t_end, f.coef, f.ray_peak = (_ptr(offs).value, _ptr(t0).value, _ptr(t1).value,
+                                                                 _ptr(coef).value, _ptr(peak).value)
+        ex = {}
+        if exact:
+            ex["offsets"] = torch.empty(n + 1, dtype=torch.int64, device="cuda")
+            ex["t"] = torch.empty(max(ecap, 1), dtype=torch.int64, device="cuda")
+            ex["end"] = torch.empty(max(ecap, 1), dtype=torch.int64, device="cuda")
+            ex["coef"] = torch.empty(max(ecap, 1) * (D + 1), dtype=torch.int64, device="cuda")
+            kcap = ex.get("kcap", ecap)
+            ex["knot_offsets"] = torch.empty(n + 1, dtype=torch.int64, device="cuda")
+            ex["knot_t"] = torch.empty(max(kcap, 1), dtype=torch.int64, device="cuda")
+            ex["knot_pid"] = torch.empty(max(kcap, 1), dtype=torch.int32, device="cuda")
+            ex["knot_kidx"] = torch.empty(max(kcap, 1), dtype=torch.int32, device="cuda")
+            f.exact_capacity = ecap
+            f.exact_offsets, f.exact_t, f.exact_end, f.exact_coef = (_ptr(ex["offsets"]).value, _ptr(ex["t"]).value,
+                                                                     _ptr(ex["end"]).value, _ptr(ex["coef"]).value)
+            f.knot_capacity = kcap
+            f.knot_offsets, f.knot_t, f.knot_pid, f.knot_kidx = (_ptr(ex["knot_offsets"]).value,
+                                                                 _ptr(ex["knot_t"]).value, _ptr(ex["knot_pid"]).value,
+                                                                 _ptr(ex["knot_kidx"]).value)
+        r = Rays(n, _ptr(o).value, _ptr(d).value, t_min, t_max)
+        st = lib().sph_hoa_approx_rays(index.handle, ctypes.byref(r), ctypes.byref(f), FLAG_EXACT if exact else 0,
+                                       _stream())
+        if st == 2 and attempt == 0 and capacity is None:
+            cap = max(cap, int(f.n_pieces) + 1)
+            ecap = max(ecap, int(f.n_exact_pieces) + 1, int(f.n_knots) + 1)
+            continue
+        _check(st)
+        break
+    out = {"ray_offsets": offs, "t_start": t0[: f.n_pieces], "t_end": t1[: f.n_pieces],
+           "coef": coef[: f.n_pieces * (D + 1)].reshape(-1, D + 1), "ray_peak": peak[:n], "n_pieces": f.n_pieces,
+           "n_pairs": f.n_pairs, "n_knots": f.n_knots, "n_exact_pieces": f.n_exact_pieces}
+    if exact:
+        out["exact_offsets"] = ex["offsets"]
+        out["exact_t"] = ex["t"][: f.n_exact_pieces]
+        out["exact_end"] = ex["end"][: f.n_exact_pieces]
+        out["exact_coef"] = ex["coef"][: f.n_exact_pieces * (D + 1)].reshape(-1, D + 1)
+        out["knot_offsets"] = ex["knot_offsets"]
+        out["knot_t"] = ex["knot_t"][: f.n_knots]
+        out["knot_pid"] = ex["knot_pid"][: f.n_knots]
+        out["knot_kidx"] = ex["knot_kidx"][: f.n_knots]
+    return out
+
+
+def make_camera(cam: dict) -> Camera:
+    c = Camera()
+    c.eye[:] = [float(x) for x in cam["eye"]]
+    c.look_at[:] = [float(x) for x in cam["look_at"]]
+    c.up[:] = [float(x) for x in cam["up"]]
+    c.fov_y_deg = float(cam.get("fov_y_deg", 0.0))
+    c.ortho = int(cam.get("ortho", 0))
+    c.ortho_half_extent = float(cam.get("ortho_half_extent", 0.0))
+    c.width, c.height = int(cam["width"]), int(cam["height"])
+    c.t_min, c.t_max = float(cam["t_min"]), float(cam["t_max"])
+    return c
+
+
+def sph_hoa_render(index, camera: dict, tf_rgba, v_min, v_max, step, out=None):
+    """Render an image (sph_hoa_render); returns a [height, width, 4] float32 device tensor."""
+    import torch
+
+    c = make_camera(camera)
+    tf = _dev_f32(tf_rgba).reshape(-1, 4)
+    if out is None:
+        out = torch.empty((c.height, c.width, 4), dtype=torch.float32, device="cuda")
+    t = TF(_ptr(tf).value, tf.shape[0], v_min, v_max, step)
+    _check(lib().sph_hoa_render(index.handle, ctypes.byref(c), ctypes.byref(t), _ptr(out), _stream()))
+    return out
+
+
+def sph_hoa_optimal_knots(kernel, pieces, degree, lam):
+    """Library's optimal knots for one distance parameter (host only)."""
+    import numpy as np
+
+    P = (pieces + 1) // 2
+    th = (ctypes.c_double * P)()
+    e2 = ctypes.c_double()
+    _check(lib().sph_hoa_optimal_knots(kernel, pieces, degree, lam, th, ctypes.byref(e2)))
+    return np.array(list(th)), e2.value
+
+
+def sph_hoa_knot_table(kernel, pieces, degree, n):
+    """Library's optimal-knot table and per-entry squared errors (host only)."""
+    import numpy as np
+
+    th = np.zeros((n, (pieces + 1) // 2))
+    e2 = np.zeros(n)
+    _check(lib().sph_hoa_knot_table(kernel, pieces, degree, n, th.ctypes.data_as(ctypes.c_void_p),
+                                    e2.ctypes.data_as(ctypes.c_void_p)))
+    return th, e2
+
+
+def sph_hoa_optimal_tau(kernel, degree, sigma, h_repr, phi_repr):
+    """Library's length quantum (host only)."""
+    t = ctypes.c_double()
+    _check(lib().sph_hoa_optimal_tau(kernel, degree, sigma, h_repr, phi_repr, ctypes.byref(t)))
+    return t.value

@@ -1,0 +1,332 @@
+// C ABI of the library (include/sph_hoa.h): argument checking, index lifetime,
+// table caching and the choice of quanta; device work lives in index.hip and
+// raycast.hip.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <tuple>
+
+#include "impl.h"
+
+struct sph_hoa_index_s {
+  sph::Index ix;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+sph_hoa_status fail(sph_hoa_status s, const std::string& m) {
+  g_last_error = m;
+  return s;
+}
+
+template <class F>
+sph_hoa_status guarded(F&& f) {
+  try {
+    g_last_error.clear();
+    f();
+    return SPH_HOA_OK;
+  } catch (const sph::Error& e) {
+    return fail(e.status, e.what());
+  } catch (const std::bad_alloc&) {
+    return fail(SPH_HOA_E_OUT_OF_MEMORY, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(SPH_HOA_E_INTERNAL, e.what());
+  }
+}
+
+void require(bool ok, const std::string& m) {
+  if (!ok) throw sph::Error(SPH_HOA_E_INVALID_ARG, m);
+}
+
+int host_threads() {
+  const unsigned h = std::thread::hardware_concurrency();
+  return (int)std::max(1u, std::min(h, 32u));
+}
+
+// Tables from the library's own optimisation, shared between indices of one process.
+std::mutex g_table_mu;
+std::map<std::tuple<int, int, int, int>, std::shared_ptr<const sph::Table>> g_tables;
+
+std::shared_ptr<const sph::Table> cached_table(sph::Kernel k, int K, int D, int n) {
+  const auto key = std::make_tuple((int)k, K, D, n);
+  {
+    std::lock_guard<std::mutex> lk(g_table_mu);
+    auto it = g_tables.find(key);
+    if (it != g_tables.end()) return it->second;
+  }
+  auto t = std::make_shared<const sph::Table>(sph::build_table(k, K, D, n, nullptr, host_threads()));
+  std::lock_guard<std::mutex> lk(g_table_mu);
+  g_tables[key] = t;
+  return t;
+}
+
+sph::Kernel kernel_of(sph_hoa_kernel k) {
+  if (k == SPH_HOA_KERNEL_CUBIC) return sph::Kernel::Cubic;
+  if (k == SPH_HOA_KERNEL_WENDLAND_C2) return sph::Kernel::Wendland;
+  throw sph::Error(SPH_HOA_E_INVALID_ARG, "unknown kernel");
+}
+
+void check_method(int K, int D) {
+  require(D >= 1 && D <= sph::kMaxD, "degree must be in 1..6");
+  require(K >= 1 && K <= 6, "pieces must be in 1..6");
+  require((K * D) / 2 >= 1, "K = D = 1 leaves only the zero function");
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* sph_hoa_status_string(sph_hoa_status s) {
+  switch (s) {
+    case SPH_HOA_OK: return "ok";
+    case SPH_HOA_E_INVALID_ARG: return "invalid argument";
+    case SPH_HOA_E_OUT_OF_MEMORY: return "out of memory or capacity too small";
+    case SPH_HOA_E_OVERFLOW: return "integer range exceeded";
+    case SPH_HOA_E_DEVICE: return "device error";
+    case SPH_HOA_E_UNSUPPORTED: return "unsupported configuration";
+    case SPH_HOA_E_INTERNAL: return "internal invariant failed";
+  }
+  return "unknown status";
+}
+
+const char* sph_hoa_last_error(void) { return g_last_error.c_str(); }
+
+sph_hoa_status sph_hoa_build_index(const float* xyz, const float* h, const float* value, int64_t n,
+                                   sph_hoa_kernel kernel, const sph_hoa_params* p, void* stream,
+                                   sph_hoa_index* out) {
+  if (!out) return fail(SPH_HOA_E_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  std::unique_ptr<sph_hoa_index_s> H(new sph_hoa_index_s());
+  const sph_hoa_status s = guarded([&]() {
+    require(xyz && h && value && p, "NULL argument");
+    require(n > 0 && n < (int64_t(1) << 31), "particle count must be in 1..2^31-1");
+    const sph::Kernel k = kernel_of(kernel);
+    check_method(p->pieces, p->degree);
+    const int n_lut = p->lut_entries == 0 ? 4096 : p->lut_entries;
+    require(n_lut >= 2 && n_lut <= 65536, "lut_entries must be in 2..65536");
+    require(p->int_bits == 0 || p->int_bits == 64, "only 64-bit integers are implemented");
+    require(std::isfinite(p->merge_tol) && p->merge_tol >= 0.0, "merge_tol must be finite and >= 0");
+    require(std::isfinite(p->a_max) && std::isfinite(p->h_repr) && std::isfinite(p->phi_repr) &&
+                std::isfinite(p->tau), "quanta parameters must be finite");
+    require(p->flags == 0, "params.flags is reserved");
+    sph::Index& ix = H->ix;
+    ix.n = n;
+    ix.kernel = k;
+    ix.K = p->pieces;
+    ix.D = p->degree;
+    ix.P = (p->pieces + 1) / 2;
+    ix.n_lut = n_lut;
+    ix.merge_tol = p->merge_tol;
+    ix.a_max = p->a_max > 0 ? p->a_max : 0.0;
+    ix.h_repr = p->h_repr > 0 ? p->h_repr : 0.0;
+    ix.phi_repr = p->phi_repr > 0 ? p->phi_repr : 0.0;
+    if (p->knot_table) {
+      for (int64_t i = 0; i < (int64_t)n_lut * ix.P; ++i)
+        require(std::isfinite(p->knot_table[i]) && p->knot_table[i] > 0.0, "knot_table entries must be > 0");
+      for (int i = 0; i < n_lut; ++i)
+        for (int m = 1; m < ix.P; ++m)
+          require(p->knot_table[i * ix.P + m] > p->knot_table[i * ix.P + m - 1], "knot_table rows must increase");
+      ix.table = sph::build_table(k, ix.K, ix.D, n_lut, p->knot_table, host_threads());
+    } else {
+      ix.table = *cached_table(k, ix.K, ix.D, n_lut);
+    }
+    hipStream_t st = (hipStream_t)stream;
+    ix.lut_theta.ensure(sizeof(double) * ix.table.theta.size());
+    ix.lut_shat.ensure(sizeof(double) * ix.table.shat.size());
+    sph::hip_check(hipMemcpyAsync(ix.lut_theta.p, ix.table.theta.data(), sizeof(double) * ix.table.theta.size(),
+                                  hipMemcpyHostToDevice, st), "copy");
+    sph::hip_check(hipMemcpyAsync(ix.lut_shat.p, ix.table.shat.data(), sizeof(double) * ix.table.shat.size(),
+                                  hipMemcpyHostToDevice, st), "copy");
+    sph::build_index_device(ix, xyz, h, value, st);
+    const double int_max = 9223372036854775807.0;  // 2^63 - 1 (rounds to 2^63 in double)
+    if (ix.a_max > 0.0) {
+      ix.sigma = ix.a_max / int_max;
+    } else {
+      ix.sigma = 1.0;  // every amplitude is zero: any quantum represents the zero field
+    }
+    if (p->tau > 0) {
+      ix.tau = p->tau;
+    } else if (ix.phi_repr > 0.0) {
+      ix.tau = sph::optimal_tau(k, ix.D, ix.sigma, ix.h_repr, ix.phi_repr);
+    } else {
+      ix.tau = ix.h_repr * 1e-3;
+    }
+    require(ix.tau > 0.0 && std::isfinite(ix.tau), "could not determine a length quantum");
+  });
+  if (s != SPH_HOA_OK) return s;
+  *out = H.release();
+  return SPH_HOA_OK;
+}
+
+sph_hoa_status sph_hoa_index_free(sph_hoa_index idx) {
+  if (!idx) return fail(SPH_HOA_E_INVALID_ARG, "NULL index");
+  return guarded([&]() {
+    if (idx->ix.last_stream) (void)hipStreamSynchronize(idx->ix.last_stream);
+    delete idx;
+  });
+}
+
+sph_hoa_status sph_hoa_approx_rays(sph_hoa_index idx, const sph_hoa_rays* rays, sph_hoa_field* out, uint32_t flags,
+                                   void* stream) {
+  return guarded([&]() {
+    require(idx && rays && out, "NULL argument");
+    require(flags == 0 || flags == SPH_HOA_FLAG_EXACT, "unknown flags");
+    require(rays->n >= 0 && rays->n < (int64_t(1) << 31), "ray count must be in 0..2^31-1");
+    require(std::isfinite(rays->t_min) && std::isfinite(rays->t_max) && rays->t_min < rays->t_max,
+            "need finite t_min < t_max");
+    require(out->capacity >= 0, "capacity must be >= 0");
+    if (rays->n > 0) {
+      require(rays->origin && rays->dir, "NULL ray arrays");
+      require(out->ray_offsets && out->ray_peak, "NULL output arrays");
+      require(out->capacity == 0 || (out->t_start && out->t_end && out->coef), "NULL piece arrays");
+    }
+    const bool exact = (flags & SPH_HOA_FLAG_EXACT) != 0;
+    if (exact && rays->n > 0) {
+      require(out->exact_offsets && out->knot_offsets, "exact mode needs offset arrays");
+      require(out->exact_capacity == 0 || (out->exact_t && out->exact_end && out->exact_coef), "exact arrays");
+      require(out->knot_capacity == 0 || (out->knot_t && out->knot_pid && out->knot_kidx), "knot arrays");
+    }
+    sph::Index& ix = idx->ix;
+    const double span = std::max(std::fabs((double)rays->t_min), std::fabs((double)rays->t_max)) +
+                        ix.grid.lv[ix.grid.n_levels - 1].c;
+    if (!(span / ix.tau < 1.0e9)) throw sph::Error(SPH_HOA_E_OVERFLOW, "ray segment too long for int32 positions");
+    sph::FieldOut fo{out, nullptr, nullptr, exact};
+    hipStream_t st = (hipStream_t)stream;
+    ix.last_stream = st;
+    if (rays->n == 0) {
+      out->n_pieces = out->n_pairs = out->n_knots = out->n_exact_pieces = 0;
+      if (out->ray_offsets) {
+        const int64_t z = 0;
+        sph::hip_check(hipMemcpyAsync(out->ray_offsets, &z, 8, hipMemcpyHostToDevice, st), "copy");
+        sph::hip_check(hipStreamSynchronize(st), "sync");
+      }
+      return;
+    }
+    sph::run_rays(ix, rays->n, false, nullptr, rays, fo, st);
+  });
+}
+
+sph_hoa_status sph_hoa_render(sph_hoa_index idx, const sph_hoa_camera* cam, const sph_hoa_tf* tf, float* rgba_out,
+                              void* stream) {
+  return guarded([&]() {
+    require(idx && cam && tf && rgba_out, "NULL argument");
+    require(cam->width > 0 && cam->height > 0 && (int64_t)cam->width * cam->height < (int64_t(1) << 31),
+            "bad image size");
+    require(std::isfinite(cam->t_min) && std::isfinite(cam->t_max) && cam->t_min < cam->t_max,
+            "need finite t_min < t_max");
+    for (int k = 0; k < 3; ++k)
+      require(std::isfinite(cam->eye[k]) && std::isfinite(cam->look_at[k]) && std::isfinite(cam->up[k]),
+              "camera vectors must be finite");
+    if (cam->ortho)
+      require(std::isfinite(cam->ortho_half_extent) && cam->ortho_half_extent > 0, "ortho_half_extent must be > 0");
+    else
+      require(cam->fov_y_deg > 0 && cam->fov_y_deg < 180, "fov_y_deg must be in (0, 180)");
+    const double fx = (double)cam->look_at[0] - cam->eye[0], fy = (double)cam->look_at[1] - cam->eye[1],
+                 fz = (double)cam->look_at[2] - cam->eye[2];
+    const double cx = fy * cam->up[2] - fz * cam->up[1], cy = fz * cam->up[0] - fx * cam->up[2],
+                 cz = fx * cam->up[1] - fy * cam->up[0];
+    require(fx * fx + fy * fy + fz * fz > 0 && cx * cx + cy * cy + cz * cz > 0, "degenerate camera frame");
+    require(tf->rgba && tf->n >= 2, "transfer function needs >= 2 control points");
+    require(std::isfinite(tf->v_min) && std::isfinite(tf->v_max) && tf->v_max > tf->v_min, "need v_min < v_max");
+    require(std::isfinite(tf->step) && tf->step > 0, "step must be > 0");
+    sph::Index& ix = idx->ix;
+    const double span = std::max(std::fabs((double)cam->t_min), std::fabs((double)cam->t_max)) +
+                        ix.grid.lv[ix.grid.n_levels - 1].c;
+    if (!(span / ix.tau < 1.0e9)) throw sph::Error(SPH_HOA_E_OVERFLOW, "ray segment too long for int32 positions");
+    hipStream_t st = (hipStream_t)stream;
+    ix.last_stream = st;
+    sph::FieldOut fo{nullptr, rgba_out, tf, false};
+    sph::run_rays(ix, (int64_t)cam->width * cam->height, true, cam, nullptr, fo, st);
+  });
+}
+
+sph_hoa_status sph_hoa_index_get_info(sph_hoa_index idx, sph_hoa_index_info* info) {
+  return guarded([&]() {
+    require(idx && info, "NULL argument");
+    const sph::Index& ix = idx->ix;
+    std::memset(info, 0, sizeof(*info));
+    info->n_particles = ix.n;
+    info->kernel = (int)ix.kernel;
+    info->degree = ix.D;
+    info->pieces = ix.K;
+    info->lut_entries = ix.n_lut;
+    info->tau = ix.tau;
+    info->sigma = ix.sigma;
+    info->a_max = ix.a_max;
+    info->h_repr = ix.h_repr;
+    info->phi_repr = ix.phi_repr;
+    for (int a = 0; a < 3; ++a) info->grid_lo[a] = ix.grid.lo[a];
+    info->cell0 = ix.cell0;
+    info->n_levels = ix.grid.n_levels;
+    for (int l = 0; l < ix.grid.n_levels; ++l)
+      for (int a = 0; a < 3; ++a) info->level_dims[l][a] = ix.grid.lv[l].n[a];
+  });
+}
+
+sph_hoa_status sph_hoa_index_get_lut(sph_hoa_index idx, double* theta, double* shat, double* smid) {
+  return guarded([&]() {
+    require(idx, "NULL index");
+    const sph::Table& t = idx->ix.table;
+    if (theta) std::memcpy(theta, t.theta.data(), sizeof(double) * t.theta.size());
+    if (shat) std::memcpy(shat, t.shat.data(), sizeof(double) * t.shat.size());
+    if (smid) std::memcpy(smid, t.smid.data(), sizeof(double) * t.smid.size());
+  });
+}
+
+sph_hoa_status sph_hoa_index_get_grid(sph_hoa_index idx, uint64_t* morton, int32_t* level, int32_t* order,
+                                      void* stream) {
+  return guarded([&]() {
+    require(idx, "NULL index");
+    sph::get_grid_device(idx->ix, morton, level, order, (hipStream_t)stream);
+  });
+}
+
+sph_hoa_status sph_hoa_index_get_stats(sph_hoa_index idx, sph_hoa_stats* stats) {
+  return guarded([&]() {
+    require(idx && stats, "NULL argument");
+    if (idx->ix.last_stream) sph::hip_check(hipStreamSynchronize(idx->ix.last_stream), "sync");
+    *stats = idx->ix.stats;
+  });
+}
+
+sph_hoa_status sph_hoa_optimal_knots(sph_hoa_kernel kernel, int32_t pieces, int32_t degree, double lambda,
+                                     double* theta_out, double* err2_out) {
+  return guarded([&]() {
+    require(theta_out && err2_out, "NULL argument");
+    check_method(pieces, degree);
+    require(lambda >= 0.0 && lambda < sph::kSupport, "lambda must be in [0, q)");
+    const sph::Kernel k = kernel_of(kernel);
+    sph::optimal_knots(k, pieces, degree, lambda, sph::default_starts((pieces + 1) / 2), theta_out, err2_out);
+  });
+}
+
+sph_hoa_status sph_hoa_knot_table(sph_hoa_kernel kernel, int32_t pieces, int32_t degree, int32_t n,
+                                  double* theta_out, double* err2_out) {
+  return guarded([&]() {
+    require(theta_out, "NULL argument");
+    check_method(pieces, degree);
+    require(n >= 2 && n <= 65536, "n must be in 2..65536");
+    auto t = cached_table(kernel_of(kernel), pieces, degree, n);
+    std::memcpy(theta_out, t->theta.data(), sizeof(double) * t->theta.size());
+    if (err2_out) std::memcpy(err2_out, t->err2.data(), sizeof(double) * t->err2.size());
+  });
+}
+
+sph_hoa_status sph_hoa_optimal_tau(sph_hoa_kernel kernel, int32_t degree, double sigma, double h_repr,
+                                   double phi_repr, double* tau_out) {
+  return guarded([&]() {
+    require(tau_out, "NULL argument");
+    require(degree >= 1 && degree <= sph::kMaxD, "degree must be in 1..6");
+    require(sigma > 0 && h_repr > 0 && phi_repr > 0, "sigma, h_repr, phi_repr must be > 0");
+    *tau_out = sph::optimal_tau(kernel_of(kernel), degree, sigma, h_repr, phi_repr);
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,136 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/sph_hoa.h"
+#include "tables.h"
+
+namespace sph {
+
+constexpr int kMaxLevels = 32;
+constexpr int kMaxD = 6;
+constexpr int kMaxP = 3;
+constexpr int kChunk = 16;          // knots per merge chunk
+constexpr int kFieldThreads = 256;  // threads per ray work-group
+constexpr int64_t kMaxAxisCells = int64_t(1) << 19;
+constexpr int64_t kMaxLevel0Cells = int64_t(1) << 24;
+constexpr double kAmaxMargin = 1.25;
+
+// error-flag bits raised by kernels
+enum : uint32_t {
+  kFlagBadInput = 1u,       // NaN / h <= 0 / non-unit direction
+  kFlagPosRange = 2u,       // a quantized position left the int32 range
+  kFlagCoefRange = 4u,      // a quantized coefficient left |x| < 2^62
+  kFlagTail = 8u,           // a ray's accumulated coefficients did not return to zero
+  kFlagWindow = 16u,        // grid enumeration window too small (internal)
+  kFlagCapacity = 32u,      // an output capacity was exceeded
+};
+
+struct Error : std::runtime_error {
+  sph_hoa_status status;
+  Error(sph_hoa_status s, const std::string& m) : std::runtime_error(m), status(s) {}
+};
+
+inline void hip_check(hipError_t e, const char* what) {
+  if (e != hipSuccess) throw Error(SPH_HOA_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+struct LevelInfo {
+  double c, inv_c;
+  int n[3];
+  int64_t cell_off;  // offset of this level's cells in the cell arrays
+  int64_t n_particles;
+};
+
+struct GridDev {
+  double lo[3];
+  int n_levels;
+  LevelInfo lv[kMaxLevels];
+};
+
+// Device buffer that grows on demand and frees itself.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  void ensure(size_t b) {
+    if (b <= bytes) return;
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+    if (b == 0) return;
+    hipError_t e = hipMalloc(&p, b);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      throw Error(SPH_HOA_E_OUT_OF_MEMORY, "device allocation of " + std::to_string(b) + " bytes failed");
+    }
+    bytes = b;
+  }
+  template <class T>
+  T* as() const { return static_cast<T*>(p); }
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+};
+
+// Per-call constants of the method.
+struct MethodConsts {
+  int K, D, P, even_k, n_lut, kernel;
+  double tau, sigma, q, merge_tol;
+};
+
+struct Index {
+  int64_t n = 0;
+  Kernel kernel = Kernel::Cubic;
+  int K = 4, D = 2, P = 2, n_lut = 4096;
+  double tau = 0, sigma = 0, a_max = 0, h_repr = 0, phi_repr = 0, merge_tol = 0;
+  GridDev grid{};
+  double cell0 = 0;
+  int grid_bits = 1;  // Morton bits per axis in the sort keys
+  Table table;
+  // device data (Morton order)
+  DevBuf pos4;    // float4 x, y, z, h
+  DevBuf val;     // float amplitude
+  DevBuf orig;    // int32 input index
+  DevBuf morton;  // uint64 key (level << 57 | morton)
+  DevBuf cell_begin, cell_end;  // uint32 per cell, all levels
+  DevBuf lut_theta, lut_shat;   // double
+  // per-call scratch
+  DevBuf rays_o, rays_v;        // double [n][3]
+  DevBuf hit_count, hit_off;    // int64 [n + 1]
+  DevBuf hits;                  // uint32 [pairs]
+  DevBuf scan_tmp;
+  DevBuf counters;              // uint64 small counters / flags
+  DevBuf slab;                  // per-work-group node / heavy-ray storage
+  DevBuf ray_meta;              // per-ray outputs of the field kernel
+  DevBuf out_stage, exact_stage;
+  sph_hoa_stats stats{};
+  hipStream_t last_stream = nullptr;
+};
+
+// build (index.hip)
+void build_index_device(Index& ix, const float* xyz, const float* h, const float* value, hipStream_t st);
+void get_grid_device(Index& ix, uint64_t* morton, int32_t* level, int32_t* order, hipStream_t st);
+
+// per-frame (raycast.hip)
+struct FieldOut {
+  sph_hoa_field* field;  // approx mode (null for render)
+  float* rgba;           // render mode
+  const sph_hoa_tf* tf;
+  bool exact;
+};
+void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam, const sph_hoa_rays* rays,
+              FieldOut& out, hipStream_t st);
+
+// small device utilities (util.hip)
+void device_exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, DevBuf& tmp, hipStream_t st);
+
+}  // namespace sph

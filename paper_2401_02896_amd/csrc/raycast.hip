@@ -1,0 +1,1403 @@
+// Per-frame path: rays, hit gathering, and the per-ray field kernel.
+//
+// Sec. 2 describes three passes: (1) approximate every particle on all rays
+// it affects, (2) sort each ray's knots by position, (3) accumulate them,
+// classify and composite.  Here pass 1 is split into a hit-gathering kernel
+// (one wave per ray walks the multi-level grid and tests candidates with the
+// exact float64 predicate) and the knot generation inside the per-ray
+// kernel, which then sorts, accumulates (Eq. accumulation-rule, exact in
+// wrap-around 64-bit integers), merges and either writes the merged pieces or
+// composites them - all for one ray per work-group, in LDS.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+
+#include "device.h"
+#include "impl.h"
+
+namespace sph {
+
+namespace {
+
+// ============================================================== rays
+
+struct CamDev {
+  double eye[3], f[3], r[3], u[3];
+  double g, aspect, half;  // tan(fov/2), W/H, ortho half extent
+  int W, H, ortho;
+};
+
+__global__ void k_camera_rays(CamDev c, int64_t n, double* o, double* v) {
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
+    const double col = (double)(p % c.W), row = (double)(p / c.W);
+    const double a = (2.0 * col + 1.0) / (double)c.W - 1.0;
+    const double b = 1.0 - (2.0 * row + 1.0) / (double)c.H;
+    if (c.ortho) {
+      const double sa = a * c.half * c.aspect, sb = b * c.half;
+      for (int k = 0; k < 3; ++k) {
+        o[3 * p + k] = c.eye[k] + sa * c.r[k] + sb * c.u[k];
+        v[3 * p + k] = c.f[k];
+      }
+    } else {
+      const double sa = a * c.g * c.aspect, sb = b * c.g;
+      const double dx = c.f[0] + sa * c.r[0] + sb * c.u[0];
+      const double dy = c.f[1] + sa * c.r[1] + sb * c.u[1];
+      const double dz = c.f[2] + sa * c.r[2] + sb * c.u[2];
+      const double nrm = sqrt(dx * dx + dy * dy + dz * dz);
+      v[3 * p] = dx / nrm;
+      v[3 * p + 1] = dy / nrm;
+      v[3 * p + 2] = dz / nrm;
+      for (int k = 0; k < 3; ++k) o[3 * p + k] = c.eye[k];
+    }
+  }
+}
+
+__global__ void k_widen_rays(const float* of, const float* vf, int64_t n, double* o, double* v, uint32_t* flags) {
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    bool bad = false;
+    for (int k = 0; k < 3; ++k) {
+      const float a = of[3 * p + k], b = vf[3 * p + k];
+      if (!isfinite(a) || !isfinite(b)) bad = true;
+      o[3 * p + k] = (double)a;
+      v[3 * p + k] = (double)b;
+      s += (double)b * (double)b;
+    }
+    if (bad || !(fabs(s - 1.0) <= 1e-5)) atomicOr(flags, kFlagBadInput);
+  }
+}
+
+// ============================================================== hit gathering
+
+constexpr int kGatherThreads = 256;  // four waves, one ray each
+
+struct GatherArgs {
+  const double* o;
+  const double* v;
+  int64_t n_rays;
+  double t_min, t_max;
+  const float4* pos4;
+  const uint32_t* cbeg;
+  const uint32_t* cend;
+  GridDev g;
+  int64_t* count;       // count pass: hits per ray
+  const int64_t* off;   // fill pass: offsets
+  uint32_t* hits;       // fill pass: permuted particle indices
+  unsigned long long* max_hits;
+  uint32_t* flags;
+};
+
+// Exact contribution test (same float64 operation order as the oracle).
+__device__ __forceinline__ bool pair_hit(const double o[3], const double v[3], float4 p, double t_min, double t_max) {
+  const double dxx = (double)p.x - o[0], dxy = (double)p.y - o[1], dxz = (double)p.z - o[2];
+  const double cx = dxy * v[2] - dxz * v[1];
+  const double cy = dxz * v[0] - dxx * v[2];
+  const double cz = dxx * v[1] - dxy * v[0];
+  const double z = (double)p.w;
+  const double lam2 = (cx * cx + cy * cy + cz * cz) / (z * z);
+  if (!(lam2 < kSupport * kSupport)) return false;
+  const double tchi = dxx * v[0] + dxy * v[1] + dxz * v[2];
+  const double s = sqrt(kSupport * kSupport - lam2);
+  const double sz = s * z;
+  return (tchi + sz > t_min) && (tchi - sz < t_max);
+}
+
+template <bool FILL>
+__global__ void __launch_bounds__(kGatherThreads) k_gather(GatherArgs A) {
+  __shared__ int64_t s_excl[kGatherThreads];
+  __shared__ uint32_t s_beg[kGatherThreads];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t r = (int64_t)blockIdx.x * (kGatherThreads / 64) + w;
+  if (r >= A.n_rays) return;  // whole wave leaves together
+  double o[3], v[3];
+  for (int k = 0; k < 3; ++k) {
+    o[k] = A.o[3 * r + k];
+    v[k] = A.v[3 * r + k];
+  }
+  int64_t* ex = s_excl + w * 64;
+  uint32_t* bg = s_beg + w * 64;
+  int64_t found = 0;
+  const int64_t out0 = FILL ? A.off[r] : 0;
+  // dominant axis
+  int ax = 0;
+  if (fabs(v[1]) > fabs(v[ax])) ax = 1;
+  if (fabs(v[2]) > fabs(v[ax])) ax = 2;
+  const int bx = (ax + 1) % 3, ex_ax = (ax + 2) % 3;
+  for (int l = 0; l < A.g.n_levels; ++l) {
+    const LevelInfo& L = A.g.lv[l];
+    if (L.n_particles == 0) continue;
+    const double c = L.c, ic = L.inv_c, eps = c * 1e-7;
+    // clip the segment to the box in which it can reach this level's particles
+    double ta = A.t_min, tb = A.t_max;
+    bool empty = false;
+    for (int a = 0; a < 3; ++a) {
+      const double bmin = A.g.lo[a] - c - eps, bmax = A.g.lo[a] + (double)(L.n[a] + 1) * c + eps;
+      if (v[a] == 0.0) {
+        if (o[a] < bmin || o[a] > bmax) empty = true;
+      } else {
+        double t1 = (bmin - o[a]) / v[a], t2 = (bmax - o[a]) / v[a];
+        if (t1 > t2) {
+          const double tt = t1;
+          t1 = t2;
+          t2 = tt;
+        }
+        ta = fmax(ta, t1);
+        tb = fmin(tb, t2);
+      }
+    }
+    if (empty || !(ta <= tb)) continue;
+    const double a0 = o[ax] + ta * v[ax], a1 = o[ax] + tb * v[ax];
+    int64_t s_lo = (int64_t)floor((fmin(a0, a1) - c - eps - A.g.lo[ax]) * ic);
+    int64_t s_hi = (int64_t)floor((fmax(a0, a1) + c + eps - A.g.lo[ax]) * ic);
+    s_lo = max(s_lo, (int64_t)0);
+    s_hi = min(s_hi, (int64_t)L.n[ax] - 1);
+    if (s_hi < s_lo) continue;
+    const int64_t total = (s_hi - s_lo + 1) * 49;
+    for (int64_t base = 0; base < total; base += 64) {
+      const int64_t idx = base + lane;
+      int64_t cnt = 0;
+      uint32_t cb = 0;
+      if (idx < total) {
+        const int64_t s = s_lo + idx / 49;
+        const int wi = (int)(idx % 49), wb = wi / 7, we = wi % 7;
+        double t1 = (A.g.lo[ax] + (double)(s - 1) * c - eps - o[ax]) / v[ax];
+        double t2 = (A.g.lo[ax] + (double)(s + 2) * c + eps - o[ax]) / v[ax];
+        if (t1 > t2) {
+          const double tt = t1;
+          t1 = t2;
+          t2 = tt;
+        }
+        t1 = fmax(t1, ta);
+        t2 = fmin(t2, tb);
+        if (t1 <= t2) {
+          const double b1 = o[bx] + t1 * v[bx], b2 = o[bx] + t2 * v[bx];
+          const double e1 = o[ex_ax] + t1 * v[ex_ax], e2 = o[ex_ax] + t2 * v[ex_ax];
+          int64_t cb_lo = (int64_t)floor((fmin(b1, b2) - c - eps - A.g.lo[bx]) * ic);
+          int64_t cb_hi = (int64_t)floor((fmax(b1, b2) + c + eps - A.g.lo[bx]) * ic);
+          int64_t ce_lo = (int64_t)floor((fmin(e1, e2) - c - eps - A.g.lo[ex_ax]) * ic);
+          int64_t ce_hi = (int64_t)floor((fmax(e1, e2) + c + eps - A.g.lo[ex_ax]) * ic);
+          if (cb_hi - cb_lo > 6 || ce_hi - ce_lo > 6) atomicOr(A.flags, kFlagWindow);
+          cb_lo = max(cb_lo, (int64_t)0);
+          ce_lo = max(ce_lo, (int64_t)0);
+          cb_hi = min(cb_hi, (int64_t)L.n[bx] - 1);
+          ce_hi = min(ce_hi, (int64_t)L.n[ex_ax] - 1);
+          const int64_t ib = cb_lo + wb, ie = ce_lo + we;
+          if (ib <= cb_hi && ie <= ce_hi) {
+            int64_t cc[3];
+            cc[ax] = s;
+            cc[bx] = ib;
+            cc[ex_ax] = ie;
+            const int64_t cell = L.cell_off + cc[0] + (int64_t)L.n[0] * (cc[1] + (int64_t)L.n[1] * cc[2]);
+            cb = A.cbeg[cell];
+            cnt = (int64_t)A.cend[cell] - (int64_t)cb;
+          }
+        }
+      }
+      const int64_t incl = wave_incl_scan(cnt);
+      const int64_t tot = __shfl(incl, 63, 64);
+      ex[lane] = incl - cnt;
+      bg[lane] = cb;
+      __builtin_amdgcn_wave_barrier();
+      for (int64_t k = 0; k < tot; k += 64) {
+        const int64_t ci = k + lane;
+        bool hit = false;
+        uint32_t j = 0;
+        if (ci < tot) {
+          // owner lane: last lane with ex <= ci
+          int lo = 0, hi = 63;
+          while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (ex[mid] <= ci) lo = mid;
+            else hi = mid - 1;
+          }
+          j = bg[lo] + (uint32_t)(ci - ex[lo]);
+          hit = pair_hit(o, v, A.pos4[j], A.t_min, A.t_max);
+        }
+        const uint64_t m = __ballot(hit);
+        if (FILL && hit) {
+          const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+          A.hits[out0 + found + __popcll(m & lt)] = j;
+        }
+        found += __popcll(m);
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
+  }
+  if (!FILL && lane == 0) {
+    A.count[r] = found;
+    atomicMax(A.max_hits, (unsigned long long)found);
+  }
+}
+
+// ============================================================== per-ray field
+
+struct MergeTables {
+  double node[kMaxD + 1], wgt[kMaxD + 1];          // Gauss-Legendre on [0, 1], D + 1 points
+  double leg_at_node[kMaxD + 1][kMaxD + 1];        // P~_j(node_i) [j][i]
+  double pow2leg[kMaxD + 1][kMaxD + 1];            // gamma_j = sum_d pow2leg[j][d] beta_d
+  double leg2pow[kMaxD + 1][kMaxD + 1];            // c_d = sum_j gamma_j leg2pow[j][d]
+};
+
+struct FieldArgs {
+  // rays
+  const double* o;
+  const double* v;
+  int64_t n_rays;
+  double t_min, t_max;
+  // hits
+  const int64_t* hit_count;
+  const int64_t* hit_off;
+  const uint32_t* hits;
+  // particles (Morton order)
+  const float4* pos4;
+  const float* val;
+  const int32_t* orig;
+  // table
+  const double* theta;  // [n_lut][P]
+  const double* shat;   // [n_lut][P][D+1]
+  MethodConsts mc;
+  MergeTables mt;
+  // scheduling
+  unsigned int* queue;
+  int hn_lds;           // hits that fit the LDS layout
+  char* slab;           // per-work-group global storage
+  int64_t slab_stride;  // bytes per work-group
+  int64_t max_knots;    // largest knot count of any ray (sizes the slab)
+  uint32_t* flags;
+  unsigned long long* counters;  // [0] merged pieces (bump), [1] exact pieces (bump), [2] pieces total, [3] rays_global
+  // approx outputs (staging, bump-allocated)
+  int64_t out_cap;
+  float* st_t0;
+  float* st_t1;
+  float* st_coef;
+  int64_t* ray_out;     // [n][2]: staging offset, count
+  float* ray_peak;
+  // exact mode
+  int exact;
+  int64_t exact_cap;
+  int64_t* ex_t;
+  int64_t* ex_end;
+  int64_t* ex_coef;
+  int64_t* ray_ex;      // [n][2]
+  const int64_t* knot_off;  // [n]
+  int64_t knot_cap;
+  int64_t* kn_t;
+  int32_t* kn_pid;
+  int32_t* kn_kidx;
+  // render
+  const float* tf;
+  int tf_n;
+  float tf_vmin, tf_vmax;
+  double tf_step;
+  float* rgba;
+};
+
+template <int D>
+struct Node {
+  int32_t a, b;
+  double g[D + 1];
+  double r;
+};
+
+__device__ __forceinline__ int64_t rint_i64(double x, uint32_t* flags) {
+  if (!(fabs(x) < 4.6e18)) {
+    atomicOr(flags, kFlagCoefRange);
+    return 0;
+  }
+  return (int64_t)rint(x);
+}
+
+template <int D>
+__device__ __forceinline__ void taylor_shift(uint64_t* a, uint32_t delta) {
+  const uint64_t dd = (uint64_t)delta;
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int j = D - 1; j >= i; --j) a[j] += a[j + 1] * dd;
+}
+
+__device__ __forceinline__ uint64_t binom_u(int n, int k) {
+  uint64_t r = 1;
+  for (int i = 1; i <= k; ++i) r = r * (uint64_t)(n - k + i) / (uint64_t)i;
+  return r;
+}
+
+// Hit record in SoA form.
+struct Recs {
+  int32_t* t0;
+  int32_t* o;   // [3][hn]
+  int32_t* li;
+  int32_t* pid;
+  double* base;
+  double* u;
+};
+
+// LUT-derived quantized jump a_kd of the knot at +theta_k (Eq. quantized-jumps-starting-from-lut).
+template <int D>
+__device__ __forceinline__ void lut_jumps(const double* shat_row, double base, double u, int k, uint64_t* out,
+                                          uint32_t* flags) {
+  double p = 1.0;
+#pragma unroll
+  for (int d = 1; d <= D; ++d) {
+    p = p * u;
+    const double scale = base * p;
+    out[d] = (uint64_t)rint_i64(shat_row[(k - 1) * (D + 1) + d] * scale, flags);
+  }
+  out[0] = 0;
+}
+
+// Jump coefficients of knot kidx of one particle, including the integer closure (Sec. 4.3, App. A.3).
+template <int D>
+__device__ void knot_jump(const MethodConsts& mc, const double* shat_row, double base, double u, const int32_t* off,
+                          int kidx, uint64_t* a, uint32_t* flags) {
+  const int P = mc.P;
+  const int k = kidx - P;
+#pragma unroll
+  for (int d = 0; d <= D; ++d) a[d] = 0;
+  const int kk = k < 0 ? -k : k;
+  if (kk >= 1 && !(mc.even_k == 0 && kk == 1)) {
+    uint64_t j[D + 1];
+    lut_jumps<D>(shat_row, base, u, kk, j, flags);
+#pragma unroll
+    for (int d = 1; d <= D; ++d) a[d] = (k < 0 && (d % 2 == 0)) ? (uint64_t)(0 - j[d]) : j[d];
+    return;
+  }
+  // left-side jumps a_{-m, j} = (-1)^(j+1) a_{m, j} for m = 1..P from the table
+  uint64_t left[kMaxP + 1][D + 1];
+  for (int m = 1; m <= P; ++m) {
+    uint64_t j[D + 1];
+    lut_jumps<D>(shat_row, base, u, m, j, flags);
+#pragma unroll
+    for (int d = 0; d <= D; ++d) left[m][d] = (d % 2 == 0) ? (uint64_t)(0 - j[d]) : j[d];
+  }
+  if (mc.even_k) {
+    // middle knot: a_0d = -2 sum_{m=1..P} sum_{j=d..D} C(j,d) a_{-m,j} o_m^(j-d), odd d
+#pragma unroll
+    for (int d = 1; d <= D; d += 2) {
+      uint64_t acc = 0;
+      for (int m = 1; m <= P; ++m) {
+        const uint64_t om = (uint64_t)(uint32_t)off[m - 1];
+        uint64_t pw = 1;
+        for (int jj = d; jj <= D; ++jj) {
+          acc += binom_u(jj, d) * left[m][jj] * pw;
+          pw *= om;
+        }
+      }
+      a[d] = (uint64_t)0 - 2 * acc;
+    }
+    return;
+  }
+  // odd K, knots -1 and +1: odd d in decreasing order
+  //   a_{-1,d} = -sum_{m=2..P} a_{-m,d} - sum_{j=d+1..D} C(j,d) sum_{m=1..P} a_{-m,j} o_m^(j-d)
+  // (for m = 1 only even j come from the table: odd j use the values already set)
+  for (int jj = 1; jj <= D; jj += 2) left[1][jj] = 0;
+  for (int d = (D % 2 == 1 ? D : D - 1); d >= 1; d -= 2) {
+    uint64_t acc = 0;
+    for (int m = 2; m <= P; ++m) acc += left[m][d];
+    for (int jj = d + 1; jj <= D; ++jj) {
+      uint64_t inner = 0;
+      for (int m = 1; m <= P; ++m) {
+        const uint64_t om = (uint64_t)(uint32_t)off[m - 1];
+        uint64_t pw = 1;
+        for (int e = 0; e < jj - d; ++e) pw *= om;
+        inner += left[m][jj] * pw;
+      }
+      acc += binom_u(jj, d) * inner;
+    }
+    left[1][d] = (uint64_t)0 - acc;
+  }
+  // knot -1: left[1]; knot +1: a_{1,d} = (-1)^(d+1) a_{-1,d}
+#pragma unroll
+  for (int d = 1; d <= D; ++d) a[d] = (k < 0 || (d % 2 == 1)) ? left[1][d] : (uint64_t)(0 - left[1][d]);
+}
+
+// Shifted Legendre P~_j(x) for j = 0..D by the three-term recurrence on y = 2x - 1.
+template <int D>
+__device__ __forceinline__ void legendre_at(double x, double* p) {
+  const double y = 2.0 * x - 1.0;
+  p[0] = 1.0;
+  if (D >= 1) p[1] = y;
+#pragma unroll
+  for (int j = 1; j < D; ++j) p[j + 1] = ((2.0 * j + 1.0) * y * p[j] - (double)j * p[j - 1]) / (double)(j + 1);
+}
+
+template <int D>
+__device__ __forceinline__ Node<D> make_leaf(const MergeTables& mt, int32_t ta, int32_t tb, const uint64_t* coef,
+                                             double sigma) {
+  Node<D> n;
+  n.a = ta;
+  n.b = tb;
+  n.r = 0.0;
+  const double L = (double)((int64_t)tb - (int64_t)ta);
+  double beta[D + 1];
+  double p = 1.0;
+#pragma unroll
+  for (int d = 0; d <= D; ++d) {
+    beta[d] = sigma * (double)(int64_t)coef[d] * p;
+    p *= L;
+  }
+#pragma unroll
+  for (int j = 0; j <= D; ++j) {
+    double s = 0.0;
+#pragma unroll
+    for (int d = 0; d <= D; ++d) s += mt.pow2leg[j][d] * beta[d];
+    n.g[j] = s;
+  }
+  return n;
+}
+
+// Union of adjacent nodes A = [a, b], B = [b, c]: projection and residual (exact from the parts).
+template <int D>
+__device__ Node<D> combine(const MergeTables& mt, const Node<D>& A, const Node<D>& B, double tau) {
+  Node<D> U;
+  U.a = A.a;
+  U.b = B.b;
+  const double la = (double)((int64_t)A.b - (int64_t)A.a), lb = (double)((int64_t)B.b - (int64_t)B.a);
+  const double lam = la / (la + lb);
+  double FA[D + 1], FB[D + 1], PA[D + 1][D + 1], PB[D + 1][D + 1];
+#pragma unroll
+  for (int i = 0; i <= D; ++i) {
+    double fa = 0.0, fb = 0.0;
+#pragma unroll
+    for (int j = 0; j <= D; ++j) {
+      fa += A.g[j] * mt.leg_at_node[j][i];
+      fb += B.g[j] * mt.leg_at_node[j][i];
+    }
+    FA[i] = fa;
+    FB[i] = fb;
+    legendre_at<D>(lam * mt.node[i], PA[i]);
+    legendre_at<D>(lam + (1.0 - lam) * mt.node[i], PB[i]);
+  }
+#pragma unroll
+  for (int j = 0; j <= D; ++j) {
+    double sa = 0.0, sb = 0.0;
+#pragma unroll
+    for (int i = 0; i <= D; ++i) {
+      sa += mt.wgt[i] * FA[i] * PA[i][j];
+      sb += mt.wgt[i] * FB[i] * PB[i][j];
+    }
+    U.g[j] = (2.0 * j + 1.0) * (lam * sa + (1.0 - lam) * sb);
+  }
+  double ra = 0.0, rb = 0.0;
+#pragma unroll
+  for (int i = 0; i <= D; ++i) {
+    double ua = 0.0, ub = 0.0;
+#pragma unroll
+    for (int j = 0; j <= D; ++j) {
+      ua += U.g[j] * PA[i][j];
+      ub += U.g[j] * PB[i][j];
+    }
+    const double da = FA[i] - ua, db = FB[i] - ub;
+    ra += mt.wgt[i] * da * da;
+    rb += mt.wgt[i] * db * db;
+  }
+  U.r = A.r + B.r + la * tau * ra + lb * tau * rb;
+  return U;
+}
+
+template <int D>
+__device__ __forceinline__ bool passes(const Node<D>& n, double thr2, double tau) {
+  return n.r <= thr2 * ((double)((int64_t)n.b - (int64_t)n.a) * tau);
+}
+
+__device__ __forceinline__ int32_t key_t(uint64_t key) { return (int32_t)((uint32_t)(key >> 32) ^ 0x80000000u); }
+__device__ __forceinline__ uint32_t key_slot(uint64_t key) { return (uint32_t)key >> 3; }
+__device__ __forceinline__ int key_kidx(uint64_t key) { return (int)((uint32_t)key & 7u); }
+
+// Scan state carried between threads.
+template <int D>
+struct Agg {
+  int64_t t;  // position of the last knot
+  uint64_t a[D + 1];
+  int valid;
+};
+
+template <int D>
+__device__ __forceinline__ void agg_combine(const Agg<D>& x, const Agg<D>& y, Agg<D>& out) {
+  if (!x.valid) {
+    out = y;
+    return;
+  }
+  if (!y.valid) {
+    out = x;
+    return;
+  }
+  out.t = y.t;
+  out.valid = 1;
+  uint64_t s[D + 1];
+#pragma unroll
+  for (int d = 0; d <= D; ++d) s[d] = x.a[d];
+  taylor_shift<D>(s, (uint32_t)(y.t - x.t));
+#pragma unroll
+  for (int d = 0; d <= D; ++d) out.a[d] = s[d] + y.a[d];
+}
+
+template <int D>
+struct Shared {
+  Agg<D> agg[kFieldThreads];
+  float part[kFieldThreads][4];
+  int64_t cnt[kFieldThreads];
+  unsigned long long peak;
+  int64_t ray;
+  int64_t base_out, base_ex;
+  int n_chunks_ok;
+};
+
+// Per-ray storage carved from LDS or from the work-group's global slab.
+struct RayStore {
+  uint64_t* hkey;
+  Recs rec;
+  uint64_t* kkey;
+  int32_t* ccnt;   // [n_chunks] nodes emitted per chunk
+  int32_t* chead;  // [n_chunks] first live node per chunk
+  int32_t* gfirst; // [n_chunks] group first node ref
+  int32_t* glast;  // [n_chunks] group last node ref
+};
+
+__host__ __device__ inline int64_t align8(int64_t x) { return (x + 7) & ~int64_t(7); }
+
+// bytes of the per-ray layout for nh hits and nk knots
+__host__ __device__ inline int64_t ray_store_bytes(int64_t nh, int64_t nk) {
+  const int64_t nc = (nk + kChunk - 1) / kChunk;
+  return align8(8 * nh) + align8(4 * nh) + align8(12 * nh) + align8(4 * nh) + align8(4 * nh) + 8 * nh + 8 * nh +
+         8 * nk + 4 * align8(4 * nc);
+}
+
+__device__ inline RayStore carve(char* p, int64_t nh, int64_t nk) {
+  RayStore s;
+  const int64_t nc = (nk + kChunk - 1) / kChunk;
+  s.hkey = (uint64_t*)p;
+  p += align8(8 * nh);
+  s.rec.t0 = (int32_t*)p;
+  p += align8(4 * nh);
+  s.rec.o = (int32_t*)p;
+  p += align8(12 * nh);
+  s.rec.li = (int32_t*)p;
+  p += align8(4 * nh);
+  s.rec.pid = (int32_t*)p;
+  p += align8(4 * nh);
+  s.rec.base = (double*)p;
+  p += 8 * nh;
+  s.rec.u = (double*)p;
+  p += 8 * nh;
+  s.kkey = (uint64_t*)p;
+  p += 8 * nk;
+  s.ccnt = (int32_t*)p;
+  p += align8(4 * nc);
+  s.chead = (int32_t*)p;
+  p += align8(4 * nc);
+  s.gfirst = (int32_t*)p;
+  p += align8(4 * nc);
+  s.glast = (int32_t*)p;
+  return s;
+}
+
+template <int D>
+__device__ __forceinline__ void jump_of(const FieldArgs& A, const RayStore& S, uint64_t key, uint64_t* a) {
+  const uint32_t slot = key_slot(key);
+  const int kidx = key_kidx(key);
+  int32_t o3[kMaxP] = {0, 0, 0};
+  for (int m = 0; m < A.mc.P; ++m) o3[m] = S.rec.o[3 * slot + m];
+  const double* row = A.shat + (int64_t)S.rec.li[slot] * A.mc.P * (D + 1);
+  knot_jump<D>(A.mc, row, S.rec.base[slot], S.rec.u[slot], o3, kidx, a, A.flags);
+}
+
+// Process one ray with all threads of the work-group.
+template <int D, bool RENDER>
+__device__ void process_ray(const FieldArgs& A, Shared<D>& sh, const RayStore& S, Node<D>* nodes, int64_t r,
+                            int64_t nh) {
+  const int tid = threadIdx.x;
+  const int K = A.mc.K, P = A.mc.P;
+  const int64_t nk = nh * (K + 1);
+  const int64_t hoff = A.hit_off[r];
+  double o[3], v[3];
+  for (int k = 0; k < 3; ++k) {
+    o[k] = A.o[3 * r + k];
+    v[k] = A.v[3 * r + k];
+  }
+  // ---- hits sorted by particle input index
+  for (int64_t s = tid; s < nh; s += kFieldThreads) {
+    const uint32_t j = A.hits[hoff + s];
+    S.hkey[s] = ((uint64_t)(uint32_t)A.orig[j] << 32) | j;
+  }
+  __syncthreads();
+  bitonic_sort<uint64_t>(S.hkey, (int)nh, tid, kFieldThreads);
+  // ---- per-hit records and knot keys (Sec. 4.3: quantized positions)
+  const double tau = A.mc.tau, sigma = A.mc.sigma;
+  for (int64_t s = tid; s < nh; s += kFieldThreads) {
+    const uint64_t hk = S.hkey[s];
+    const uint32_t j = (uint32_t)hk;
+    const float4 p = A.pos4[j];
+    const double dxx = (double)p.x - o[0], dxy = (double)p.y - o[1], dxz = (double)p.z - o[2];
+    const double cx = dxy * v[2] - dxz * v[1];
+    const double cy = dxz * v[0] - dxx * v[2];
+    const double cz = dxx * v[1] - dxy * v[0];
+    const double z = (double)p.w;
+    const double lam2 = (cx * cx + cy * cy + cz * cz) / (z * z);
+    const double tchi = dxx * v[0] + dxy * v[1] + dxz * v[2];
+    const double lam = sqrt(lam2);
+    int li = (int)floor(lam * (double)A.mc.n_lut / kSupport);
+    li = li < 0 ? 0 : (li > A.mc.n_lut - 1 ? A.mc.n_lut - 1 : li);
+    const double t0d = rint(tchi / tau);
+    bool bad = !(fabs(t0d) < 1.0e9);
+    const int32_t t0 = bad ? 0 : (int32_t)t0d;
+    int32_t offs[kMaxP] = {0, 0, 0};
+    for (int m = 0; m < P; ++m) {
+      const double od = rint(z * A.theta[(int64_t)li * P + m] / tau);
+      if (!(od < 1.0e9)) bad = true;
+      offs[m] = bad ? 0 : (int32_t)od;
+    }
+    if (bad) atomicOr(A.flags, kFlagPosRange);
+    S.rec.t0[s] = t0;
+    for (int m = 0; m < P; ++m) S.rec.o[3 * s + m] = offs[m];
+    S.rec.li[s] = li;
+    S.rec.pid[s] = (int32_t)(hk >> 32);
+    S.rec.base[s] = (double)A.val[j] / (sigma * (z * z * z));
+    S.rec.u[s] = tau / z;
+    // knots kidx = k + P for positions t0 + sign(k) o_|k|
+    for (int kidx = 0; kidx <= 2 * P; ++kidx) {
+      const int k = kidx - P;
+      if (k == 0 && !A.mc.even_k) continue;
+      const int64_t t = (int64_t)t0 + (k < 0 ? -(int64_t)offs[-k - 1] : (k > 0 ? (int64_t)offs[k - 1] : 0));
+      const int slotk = A.mc.even_k ? kidx : (k < 0 ? kidx : kidx - 1);
+      S.kkey[s * (K + 1) + slotk] =
+          ((uint64_t)((uint32_t)(int32_t)t ^ 0x80000000u) << 32) | ((uint64_t)s << 3) | (uint64_t)kidx;
+    }
+  }
+  __syncthreads();
+  bitonic_sort<uint64_t>(S.kkey, (int)nk, tid, kFieldThreads);
+  // ---- thread ranges of chunks
+  const int64_t n_chunks = (nk + kChunk - 1) / kChunk;
+  const int64_t per = (n_chunks + kFieldThreads - 1) / kFieldThreads;
+  const int64_t c_lo = min((int64_t)tid * per, n_chunks), c_hi = min(c_lo + per, n_chunks);
+  const int64_t k_lo = c_lo * kChunk, k_hi = min(c_hi * kChunk, nk);
+  // ---- pass A: aggregate of this thread's knots
+  {
+    Agg<D> g;
+    g.valid = 0;
+    g.t = 0;
+    for (int d = 0; d <= D; ++d) g.a[d] = 0;
+    for (int64_t i = k_lo; i < k_hi; ++i) {
+      const uint64_t key = S.kkey[i];
+      const int64_t t = key_t(key);
+      uint64_t jmp[D + 1];
+      jump_of<D>(A, S, key, jmp);
+      if (g.valid) taylor_shift<D>(g.a, (uint32_t)(t - g.t));
+      for (int d = 0; d <= D; ++d) g.a[d] += jmp[d];
+      g.t = t;
+      g.valid = 1;
+    }
+    sh.agg[tid] = g;
+  }
+  __syncthreads();
+  // inclusive Hillis-Steele scan over the thread aggregates
+  for (int ofs = 1; ofs < kFieldThreads; ofs <<= 1) {
+    Agg<D> mine = sh.agg[tid];
+    Agg<D> res = mine;
+    if (tid >= ofs) {
+      Agg<D> prev = sh.agg[tid - ofs];
+      agg_combine<D>(prev, mine, res);
+    }
+    __syncthreads();
+    sh.agg[tid] = res;
+    __syncthreads();
+  }
+  Agg<D> carry;
+  if (tid > 0) carry = sh.agg[tid - 1];
+  else {
+    carry.valid = 0;
+    carry.t = 0;
+    for (int d = 0; d <= D; ++d) carry.a[d] = 0;
+  }
+  // ---- pass B: peak over piece starts, tail check, piece counts
+  if (tid == 0) sh.peak = 0;
+  __syncthreads();
+  unsigned long long pk = 0;
+  int64_t npieces = 0;
+  {
+    Agg<D> st = carry;
+    for (int64_t i = k_lo; i < k_hi; ++i) {
+      const uint64_t key = S.kkey[i];
+      const int64_t t = key_t(key);
+      uint64_t jmp[D + 1];
+      jump_of<D>(A, S, key, jmp);
+      if (st.valid) taylor_shift<D>(st.a, (uint32_t)(t - st.t));
+      for (int d = 0; d <= D; ++d) st.a[d] += jmp[d];
+      st.t = t;
+      st.valid = 1;
+      const bool last = (i + 1 == nk);
+      if (!last && key_t(S.kkey[i + 1]) != t) {
+        const int64_t a0 = (int64_t)st.a[0];
+        const unsigned long long m = (unsigned long long)(a0 < 0 ? -a0 : a0);
+        pk = pk > m ? pk : m;
+        ++npieces;
+      }
+      if (last) {
+        bool zero = true;
+        for (int d = 0; d <= D; ++d) zero = zero && (st.a[d] == 0);
+        if (!zero) atomicOr(A.flags, kFlagTail);
+      }
+      if (A.exact) {
+        const int64_t ko = A.knot_off[r] + i;
+        if (ko < A.knot_cap) {
+          A.kn_t[ko] = t;
+          A.kn_pid[ko] = S.rec.pid[key_slot(key)];
+          A.kn_kidx[ko] = key_kidx(key);
+        }
+      }
+    }
+  }
+  atomicMax(&sh.peak, pk);
+  sh.cnt[tid] = npieces;
+  __syncthreads();
+  const double peak = sigma * (double)(int64_t)sh.peak;
+  // exclusive scan of piece counts (exact-mode positions)
+  if (tid == 0) {
+    int64_t run = 0;
+    for (int i = 0; i < kFieldThreads; ++i) {
+      const int64_t c = sh.cnt[i];
+      sh.cnt[i] = run;
+      run += c;
+    }
+    if (A.exact) {
+      sh.base_ex = (int64_t)atomicAdd(&A.counters[1], (unsigned long long)run);
+      A.ray_ex[2 * r] = sh.base_ex;
+      A.ray_ex[2 * r + 1] = run;
+    }
+    atomicAdd(&A.counters[2], (unsigned long long)run);
+  }
+  __syncthreads();
+  // ---- pass C: exact pieces -> leaves -> greedy merge within chunks -> nodes
+  const double tol = A.mc.merge_tol;
+  const double thr2 = (tol * peak) * (tol * peak);
+  {
+    Agg<D> st = carry;
+    int64_t ex_pos = sh.cnt[tid];
+    int64_t cur_chunk = -1;
+    Node<D> cur;
+    bool have = false;
+    int32_t emitted = 0;
+    auto flush = [&](int64_t chunk) {
+      if (have) {
+        nodes[chunk * kChunk + emitted] = cur;
+        ++emitted;
+        have = false;
+      }
+    };
+    for (int64_t c = c_lo; c < c_hi; ++c) S.ccnt[c] = 0;
+    for (int64_t i = k_lo; i < k_hi; ++i) {
+      const uint64_t key = S.kkey[i];
+      const int64_t t = key_t(key);
+      uint64_t jmp[D + 1];
+      jump_of<D>(A, S, key, jmp);
+      if (st.valid) taylor_shift<D>(st.a, (uint32_t)(t - st.t));
+      for (int d = 0; d <= D; ++d) st.a[d] += jmp[d];
+      st.t = t;
+      st.valid = 1;
+      const int64_t chunk = i / kChunk;
+      if (chunk != cur_chunk) {
+        if (cur_chunk >= 0) {
+          flush(cur_chunk);
+          S.ccnt[cur_chunk] = emitted;
+        }
+        cur_chunk = chunk;
+        emitted = 0;
+      }
+      if (i + 1 < nk) {
+        const int32_t tn = key_t(S.kkey[i + 1]);
+        if (tn != (int32_t)t) {
+          if (A.exact) {
+            const int64_t e = sh.base_ex + ex_pos;
+            if (e < A.exact_cap) {
+              A.ex_t[e] = t;
+              A.ex_end[e] = tn;
+              for (int d = 0; d <= D; ++d) A.ex_coef[e * (D + 1) + d] = (int64_t)st.a[d];
+            }
+          }
+          ++ex_pos;
+          Node<D> leaf = make_leaf<D>(A.mt, (int32_t)t, tn, st.a, sigma);
+          if (!have) {
+            cur = leaf;
+            have = true;
+          } else if (tol > 0.0) {
+            Node<D> cand = combine<D>(A.mt, cur, leaf, tau);
+            if (passes<D>(cand, thr2, tau)) cur = cand;
+            else {
+              flush(chunk);
+              cur = leaf;
+              have = true;
+            }
+          } else {
+            flush(chunk);
+            cur = leaf;
+            have = true;
+          }
+        }
+      }
+    }
+    if (cur_chunk >= 0) {
+      flush(cur_chunk);
+      S.ccnt[cur_chunk] = emitted;
+    }
+  }
+  __syncthreads();
+  // ---- junction merges across chunk groups (levels 1, 2, 4, ...)
+  for (int64_t c = tid; c < n_chunks; c += kFieldThreads) {
+    S.chead[c] = 0;
+    const int32_t cn = S.ccnt[c];
+    S.gfirst[c] = cn > 0 ? (int32_t)(c * kChunk) : -1;
+    S.glast[c] = cn > 0 ? (int32_t)(c * kChunk + cn - 1) : -1;
+  }
+  __syncthreads();
+  if (tol > 0.0) {
+    for (int64_t w = 1; w < n_chunks; w <<= 1) {
+      for (int64_t L = (int64_t)tid * 2 * w; L < n_chunks; L += (int64_t)kFieldThreads * 2 * w) {
+        const int64_t R = L + w;
+        if (R >= n_chunks) continue;
+        const int32_t lf = S.gfirst[L], ll = S.glast[L], rf = S.gfirst[R], rl = S.glast[R];
+        int32_t nf = lf >= 0 ? lf : rf;
+        int32_t nl = rl >= 0 ? rl : ll;
+        if (ll >= 0 && rf >= 0) {
+          Node<D> cand = combine<D>(A.mt, nodes[ll], nodes[rf], tau);
+          if (passes<D>(cand, thr2, tau)) {
+            nodes[ll] = cand;
+            const int64_t rc = rf / kChunk;
+            S.chead[rc] = S.chead[rc] + 1;
+            // next live node of group R
+            int32_t nxt = -1;
+            const int64_t r_end = min(R + w, n_chunks);
+            for (int64_t c = rc; c < r_end && nxt < 0; ++c) {
+              if (S.chead[c] < S.ccnt[c]) nxt = (int32_t)(c * kChunk + S.chead[c]);
+            }
+            if (nxt < 0) nl = ll;  // group R became empty
+            nf = lf;
+          }
+        }
+        S.gfirst[L] = nf;
+        S.glast[L] = nl;
+      }
+      __syncthreads();
+    }
+  }
+  // ---- live nodes per thread range, in order
+  int64_t mine = 0;
+  for (int64_t c = c_lo; c < c_hi; ++c) mine += S.ccnt[c] - S.chead[c];
+  sh.cnt[tid] = mine;
+  __syncthreads();
+  if (tid == 0) {
+    int64_t run = 0;
+    for (int i = 0; i < kFieldThreads; ++i) {
+      const int64_t c = sh.cnt[i];
+      sh.cnt[i] = run;
+      run += c;
+    }
+    if (!RENDER) {
+      sh.base_out = (int64_t)atomicAdd(&A.counters[0], (unsigned long long)run);
+      A.ray_out[2 * r] = sh.base_out;
+      A.ray_out[2 * r + 1] = run;
+      A.ray_peak[r] = (float)peak;
+    }
+  }
+  __syncthreads();
+  if (!RENDER) {
+    int64_t pos = sh.base_out + sh.cnt[tid];
+    for (int64_t c = c_lo; c < c_hi; ++c) {
+      for (int32_t q = S.chead[c]; q < S.ccnt[c]; ++q) {
+        const Node<D>& nd = nodes[c * kChunk + q];
+        if (pos < A.out_cap) {
+          A.st_t0[pos] = (float)((double)nd.a * tau);
+          A.st_t1[pos] = (float)((double)nd.b * tau);
+          for (int d = 0; d <= D; ++d) {
+            double s = 0.0;
+            for (int j = 0; j <= D; ++j) s += nd.g[j] * A.mt.leg2pow[j][d];
+            A.st_coef[pos * (D + 1) + d] = (float)s;
+          }
+        }
+        ++pos;
+      }
+    }
+  } else {
+    // classification and front-to-back compositing of this thread's nodes
+    float C0 = 0.f, C1 = 0.f, C2 = 0.f, T = 1.f;
+    const float vmin = A.tf_vmin, vr = A.tf_vmax - A.tf_vmin;
+    const int ntf = A.tf_n;
+    for (int64_t c = c_lo; c < c_hi; ++c) {
+      for (int32_t q = S.chead[c]; q < S.ccnt[c]; ++q) {
+        const Node<D>& nd = nodes[c * kChunk + q];
+        const double ta = (double)nd.a * tau, tb = (double)nd.b * tau;
+        const double a = fmax(ta, A.t_min), b = fmin(tb, A.t_max);
+        if (!(b > a)) continue;
+        const double Sd = fmax(1.0, ceil((b - a) / A.tf_step));
+        const int64_t S_n = (int64_t)Sd;
+        const double delta = (b - a) / Sd;
+        float cf[D + 1];
+        for (int d = 0; d <= D; ++d) {
+          double s = 0.0;
+          for (int j = 0; j <= D; ++j) s += nd.g[j] * A.mt.leg2pow[j][d];
+          cf[d] = (float)s;
+        }
+        const float u0 = (float)((a - ta) / (tb - ta)), du = (float)(delta / (tb - ta));
+        const float dl = (float)delta;
+        for (int64_t j = 0; j < S_n; ++j) {
+          const float uu = u0 + ((float)j + 0.5f) * du;
+          float val = cf[D];
+          for (int d = D - 1; d >= 0; --d) val = val * uu + cf[d];
+          float x = (val - vmin) / vr * (float)(ntf - 1);
+          x = fminf(fmaxf(x, 0.f), (float)(ntf - 1));
+          const int i0 = (int)floorf(x);
+          const int i1 = min(i0 + 1, ntf - 1);
+          const float f = x - (float)i0;
+          const float* p0 = A.tf + 4 * i0;
+          const float* p1 = A.tf + 4 * i1;
+          const float er = (1.f - f) * p0[0] + f * p1[0];
+          const float eg = (1.f - f) * p0[1] + f * p1[1];
+          const float eb = (1.f - f) * p0[2] + f * p1[2];
+          const float sg = (1.f - f) * p0[3] + f * p1[3];
+          const float xx = sg * dl;
+          const float frac = (xx == 0.f) ? dl : -expm1f(-xx) / sg;
+          C0 += T * er * frac;
+          C1 += T * eg * frac;
+          C2 += T * eb * frac;
+          T *= expf(-xx);
+        }
+      }
+    }
+    sh.part[tid][0] = C0;
+    sh.part[tid][1] = C1;
+    sh.part[tid][2] = C2;
+    sh.part[tid][3] = T;
+    __syncthreads();
+    // ordered tree reduction: (C1, T1) then (C2, T2) = (C1 + T1 C2, T1 T2)
+    for (int s = 1; s < kFieldThreads; s <<= 1) {
+      if ((tid % (2 * s)) == 0 && tid + s < kFieldThreads) {
+        const float t1 = sh.part[tid][3];
+        sh.part[tid][0] += t1 * sh.part[tid + s][0];
+        sh.part[tid][1] += t1 * sh.part[tid + s][1];
+        sh.part[tid][2] += t1 * sh.part[tid + s][2];
+        sh.part[tid][3] = t1 * sh.part[tid + s][3];
+      }
+      __syncthreads();
+    }
+    if (tid == 0) {
+      A.rgba[4 * r] = sh.part[0][0];
+      A.rgba[4 * r + 1] = sh.part[0][1];
+      A.rgba[4 * r + 2] = sh.part[0][2];
+      A.rgba[4 * r + 3] = 1.f - sh.part[0][3];
+    }
+  }
+}
+
+template <int D, bool RENDER>
+__global__ void __launch_bounds__(kFieldThreads) k_field(FieldArgs A) {
+  extern __shared__ __align__(16) char lds[];
+  __shared__ Shared<D> sh;
+  char* slab = A.slab + (int64_t)blockIdx.x * A.slab_stride;
+  Node<D>* nodes = (Node<D>*)slab;
+  char* gstore = slab + align8((int64_t)sizeof(Node<D>) * ((A.max_knots + kChunk - 1) / kChunk) * kChunk);
+  for (;;) {
+    if (threadIdx.x == 0) sh.ray = (int64_t)atomicAdd(A.queue, 1u);
+    __syncthreads();
+    const int64_t r = sh.ray;
+    if (r >= A.n_rays) break;
+    const int64_t nh = A.hit_count[r];
+    if (nh == 0) {
+      if (threadIdx.x == 0) {
+        if (RENDER) {
+          for (int k = 0; k < 4; ++k) A.rgba[4 * r + k] = 0.f;
+        } else {
+          A.ray_out[2 * r] = 0;
+          A.ray_out[2 * r + 1] = 0;
+          A.ray_peak[r] = 0.f;
+          if (A.exact) {
+            A.ray_ex[2 * r] = 0;
+            A.ray_ex[2 * r + 1] = 0;
+          }
+        }
+      }
+    } else {
+      const int64_t nk = nh * (A.mc.K + 1);
+      if (nh <= A.hn_lds) {
+        const RayStore S = carve(lds, nh, nk);
+        process_ray<D, RENDER>(A, sh, S, nodes, r, nh);
+      } else {
+        if (threadIdx.x == 0) atomicAdd(&A.counters[3], 1ull);
+        const RayStore S = carve(gstore, nh, nk);
+        process_ray<D, RENDER>(A, sh, S, nodes, r, nh);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ============================================================== finalize (approx mode)
+
+__global__ void k_ray_counts(const int64_t* ray_pair, int64_t n, int64_t* counts) {
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x)
+    counts[r] = ray_pair[2 * r + 1];
+}
+
+__global__ void k_copy_pieces(const int64_t* ray_out, const int64_t* final_off, int64_t n, int D1, const float* s0,
+                              const float* s1, const float* sc, float* t0, float* t1, float* coef) {
+  const int64_t r = (int64_t)blockIdx.x;
+  if (r >= n) return;
+  const int64_t src = ray_out[2 * r], cnt = ray_out[2 * r + 1], dst = final_off[r];
+  for (int64_t i = threadIdx.x; i < cnt; i += blockDim.x) {
+    t0[dst + i] = s0[src + i];
+    t1[dst + i] = s1[src + i];
+  }
+  for (int64_t i = threadIdx.x; i < cnt * D1; i += blockDim.x) coef[dst * D1 + i] = sc[src * D1 + i];
+}
+
+__global__ void k_copy_exact(const int64_t* ray_ex, const int64_t* final_off, int64_t n, int D1, const int64_t* s0,
+                             const int64_t* s1, const int64_t* sc, int64_t* t0, int64_t* t1, int64_t* coef) {
+  const int64_t r = (int64_t)blockIdx.x;
+  if (r >= n) return;
+  const int64_t src = ray_ex[2 * r], cnt = ray_ex[2 * r + 1], dst = final_off[r];
+  for (int64_t i = threadIdx.x; i < cnt; i += blockDim.x) {
+    t0[dst + i] = s0[src + i];
+    t1[dst + i] = s1[src + i];
+  }
+  for (int64_t i = threadIdx.x; i < cnt * D1; i += blockDim.x) coef[dst * D1 + i] = sc[src * D1 + i];
+}
+
+__global__ void k_scale_i64(const int64_t* a, int64_t* b, int64_t n, int64_t f) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    b[i] = a[i] * f;
+}
+
+__global__ void k_set_last(int64_t* off, const int64_t* cnt, int64_t n) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) off[n] = (n > 0 ? off[n - 1] + cnt[n - 1] : 0);
+}
+
+// ============================================================== host
+
+MergeTables make_merge_tables(int D) {
+  MergeTables t{};
+  // Gauss-Legendre nodes on [0, 1] with D + 1 points (Newton on P_{D+1})
+  const int n = D + 1;
+  for (int i = 0; i < n; ++i) {
+    double z = std::cos(3.14159265358979323846 * (i + 0.75) / (n + 0.5));
+    double dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= n; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      if (n == 1) {
+        p1 = z;
+        p0 = 1.0;
+      }
+      dp = n * (z * p1 - p0) / (z * z - 1.0);
+      const double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= n; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = n * (z * p1 - p0) / (z * z - 1.0);
+    }
+    t.node[i] = 0.5 * (z + 1.0);
+    t.wgt[i] = 0.5 * 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+  // shifted Legendre power coefficients: P~_j(u) = sum_k (-1)^(j+k) C(j,k) C(j+k,k) u^k
+  auto C = [](int a, int b) {
+    double v = 1.0;
+    for (int i = 1; i <= b; ++i) v = v * (a - b + i) / i;
+    return v;
+  };
+  for (int j = 0; j <= D; ++j)
+    for (int k = 0; k <= D; ++k) t.leg2pow[j][k] = (k <= j) ? (((j + k) % 2) ? -1.0 : 1.0) * C(j, k) * C(j + k, k) : 0.0;
+  for (int j = 0; j <= D; ++j)
+    for (int i = 0; i <= D; ++i) {
+      double s = 0.0, p = 1.0;
+      for (int k = 0; k <= D; ++k) {
+        s += t.leg2pow[j][k] * p;
+        p *= t.node[i];
+      }
+      t.leg_at_node[j][i] = s;
+    }
+  // gamma_j = (2j+1) int_0^1 u^d P~_j(u) du = (2j+1) sum_k coef_jk / (d + k + 1)
+  for (int j = 0; j <= D; ++j)
+    for (int d = 0; d <= D; ++d) {
+      double s = 0.0;
+      for (int k = 0; k <= j; ++k) s += t.leg2pow[j][k] / (double)(d + k + 1);
+      t.pow2leg[j][d] = (2.0 * j + 1.0) * s;
+    }
+  return t;
+}
+
+template <int D>
+size_t shared_static_bytes() {
+  return sizeof(Shared<D>);
+}
+
+template <int D, bool RENDER>
+void launch_field(FieldArgs& A, int grid, size_t lds, hipStream_t st) {
+  hip_check(hipFuncSetAttribute((const void*)k_field<D, RENDER>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds),
+            "set lds");
+  k_field<D, RENDER><<<grid, kFieldThreads, lds, st>>>(A);
+  hip_check(hipGetLastError(), "field launch");
+}
+
+template <bool RENDER>
+void dispatch_field(int D, FieldArgs& A, int grid, size_t lds, hipStream_t st) {
+  switch (D) {
+    case 1: launch_field<1, RENDER>(A, grid, lds, st); break;
+    case 2: launch_field<2, RENDER>(A, grid, lds, st); break;
+    case 3: launch_field<3, RENDER>(A, grid, lds, st); break;
+    case 4: launch_field<4, RENDER>(A, grid, lds, st); break;
+    case 5: launch_field<5, RENDER>(A, grid, lds, st); break;
+    case 6: launch_field<6, RENDER>(A, grid, lds, st); break;
+    default: throw Error(SPH_HOA_E_UNSUPPORTED, "degree");
+  }
+}
+
+size_t node_bytes(int D) { return 8 + 8 * (size_t)(D + 2); }
+
+size_t static_lds(int D) {
+  switch (D) {
+    case 1: return shared_static_bytes<1>();
+    case 2: return shared_static_bytes<2>();
+    case 3: return shared_static_bytes<3>();
+    case 4: return shared_static_bytes<4>();
+    case 5: return shared_static_bytes<5>();
+    default: return shared_static_bytes<6>();
+  }
+}
+
+unsigned blocks_for(int64_t n, int t) {
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + t - 1) / t, 65536));
+}
+
+}  // namespace
+
+void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam, const sph_hoa_rays* rays,
+              FieldOut& out, hipStream_t st) {
+  const int D = ix.D, K = ix.K, P = ix.P;
+  ix.stats = sph_hoa_stats{};
+  ix.stats.n_rays = n_rays;
+  ix.counters.ensure(256);
+  unsigned long long* ctr = ix.counters.as<unsigned long long>();
+  uint32_t* flags = reinterpret_cast<uint32_t*>(ctr + 16);
+  unsigned int* queue = reinterpret_cast<unsigned int*>(ctr + 17);
+  unsigned long long* max_hits = ctr + 18;
+  hip_check(hipMemsetAsync(ix.counters.p, 0, 256, st), "memset");
+  if (n_rays == 0) return;
+  ix.rays_o.ensure(sizeof(double) * 3 * n_rays);
+  ix.rays_v.ensure(sizeof(double) * 3 * n_rays);
+  double t_min, t_max;
+  if (camera) {
+    CamDev c{};
+    double e[3], la[3], up[3];
+    for (int k = 0; k < 3; ++k) {
+      e[k] = (double)cam->eye[k];
+      la[k] = (double)cam->look_at[k];
+      up[k] = (double)cam->up[k];
+    }
+    auto norm3 = [](double& x, double& y, double& z) {
+      const double nn = std::sqrt(x * x + y * y + z * z);
+      x = x / nn;
+      y = y / nn;
+      z = z / nn;
+    };
+    double fx = la[0] - e[0], fy = la[1] - e[1], fz = la[2] - e[2];
+    norm3(fx, fy, fz);
+    double rx = fy * up[2] - fz * up[1], ry = fz * up[0] - fx * up[2], rz = fx * up[1] - fy * up[0];
+    norm3(rx, ry, rz);
+    const double ux = ry * fz - rz * fy, uy = rz * fx - rx * fz, uz = rx * fy - ry * fx;
+    const double f[3] = {fx, fy, fz}, rr[3] = {rx, ry, rz}, uu[3] = {ux, uy, uz};
+    for (int k = 0; k < 3; ++k) {
+      c.eye[k] = e[k];
+      c.f[k] = f[k];
+      c.r[k] = rr[k];
+      c.u[k] = uu[k];
+    }
+    const double fov = (double)cam->fov_y_deg;
+    c.g = std::tan(fov * 3.14159265358979323846 / 180.0 / 2.0);
+    c.aspect = (double)cam->width / (double)cam->height;
+    c.half = (double)cam->ortho_half_extent;
+    c.W = cam->width;
+    c.H = cam->height;
+    c.ortho = cam->ortho;
+    k_camera_rays<<<blocks_for(n_rays, 256), 256, 0, st>>>(c, n_rays, ix.rays_o.as<double>(), ix.rays_v.as<double>());
+    t_min = (double)cam->t_min;
+    t_max = (double)cam->t_max;
+  } else {
+    k_widen_rays<<<blocks_for(n_rays, 256), 256, 0, st>>>(rays->origin, rays->dir, n_rays, ix.rays_o.as<double>(),
+                                                          ix.rays_v.as<double>(), flags);
+    t_min = (double)rays->t_min;
+    t_max = (double)rays->t_max;
+  }
+  hip_check(hipGetLastError(), "ray launch");
+  // hit counts
+  ix.hit_count.ensure(sizeof(int64_t) * (n_rays + 1));
+  ix.hit_off.ensure(sizeof(int64_t) * (n_rays + 1));
+  GatherArgs G{};
+  G.o = ix.rays_o.as<double>();
+  G.v = ix.rays_v.as<double>();
+  G.n_rays = n_rays;
+  G.t_min = t_min;
+  G.t_max = t_max;
+  G.pos4 = ix.pos4.as<float4>();
+  G.cbeg = ix.cell_begin.as<uint32_t>();
+  G.cend = ix.cell_end.as<uint32_t>();
+  G.g = ix.grid;
+  G.count = ix.hit_count.as<int64_t>();
+  G.max_hits = max_hits;
+  G.flags = flags;
+  const unsigned gblocks = (unsigned)((n_rays + 3) / 4);
+  k_gather<false><<<gblocks, kGatherThreads, 0, st>>>(G);
+  hip_check(hipGetLastError(), "gather launch");
+  device_exclusive_scan_i64(ix.hit_count.as<int64_t>(), ix.hit_off.as<int64_t>(), n_rays, ix.scan_tmp, st);
+  k_set_last<<<1, 1, 0, st>>>(ix.hit_off.as<int64_t>(), ix.hit_count.as<int64_t>(), n_rays);
+  int64_t total_pairs = 0;
+  unsigned long long mh = 0;
+  uint32_t fl = 0;
+  hip_check(hipMemcpyAsync(&total_pairs, ix.hit_off.as<int64_t>() + n_rays, 8, hipMemcpyDeviceToHost, st), "copy");
+  hip_check(hipMemcpyAsync(&mh, max_hits, 8, hipMemcpyDeviceToHost, st), "copy");
+  hip_check(hipMemcpyAsync(&fl, flags, 4, hipMemcpyDeviceToHost, st), "copy");
+  hip_check(hipStreamSynchronize(st), "sync");
+  if (fl & kFlagBadInput) throw Error(SPH_HOA_E_INVALID_ARG, "ray origin/direction not finite or direction not unit");
+  if (fl & kFlagWindow) throw Error(SPH_HOA_E_INTERNAL, "grid enumeration window exceeded");
+  ix.stats.n_pairs = total_pairs;
+  ix.stats.max_hits = (int64_t)mh;
+  ix.stats.n_knots = total_pairs * (K + 1);
+  if ((int64_t)mh * (K + 1) >= (int64_t(1) << 29))
+    throw Error(SPH_HOA_E_UNSUPPORTED, "more than 2^29 knots on one ray");
+  ix.hits.ensure(sizeof(uint32_t) * std::max<int64_t>(1, total_pairs));
+  G.off = ix.hit_off.as<int64_t>();
+  G.hits = ix.hits.as<uint32_t>();
+  k_gather<true><<<gblocks, kGatherThreads, 0, st>>>(G);
+  hip_check(hipGetLastError(), "gather launch");
+  // ---- field kernel
+  FieldArgs A{};
+  A.o = G.o;
+  A.v = G.v;
+  A.n_rays = n_rays;
+  A.t_min = t_min;
+  A.t_max = t_max;
+  A.hit_count = ix.hit_count.as<int64_t>();
+  A.hit_off = ix.hit_off.as<int64_t>();
+  A.hits = ix.hits.as<uint32_t>();
+  A.pos4 = ix.pos4.as<float4>();
+  A.val = ix.val.as<float>();
+  A.orig = ix.orig.as<int32_t>();
+  A.theta = ix.lut_theta.as<double>();
+  A.shat = ix.lut_shat.as<double>();
+  A.mc = MethodConsts{K, D, P, (K % 2 == 0) ? 1 : 0, ix.n_lut, (int)ix.kernel, ix.tau, ix.sigma, kSupport, ix.merge_tol};
+  A.mt = make_merge_tables(D);
+  A.queue = queue;
+  A.flags = flags;
+  A.counters = ctr;
+  const int64_t max_knots = std::max<int64_t>(1, (int64_t)mh * (K + 1));
+  A.max_knots = max_knots;
+  // LDS layout capacity
+  const size_t lds_static = static_lds(D);
+  const size_t lds_limit = 160 * 1024 - lds_static - 1024;
+  int64_t hn = std::max<int64_t>(1, (int64_t)mh);
+  while (hn > 1 && (size_t)ray_store_bytes(hn, hn * (K + 1)) > lds_limit) hn = hn * 7 / 8;
+  // test hook: a smaller LDS capacity sends more rays down the device-memory path
+  if (const char* cap = std::getenv("SPH_HOA_MAX_LDS_HITS")) hn = std::max<int64_t>(1, std::min<int64_t>(hn, std::atoll(cap)));
+  A.hn_lds = (int)hn;
+  const size_t lds = (size_t)ray_store_bytes(hn, hn * (K + 1));
+  int per_cu = 0;
+  hipDeviceProp_t prop;
+  int dev = 0;
+  hip_check(hipGetDevice(&dev), "device");
+  hip_check(hipGetDeviceProperties(&prop, dev), "props");
+  per_cu = (int)std::max<size_t>(1, std::min<size_t>(8, (160 * 1024) / (lds + lds_static + 1)));
+  const int grid = (int)std::min<int64_t>((int64_t)prop.multiProcessorCount * per_cu, n_rays);
+  const int64_t heavy = ((int64_t)mh > hn) ? ray_store_bytes((int64_t)mh, max_knots) : 0;
+  A.slab_stride = align8((int64_t)node_bytes(D) * ((max_knots + kChunk - 1) / kChunk) * kChunk) + align8(heavy) + 64;
+  ix.slab.ensure((size_t)A.slab_stride * grid);
+  A.slab = ix.slab.as<char>();
+  const bool render = (out.rgba != nullptr);
+  if (render) {
+    A.tf = out.tf->rgba;
+    A.tf_n = out.tf->n;
+    A.tf_vmin = out.tf->v_min;
+    A.tf_vmax = out.tf->v_max;
+    A.tf_step = (double)out.tf->step;
+    A.rgba = out.rgba;
+    dispatch_field<true>(D, A, grid, lds, st);
+  } else {
+    sph_hoa_field* f = out.field;
+    A.out_cap = f->capacity;
+    ix.out_stage.ensure(std::max<size_t>(16, (size_t)f->capacity * sizeof(float) * (D + 3)));
+    A.st_t0 = ix.out_stage.as<float>();
+    A.st_t1 = A.st_t0 + f->capacity;
+    A.st_coef = A.st_t1 + f->capacity;
+    ix.ray_meta.ensure(sizeof(int64_t) * (4 * n_rays + 2));
+    A.ray_out = ix.ray_meta.as<int64_t>();
+    A.ray_ex = A.ray_out + 2 * n_rays;
+    A.ray_peak = f->ray_peak;
+    A.exact = out.exact ? 1 : 0;
+    DevBuf knot_off;
+    if (out.exact) {
+      A.exact_cap = f->exact_capacity;
+      ix.exact_stage.ensure(std::max<size_t>(16, (size_t)f->exact_capacity * sizeof(int64_t) * (D + 3)));
+      A.ex_t = ix.exact_stage.as<int64_t>();
+      A.ex_end = A.ex_t + f->exact_capacity;
+      A.ex_coef = A.ex_end + f->exact_capacity;
+      knot_off.ensure(sizeof(int64_t) * (n_rays + 1));
+      k_scale_i64<<<blocks_for(n_rays + 1, 256), 256, 0, st>>>(ix.hit_off.as<int64_t>(), knot_off.as<int64_t>(),
+                                                               n_rays + 1, K + 1);
+      A.knot_off = knot_off.as<int64_t>();
+      A.knot_cap = f->knot_capacity;
+      A.kn_t = f->knot_t;
+      A.kn_pid = f->knot_pid;
+      A.kn_kidx = f->knot_kidx;
+      if (f->knot_offsets)
+        hip_check(hipMemcpyAsync(f->knot_offsets, knot_off.p, sizeof(int64_t) * (n_rays + 1), hipMemcpyDeviceToDevice, st),
+                  "copy");
+    }
+    dispatch_field<false>(D, A, grid, lds, st);
+    // counts -> final offsets, then reorder staged pieces by ray
+    DevBuf cnt;
+    cnt.ensure(sizeof(int64_t) * (n_rays + 1));
+    k_ray_counts<<<blocks_for(n_rays, 256), 256, 0, st>>>(A.ray_out, n_rays, cnt.as<int64_t>());
+    device_exclusive_scan_i64(cnt.as<int64_t>(), f->ray_offsets, n_rays, ix.scan_tmp, st);
+    k_set_last<<<1, 1, 0, st>>>(f->ray_offsets, cnt.as<int64_t>(), n_rays);
+    unsigned long long c4[4];
+    hip_check(hipMemcpyAsync(c4, ctr, sizeof(c4), hipMemcpyDeviceToHost, st), "copy");
+    hip_check(hipMemcpyAsync(&fl, flags, 4, hipMemcpyDeviceToHost, st), "copy");
+    hip_check(hipStreamSynchronize(st), "sync");
+    f->n_pieces = (int64_t)c4[0];
+    f->n_exact_pieces = (int64_t)c4[2];
+    f->n_pairs = total_pairs;
+    f->n_knots = total_pairs * (K + 1);
+    ix.stats.n_pieces = (int64_t)c4[0];
+    ix.stats.rays_global = (int64_t)c4[3];
+    if (fl & kFlagPosRange) throw Error(SPH_HOA_E_OVERFLOW, "a quantized knot position left the int32 range");
+    if (fl & kFlagCoefRange) throw Error(SPH_HOA_E_OVERFLOW, "a quantized coefficient left the int64 range");
+    if (fl & kFlagTail) throw Error(SPH_HOA_E_INTERNAL, "a ray's knots did not cancel exactly");
+    bool short_cap = f->n_pieces > f->capacity;
+    if (out.exact) short_cap = short_cap || f->n_exact_pieces > f->exact_capacity || f->n_knots > f->knot_capacity;
+    if (short_cap) throw Error(SPH_HOA_E_OUT_OF_MEMORY, "output capacity too small");
+    k_copy_pieces<<<(unsigned)n_rays, 64, 0, st>>>(A.ray_out, f->ray_offsets, n_rays, D + 1, A.st_t0, A.st_t1,
+                                                   A.st_coef, f->t_start, f->t_end, f->coef);
+    if (out.exact) {
+      k_ray_counts<<<blocks_for(n_rays, 256), 256, 0, st>>>(A.ray_ex, n_rays, cnt.as<int64_t>());
+      device_exclusive_scan_i64(cnt.as<int64_t>(), f->exact_offsets, n_rays, ix.scan_tmp, st);
+      k_set_last<<<1, 1, 0, st>>>(f->exact_offsets, cnt.as<int64_t>(), n_rays);
+      k_copy_exact<<<(unsigned)n_rays, 64, 0, st>>>(A.ray_ex, f->exact_offsets, n_rays, D + 1, A.ex_t, A.ex_end,
+                                                    A.ex_coef, f->exact_t, f->exact_end, f->exact_coef);
+    }
+    hip_check(hipGetLastError(), "copy launch");
+    hip_check(hipStreamSynchronize(st), "sync");
+    return;
+  }
+  ix.last_stream = st;
+}
+
+}  // namespace sph

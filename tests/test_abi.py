@@ -1,0 +1,50 @@
+"""The C ABI library loads, exports every symbol the header declares, and its
+host-only table / quantum routines agree with the oracle (no GPU needed)."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2401_02896_amd as L
+from oracle import quanta
+from tests.golden.make_knot_tables import TABLES, load
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_every_declared_symbol_is_exported():
+    hdr = open(os.path.join(ROOT, "include", "sph_hoa.h")).read()
+    names = sorted(set(re.findall(r"\b(sph_hoa_[a-z_]+)\s*\(", hdr)))
+    assert len(names) >= 12
+    lib = L.lib()
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(L.EXPORTS) <= set(names)
+
+
+def test_status_strings():
+    lib = L.lib()
+    for s in range(7):
+        assert lib.sph_hoa_status_string(s)
+
+
+@pytest.mark.parametrize("spec", [t for t in TABLES if t[3] <= 256 or t[:3] == ("cubic", 4, 2)])
+def test_library_knot_tables_match_oracle(spec):
+    """The library's own knot optimisation reproduces the oracle's tables (Sec. 3.4).
+
+    Flat minima (E^2 below 1e-12 of the kernel norm, where the knots are not determined
+    to more than a few digits) are compared on their error instead of their position.
+    """
+    kind, K, D, n = spec
+    th, e2 = L.sph_hoa_knot_table(0 if kind == "cubic" else 1, K, D, n)
+    ref = load(*spec)
+    d = np.abs(th / ref - 1).max(axis=1)
+    flat = e2 < 1e-12 * 0.1
+    assert np.all(d[~flat] < 1e-6), (np.argmax(d), d.max())
+
+
+@pytest.mark.parametrize("D", [1, 2, 3, 4, 6])
+def test_library_tau_matches_oracle(D):
+    r = quanta.fig4_sigma_ratio("cubic")
+    assert abs(L.sph_hoa_optimal_tau(0, D, r, 0.7, 3.0) / (0.7 * quanta.optimal_tau("cubic", D, r / 3.0)) - 1) < 1e-13

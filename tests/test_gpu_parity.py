@@ -1,0 +1,290 @@
+"""GPU parity of the HIP library against the oracle (calls go through the C ABI).
+
+Bars (derived in the design doc): grid keys, hit sets, knot order, quantized
+positions and exact-piece boundaries bit-exact; integer coefficients and the
+ray peak within 1e-9 relative (the projection coefficients are computed
+independently on both sides); merged FP32 field within 1e-5 of the ray peak;
+pixels within 1e-4.  Merge decisions closer than 1e-6 (relative) to their
+threshold may legitimately differ; such rays are checked by the invariants of
+the merge instead of equality.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import field, geometry, grid, lut, quanta, render
+from tests import gpu_helpers as H
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - only on the GPU machine
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_2401_02896_amd as L  # noqa: E402
+
+RNG = np.random.default_rng(12345)
+TINY_SAMPLE = np.unique(np.concatenate([np.arange(0, 130), np.arange(2000, 2070), np.arange(4030, 4096),
+                                        RNG.integers(0, 4096, 40)]))
+
+
+def _check_ray(sc, out, r, f, peak_tol=1e-9, coef_tol=1e-8, field_tol=1e-5):
+    """Compare ray r of an exact-mode approx_rays result with the oracle's ray field f."""
+    D = sc.D
+    ko = out["knot_offsets"].cpu().numpy()
+    kt = out["knot_t"][ko[r]:ko[r + 1]].cpu().numpy()
+    kp = out["knot_pid"][ko[r]:ko[r + 1]].cpu().numpy()
+    kk = out["knot_kidx"][ko[r]:ko[r + 1]].cpu().numpy()
+    ref = f["knots"]
+    assert len(kt) == len(ref), (r, len(kt), len(ref))
+    assert list(zip(kt.tolist(), kp.tolist(), kk.tolist())) == [(t, p, k) for (t, p, k, _) in ref]
+    eo = out["exact_offsets"].cpu().numpy()
+    et = out["exact_t"][eo[r]:eo[r + 1]].cpu().numpy()
+    ee = out["exact_end"][eo[r]:eo[r + 1]].cpu().numpy()
+    ec = out["exact_coef"][eo[r]:eo[r + 1]].cpu().numpy()
+    pcs = f["pieces"]
+    assert et.tolist() == [p[0] for p in pcs] and ee.tolist() == [p[1] for p in pcs]
+    if pcs:
+        oc = np.array([[float(x) for x in p[2]] for p in pcs])
+        scale = np.maximum(np.abs(oc).max(axis=0), 1.0)
+        assert np.all(np.abs(ec.astype(np.float64) - oc) <= coef_tol * scale + 1.0), r
+    pk = float(out["ray_peak"][r].cpu())
+    assert abs(pk - f["peak"]) <= max(peak_tol * f["peak"], 6e-8 * f["peak"]), (r, pk, f["peak"])
+    # merged field
+    t0, t1, cf = H.field_of_ray(out, r, D)
+    onodes = [field.node_output(n, f["merger"]) for n in f["nodes"]]
+    if not onodes:
+        assert len(t0) == 0
+        return True
+    same = len(onodes) == len(t0) and all(np.float32(a) == x and np.float32(b) == y
+                                          for (a, b, _), x, y in zip(onodes, t0, t1))
+    if f["margin"] > 1e-6:
+        assert same, (r, len(onodes), len(t0), f["margin"])
+    if same:
+        ts = np.concatenate([np.linspace(a, b, 9, endpoint=False)[1:] for (a, b, _) in onodes])
+        ref_v = H.eval_pieces(np.array([a for a, _, _ in onodes]), np.array([b for _, b, _ in onodes]),
+                              np.array([c for _, _, c in onodes]), ts)
+        got_v = H.eval_pieces(t0.astype(np.float64), t1.astype(np.float64), cf, ts)
+        assert np.max(np.abs(got_v - ref_v)) <= field_tol * f["peak"], (r, np.max(np.abs(got_v - ref_v)) / f["peak"])
+    else:
+        # partition invariants only
+        assert t0[0] == np.float32(onodes[0][0]) and t1[-1] == np.float32(onodes[-1][1])
+        assert np.all(t1[:-1] == t0[1:])
+    return same
+
+
+def _approx(sc, o, v, t_min, t_max, exact=True):
+    idx = sc.index()
+    return L.sph_hoa_approx_rays(idx, torch.as_tensor(o), torch.as_tensor(v), t_min, t_max, exact=exact)
+
+
+def test_grid_keys_bit_exact():
+    sc = H.tiny_scene()
+    morton, level, order = sc.index().grid()
+    g, codes, perm = grid.morton_order(sc.xyz, sc.h)
+    assert np.array_equal(order.cpu().numpy(), perm.astype(np.int32))
+    assert np.array_equal(level.cpu().numpy(), g["level"][perm].astype(np.int32))
+    assert np.array_equal(morton.cpu().numpy().astype(np.uint64), codes[perm])
+    info = sc.index().info()
+    assert info["cell0"] == g["c0"] and info["n_levels"] == g["n_levels"]
+    assert [list(d) for d in info["level_dims"]] == [list(d) for d in g["dims"]]
+
+
+def test_library_quanta_match_oracle():
+    """With nothing given, the library derives a_max, h_repr, phi_repr, sigma and tau itself."""
+    sc = H.tiny_scene()
+    idx = L.sph_hoa_build_index(sc.xyz, sc.h, sc.val, kernel=0, degree=2, pieces=4, lut_entries=64, merge_tol=1e-3)
+    inf = idx.info()
+    assert inf["a_max"] == sc.a_max
+    assert inf["h_repr"] == sc.h_repr and inf["phi_repr"] == sc.phi_repr
+    assert abs(inf["sigma"] / sc.sigma - 1) < 1e-15
+    assert abs(inf["tau"] / sc.tau - 1) < 1e-12
+    idx.free()
+
+
+def test_lut_projection_matches_oracle():
+    sc = H.tiny_scene()
+    theta, shat, smid = sc.index().lut()
+    assert np.array_equal(theta, sc.theta)
+    for i in list(range(0, 4096, 97)) + [4095]:
+        ref = sc.shat[i]
+        scale = np.abs(ref).max()
+        assert np.max(np.abs(shat[i] - ref)) <= 1e-9 * scale, i
+
+
+def test_tiny_exact_and_merged_fields():
+    """Plain method, tiny scene (4,096 particles, 64 x 64 orthographic rays, D = 2, cubic)."""
+    sc = H.tiny_scene()
+    o, v = synth.ortho_rays()
+    out = _approx(sc, o, v, 0.0, 1.4)
+    assert out["n_pairs"] > 200000
+    same = 0
+    for r in TINY_SAMPLE:
+        f = sc.oracle_ray(o[r], v[r], 0.0, 1.4)
+        same += _check_ray(sc, out, int(r), f)
+    assert same >= 0.97 * len(TINY_SAMPLE)
+
+
+def test_tiny_render_pixels():
+    sc = H.tiny_scene()
+    cam = synth.tiny_camera()
+    tf = synth.transfer_function()
+    vmax = 4.0e4
+    step = 1.4 / 256
+    img = L.sph_hoa_render(sc.index(), cam, tf, 0.0, vmax, step).cpu().numpy().reshape(-1, 4)
+    oo, vv = geometry.camera_rays(cam)
+    checked = 0
+    for r in TINY_SAMPLE[::2]:
+        f = sc.oracle_ray(oo[r], vv[r], 0.0, 1.4)
+        if f["margin"] <= 1e-6:
+            continue
+        px = H.oracle_pixel(sc, f, 0.0, 1.4, tf.astype(np.float64), 0.0, vmax, step)
+        assert np.max(np.abs(img[r] - px)) <= 1e-4, (r, img[r], px)
+        checked += 1
+    assert checked > 0.9 * len(TINY_SAMPLE[::2])
+    assert np.all(img[:, 3] >= 0) and np.all(img[:, 3] <= 1)
+
+
+@pytest.mark.parametrize("kind,K,D,n_lut", [("cubic", 3, 3, 256), ("wendland", 2, 2, 256), ("cubic", 1, 2, 128),
+                                            ("cubic", 5, 2, 128), ("wendland", 6, 4, 128), ("cubic", 4, 4, 256),
+                                            ("wendland", 4, 1, 256)])
+def test_configurations(kind, K, D, n_lut):
+    """K odd and even (middle knot / closure at +-theta_1), D = 1..4, signed amplitudes."""
+    xyz, h, val = synth.random_scene(21 + K + 10 * D, 500, h_lo=0.03, h_hi=0.1, signed=True)
+    sc = H.Scene(kind, K, D, n_lut, xyz, h, val, 1e-3)
+    o, v = synth.random_rays(7 + K, 37)
+    out = _approx(sc, o, v, -0.5, 3.5)
+    same = 0
+    for r in range(37):
+        f = sc.oracle_ray(o[r], v[r], -0.5, 3.5)
+        same += _check_ray(sc, out, r, f)
+    assert same >= 35
+
+
+def test_no_merge_outputs_exact_pieces():
+    xyz, h, val = synth.random_scene(31, 400, h_lo=0.03, h_hi=0.1)
+    sc = H.Scene("cubic", 4, 2, 4096, xyz, h, val, 0.0)
+    o, v = synth.random_rays(3, 21)
+    out = _approx(sc, o, v, -0.5, 3.5)
+    assert out["n_pieces"] == out["n_exact_pieces"]
+    for r in range(21):
+        f = sc.oracle_ray(o[r], v[r], -0.5, 3.5, tol=0.0)
+        assert _check_ray(sc, out, r, f)
+
+
+def test_device_memory_path_is_identical():
+    """Rays too long for the LDS layout take the device-memory path with the same arithmetic."""
+    sc = H.tiny_scene()
+    o, v = synth.ortho_rays()
+    o, v = o[:300], v[:300]
+    a = _approx(sc, o, v, 0.0, 1.4)
+    os.environ["SPH_HOA_MAX_LDS_HITS"] = "16"
+    try:
+        b = _approx(sc, o, v, 0.0, 1.4)
+        st = sc.index().stats()
+    finally:
+        del os.environ["SPH_HOA_MAX_LDS_HITS"]
+    assert st["rays_global"] > 100
+    for k in ("ray_offsets", "t_start", "t_end", "coef", "ray_peak", "exact_t", "exact_coef", "knot_t", "knot_pid"):
+        assert torch.equal(a[k], b[k]), k
+
+
+def test_deterministic():
+    sc = H.tiny_scene()
+    o, v = synth.ortho_rays()
+    a = _approx(sc, o[:512], v[:512], 0.0, 1.4)
+    b = _approx(sc, o[:512], v[:512], 0.0, 1.4)
+    for k in ("ray_offsets", "t_start", "coef", "exact_coef", "knot_t"):
+        assert torch.equal(a[k], b[k]), k
+
+
+def test_edge_cases():
+    sc = H.tiny_scene()
+    # rays that miss the volume, a ray count that is not a multiple of the wave/work-group sizes
+    o = np.array([[5.0, 5.0, 5.0], [0.5, 0.5, -0.2], [-3.0, 0.5, 0.5]], np.float32)
+    v = np.array([[0.0, 0.0, 1.0], [0.0, 0.0, 1.0], [0.0, 1.0, 0.0]], np.float32)
+    out = _approx(sc, o, v, 0.0, 1.4)
+    offs = out["ray_offsets"].cpu().numpy()
+    assert offs[1] - offs[0] == 0 and offs[3] - offs[2] == 0 and offs[2] - offs[1] > 0
+    assert float(out["ray_peak"][0]) == 0.0
+    f = sc.oracle_ray(o[1], v[1], 0.0, 1.4)
+    _check_ray(sc, out, 1, f)
+    # a segment that ends before every particle
+    out = _approx(sc, o[1:2], v[1:2], 0.0, 0.1)
+    f = sc.oracle_ray(o[1], v[1], 0.0, 0.1)
+    _check_ray(sc, out, 0, f)
+    # no rays at all
+    out = L.sph_hoa_approx_rays(sc.index(), torch.zeros((0, 3)), torch.zeros((0, 3)), 0.0, 1.0)
+    assert out["n_pieces"] == 0
+
+
+def test_duplicate_particle_doubles_integers():
+    """Two coincident particles give exactly twice the integer jumps of one."""
+    xyz = np.array([[0.5, 0.5, 0.5], [0.2, 0.2, 0.2]], np.float32)
+    h = np.array([0.05, 0.05], np.float32)
+    val = np.array([1.0, 1.0], np.float32)
+    kw = dict(kernel=0, degree=3, pieces=4, lut_entries=256, merge_tol=0.0, a_max=100.0, h_repr=0.05,
+              phi_repr=8000.0, tau=1e-5)
+    one = L.sph_hoa_build_index(xyz, h, val, **kw)
+    two = L.sph_hoa_build_index(np.concatenate([xyz, xyz[:1]]), np.concatenate([h, h[:1]]),
+                                np.concatenate([val, val[:1]]), **kw)
+    o = torch.tensor([[0.51, 0.49, 0.0]])
+    v = torch.tensor([[0.0, 0.0, 1.0]])
+    a = L.sph_hoa_approx_rays(one, o, v, 0.0, 1.0, exact=True)
+    b = L.sph_hoa_approx_rays(two, o, v, 0.0, 1.0, exact=True)
+    assert torch.equal(a["exact_t"], b["exact_t"])
+    assert torch.equal(2 * a["exact_coef"], b["exact_coef"])
+
+
+def test_argument_errors():
+    sc = H.tiny_scene()
+    xyz = sc.xyz.copy()
+    xyz[3, 1] = np.nan
+    with pytest.raises(L.SphHoaError) as e:
+        L.sph_hoa_build_index(xyz, sc.h, sc.val)
+    assert e.value.status == 1
+    h = sc.h.copy()
+    h[7] = 0.0
+    with pytest.raises(L.SphHoaError):
+        L.sph_hoa_build_index(sc.xyz, h, sc.val)
+    with pytest.raises(L.SphHoaError):
+        L.sph_hoa_build_index(sc.xyz, sc.h, sc.val, degree=1, pieces=1)
+    o = torch.tensor([[0.5, 0.5, -0.2]])
+    with pytest.raises(L.SphHoaError) as e:
+        L.sph_hoa_approx_rays(sc.index(), o, torch.tensor([[0.0, 0.0, 2.0]]), 0.0, 1.4)
+    assert e.value.status == 1
+    with pytest.raises(L.SphHoaError) as e:
+        L.sph_hoa_approx_rays(sc.index(), o, torch.tensor([[0.0, 0.0, 1.0]]), 0.0, 1.4, capacity=1)
+    assert e.value.status == 2
+
+
+def test_full_size_plain_config_sampled():
+    """Plain GPU path at full size (1M clustered particles, Wendland C2, D = 3, 512 x 512
+    perspective): the rendered frame in the benchmark's launch configuration, checked on
+    sampled pixels and on the exact/merged fields of sampled rays."""
+    xyz, h, val = synth.clustered_particles()
+    sc = H.Scene("wendland", 4, 3, 4096, xyz, h, val, 1e-3)
+    cam = synth.plain_camera()
+    tf = synth.transfer_function()
+    vmax, step = 300.0, 2.0 / 512
+    img = L.sph_hoa_render(sc.index(), cam, tf, 0.0, vmax, step).cpu().numpy().reshape(-1, 4)
+    st = sc.index().stats()
+    assert st["n_pairs"] > 1.5e8
+    oo, vv = geometry.camera_rays(cam)
+    rng = np.random.default_rng(77)
+    pix = np.concatenate([[512 * 256 + 256, 512 * 200 + 300], rng.integers(0, 512 * 512, 8)])
+    for r in pix:
+        f = sc.oracle_ray(oo[r], vv[r], 1.0, 3.0)
+        if f["margin"] <= 1e-6:
+            continue
+        px = H.oracle_pixel(sc, f, 1.0, 3.0, tf.astype(np.float64), 0.0, vmax, step)
+        assert np.max(np.abs(img[r] - px)) <= 1e-4, (r, img[r], px)
+    # fields of a few sampled rays (float32 copies of the camera rays)
+    o32, v32 = oo[pix[:4]].astype(np.float32), vv[pix[:4]].astype(np.float32)
+    out = _approx(sc, o32, v32, 1.0, 3.0)
+    for i in range(4):
+        f = sc.oracle_ray(o32[i], v32[i], 1.0, 3.0)
+        _check_ray(sc, out, i, f)
