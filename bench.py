@@ -1,0 +1,227 @@
+"""Benchmark: particle-ray contributions per second of the rendering path on one MI355X.
+
+Workload (default): the plain GPU configuration - 1,000,000 particles from a
+16-cluster Gaussian mixture plus 10 % uniform background, h = r32 / 2, values
+= SPH density (amplitude 1/N), Wendland C2, K = 4, D = 3, merge tolerance
+1e-3, 512 x 512 perspective rays, t in [1, 3].  One step = one full frame:
+camera rays, hit gathering, knot generation, sort, exact accumulation, merge,
+classification and compositing (sph_hoa_render).  The index (grid, tables,
+quanta) is built once before the timed region, as a viewer would keep it
+resident.
+
+Prints one JSON line.  `value` = contributions (particle, ray pairs) over the
+timed frames divided by the timed wall time; p50/p99 are per-frame wall
+latencies.  `roofline` covers the per-ray field kernel, timed with hipEvents
+inside the library on the rendering stream; `cpu_baseline` times the oracle on
+a bounded sample of the same frame's rays on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X published peaks and the integer arithmetic rates used for the ALU roofline
+# (256 CUs x 4 SIMD x 16 lanes x 2.4 GHz; 32-bit integer multiplies issue at a quarter rate).
+N_CU, CLOCK_HZ = 256, 2.4e9
+LANES_PER_CLK = N_CU * 64                       # full-rate 32-bit VALU lanes per clock
+INT32_MUL_PER_S = LANES_PER_CLK / 4 * CLOCK_HZ  # 9.83e12 32-bit multiplies / s
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--particles", type=int, default=1_000_000)
+    ap.add_argument("--size", type=int, default=512)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0, help="budget of the oracle baseline")
+    ap.add_argument("--no-cpu", action="store_true")
+    return ap.parse_args()
+
+
+def oracle_worker(args):
+    """CPU baseline leg: the oracle on a batch of rays (runs in a forked worker)."""
+    rays, state = args
+    from oracle import field, render
+
+    sc = state
+    out = []
+    for (r, o, v) in rays:
+        t0 = time.perf_counter()
+        f = field.ray_field(o, v, sc["t_min"], sc["t_max"], sc["xyz"], sc["h"], sc["val"], sc["table"],
+                            (sc["tau"], sc["sigma"]), sc["K"], sc["D"], sc["kind"], sc["tol"])
+        nodes = [field.node_output(n, f["merger"]) for n in f["nodes"]]
+        px = render.composite(nodes, sc["t_min"], sc["t_max"], sc["tf"], sc["vmin"], sc["vmax"], sc["step"])
+        out.append((r, len(f["hits"]), px, f["margin"], time.perf_counter() - t0))
+    return out
+
+
+_STATE = None
+
+
+def _init_state(s):
+    global _STATE
+    _STATE = s
+
+
+def _run_batch(rays):
+    return oracle_worker((rays, _STATE))
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {a.gpus}): every ray is independent, so N GPUs would "
+              "split the image; this build measures the one-GPU share.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_2401_02896_amd as L
+    import synth
+
+    assert torch.cuda.is_available(), "bench.py needs the GPU"
+    L.lib()
+    t_gen = time.time()
+    xyz, h, val = synth.clustered_particles(n=a.particles)
+    gen_s = time.time() - t_gen
+    kind, K, D, tol = "wendland", 4, 3, 1e-3
+    cam = synth.plain_camera(a.size, a.size)
+    tf = synth.transfer_function()
+    vmin, vmax, step = 0.0, 300.0, 2.0 / 512
+    t_idx = time.time()
+    idx = L.sph_hoa_build_index(xyz, h, val, kernel=L.KERNEL_WENDLAND_C2, degree=D, pieces=K, lut_entries=4096,
+                                merge_tol=tol)
+    torch.cuda.synchronize()
+    index_s = time.time() - t_idx
+    info = idx.info()
+    out = torch.empty((cam["height"], cam["width"], 4), dtype=torch.float32, device="cuda")
+    for _ in range(a.warmup):
+        L.sph_hoa_render(idx, cam, tf, vmin, vmax, step, out=out)
+    torch.cuda.synchronize()
+    idx.set_timing(True)
+    lat = []
+    pairs = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        ts = time.perf_counter()
+        L.sph_hoa_render(idx, cam, tf, vmin, vmax, step, out=out)
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - ts)
+        pairs += idx.stats()["n_pairs"]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    st = idx.stats()
+    idx.set_timing(False)
+    pairs_per_frame = st["n_pairs"]
+    value = pairs / elapsed
+    lat_ms = np.array(lat) * 1e3
+    field_ms = st["ms_field"] / max(1, st["timed_calls"])
+    gather_ms = st["ms_gather"] / max(1, st["timed_calls"])
+    # Roofline of the field kernel (ALU bound, integer multiplies): per contribution the
+    # knots of one particle are accumulated three times (aggregate, peak, pieces) with a
+    # D(D+1)/2-step Taylor shift per knot, each step one 64x32-bit multiply = two 32-bit
+    # multiplies; the closure of the middle knot adds sum_{d odd} P * (D - d + 1) 64-bit
+    # multiply-adds (three 32-bit multiplies each), also three times.
+    P = (K + 1) // 2
+    knots = K + 1
+    shift_mul32 = 2 * (D * (D + 1) // 2)
+    closure_mul32 = 3 * sum(P * (D - d + 1) * 2 for d in range(1, D + 1, 2))
+    mul32_per_pair = 3 * (knots * shift_mul32 + closure_mul32)
+    achieved = mul32_per_pair * pairs_per_frame / (field_ms * 1e-3) / 1e12
+    peak = INT32_MUL_PER_S / 1e12
+    roofline = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tmul32/s",
+                "frac": achieved / peak, "traffic": None, "kernel": "k_field",
+                "kernel_ms": field_ms, "gather_ms": gather_ms,
+                "algorithmic_mul32_per_pair": mul32_per_pair}
+    result = {
+        "metric": "particle-ray contributions/s at rel err <=1e-5; p50/p99 frame latency",
+        "value": value, "unit": "contributions/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": elapsed / a.steps * 1e3, "p50_ms": float(np.percentile(lat_ms, 50)),
+        "p99_ms": float(np.percentile(lat_ms, 99)), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+        "config": {"workload": f"plain GPU path: {a.particles} clustered particles (16 Gaussians + 10% uniform, "
+                               f"h=r32/2, SPH density), Wendland C2, K=4, D=3, tol 1e-3, {a.size}x{a.size} "
+                               "perspective rays, render", "pairs_per_frame": pairs_per_frame,
+                   "max_hits_per_ray": st["max_hits"], "rays_device_memory": st["rays_global"],
+                   "tau": info["tau"], "sigma": info["sigma"], "index_build_s": index_s, "generate_s": gen_s},
+        "roofline": roofline,
+    }
+    img = out.cpu().numpy().reshape(-1, 4)
+    if not a.no_cpu:
+        result["cpu_baseline"], result["parity"] = cpu_baseline(a, xyz, h, val, info, cam, tf, vmin, vmax, step,
+                                                                kind, K, D, tol, img)
+    print(json.dumps(result), flush=True)
+
+
+def cpu_baseline(a, xyz, h, val, info, cam, tf, vmin, vmax, step, kind, K, D, tol, img):
+    """The oracle on a bounded random sample of this frame's rays, in a process pool."""
+    import multiprocessing as mp
+
+    from oracle import geometry, lut
+    from tests.golden.make_knot_tables import load
+
+    theta = load(kind, K, D, 4096)
+    lams = lut.lambda_midpoints(kind, 4096)
+
+    class Rows:
+        def __init__(self):
+            self.c = {}
+
+        def __getitem__(self, i):
+            if i not in self.c:
+                self.c[i], _ = lut.difference_coefficients(kind, float(lams[i]), theta[i], K, D)
+            return self.c[i]
+
+    # the oracle's own quanta for the same data
+    from oracle import grid, quanta
+
+    am = grid.a_max(kind, xyz, h, val)
+    hr, pr = grid.representatives(h, val)
+    tau, sigma = quanta.choose_quanta(kind, D, am, hr, pr)
+    oo, vv = geometry.camera_rays(cam)
+    rng = np.random.default_rng(2024)
+    sample = rng.choice(len(oo), size=4096, replace=False)
+    state = {"xyz": xyz, "h": h, "val": val, "table": {"theta": theta, "shat": Rows()}, "tau": tau, "sigma": sigma,
+             "K": K, "D": D, "kind": kind, "tol": tol, "t_min": float(cam["t_min"]), "t_max": float(cam["t_max"]),
+             "tf": tf.astype(np.float64), "vmin": vmin, "vmax": vmax, "step": step}
+    cores = max(1, min(16, os.cpu_count() or 1))
+    ctx = mp.get_context("fork")
+    results = []
+    budget = a.cpu_seconds
+    t0 = time.perf_counter()
+    with ctx.Pool(cores, initializer=_init_state, initargs=(state,)) as pool:
+        batch = 4
+        pos = 0
+        pending = []
+        while pos < len(sample) or pending:
+            while pos < len(sample) and len(pending) < 2 * cores and time.perf_counter() - t0 < budget:
+                rays = [(int(r), oo[r], vv[r]) for r in sample[pos:pos + batch]]
+                pending.append(pool.apply_async(_run_batch, (rays,)))
+                pos += batch
+            if not pending:
+                break
+            results.extend(pending.pop(0).get())
+        elapsed = time.perf_counter() - t0
+    hits = sum(r[1] for r in results)
+    diffs = [float(np.max(np.abs(img[r] - px))) for (r, _, px, m, _) in results if m > 1e-6]
+    base = {"value": hits / elapsed, "unit": "contributions/s", "cores": cores, "kind": "oracle",
+            "sample": f"{len(results)} random pixel rays of the same 512x512 frame (FP64 oracle with Python-integer "
+                      f"accumulation, {cores} worker processes, {elapsed:.1f} s wall)"}
+    parity = {"rays": len(results), "rays_compared": len(diffs),
+              "max_abs_rgba": max(diffs) if diffs else None, "tol": 1e-4,
+              "quanta_rel_diff": {"tau": abs(info["tau"] / tau - 1), "sigma": abs(info["sigma"] / sigma - 1)}}
+    return base, parity
+
+
+if __name__ == "__main__":
+    main()

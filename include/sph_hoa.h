@@ -138,6 +138,11 @@ typedef struct {
   int64_t n_pieces;       /* merged pieces (render: pieces composited) */
   int64_t max_hits;       /* largest number of contributions on one ray */
   int64_t rays_global;    /* rays processed from device memory instead of LDS */
+  /* with timing enabled (sph_hoa_index_set_timing): device time summed over the timed calls
+   * since timing was (re-)enabled, from hipEvents recorded on the call's stream */
+  int64_t timed_calls;
+  double ms_gather;       /* hit gathering (both passes) */
+  double ms_field;        /* per-ray field kernel (knots, sort, accumulation, merge, composite) */
 } sph_hoa_stats;
 
 /*
@@ -188,6 +193,10 @@ sph_hoa_status sph_hoa_index_get_grid(sph_hoa_index idx, uint64_t* morton, int32
 
 /* Counters of the last call on this index; synchronises the stream of that call. */
 sph_hoa_status sph_hoa_index_get_stats(sph_hoa_index idx, sph_hoa_stats* stats);
+
+/* on != 0: record hipEvents around the gather and field kernels of every later call and
+ * accumulate their durations into the stats (resets the sums); 0: stop. */
+sph_hoa_status sph_hoa_index_set_timing(sph_hoa_index idx, int32_t on);
 
 /* Host-only: the library's optimal knots for one Lambda (Sec. 3.4), theta_out[ceil(K/2)],
  * and the squared L2 error of the optimum.  No GPU work. */

@@ -72,11 +72,13 @@ class TF(ctypes.Structure):
 
 class Stats(ctypes.Structure):
     _fields_ = [("n_rays", ctypes.c_int64), ("n_pairs", ctypes.c_int64), ("n_knots", ctypes.c_int64),
-                ("n_pieces", ctypes.c_int64), ("max_hits", ctypes.c_int64), ("rays_global", ctypes.c_int64)]
+                ("n_pieces", ctypes.c_int64), ("max_hits", ctypes.c_int64), ("rays_global", ctypes.c_int64),
+                ("timed_calls", ctypes.c_int64), ("ms_gather", ctypes.c_double), ("ms_field", ctypes.c_double)]
 
 
 EXPORTS = ["sph_hoa_build_index", "sph_hoa_approx_rays", "sph_hoa_render", "sph_hoa_index_free",
            "sph_hoa_index_get_info", "sph_hoa_index_get_lut", "sph_hoa_index_get_grid", "sph_hoa_index_get_stats",
+           "sph_hoa_index_set_timing",
            "sph_hoa_optimal_knots", "sph_hoa_knot_table", "sph_hoa_optimal_tau", "sph_hoa_status_string", "sph_hoa_last_error"]
 
 _lib = None
@@ -99,6 +101,7 @@ def lib():
     L.sph_hoa_index_get_lut.argtypes = [vp, vp, vp, vp]
     L.sph_hoa_index_get_grid.argtypes = [vp, vp, vp, vp, vp]
     L.sph_hoa_index_get_stats.argtypes = [vp, ctypes.POINTER(Stats)]
+    L.sph_hoa_index_set_timing.argtypes = [vp, i32]
     L.sph_hoa_optimal_knots.argtypes = [ctypes.c_int, i32, i32, dbl, ctypes.POINTER(dbl), ctypes.POINTER(dbl)]
     L.sph_hoa_knot_table.argtypes = [ctypes.c_int, i32, i32, i32, vp, vp]
     L.sph_hoa_optimal_tau.argtypes = [ctypes.c_int, i32, dbl, dbl, dbl, ctypes.POINTER(dbl)]
@@ -181,6 +184,9 @@ class Index:
         order = torch.empty(self.n, dtype=torch.int32, device="cuda")
         _check(lib().sph_hoa_index_get_grid(self.handle, _ptr(morton), _ptr(level), _ptr(order), _stream()))
         return morton, level, order
+
+    def set_timing(self, on=True):
+        _check(lib().sph_hoa_index_set_timing(self.handle, 1 if on else 0))
 
     def stats(self):
         s = Stats()

@@ -292,7 +292,26 @@ sph_hoa_status sph_hoa_index_get_stats(sph_hoa_index idx, sph_hoa_stats* stats) 
   return guarded([&]() {
     require(idx && stats, "NULL argument");
     if (idx->ix.last_stream) sph::hip_check(hipStreamSynchronize(idx->ix.last_stream), "sync");
+    idx->ix.collect_timing();
     *stats = idx->ix.stats;
+    stats->timed_calls = idx->ix.timed_calls;
+    stats->ms_gather = idx->ix.ms_gather;
+    stats->ms_field = idx->ix.ms_field;
+  });
+}
+
+sph_hoa_status sph_hoa_index_set_timing(sph_hoa_index idx, int32_t on) {
+  return guarded([&]() {
+    require(idx, "NULL index");
+    sph::Index& ix = idx->ix;
+    if (ix.last_stream) sph::hip_check(hipStreamSynchronize(ix.last_stream), "sync");
+    ix.collect_timing();
+    if (on)
+      for (auto& e : ix.ev)
+        if (!e) sph::hip_check(hipEventCreate(&e), "event create");
+    ix.timing = on != 0;
+    ix.timed_calls = 0;
+    ix.ms_gather = ix.ms_field = 0.0;
   });
 }
 

@@ -114,6 +114,17 @@ struct Index {
   DevBuf out_stage, exact_stage;
   sph_hoa_stats stats{};
   hipStream_t last_stream = nullptr;
+  // optional event timing of the kernels (sph_hoa_index_set_timing)
+  bool timing = false;
+  bool timing_pending = false;
+  hipEvent_t ev[6] = {};
+  int64_t timed_calls = 0;
+  double ms_gather = 0.0, ms_field = 0.0;
+  void collect_timing();
+  ~Index() {
+    for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
 };
 
 // build (index.hip)

@@ -1181,9 +1181,23 @@ unsigned blocks_for(int64_t n, int t) {
 
 }  // namespace
 
+void Index::collect_timing() {
+  if (!timing_pending) return;
+  timing_pending = false;
+  hip_check(hipEventSynchronize(ev[5]), "event sync");
+  float a = 0.f, b = 0.f, c = 0.f;
+  hip_check(hipEventElapsedTime(&a, ev[0], ev[1]), "elapsed");
+  hip_check(hipEventElapsedTime(&b, ev[2], ev[3]), "elapsed");
+  hip_check(hipEventElapsedTime(&c, ev[4], ev[5]), "elapsed");
+  ms_gather += (double)a + (double)b;
+  ms_field += (double)c;
+  ++timed_calls;
+}
+
 void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam, const sph_hoa_rays* rays,
               FieldOut& out, hipStream_t st) {
   const int D = ix.D, K = ix.K, P = ix.P;
+  ix.collect_timing();
   ix.stats = sph_hoa_stats{};
   ix.stats.n_rays = n_rays;
   ix.counters.ensure(256);
@@ -1256,7 +1270,9 @@ void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam,
   G.max_hits = max_hits;
   G.flags = flags;
   const unsigned gblocks = (unsigned)((n_rays + 3) / 4);
+  if (ix.timing) hip_check(hipEventRecord(ix.ev[0], st), "event");
   k_gather<false><<<gblocks, kGatherThreads, 0, st>>>(G);
+  if (ix.timing) hip_check(hipEventRecord(ix.ev[1], st), "event");
   hip_check(hipGetLastError(), "gather launch");
   device_exclusive_scan_i64(ix.hit_count.as<int64_t>(), ix.hit_off.as<int64_t>(), n_rays, ix.scan_tmp, st);
   k_set_last<<<1, 1, 0, st>>>(ix.hit_off.as<int64_t>(), ix.hit_count.as<int64_t>(), n_rays);
@@ -1277,7 +1293,9 @@ void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam,
   ix.hits.ensure(sizeof(uint32_t) * std::max<int64_t>(1, total_pairs));
   G.off = ix.hit_off.as<int64_t>();
   G.hits = ix.hits.as<uint32_t>();
+  if (ix.timing) hip_check(hipEventRecord(ix.ev[2], st), "event");
   k_gather<true><<<gblocks, kGatherThreads, 0, st>>>(G);
+  if (ix.timing) hip_check(hipEventRecord(ix.ev[3], st), "event");
   hip_check(hipGetLastError(), "gather launch");
   // ---- field kernel
   FieldArgs A{};
@@ -1329,7 +1347,12 @@ void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam,
     A.tf_vmax = out.tf->v_max;
     A.tf_step = (double)out.tf->step;
     A.rgba = out.rgba;
+    if (ix.timing) hip_check(hipEventRecord(ix.ev[4], st), "event");
     dispatch_field<true>(D, A, grid, lds, st);
+    if (ix.timing) {
+      hip_check(hipEventRecord(ix.ev[5], st), "event");
+      ix.timing_pending = true;
+    }
   } else {
     sph_hoa_field* f = out.field;
     A.out_cap = f->capacity;
@@ -1361,7 +1384,12 @@ void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam,
         hip_check(hipMemcpyAsync(f->knot_offsets, knot_off.p, sizeof(int64_t) * (n_rays + 1), hipMemcpyDeviceToDevice, st),
                   "copy");
     }
+    if (ix.timing) hip_check(hipEventRecord(ix.ev[4], st), "event");
     dispatch_field<false>(D, A, grid, lds, st);
+    if (ix.timing) {
+      hip_check(hipEventRecord(ix.ev[5], st), "event");
+      ix.timing_pending = true;
+    }
     // counts -> final offsets, then reorder staged pieces by ray
     DevBuf cnt;
     cnt.ensure(sizeof(int64_t) * (n_rays + 1));

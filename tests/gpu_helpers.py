@@ -40,6 +40,21 @@ class Scene:
     def table(self):
         return {"theta": self.theta, "shat": self.shat}
 
+    def index(self):
+        import paper_2401_02896_amd as L
+
+        if self._index is None:
+            self._index = L.sph_hoa_build_index(self.xyz, self.h, self.val, kernel=KIND_ID[self.kind], degree=self.D,
+                                                pieces=self.K, lut_entries=self.n_lut, merge_tol=self.tol,
+                                                a_max=self.a_max, h_repr=self.h_repr, phi_repr=self.phi_repr,
+                                                tau=self.tau, knot_table=self.theta)
+        return self._index
+
+    def oracle_ray(self, o, v, t_min, t_max, tol=None):
+        return field.ray_field(np.asarray(o, np.float64), np.asarray(v, np.float64), t_min, t_max, self.xyz, self.h,
+                               self.val, self.table(), (self.tau, self.sigma), self.K, self.D, self.kind,
+                               self.tol if tol is None else tol)
+
 
 class LazyRows:
     """Oracle jump coefficients of table rows, computed when first used."""
@@ -56,20 +71,7 @@ class LazyRows:
                                                           self.sc.K, self.sc.D)
         return self.rows[i]
 
-    def index(self):
-        import paper_2401_02896_amd as L
 
-        if self._index is None:
-            self._index = L.sph_hoa_build_index(self.xyz, self.h, self.val, kernel=KIND_ID[self.kind], degree=self.D,
-                                                pieces=self.K, lut_entries=self.n_lut, merge_tol=self.tol,
-                                                a_max=self.a_max, h_repr=self.h_repr, phi_repr=self.phi_repr,
-                                                tau=self.tau, knot_table=self.theta)
-        return self._index
-
-    def oracle_ray(self, o, v, t_min, t_max, tol=None):
-        return field.ray_field(np.asarray(o, np.float64), np.asarray(v, np.float64), t_min, t_max, self.xyz, self.h,
-                               self.val, self.table(), (self.tau, self.sigma), self.K, self.D, self.kind,
-                               self.tol if tol is None else tol)
 
 
 @functools.lru_cache(maxsize=None)
