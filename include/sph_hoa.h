@@ -208,6 +208,13 @@ sph_hoa_status sph_hoa_optimal_knots(sph_hoa_kernel kernel, int32_t pieces, int3
 sph_hoa_status sph_hoa_knot_table(sph_hoa_kernel kernel, int32_t pieces, int32_t degree, int32_t n, double* theta_out,
                                   double* err2_out);
 
+/* Host-only: the projection of B_Lambda onto the candidate space for given knots (Sec. 3.3,
+ * Eq. optimal-approx-for-given-knots) as localized jump coefficients, for every entry of a table:
+ * theta [n][ceil(K/2)] (input), shat_out [n][ceil(K/2)][D+1] (jump at +theta_k), smid_out [n][D+1]
+ * (jump at 0 for even K; may be NULL), err2_out [n] (may be NULL). */
+sph_hoa_status sph_hoa_lut_coefficients(sph_hoa_kernel kernel, int32_t pieces, int32_t degree, int32_t n,
+                                        const double* theta, double* shat_out, double* smid_out, double* err2_out);
+
 /* Host-only: the length quantum minimising Q_D(tau / h_repr, sigma / phi_repr) (Sec. 4.4, App. A.5). */
 sph_hoa_status sph_hoa_optimal_tau(sph_hoa_kernel kernel, int32_t degree, double sigma, double h_repr,
                                    double phi_repr, double* tau_out);

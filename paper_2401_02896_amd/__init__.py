@@ -79,7 +79,8 @@ class Stats(ctypes.Structure):
 EXPORTS = ["sph_hoa_build_index", "sph_hoa_approx_rays", "sph_hoa_render", "sph_hoa_index_free",
            "sph_hoa_index_get_info", "sph_hoa_index_get_lut", "sph_hoa_index_get_grid", "sph_hoa_index_get_stats",
            "sph_hoa_index_set_timing",
-           "sph_hoa_optimal_knots", "sph_hoa_knot_table", "sph_hoa_optimal_tau", "sph_hoa_status_string", "sph_hoa_last_error"]
+           "sph_hoa_optimal_knots", "sph_hoa_knot_table", "sph_hoa_lut_coefficients",
+           "sph_hoa_optimal_tau", "sph_hoa_status_string", "sph_hoa_last_error"]
 
 _lib = None
 
@@ -104,6 +105,7 @@ def lib():
     L.sph_hoa_index_set_timing.argtypes = [vp, i32]
     L.sph_hoa_optimal_knots.argtypes = [ctypes.c_int, i32, i32, dbl, ctypes.POINTER(dbl), ctypes.POINTER(dbl)]
     L.sph_hoa_knot_table.argtypes = [ctypes.c_int, i32, i32, i32, vp, vp]
+    L.sph_hoa_lut_coefficients.argtypes = [ctypes.c_int, i32, i32, i32, vp, vp, vp, vp]
     L.sph_hoa_optimal_tau.argtypes = [ctypes.c_int, i32, dbl, dbl, dbl, ctypes.POINTER(dbl)]
     L.sph_hoa_status_string.argtypes = [ctypes.c_int]
     L.sph_hoa_status_string.restype = ctypes.c_char_p
@@ -327,6 +329,21 @@ def sph_hoa_knot_table(kernel, pieces, degree, n):
     _check(lib().sph_hoa_knot_table(kernel, pieces, degree, n, th.ctypes.data_as(ctypes.c_void_p),
                                     e2.ctypes.data_as(ctypes.c_void_p)))
     return th, e2
+
+
+def sph_hoa_lut_coefficients(kernel, pieces, degree, theta):
+    """Library's projection jumps for the given knot table (host only): (shat, smid, err2)."""
+    import numpy as np
+
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    n, P = th.shape
+    shat = np.zeros((n, P, degree + 1))
+    smid = np.zeros((n, degree + 1))
+    e2 = np.zeros(n)
+    _check(lib().sph_hoa_lut_coefficients(kernel, pieces, degree, n, th.ctypes.data_as(ctypes.c_void_p),
+                                          shat.ctypes.data_as(ctypes.c_void_p), smid.ctypes.data_as(ctypes.c_void_p),
+                                          e2.ctypes.data_as(ctypes.c_void_p)))
+    return shat, smid, e2
 
 
 def sph_hoa_optimal_tau(kernel, degree, sigma, h_repr, phi_repr):

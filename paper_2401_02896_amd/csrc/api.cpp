@@ -196,7 +196,8 @@ sph_hoa_status sph_hoa_approx_rays(sph_hoa_index idx, const sph_hoa_rays* rays, 
     sph::Index& ix = idx->ix;
     const double span = std::max(std::fabs((double)rays->t_min), std::fabs((double)rays->t_max)) +
                         ix.grid.lv[ix.grid.n_levels - 1].c;
-    if (!(span / ix.tau < 1.0e9)) throw sph::Error(SPH_HOA_E_OVERFLOW, "ray segment too long for int32 positions");
+    if (!(span / ix.tau < 2.1e9))
+      throw sph::Error(SPH_HOA_E_OVERFLOW, "ray segment too long for int32 positions (|t| + q h_max >= 2^31 tau)");
     sph::FieldOut fo{out, nullptr, nullptr, exact};
     hipStream_t st = (hipStream_t)stream;
     ix.last_stream = st;
@@ -239,7 +240,8 @@ sph_hoa_status sph_hoa_render(sph_hoa_index idx, const sph_hoa_camera* cam, cons
     sph::Index& ix = idx->ix;
     const double span = std::max(std::fabs((double)cam->t_min), std::fabs((double)cam->t_max)) +
                         ix.grid.lv[ix.grid.n_levels - 1].c;
-    if (!(span / ix.tau < 1.0e9)) throw sph::Error(SPH_HOA_E_OVERFLOW, "ray segment too long for int32 positions");
+    if (!(span / ix.tau < 2.1e9))
+      throw sph::Error(SPH_HOA_E_OVERFLOW, "ray segment too long for int32 positions (|t| + q h_max >= 2^31 tau)");
     hipStream_t st = (hipStream_t)stream;
     ix.last_stream = st;
     sph::FieldOut fo{nullptr, rgba_out, tf, false};
@@ -335,6 +337,21 @@ sph_hoa_status sph_hoa_knot_table(sph_hoa_kernel kernel, int32_t pieces, int32_t
     auto t = cached_table(kernel_of(kernel), pieces, degree, n);
     std::memcpy(theta_out, t->theta.data(), sizeof(double) * t->theta.size());
     if (err2_out) std::memcpy(err2_out, t->err2.data(), sizeof(double) * t->err2.size());
+  });
+}
+
+sph_hoa_status sph_hoa_lut_coefficients(sph_hoa_kernel kernel, int32_t pieces, int32_t degree, int32_t n,
+                                        const double* theta, double* shat_out, double* smid_out, double* err2_out) {
+  return guarded([&]() {
+    require(theta && shat_out, "NULL argument");
+    check_method(pieces, degree);
+    require(n >= 2 && n <= 65536, "n must be in 2..65536");
+    const int P = (pieces + 1) / 2;
+    for (int64_t i = 0; i < (int64_t)n * P; ++i) require(std::isfinite(theta[i]) && theta[i] > 0, "theta must be > 0");
+    sph::Table t = sph::build_table(kernel_of(kernel), pieces, degree, n, theta, host_threads());
+    std::memcpy(shat_out, t.shat.data(), sizeof(double) * t.shat.size());
+    if (smid_out) std::memcpy(smid_out, t.smid.data(), sizeof(double) * t.smid.size());
+    if (err2_out) std::memcpy(err2_out, t.err2.data(), sizeof(double) * t.err2.size());
   });
 }
 

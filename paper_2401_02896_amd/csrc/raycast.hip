@@ -642,12 +642,12 @@ __device__ void process_ray(const FieldArgs& A, Shared<D>& sh, const RayStore& S
     int li = (int)floor(lam * (double)A.mc.n_lut / kSupport);
     li = li < 0 ? 0 : (li > A.mc.n_lut - 1 ? A.mc.n_lut - 1 : li);
     const double t0d = rint(tchi / tau);
-    bool bad = !(fabs(t0d) < 1.0e9);
+    bool bad = !(fabs(t0d) < 2.0e9);
     const int32_t t0 = bad ? 0 : (int32_t)t0d;
     int32_t offs[kMaxP] = {0, 0, 0};
     for (int m = 0; m < P; ++m) {
       const double od = rint(z * A.theta[(int64_t)li * P + m] / tau);
-      if (!(od < 1.0e9)) bad = true;
+      if (!(od < 2.0e9) || !(fabs(t0d) + od < 2147483647.0)) bad = true;
       offs[m] = bad ? 0 : (int32_t)od;
     }
     if (bad) atomicOr(A.flags, kFlagPosRange);

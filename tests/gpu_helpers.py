@@ -21,7 +21,7 @@ KIND_ID = {"cubic": 0, "wendland": 1}
 
 
 class Scene:
-    def __init__(self, kind, K, D, n_lut, xyz, h, val, tol):
+    def __init__(self, kind, K, D, n_lut, xyz, h, val, tol, tau_scale=1.0):
         self.kind, self.K, self.D, self.n_lut, self.tol = kind, K, D, n_lut, tol
         self.xyz, self.h, self.val = xyz, h, val
         self.theta = load_knots(kind, K, D, n_lut)
@@ -29,6 +29,7 @@ class Scene:
         self.a_max = grid.a_max(kind, xyz, h, val)
         self.h_repr, self.phi_repr = grid.representatives(h, val)
         self.tau, self.sigma = quanta.choose_quanta(kind, D, self.a_max, self.h_repr, self.phi_repr)
+        self.tau *= tau_scale
         self._index = None
 
     @property

@@ -44,6 +44,26 @@ def test_library_knot_tables_match_oracle(spec):
     assert np.all(d[~flat] < 1e-6), (np.argmax(d), d.max())
 
 
+@pytest.mark.parametrize("spec", [t for t in TABLES if t[3] <= 256] + [("wendland", 4, 3, 4096)])
+def test_library_projection_matches_oracle(spec):
+    """For the same knots, the library's projection jumps (Sec. 3.3) equal the oracle's to the
+    conditioning of the normal equations (grows with D; 1e-9 of the row's largest jump at D <= 3)."""
+    from oracle import lut
+
+    kind, K, D, n = spec
+    theta = load(*spec)
+    shat, smid, e2 = L.sph_hoa_lut_coefficients(0 if kind == "cubic" else 1, K, D, theta)
+    lams = lut.lambda_midpoints(kind, n)
+    rows = sorted(set(list(range(0, n, max(1, n // 24))) + [n - 1]))
+    tol = 1e-9 if D <= 3 else 1e-7
+    for i in rows:
+        ref, ref_mid = lut.difference_coefficients(kind, float(lams[i]), theta[i], K, D)
+        scale = max(np.abs(ref).max(), np.abs(ref_mid).max())
+        assert np.max(np.abs(shat[i] - ref)) <= tol * scale, (i, np.max(np.abs(shat[i] - ref)) / scale)
+        assert np.max(np.abs(smid[i] - ref_mid)) <= tol * scale, i
+        assert abs(e2[i] - lut.project(kind, float(lams[i]), theta[i], K, D)["E2"]) <= 1e-6 * e2[i] + 1e-25
+
+
 @pytest.mark.parametrize("D", [1, 2, 3, 4, 6])
 def test_library_tau_matches_oracle(D):
     r = quanta.fig4_sigma_ratio("cubic")
