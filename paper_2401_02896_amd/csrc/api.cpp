@@ -188,6 +188,8 @@ sph_hoa_status sph_hoa_approx_rays(sph_hoa_index idx, const sph_hoa_rays* rays, 
       require(out->capacity == 0 || (out->t_start && out->t_end && out->coef), "NULL piece arrays");
     }
     const bool exact = (flags & SPH_HOA_FLAG_EXACT) != 0;
+    if (exact && idx->ix.n >= (int64_t(1) << 29))
+      throw sph::Error(SPH_HOA_E_UNSUPPORTED, "exact mode needs fewer than 2^29 particles");
     if (exact && rays->n > 0) {
       require(out->exact_offsets && out->knot_offsets, "exact mode needs offset arrays");
       require(out->exact_capacity == 0 || (out->exact_t && out->exact_end && out->exact_coef), "exact arrays");

@@ -83,4 +83,66 @@ __device__ void bitonic_sort(T* a, int n, int tid, int nthreads) {
   }
 }
 
+// Stable LSD radix sort of a[0..n) by bits [lo_bit, lo_bit + nbits) with 4-bit digits, by all
+// NT threads of the work-group.  Thread t owns the contiguous block [t m, (t+1) m), m = ceil(n/NT),
+// counts its digits in packed 16-bit register fields, and scatters its block in order after a
+// work-group scan of the (digit, thread) counts, so equal digits keep their order.
+// tmp: n elements of scratch; hist: 16 * NT uint32 (LDS); wsum: NT / 64 + 1 uint32 (LDS).
+// The result ends in `a`.  Caller guarantees a barrier before; ends with a barrier.
+template <int NT>
+__device__ void radix_sort_u64(uint64_t* a, uint64_t* tmp, int n, int lo_bit, int nbits, uint32_t* hist,
+                               uint32_t* wsum, int tid) {
+  const int m = (n + NT - 1) / NT;
+  const int b0 = min(tid * m, n), b1 = min(b0 + m, n);
+  uint64_t* src = a;
+  uint64_t* dst = tmp;
+  for (int shift = lo_bit; shift < lo_bit + nbits; shift += 4) {
+    uint64_t c[4] = {0, 0, 0, 0};  // 16 counters of 16 bits
+    for (int i = b0; i < b1; ++i) {
+      const uint32_t d = (uint32_t)(src[i] >> shift) & 15u;
+      const uint64_t inc = 1ull << (16 * (d & 3));
+      const uint32_t q = d >> 2;
+      c[0] += (q == 0) ? inc : 0ull;
+      c[1] += (q == 1) ? inc : 0ull;
+      c[2] += (q == 2) ? inc : 0ull;
+      c[3] += (q == 3) ? inc : 0ull;
+    }
+#pragma unroll
+    for (int d = 0; d < 16; ++d) hist[d * NT + tid] = (uint32_t)((c[d >> 2] >> (16 * (d & 3))) & 0xffffu);
+    __syncthreads();
+    // exclusive scan of hist[0 .. 16 NT) in memory order: thread t takes entries [16 t, 16 t + 16)
+    uint32_t loc[16];
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      loc[k] = s;
+      s += hist[tid * 16 + k];
+    }
+    const uint32_t incl = wave_incl_scan(s);
+    const int w = tid >> 6;
+    if ((tid & 63) == 63) wsum[w] = incl;
+    __syncthreads();
+    uint32_t pre = incl - s;
+    for (int i = 0; i < w; ++i) pre += wsum[i];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) hist[tid * 16 + k] = loc[k] + pre;
+    __syncthreads();
+    for (int i = b0; i < b1; ++i) {
+      const uint64_t v = src[i];
+      const uint32_t d = (uint32_t)(v >> shift) & 15u;
+      const uint32_t p = hist[d * NT + tid];
+      hist[d * NT + tid] = p + 1;
+      dst[p] = v;
+    }
+    __syncthreads();
+    uint64_t* t = src;
+    src = dst;
+    dst = t;
+  }
+  if (src != a) {
+    for (int i = tid; i < n; i += NT) a[i] = src[i];
+    __syncthreads();
+  }
+}
+
 }  // namespace sph

@@ -232,6 +232,154 @@ __global__ void __launch_bounds__(kGatherThreads) k_gather(GatherArgs A) {
   }
 }
 
+// ============================================================== camera rays: screen-tile binning
+//
+// For camera rays the relevant rays of a particle (Sec. 2, first pass) are the pixels inside the
+// projection of its support sphere.  Each particle is binned into the 8 x 8-pixel tiles its
+// projection's bounding box covers (a conservative box with a one-pixel margin; spheres that
+// reach the eye plane cover every tile); the exact float64 test then decides per (pixel ray,
+// candidate).  Replaces the grid walk for rendering: every tile's rays share one candidate list.
+
+constexpr int kTile = 8;
+
+struct BinArgs {
+  const float4* pos4;
+  int64_t n;
+  CamDev c;
+  int tiles_x, tiles_y;
+  double t_min, t_max;
+  unsigned int* tile_count;
+  const int64_t* tile_off;
+  unsigned int* tile_cursor;
+  uint32_t* items;
+};
+
+// pixel range [c0, c1] x [r0, r1] covered by the projection of the particle's support sphere
+__device__ bool particle_pixels(const BinArgs& B, float4 p, int* c0, int* c1, int* r0, int* r1) {
+  const CamDev& c = B.c;
+  const double dx = (double)p.x - c.eye[0], dy = (double)p.y - c.eye[1], dz = (double)p.z - c.eye[2];
+  const double z = dx * c.f[0] + dy * c.f[1] + dz * c.f[2];
+  const double x = dx * c.r[0] + dy * c.r[1] + dz * c.r[2];
+  const double y = dx * c.u[0] + dy * c.u[1] + dz * c.u[2];
+  const double R = kSupport * (double)p.w * (1.0 + 1e-6) + 1e-12;
+  double a0, a1, b0, b1;
+  if (c.ortho) {
+    if (z + R < B.t_min || z - R > B.t_max) return false;
+    a0 = (x - R) / (c.half * c.aspect);
+    a1 = (x + R) / (c.half * c.aspect);
+    b0 = (y - R) / c.half;
+    b1 = (y + R) / c.half;
+  } else {
+    const double dist = sqrt(dx * dx + dy * dy + dz * dz);
+    if (dist - R >= B.t_max || dist + R <= B.t_min) return false;
+    if (z <= R * 1.0001) {
+      a0 = b0 = -1e30;
+      a1 = b1 = 1e30;
+    } else {
+      const double hp = 1.5707963267948966;
+      const double rx = sqrt(x * x + z * z), ry = sqrt(y * y + z * z);
+      const double ax = asin(fmin(1.0, R / rx)), ay = asin(fmin(1.0, R / ry));
+      const double tx = atan2(x, z), ty = atan2(y, z);
+      a0 = (tx - ax <= -hp) ? -1e30 : tan(tx - ax) / (c.g * c.aspect);
+      a1 = (tx + ax >= hp) ? 1e30 : tan(tx + ax) / (c.g * c.aspect);
+      b0 = (ty - ay <= -hp) ? -1e30 : tan(ty - ay) / c.g;
+      b1 = (ty + ay >= hp) ? 1e30 : tan(ty + ay) / c.g;
+    }
+  }
+  // a = (2 col + 1) / W - 1  and  b = 1 - (2 row + 1) / H
+  const double W = (double)c.W, H = (double)c.H;
+  const double fc0 = fmax(-2.0, fmin(W + 2.0, ((a0 + 1.0) * W - 1.0) * 0.5));
+  const double fc1 = fmax(-2.0, fmin(W + 2.0, ((a1 + 1.0) * W - 1.0) * 0.5));
+  const double fr0 = fmax(-2.0, fmin(H + 2.0, ((1.0 - b1) * H - 1.0) * 0.5));
+  const double fr1 = fmax(-2.0, fmin(H + 2.0, ((1.0 - b0) * H - 1.0) * 0.5));
+  *c0 = max(0, (int)floor(fc0) - 1);
+  *c1 = min(c.W - 1, (int)ceil(fc1) + 1);
+  *r0 = max(0, (int)floor(fr0) - 1);
+  *r1 = min(c.H - 1, (int)ceil(fr1) + 1);
+  return *c0 <= *c1 && *r0 <= *r1;
+}
+
+template <bool FILL>
+__global__ void __launch_bounds__(256) k_bin(BinArgs B) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < B.n; i += (int64_t)gridDim.x * blockDim.x) {
+    int c0, c1, r0, r1;
+    if (!particle_pixels(B, B.pos4[i], &c0, &c1, &r0, &r1)) continue;
+    for (int ty = r0 / kTile; ty <= r1 / kTile; ++ty)
+      for (int tx = c0 / kTile; tx <= c1 / kTile; ++tx) {
+        const int64_t t = (int64_t)ty * B.tiles_x + tx;
+        if (FILL) {
+          const unsigned int k = atomicAdd(&B.tile_cursor[t], 1u);
+          B.items[B.tile_off[t] + k] = (uint32_t)i;
+        } else {
+          atomicAdd(&B.tile_count[t], 1u);
+        }
+      }
+  }
+}
+
+__global__ void k_u32_to_i64_n(const unsigned int* a, int64_t* b, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    b[i] = a[i];
+}
+
+struct TileHitArgs {
+  const double* o;
+  const double* v;
+  int W, H, tiles_x;
+  double t_min, t_max;
+  const float4* pos4;
+  const int64_t* tile_off;
+  const uint32_t* items;
+  int64_t* count;
+  const int64_t* off;
+  uint32_t* hits;
+  unsigned long long* max_hits;
+};
+
+// one wave per tile, one lane per pixel ray; candidates staged through LDS 64 at a time
+template <bool FILL>
+__global__ void __launch_bounds__(64) k_tile_hits(TileHitArgs T) {
+  __shared__ float4 cp[64];
+  __shared__ uint32_t cj[64];
+  const int tile = blockIdx.x, lane = threadIdx.x;
+  const int tx = tile % T.tiles_x, ty = tile / T.tiles_x;
+  const int col = tx * kTile + (lane % kTile), row = ty * kTile + (lane / kTile);
+  const bool valid = col < T.W && row < T.H;
+  const int64_t r = valid ? (int64_t)row * T.W + col : 0;
+  double o[3] = {0, 0, 0}, v[3] = {0, 0, 1};
+  if (valid)
+    for (int k = 0; k < 3; ++k) {
+      o[k] = T.o[3 * r + k];
+      v[k] = T.v[3 * r + k];
+    }
+  const int64_t b = T.tile_off[tile], e = T.tile_off[tile + 1];
+  int64_t cnt = 0;
+  const int64_t out0 = (FILL && valid) ? T.off[r] : 0;
+  for (int64_t base = b; base < e; base += 64) {
+    const int64_t k = base + lane;
+    if (k < e) {
+      const uint32_t j = T.items[k];
+      cj[lane] = j;
+      cp[lane] = T.pos4[j];
+    }
+    __syncthreads();
+    const int m = (int)min((int64_t)64, e - base);
+    if (valid) {
+      for (int q = 0; q < m; ++q) {
+        if (pair_hit(o, v, cp[q], T.t_min, T.t_max)) {
+          if (FILL) T.hits[out0 + cnt] = cj[q];
+          ++cnt;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (!FILL && valid) {
+    T.count[r] = cnt;
+    atomicMax(T.max_hits, (unsigned long long)cnt);
+  }
+}
+
 // ============================================================== per-ray field
 
 struct MergeTables {
@@ -452,13 +600,17 @@ __device__ __forceinline__ Node<D> make_leaf(const MergeTables& mt, int32_t ta, 
 // Union of adjacent nodes A = [a, b], B = [b, c]: projection and residual (exact from the parts).
 template <int D>
 __device__ Node<D> combine(const MergeTables& mt, const Node<D>& A, const Node<D>& B, double tau) {
+  // two sweeps over the D + 1 Gauss-Legendre nodes of each part, recomputing the Legendre values
+  // instead of keeping (D + 1)^2 of them live (register pressure)
   Node<D> U;
   U.a = A.a;
   U.b = B.b;
   const double la = (double)((int64_t)A.b - (int64_t)A.a), lb = (double)((int64_t)B.b - (int64_t)B.a);
   const double lam = la / (la + lb);
-  double FA[D + 1], FB[D + 1], PA[D + 1][D + 1], PB[D + 1][D + 1];
+  double g[D + 1];
 #pragma unroll
+  for (int j = 0; j <= D; ++j) g[j] = 0.0;
+#pragma unroll 1
   for (int i = 0; i <= D; ++i) {
     double fa = 0.0, fb = 0.0;
 #pragma unroll
@@ -466,31 +618,34 @@ __device__ Node<D> combine(const MergeTables& mt, const Node<D>& A, const Node<D
       fa += A.g[j] * mt.leg_at_node[j][i];
       fb += B.g[j] * mt.leg_at_node[j][i];
     }
-    FA[i] = fa;
-    FB[i] = fb;
-    legendre_at<D>(lam * mt.node[i], PA[i]);
-    legendre_at<D>(lam + (1.0 - lam) * mt.node[i], PB[i]);
+    double pa[D + 1], pb[D + 1];
+    legendre_at<D>(lam * mt.node[i], pa);
+    legendre_at<D>(lam + (1.0 - lam) * mt.node[i], pb);
+    const double wa = mt.wgt[i] * fa * lam, wb = mt.wgt[i] * fb * (1.0 - lam);
+#pragma unroll
+    for (int j = 0; j <= D; ++j) g[j] += wa * pa[j] + wb * pb[j];
   }
 #pragma unroll
-  for (int j = 0; j <= D; ++j) {
-    double sa = 0.0, sb = 0.0;
-#pragma unroll
-    for (int i = 0; i <= D; ++i) {
-      sa += mt.wgt[i] * FA[i] * PA[i][j];
-      sb += mt.wgt[i] * FB[i] * PB[i][j];
-    }
-    U.g[j] = (2.0 * j + 1.0) * (lam * sa + (1.0 - lam) * sb);
-  }
+  for (int j = 0; j <= D; ++j) U.g[j] = (2.0 * j + 1.0) * g[j];
   double ra = 0.0, rb = 0.0;
-#pragma unroll
+#pragma unroll 1
   for (int i = 0; i <= D; ++i) {
+    double fa = 0.0, fb = 0.0;
+#pragma unroll
+    for (int j = 0; j <= D; ++j) {
+      fa += A.g[j] * mt.leg_at_node[j][i];
+      fb += B.g[j] * mt.leg_at_node[j][i];
+    }
+    double pa[D + 1], pb[D + 1];
+    legendre_at<D>(lam * mt.node[i], pa);
+    legendre_at<D>(lam + (1.0 - lam) * mt.node[i], pb);
     double ua = 0.0, ub = 0.0;
 #pragma unroll
     for (int j = 0; j <= D; ++j) {
-      ua += U.g[j] * PA[i][j];
-      ub += U.g[j] * PB[i][j];
+      ua += U.g[j] * pa[j];
+      ub += U.g[j] * pb[j];
     }
-    const double da = FA[i] - ua, db = FB[i] - ub;
+    const double da = fa - ua, db = fb - ub;
     ra += mt.wgt[i] * da * da;
     rb += mt.wgt[i] * db * db;
   }
@@ -503,7 +658,6 @@ __device__ __forceinline__ bool passes(const Node<D>& n, double thr2, double tau
   return n.r <= thr2 * ((double)((int64_t)n.b - (int64_t)n.a) * tau);
 }
 
-__device__ __forceinline__ int32_t key_t(uint64_t key) { return (int32_t)((uint32_t)(key >> 32) ^ 0x80000000u); }
 __device__ __forceinline__ uint32_t key_slot(uint64_t key) { return (uint32_t)key >> 3; }
 __device__ __forceinline__ int key_kidx(uint64_t key) { return (int)((uint32_t)key & 7u); }
 
@@ -537,20 +691,24 @@ __device__ __forceinline__ void agg_combine(const Agg<D>& x, const Agg<D>& y, Ag
 
 template <int D>
 struct Shared {
-  Agg<D> agg[kFieldThreads];
+  union {
+    Agg<D> agg[kFieldThreads];
+    uint32_t hist[16 * kFieldThreads];  // radix sort counters
+  };
   float part[kFieldThreads][4];
   int64_t cnt[kFieldThreads];
+  uint32_t wsum[kFieldThreads / 64 + 1];
   unsigned long long peak;
   int64_t ray;
   int64_t base_out, base_ex;
-  int n_chunks_ok;
+  int32_t t_lo, t_hi;  // range of the ray's knot positions
 };
 
 // Per-ray storage carved from LDS or from the work-group's global slab.
 struct RayStore {
-  uint64_t* hkey;
   Recs rec;
   uint64_t* kkey;
+  uint64_t* kkey2;  // radix sort scratch
   int32_t* ccnt;   // [n_chunks] nodes emitted per chunk
   int32_t* chead;  // [n_chunks] first live node per chunk
   int32_t* gfirst; // [n_chunks] group first node ref
@@ -562,15 +720,13 @@ __host__ __device__ inline int64_t align8(int64_t x) { return (x + 7) & ~int64_t
 // bytes of the per-ray layout for nh hits and nk knots
 __host__ __device__ inline int64_t ray_store_bytes(int64_t nh, int64_t nk) {
   const int64_t nc = (nk + kChunk - 1) / kChunk;
-  return align8(8 * nh) + align8(4 * nh) + align8(12 * nh) + align8(4 * nh) + align8(4 * nh) + 8 * nh + 8 * nh +
-         8 * nk + 4 * align8(4 * nc);
+  return align8(4 * nh) + align8(12 * nh) + align8(4 * nh) + align8(4 * nh) + 8 * nh + 8 * nh + 8 * nk + 8 * nk +
+         4 * align8(4 * nc);
 }
 
 __device__ inline RayStore carve(char* p, int64_t nh, int64_t nk) {
   RayStore s;
   const int64_t nc = (nk + kChunk - 1) / kChunk;
-  s.hkey = (uint64_t*)p;
-  p += align8(8 * nh);
   s.rec.t0 = (int32_t*)p;
   p += align8(4 * nh);
   s.rec.o = (int32_t*)p;
@@ -584,6 +740,8 @@ __device__ inline RayStore carve(char* p, int64_t nh, int64_t nk) {
   s.rec.u = (double*)p;
   p += 8 * nh;
   s.kkey = (uint64_t*)p;
+  p += 8 * nk;
+  s.kkey2 = (uint64_t*)p;
   p += 8 * nk;
   s.ccnt = (int32_t*)p;
   p += align8(4 * nc);
@@ -618,18 +776,17 @@ __device__ void process_ray(const FieldArgs& A, Shared<D>& sh, const RayStore& S
     o[k] = A.o[3 * r + k];
     v[k] = A.v[3 * r + k];
   }
-  // ---- hits sorted by particle input index
-  for (int64_t s = tid; s < nh; s += kFieldThreads) {
-    const uint32_t j = A.hits[hoff + s];
-    S.hkey[s] = ((uint64_t)(uint32_t)A.orig[j] << 32) | j;
+  if (tid == 0) {
+    sh.t_lo = 0x7fffffff;
+    sh.t_hi = (int32_t)0x80000000;
   }
   __syncthreads();
-  bitonic_sort<uint64_t>(S.hkey, (int)nh, tid, kFieldThreads);
-  // ---- per-hit records and knot keys (Sec. 4.3: quantized positions)
+  // ---- per-hit records (Sec. 4.3: quantized positions); the hit order does not matter: knots at
+  // equal positions add exactly, so the field, its pieces and the merge are independent of it
   const double tau = A.mc.tau, sigma = A.mc.sigma;
+  int32_t my_lo = 0x7fffffff, my_hi = (int32_t)0x80000000;
   for (int64_t s = tid; s < nh; s += kFieldThreads) {
-    const uint64_t hk = S.hkey[s];
-    const uint32_t j = (uint32_t)hk;
+    const uint32_t j = A.hits[hoff + s];
     const float4 p = A.pos4[j];
     const double dxx = (double)p.x - o[0], dxy = (double)p.y - o[1], dxz = (double)p.z - o[2];
     const double cx = dxy * v[2] - dxz * v[1];
@@ -654,21 +811,38 @@ __device__ void process_ray(const FieldArgs& A, Shared<D>& sh, const RayStore& S
     S.rec.t0[s] = t0;
     for (int m = 0; m < P; ++m) S.rec.o[3 * s + m] = offs[m];
     S.rec.li[s] = li;
-    S.rec.pid[s] = (int32_t)(hk >> 32);
+    S.rec.pid[s] = A.orig[j];
     S.rec.base[s] = (double)A.val[j] / (sigma * (z * z * z));
     S.rec.u[s] = tau / z;
-    // knots kidx = k + P for positions t0 + sign(k) o_|k|
+    my_lo = min(my_lo, t0 - offs[P - 1]);
+    my_hi = max(my_hi, t0 + offs[P - 1]);
+  }
+  atomicMin(&sh.t_lo, my_lo);
+  atomicMax(&sh.t_hi, my_hi);
+  __syncthreads();
+  const int32_t t_lo = sh.t_lo;
+  auto key_t = [t_lo](uint64_t key) { return (int32_t)((uint32_t)t_lo + (uint32_t)(key >> 32)); };
+  // ---- knot keys: (position - t_lo) in the high half, (slot, kidx) in the low half; kidx = k + P
+  // for the knot at t0 + sign(k) o_|k|, laid out slot-major so that the stable sort leaves equal
+  // positions in (slot, kidx) order
+  for (int64_t s = tid; s < nh; s += kFieldThreads) {
+    const int32_t t0 = S.rec.t0[s];
     for (int kidx = 0; kidx <= 2 * P; ++kidx) {
       const int k = kidx - P;
       if (k == 0 && !A.mc.even_k) continue;
-      const int64_t t = (int64_t)t0 + (k < 0 ? -(int64_t)offs[-k - 1] : (k > 0 ? (int64_t)offs[k - 1] : 0));
+      const int32_t t = t0 + (k < 0 ? -S.rec.o[3 * s - k - 1] : (k > 0 ? S.rec.o[3 * s + k - 1] : 0));
       const int slotk = A.mc.even_k ? kidx : (k < 0 ? kidx : kidx - 1);
       S.kkey[s * (K + 1) + slotk] =
-          ((uint64_t)((uint32_t)(int32_t)t ^ 0x80000000u) << 32) | ((uint64_t)s << 3) | (uint64_t)kidx;
+          ((uint64_t)((uint32_t)t - (uint32_t)t_lo) << 32) | ((uint64_t)s << 3) | (uint64_t)kidx;
     }
   }
   __syncthreads();
-  bitonic_sort<uint64_t>(S.kkey, (int)nk, tid, kFieldThreads);
+  {
+    const uint32_t range = (uint32_t)sh.t_hi - (uint32_t)t_lo;
+    int nbits = 4;
+    while (nbits < 32 && (range >> nbits) != 0) nbits += 4;
+    radix_sort_u64<kFieldThreads>(S.kkey, S.kkey2, (int)nk, 32, nbits, sh.hist, sh.wsum, tid);
+  }
   // ---- thread ranges of chunks
   const int64_t n_chunks = (nk + kChunk - 1) / kChunk;
   const int64_t per = (n_chunks + kFieldThreads - 1) / kFieldThreads;
@@ -739,14 +913,6 @@ __device__ void process_ray(const FieldArgs& A, Shared<D>& sh, const RayStore& S
         bool zero = true;
         for (int d = 0; d <= D; ++d) zero = zero && (st.a[d] == 0);
         if (!zero) atomicOr(A.flags, kFlagTail);
-      }
-      if (A.exact) {
-        const int64_t ko = A.knot_off[r] + i;
-        if (ko < A.knot_cap) {
-          A.kn_t[ko] = t;
-          A.kn_pid[ko] = S.rec.pid[key_slot(key)];
-          A.kn_kidx[ko] = key_kidx(key);
-        }
       }
     }
   }
@@ -917,6 +1083,29 @@ __device__ void process_ray(const FieldArgs& A, Shared<D>& sh, const RayStore& S
           }
         }
         ++pos;
+      }
+    }
+    if (A.exact) {
+      // sorted knot list in the canonical order (position, particle input index, kidx)
+      __syncthreads();
+      for (int64_t i = tid; i < nk; i += kFieldThreads) {
+        const uint64_t key = S.kkey[i];
+        S.kkey2[i] = (key & 0xffffffff00000000ull) | ((uint64_t)(uint32_t)S.rec.pid[key_slot(key)] << 3) |
+                     (uint64_t)key_kidx(key);
+      }
+      __syncthreads();
+      const uint32_t range = (uint32_t)sh.t_hi - (uint32_t)t_lo;
+      int nbits = 36;
+      while (nbits < 64 && (range >> (nbits - 32)) != 0) nbits += 4;
+      radix_sort_u64<kFieldThreads>(S.kkey2, S.kkey, (int)nk, 0, nbits, sh.hist, sh.wsum, tid);
+      for (int64_t i = tid; i < nk; i += kFieldThreads) {
+        const uint64_t key = S.kkey2[i];
+        const int64_t ko = A.knot_off[r] + i;
+        if (ko < A.knot_cap) {
+          A.kn_t[ko] = key_t(key);
+          A.kn_pid[ko] = (int32_t)((uint32_t)key >> 3);
+          A.kn_kidx[ko] = (int32_t)(key & 7u);
+        }
       }
     }
   } else {
@@ -1210,8 +1399,9 @@ void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam,
   ix.rays_o.ensure(sizeof(double) * 3 * n_rays);
   ix.rays_v.ensure(sizeof(double) * 3 * n_rays);
   double t_min, t_max;
+  CamDev cam_dev{};
   if (camera) {
-    CamDev c{};
+    CamDev& c = cam_dev;
     double e[3], la[3], up[3];
     for (int k = 0; k < 3; ++k) {
       e[k] = (double)cam->eye[k];
@@ -1270,9 +1460,58 @@ void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam,
   G.max_hits = max_hits;
   G.flags = flags;
   const unsigned gblocks = (unsigned)((n_rays + 3) / 4);
-  if (ix.timing) hip_check(hipEventRecord(ix.ev[0], st), "event");
-  k_gather<false><<<gblocks, kGatherThreads, 0, st>>>(G);
-  if (ix.timing) hip_check(hipEventRecord(ix.ev[1], st), "event");
+  BinArgs B{};
+  TileHitArgs TH{};
+  int64_t n_tiles = 0;
+  if (camera) {
+    // bin particles into screen tiles, then count hits per pixel ray from the tile lists
+    B.pos4 = ix.pos4.as<float4>();
+    B.n = ix.n;
+    B.c = cam_dev;
+    B.tiles_x = (cam->width + kTile - 1) / kTile;
+    B.tiles_y = (cam->height + kTile - 1) / kTile;
+    B.t_min = t_min;
+    B.t_max = t_max;
+    n_tiles = (int64_t)B.tiles_x * B.tiles_y;
+    ix.tile_count.ensure(sizeof(unsigned int) * (n_tiles + 1) * 2);
+    ix.tile_off.ensure(sizeof(int64_t) * (n_tiles + 1) * 2);
+    unsigned int* tcount = ix.tile_count.as<unsigned int>();
+    unsigned int* tcur = tcount + (n_tiles + 1);
+    int64_t* tcnt64 = ix.tile_off.as<int64_t>() + (n_tiles + 1);
+    B.tile_count = tcount;
+    B.tile_cursor = tcur;
+    B.tile_off = ix.tile_off.as<int64_t>();
+    if (ix.timing) hip_check(hipEventRecord(ix.ev[0], st), "event");
+    hip_check(hipMemsetAsync(tcount, 0, sizeof(unsigned int) * (n_tiles + 1) * 2, st), "memset");
+    k_bin<false><<<blocks_for(ix.n, 256), 256, 0, st>>>(B);
+    k_u32_to_i64_n<<<blocks_for(n_tiles, 256), 256, 0, st>>>(tcount, tcnt64, n_tiles);
+    device_exclusive_scan_i64(tcnt64, ix.tile_off.as<int64_t>(), n_tiles, ix.scan_tmp, st);
+    k_set_last<<<1, 1, 0, st>>>(ix.tile_off.as<int64_t>(), tcnt64, n_tiles);
+    int64_t n_items = 0;
+    hip_check(hipMemcpyAsync(&n_items, ix.tile_off.as<int64_t>() + n_tiles, 8, hipMemcpyDeviceToHost, st), "copy");
+    hip_check(hipStreamSynchronize(st), "sync");
+    ix.tile_items.ensure(sizeof(uint32_t) * std::max<int64_t>(1, n_items));
+    B.items = ix.tile_items.as<uint32_t>();
+    k_bin<true><<<blocks_for(ix.n, 256), 256, 0, st>>>(B);
+    TH.o = G.o;
+    TH.v = G.v;
+    TH.W = cam->width;
+    TH.H = cam->height;
+    TH.tiles_x = B.tiles_x;
+    TH.t_min = t_min;
+    TH.t_max = t_max;
+    TH.pos4 = B.pos4;
+    TH.tile_off = B.tile_off;
+    TH.items = B.items;
+    TH.count = G.count;
+    TH.max_hits = max_hits;
+    k_tile_hits<false><<<(unsigned)n_tiles, 64, 0, st>>>(TH);
+    if (ix.timing) hip_check(hipEventRecord(ix.ev[1], st), "event");
+  } else {
+    if (ix.timing) hip_check(hipEventRecord(ix.ev[0], st), "event");
+    k_gather<false><<<gblocks, kGatherThreads, 0, st>>>(G);
+    if (ix.timing) hip_check(hipEventRecord(ix.ev[1], st), "event");
+  }
   hip_check(hipGetLastError(), "gather launch");
   device_exclusive_scan_i64(ix.hit_count.as<int64_t>(), ix.hit_off.as<int64_t>(), n_rays, ix.scan_tmp, st);
   k_set_last<<<1, 1, 0, st>>>(ix.hit_off.as<int64_t>(), ix.hit_count.as<int64_t>(), n_rays);
@@ -1294,7 +1533,13 @@ void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam,
   G.off = ix.hit_off.as<int64_t>();
   G.hits = ix.hits.as<uint32_t>();
   if (ix.timing) hip_check(hipEventRecord(ix.ev[2], st), "event");
-  k_gather<true><<<gblocks, kGatherThreads, 0, st>>>(G);
+  if (camera) {
+    TH.off = G.off;
+    TH.hits = G.hits;
+    k_tile_hits<true><<<(unsigned)n_tiles, 64, 0, st>>>(TH);
+  } else {
+    k_gather<true><<<gblocks, kGatherThreads, 0, st>>>(G);
+  }
   if (ix.timing) hip_check(hipEventRecord(ix.ev[3], st), "event");
   hip_check(hipGetLastError(), "gather launch");
   // ---- field kernel
