@@ -86,7 +86,9 @@ typedef struct {
 
 /* Output of approx_rays.  Merged piece i of ray r is index ray_offsets[r] + j:
  * F(t) = sum_d coef[i][d] * u^d with u = (t - t_start[i]) / (t_end[i] - t_start[i]),
- * valid on [t_start[i], t_end[i]]; the field is zero outside a ray's pieces. */
+ * valid on [t_start[i], t_end[i]]; the field is zero outside a ray's pieces.  u is defined by
+ * the exact piece ends (integer knot positions times tau); t_start / t_end are their float32
+ * roundings, so evaluating u from them adds at most |dF/dt| * ulp(t). */
 typedef struct {
   int64_t capacity;      /* pieces allocated by the caller */
   int64_t* ray_offsets;  /* device [n + 1] */
