@@ -32,7 +32,7 @@ TINY_SAMPLE = np.unique(np.concatenate([np.arange(0, 130), np.arange(2000, 2070)
                                         RNG.integers(0, 4096, 40)]))
 
 
-def _check_ray(sc, out, r, f, peak_tol=1e-9, coef_tol=1e-8, field_tol=1e-5):
+def _check_ray(sc, out, r, f, coef_tol=1e-8, field_tol=1e-5):
     """Compare ray r of an exact-mode approx_rays result with the oracle's ray field f."""
     D = sc.D
     ko = out["knot_offsets"].cpu().numpy()
@@ -48,6 +48,7 @@ def _check_ray(sc, out, r, f, peak_tol=1e-9, coef_tol=1e-8, field_tol=1e-5):
     ec = out["exact_coef"][eo[r]:eo[r + 1]].cpu().numpy()
     pcs = f["pieces"]
     assert et.tolist() == [p[0] for p in pcs] and ee.tolist() == [p[1] for p in pcs]
+    vtol = 1e-9 if D <= 3 else 1e-6
     if pcs:
         # integer coefficients: the jumps come from independently computed projections, whose
         # conditioning grows with D, so each order is compared relative to its largest value on
@@ -64,10 +65,10 @@ def _check_ray(sc, out, r, f, peak_tol=1e-9, coef_tol=1e-8, field_tol=1e-5):
             xs = x * L
             vg = sum(ec[:, d].astype(np.float64) * xs ** d for d in range(D + 1))
             vo = sum(oc[:, d] * xs ** d for d in range(D + 1))
-            vtol = 1e-9 if D <= 3 else 1e-6
             assert np.max(np.abs(vg - vo)) * sc.sigma <= vtol * max(f["peak"], 1e-300) + 4 * sc.sigma, r
     pk = float(out["ray_peak"][r].cpu())
-    assert abs(pk - f["peak"]) <= max(peak_tol * f["peak"], 6e-8 * f["peak"]), (r, pk, f["peak"])
+    # the peak is a float32 of the largest piece value: its rounding plus the value bar
+    assert abs(pk - f["peak"]) <= (vtol + 6e-8) * f["peak"], (r, pk, f["peak"])
     # merged field
     t0, t1, cf = H.field_of_ray(out, r, D)
     onodes = [field.node_output(n, f["merger"]) for n in f["nodes"]]
