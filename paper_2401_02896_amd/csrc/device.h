@@ -38,6 +38,28 @@ __device__ __forceinline__ T wave_max(T v) {
   return v;
 }
 
+// Exclusive prefix sum of one int64 per thread over the NT threads of the work-group (in thread
+// order); *total receives the sum.  wtot: NT / 64 int64 of LDS.  Starts and ends with a barrier
+// on wtot, so it can be called back to back.
+template <int NT>
+__device__ int64_t block_excl_scan_i64(int64_t v, int64_t* wtot, int tid, int64_t* total) {
+  const int64_t incl = wave_incl_scan<long>((long)v);
+  const int w = tid >> 6;
+  __syncthreads();
+  if ((tid & 63) == 63) wtot[w] = incl;
+  __syncthreads();
+  int64_t pre = 0, tot = 0;
+#pragma unroll
+  for (int i = 0; i < NT / 64; ++i) {
+    const int64_t x = wtot[i];
+    pre += (i < w) ? x : 0;
+    tot += x;
+  }
+  *total = tot;
+  __syncthreads();
+  return pre + incl - v;
+}
+
 __device__ __forceinline__ int next_pow2(int n) {
   int p = 1;
   while (p < n) p <<= 1;

@@ -410,12 +410,16 @@ struct FieldArgs {
   MergeTables mt;
   // scheduling
   unsigned int* queue;
-  int hn_lds;           // hits that fit the LDS layout
+  int64_t lds_bytes;    // dynamic LDS of the launch (per-ray layouts up to this size live there)
+  int nj;               // jump values per hit
   char* slab;           // per-work-group global storage
   int64_t slab_stride;  // bytes per work-group
   int64_t max_knots;    // largest knot count of any ray (sizes the slab)
+  int64_t slab_jmp;     // offset of the jump rows in a work-group's slab
+  int64_t slab_store;   // offset of the whole per-ray layout in a work-group's slab
   uint32_t* flags;
-  unsigned long long* counters;  // [0] merged pieces (bump), [1] exact pieces (bump), [2] pieces total, [3] rays_global
+  unsigned long long* counters;  // [0] merged pieces (bump), [1] exact pieces (bump), [2] pieces total,
+                                 // [3] rays in device memory, [4] rays with jump rows in device memory
   // approx outputs (staging, bump-allocated)
   int64_t out_cap;
   float* st_t0;
@@ -467,109 +471,106 @@ __device__ __forceinline__ void taylor_shift(uint64_t* a, uint32_t delta) {
     for (int j = D - 1; j >= i; --j) a[j] += a[j + 1] * dd;
 }
 
-__device__ __forceinline__ uint64_t binom_u(int n, int k) {
-  uint64_t r = 1;
-  for (int i = 1; i <= k; ++i) r = r * (uint64_t)(n - k + i) / (uint64_t)i;
-  return r;
+__host__ __device__ constexpr uint64_t binom_c(int n, int k) {
+  return (k < 0 || k > n) ? 0 : ((k == 0 || k == n) ? 1 : binom_c(n - 1, k - 1) + binom_c(n - 1, k));
 }
 
-// Hit record in SoA form.
-struct Recs {
-  int32_t* t0;
-  int32_t* o;   // [3][hn]
-  int32_t* li;
-  int32_t* pid;
-  double* base;
-  double* u;
-};
+// Rows of jump values stored per hit: one row of D orders for each knot pair +-theta_k, plus the
+// middle knot for even K.
+__host__ __device__ inline int jump_values_per_hit(int P, int even_k, int D) { return (P + even_k) * D; }
 
-// LUT-derived quantized jump a_kd of the knot at +theta_k (Eq. quantized-jumps-starting-from-lut).
+// Quantized jump coefficients of all knots of one particle on one ray (Eq. quantized jumps from
+// the table, Sec. 4.3, with the integer closure of App. A.3), written as rows of orders 1..D
+// (order 0 never jumps):
+//   row k-1, k = 1..P: the knot at +theta_k; the knot at -theta_k mirrors it (even orders negated);
+//   odd K: row 0 is the knot at +theta_1, whose odd orders come from the closure;
+//   even K: row P is the middle knot (odd orders from the closure, even orders zero).
+// The knot pairs are visited one at a time, keeping only the closure sums live.  Computed once per
+// hit, so the scans over the sorted knots only look values up.  Returns false if a quantized
+// coefficient left the int64 range.
 template <int D>
-__device__ __forceinline__ void lut_jumps(const double* shat_row, double base, double u, int k, uint64_t* out,
-                                          uint32_t* flags) {
-  double p = 1.0;
-#pragma unroll
-  for (int d = 1; d <= D; ++d) {
-    p = p * u;
-    const double scale = base * p;
-    out[d] = (uint64_t)rint_i64(shat_row[(k - 1) * (D + 1) + d] * scale, flags);
-  }
-  out[0] = 0;
-}
-
-// Jump coefficients of knot kidx of one particle, including the integer closure (Sec. 4.3, App. A.3).
-template <int D>
-__device__ void knot_jump(const MethodConsts& mc, const double* shat_row, double base, double u, const int32_t* off,
-                          int kidx, uint64_t* a, uint32_t* flags) {
+__device__ bool hit_jumps(const MethodConsts& mc, const double* shat_row, double base, double u, const int32_t* off,
+                          uint64_t* rows) {
   const int P = mc.P;
-  const int k = kidx - P;
+  constexpr int ND = (D + 1) / 2;  // odd orders 1, 3, ...
+  uint64_t acc[ND];
 #pragma unroll
-  for (int d = 0; d <= D; ++d) a[d] = 0;
-  const int kk = k < 0 ? -k : k;
-  if (kk >= 1 && !(mc.even_k == 0 && kk == 1)) {
-    uint64_t j[D + 1];
-    lut_jumps<D>(shat_row, base, u, kk, j, flags);
+  for (int i = 0; i < ND; ++i) acc[i] = 0;
+  bool ok = true;
+  // left[j]: jump of order j at -theta_{m+1} = (-1)^(j+1) times the table jump at +theta_{m+1}
+  auto table_left = [&](int m, uint64_t* left) {
+    double p = 1.0;
 #pragma unroll
-    for (int d = 1; d <= D; ++d) a[d] = (k < 0 && (d % 2 == 0)) ? (uint64_t)(0 - j[d]) : j[d];
-    return;
-  }
-  // left-side jumps a_{-m, j} = (-1)^(j+1) a_{m, j} for m = 1..P from the table
-  uint64_t left[kMaxP + 1][D + 1];
-  for (int m = 1; m <= P; ++m) {
-    uint64_t j[D + 1];
-    lut_jumps<D>(shat_row, base, u, m, j, flags);
+    for (int d = 1; d <= D; ++d) {
+      p = p * u;
+      const double scale = base * p;
+      const double x = shat_row[m * (D + 1) + d] * scale;
+      ok = ok && (fabs(x) < 4.6e18);
+      const uint64_t j = (fabs(x) < 4.6e18) ? (uint64_t)(int64_t)rint(x) : 0ull;
+      left[d] = (d % 2 == 0) ? (uint64_t)0 - j : j;
+    }
+  };
+  // knot pairs whose table jumps enter the closure sums directly: all of them for even K
+  // (middle knot), m = 1..P-1 for odd K (the pair +-theta_1 is solved for below)
+  for (int m = mc.even_k ? 0 : 1; m < P; ++m) {
+    uint64_t left[D + 1];
+    table_left(m, left);
+    uint64_t pw[D + 1];
+    pw[0] = 1;
 #pragma unroll
-    for (int d = 0; d <= D; ++d) left[m][d] = (d % 2 == 0) ? (uint64_t)(0 - j[d]) : j[d];
-  }
-  if (mc.even_k) {
-    // middle knot: a_0d = -2 sum_{m=1..P} sum_{j=d..D} C(j,d) a_{-m,j} o_m^(j-d), odd d
+    for (int e = 1; e <= D; ++e) pw[e] = pw[e - 1] * (uint64_t)(uint32_t)off[m];
 #pragma unroll
     for (int d = 1; d <= D; d += 2) {
-      uint64_t acc = 0;
-      for (int m = 1; m <= P; ++m) {
-        const uint64_t om = (uint64_t)(uint32_t)off[m - 1];
-        uint64_t pw = 1;
-        for (int jj = d; jj <= D; ++jj) {
-          acc += binom_u(jj, d) * left[m][jj] * pw;
-          pw *= om;
-        }
-      }
-      a[d] = (uint64_t)0 - 2 * acc;
+      // even K: sum_{j=d..D} C(j,d) a_{-m,j} o^(j-d); odd K: a_{-m,d} + sum_{j>d} (same terms)
+      uint64_t t = 0;
+#pragma unroll
+      for (int jj = d; jj <= D; ++jj) t += binom_c(jj, d) * left[jj] * pw[jj - d];
+      acc[d / 2] += t;
     }
-    return;
+#pragma unroll
+    for (int d = 1; d <= D; ++d) rows[m * D + d - 1] = (d % 2 == 0) ? (uint64_t)0 - left[d] : left[d];
+  }
+  if (mc.even_k) {
+    // middle knot: a_0d = -2 sum_m sum_{j=d..D} C(j,d) a_{-m,j} o_m^(j-d), odd d
+#pragma unroll
+    for (int d = 1; d <= D; ++d) rows[P * D + d - 1] = (d % 2 == 1) ? (uint64_t)0 - 2 * acc[d / 2] : 0ull;
+    return ok;
   }
   // odd K, knots -1 and +1: odd d in decreasing order
   //   a_{-1,d} = -sum_{m=2..P} a_{-m,d} - sum_{j=d+1..D} C(j,d) sum_{m=1..P} a_{-m,j} o_m^(j-d)
-  // (for m = 1 only even j come from the table: odd j use the values already set)
-  for (int jj = 1; jj <= D; jj += 2) left[1][jj] = 0;
-  for (int d = (D % 2 == 1 ? D : D - 1); d >= 1; d -= 2) {
-    uint64_t acc = 0;
-    for (int m = 2; m <= P; ++m) acc += left[m][d];
-    for (int jj = d + 1; jj <= D; ++jj) {
-      uint64_t inner = 0;
-      for (int m = 1; m <= P; ++m) {
-        const uint64_t om = (uint64_t)(uint32_t)off[m - 1];
-        uint64_t pw = 1;
-        for (int e = 0; e < jj - d; ++e) pw *= om;
-        inner += left[m][jj] * pw;
-      }
-      acc += binom_u(jj, d) * inner;
-    }
-    left[1][d] = (uint64_t)0 - acc;
-  }
-  // knot -1: left[1]; knot +1: a_{1,d} = (-1)^(d+1) a_{-1,d}
+  // (for m = 1 only even j come from the table: odd j use the values already solved)
+  uint64_t left[D + 1];
+  table_left(0, left);
+  uint64_t pw[D + 1];
+  pw[0] = 1;
 #pragma unroll
-  for (int d = 1; d <= D; ++d) a[d] = (k < 0 || (d % 2 == 1)) ? left[1][d] : (uint64_t)(0 - left[1][d]);
+  for (int e = 1; e <= D; ++e) pw[e] = pw[e - 1] * (uint64_t)(uint32_t)off[0];
+#pragma unroll
+  for (int d = (D % 2 == 1 ? D : D - 1); d >= 1; d -= 2) {
+    uint64_t t = acc[d / 2];
+#pragma unroll
+    for (int jj = d + 1; jj <= D; ++jj) t += binom_c(jj, d) * left[jj] * pw[jj - d];
+    left[d] = (uint64_t)0 - t;
+  }
+  // row 0: the knot at +theta_1, a_{1,d} = (-1)^(d+1) a_{-1,d}
+#pragma unroll
+  for (int d = 1; d <= D; ++d) rows[d - 1] = (d % 2 == 0) ? (uint64_t)0 - left[d] : left[d];
+  return ok;
 }
 
-// Shifted Legendre P~_j(x) for j = 0..D by the three-term recurrence on y = 2x - 1.
+// Shifted Legendre P~_j(x) for j = 0..D by the three-term recurrence on y = 2x - 1,
+// (j + 1) P_{j+1} = (2j + 1) y P_j - j P_{j-1}, with the constant ratios folded in.
 template <int D>
 __device__ __forceinline__ void legendre_at(double x, double* p) {
   const double y = 2.0 * x - 1.0;
   p[0] = 1.0;
   if (D >= 1) p[1] = y;
 #pragma unroll
-  for (int j = 1; j < D; ++j) p[j + 1] = ((2.0 * j + 1.0) * y * p[j] - (double)j * p[j - 1]) / (double)(j + 1);
+  for (int j = 1; j < D; ++j) {
+    constexpr double one = 1.0;
+    const double a = (2.0 * j + 1.0) * (one / (j + 1)), b = (double)j * (one / (j + 1));
+    p[j + 1] = a * y * p[j] - b * p[j - 1];
+  }
 }
 
 template <int D>
@@ -696,7 +697,7 @@ struct Shared {
     uint32_t hist[16 * kFieldThreads];  // radix sort counters
   };
   float part[kFieldThreads][4];
-  int64_t cnt[kFieldThreads];
+  int64_t wtot[kFieldThreads / 64];
   uint32_t wsum[kFieldThreads / 64 + 1];
   unsigned long long peak;
   int64_t ray;
@@ -706,9 +707,10 @@ struct Shared {
 
 // Per-ray storage carved from LDS or from the work-group's global slab.
 struct RayStore {
-  Recs rec;
   uint64_t* kkey;
   uint64_t* kkey2;  // radix sort scratch
+  uint64_t* jmp;    // [nh][nj] jump rows of every hit (hit_jumps)
+  int nj;
   int32_t* ccnt;   // [n_chunks] nodes emitted per chunk
   int32_t* chead;  // [n_chunks] first live node per chunk
   int32_t* gfirst; // [n_chunks] group first node ref
@@ -717,32 +719,27 @@ struct RayStore {
 
 __host__ __device__ inline int64_t align8(int64_t x) { return (x + 7) & ~int64_t(7); }
 
-// bytes of the per-ray layout for nh hits and nk knots
-__host__ __device__ inline int64_t ray_store_bytes(int64_t nh, int64_t nk) {
+// bytes of the per-ray layout for nh hits and nk knots (with_jumps: the jump rows included)
+__host__ __device__ inline int64_t ray_store_bytes(int64_t nh, int64_t nk, int nj, bool with_jumps) {
   const int64_t nc = (nk + kChunk - 1) / kChunk;
-  return align8(4 * nh) + align8(12 * nh) + align8(4 * nh) + align8(4 * nh) + 8 * nh + 8 * nh + 8 * nk + 8 * nk +
-         4 * align8(4 * nc);
+  return 8 * nk + 8 * nk + (with_jumps ? 8 * (int64_t)nj * nh : 0) + 4 * align8(4 * nc);
 }
 
-__device__ inline RayStore carve(char* p, int64_t nh, int64_t nk) {
+// jmp_ext: jump rows kept elsewhere (device memory) instead of in this layout
+__device__ inline RayStore carve(char* p, int64_t nh, int64_t nk, int nj, uint64_t* jmp_ext) {
   RayStore s;
   const int64_t nc = (nk + kChunk - 1) / kChunk;
-  s.rec.t0 = (int32_t*)p;
-  p += align8(4 * nh);
-  s.rec.o = (int32_t*)p;
-  p += align8(12 * nh);
-  s.rec.li = (int32_t*)p;
-  p += align8(4 * nh);
-  s.rec.pid = (int32_t*)p;
-  p += align8(4 * nh);
-  s.rec.base = (double*)p;
-  p += 8 * nh;
-  s.rec.u = (double*)p;
-  p += 8 * nh;
+  s.nj = nj;
   s.kkey = (uint64_t*)p;
   p += 8 * nk;
   s.kkey2 = (uint64_t*)p;
   p += 8 * nk;
+  if (jmp_ext) {
+    s.jmp = jmp_ext;
+  } else {
+    s.jmp = (uint64_t*)p;
+    p += 8 * (int64_t)nj * nh;
+  }
   s.ccnt = (int32_t*)p;
   p += align8(4 * nc);
   s.chead = (int32_t*)p;
@@ -753,14 +750,16 @@ __device__ inline RayStore carve(char* p, int64_t nh, int64_t nk) {
   return s;
 }
 
+// Jump coefficients a_0..a_D of the knot named by a sort key, from its hit's rows.
 template <int D>
-__device__ __forceinline__ void jump_of(const FieldArgs& A, const RayStore& S, uint64_t key, uint64_t* a) {
+__device__ __forceinline__ void jump_of(const MethodConsts& mc, const RayStore& S, uint64_t key, uint64_t* a) {
   const uint32_t slot = key_slot(key);
-  const int kidx = key_kidx(key);
-  int32_t o3[kMaxP] = {0, 0, 0};
-  for (int m = 0; m < A.mc.P; ++m) o3[m] = S.rec.o[3 * slot + m];
-  const double* row = A.shat + (int64_t)S.rec.li[slot] * A.mc.P * (D + 1);
-  knot_jump<D>(A.mc, row, S.rec.base[slot], S.rec.u[slot], o3, kidx, a, A.flags);
+  const int k = key_kidx(key) - mc.P;
+  const int row = (k == 0) ? mc.P : (k < 0 ? -k : k) - 1;
+  const uint64_t* v = S.jmp + ((int64_t)slot * S.nj + row * D);
+  a[0] = 0;
+#pragma unroll
+  for (int d = 1; d <= D; ++d) a[d] = (k < 0 && (d % 2 == 0)) ? (uint64_t)0 - v[d - 1] : v[d - 1];
 }
 
 // Process one ray with all threads of the work-group.
@@ -781,10 +780,15 @@ __device__ void process_ray(const FieldArgs& A, Shared<D>& sh, const RayStore& S
     sh.t_hi = (int32_t)0x80000000;
   }
   __syncthreads();
-  // ---- per-hit records (Sec. 4.3: quantized positions); the hit order does not matter: knots at
-  // equal positions add exactly, so the field, its pieces and the merge are independent of it
+  // ---- per-hit records (Sec. 4.3: quantized positions and jumps); the hit order does not matter:
+  // knots at equal positions add exactly, so the field, its pieces and the merge are independent
+  // of it.  The position t0 and offsets o_1..o_P of hit s are parked in the first words of the
+  // hit's own key span until the keys replace them.
   const double tau = A.mc.tau, sigma = A.mc.sigma;
+  int32_t* park = reinterpret_cast<int32_t*>(S.kkey);
+  const int64_t span32 = 2 * (int64_t)(K + 1);
   int32_t my_lo = 0x7fffffff, my_hi = (int32_t)0x80000000;
+#pragma unroll 1
   for (int64_t s = tid; s < nh; s += kFieldThreads) {
     const uint32_t j = A.hits[hoff + s];
     const float4 p = A.pos4[j];
@@ -808,12 +812,12 @@ __device__ void process_ray(const FieldArgs& A, Shared<D>& sh, const RayStore& S
       offs[m] = bad ? 0 : (int32_t)od;
     }
     if (bad) atomicOr(A.flags, kFlagPosRange);
-    S.rec.t0[s] = t0;
-    for (int m = 0; m < P; ++m) S.rec.o[3 * s + m] = offs[m];
-    S.rec.li[s] = li;
-    S.rec.pid[s] = A.orig[j];
-    S.rec.base[s] = (double)A.val[j] / (sigma * (z * z * z));
-    S.rec.u[s] = tau / z;
+    park[s * span32] = t0;
+    for (int m = 0; m < P; ++m) park[s * span32 + 1 + m] = offs[m];
+    const double base = (double)A.val[j] / (sigma * (z * z * z));
+    const double u = tau / z;
+    if (!hit_jumps<D>(A.mc, A.shat + (int64_t)li * P * (D + 1), base, u, offs, S.jmp + s * S.nj))
+      atomicOr(A.flags, kFlagCoefRange);
     my_lo = min(my_lo, t0 - offs[P - 1]);
     my_hi = max(my_hi, t0 + offs[P - 1]);
   }
@@ -824,13 +828,19 @@ __device__ void process_ray(const FieldArgs& A, Shared<D>& sh, const RayStore& S
   auto key_t = [t_lo](uint64_t key) { return (int32_t)((uint32_t)t_lo + (uint32_t)(key >> 32)); };
   // ---- knot keys: (position - t_lo) in the high half, (slot, kidx) in the low half; kidx = k + P
   // for the knot at t0 + sign(k) o_|k|, laid out slot-major so that the stable sort leaves equal
-  // positions in (slot, kidx) order
+  // positions in (slot, kidx) order.  Each thread rewrites the spans of the hits it parked.
   for (int64_t s = tid; s < nh; s += kFieldThreads) {
-    const int32_t t0 = S.rec.t0[s];
+    const int32_t t0 = park[s * span32];
+    int32_t o3[kMaxP];
+#pragma unroll
+    for (int m = 0; m < kMaxP; ++m) o3[m] = (m < P) ? park[s * span32 + 1 + m] : 0;
     for (int kidx = 0; kidx <= 2 * P; ++kidx) {
       const int k = kidx - P;
       if (k == 0 && !A.mc.even_k) continue;
-      const int32_t t = t0 + (k < 0 ? -S.rec.o[3 * s - k - 1] : (k > 0 ? S.rec.o[3 * s + k - 1] : 0));
+      int32_t om = 0;
+#pragma unroll
+      for (int m = 0; m < kMaxP; ++m) om = (m == (k < 0 ? -k : k) - 1) ? o3[m] : om;
+      const int32_t t = t0 + (k < 0 ? -om : om);
       const int slotk = A.mc.even_k ? kidx : (k < 0 ? kidx : kidx - 1);
       S.kkey[s * (K + 1) + slotk] =
           ((uint64_t)((uint32_t)t - (uint32_t)t_lo) << 32) | ((uint64_t)s << 3) | (uint64_t)kidx;
@@ -858,7 +868,7 @@ __device__ void process_ray(const FieldArgs& A, Shared<D>& sh, const RayStore& S
       const uint64_t key = S.kkey[i];
       const int64_t t = key_t(key);
       uint64_t jmp[D + 1];
-      jump_of<D>(A, S, key, jmp);
+      jump_of<D>(A.mc, S, key, jmp);
       if (g.valid) taylor_shift<D>(g.a, (uint32_t)(t - g.t));
       for (int d = 0; d <= D; ++d) g.a[d] += jmp[d];
       g.t = t;
@@ -897,7 +907,7 @@ __device__ void process_ray(const FieldArgs& A, Shared<D>& sh, const RayStore& S
       const uint64_t key = S.kkey[i];
       const int64_t t = key_t(key);
       uint64_t jmp[D + 1];
-      jump_of<D>(A, S, key, jmp);
+      jump_of<D>(A.mc, S, key, jmp);
       if (st.valid) taylor_shift<D>(st.a, (uint32_t)(t - st.t));
       for (int d = 0; d <= D; ++d) st.a[d] += jmp[d];
       st.t = t;
@@ -917,17 +927,11 @@ __device__ void process_ray(const FieldArgs& A, Shared<D>& sh, const RayStore& S
     }
   }
   atomicMax(&sh.peak, pk);
-  sh.cnt[tid] = npieces;
-  __syncthreads();
-  const double peak = sigma * (double)(int64_t)sh.peak;
   // exclusive scan of piece counts (exact-mode positions)
+  int64_t run = 0;
+  const int64_t ex_first = block_excl_scan_i64<kFieldThreads>(npieces, sh.wtot, tid, &run);
+  const double peak = sigma * (double)(int64_t)sh.peak;
   if (tid == 0) {
-    int64_t run = 0;
-    for (int i = 0; i < kFieldThreads; ++i) {
-      const int64_t c = sh.cnt[i];
-      sh.cnt[i] = run;
-      run += c;
-    }
     if (A.exact) {
       sh.base_ex = (int64_t)atomicAdd(&A.counters[1], (unsigned long long)run);
       A.ray_ex[2 * r] = sh.base_ex;
@@ -941,7 +945,7 @@ __device__ void process_ray(const FieldArgs& A, Shared<D>& sh, const RayStore& S
   const double thr2 = (tol * peak) * (tol * peak);
   {
     Agg<D> st = carry;
-    int64_t ex_pos = sh.cnt[tid];
+    int64_t ex_pos = ex_first;
     int64_t cur_chunk = -1;
     Node<D> cur;
     bool have = false;
@@ -958,7 +962,7 @@ __device__ void process_ray(const FieldArgs& A, Shared<D>& sh, const RayStore& S
       const uint64_t key = S.kkey[i];
       const int64_t t = key_t(key);
       uint64_t jmp[D + 1];
-      jump_of<D>(A, S, key, jmp);
+      jump_of<D>(A.mc, S, key, jmp);
       if (st.valid) taylor_shift<D>(st.a, (uint32_t)(t - st.t));
       for (int d = 0; d <= D; ++d) st.a[d] += jmp[d];
       st.t = t;
@@ -1051,25 +1055,17 @@ __device__ void process_ray(const FieldArgs& A, Shared<D>& sh, const RayStore& S
   // ---- live nodes per thread range, in order
   int64_t mine = 0;
   for (int64_t c = c_lo; c < c_hi; ++c) mine += S.ccnt[c] - S.chead[c];
-  sh.cnt[tid] = mine;
-  __syncthreads();
-  if (tid == 0) {
-    int64_t run = 0;
-    for (int i = 0; i < kFieldThreads; ++i) {
-      const int64_t c = sh.cnt[i];
-      sh.cnt[i] = run;
-      run += c;
-    }
-    if (!RENDER) {
-      sh.base_out = (int64_t)atomicAdd(&A.counters[0], (unsigned long long)run);
+  int64_t n_live = 0;
+  const int64_t live_first = block_excl_scan_i64<kFieldThreads>(mine, sh.wtot, tid, &n_live);
+  if (!RENDER) {
+    if (tid == 0) {
+      sh.base_out = (int64_t)atomicAdd(&A.counters[0], (unsigned long long)n_live);
       A.ray_out[2 * r] = sh.base_out;
-      A.ray_out[2 * r + 1] = run;
+      A.ray_out[2 * r + 1] = n_live;
       A.ray_peak[r] = (float)peak;
     }
-  }
-  __syncthreads();
-  if (!RENDER) {
-    int64_t pos = sh.base_out + sh.cnt[tid];
+    __syncthreads();
+    int64_t pos = sh.base_out + live_first;
     for (int64_t c = c_lo; c < c_hi; ++c) {
       for (int32_t q = S.chead[c]; q < S.ccnt[c]; ++q) {
         const Node<D>& nd = nodes[c * kChunk + q];
@@ -1090,7 +1086,7 @@ __device__ void process_ray(const FieldArgs& A, Shared<D>& sh, const RayStore& S
       __syncthreads();
       for (int64_t i = tid; i < nk; i += kFieldThreads) {
         const uint64_t key = S.kkey[i];
-        S.kkey2[i] = (key & 0xffffffff00000000ull) | ((uint64_t)(uint32_t)S.rec.pid[key_slot(key)] << 3) |
+        S.kkey2[i] = (key & 0xffffffff00000000ull) | ((uint64_t)(uint32_t)A.orig[A.hits[hoff + key_slot(key)]] << 3) |
                      (uint64_t)key_kidx(key);
       }
       __syncthreads();
@@ -1113,6 +1109,14 @@ __device__ void process_ray(const FieldArgs& A, Shared<D>& sh, const RayStore& S
     float C0 = 0.f, C1 = 0.f, C2 = 0.f, T = 1.f;
     const float vmin = A.tf_vmin, vr = A.tf_vmax - A.tf_vmin;
     const int ntf = A.tf_n;
+    // the transfer function is read once per sample: stage it in the (now free) sort scratch
+    const float* tfp = A.tf;
+    if ((int64_t)ntf * 16 <= 8 * nk) {
+      float* t = reinterpret_cast<float*>(S.kkey2);
+      for (int i = tid; i < 4 * ntf; i += kFieldThreads) t[i] = A.tf[i];
+      __syncthreads();
+      tfp = t;
+    }
     for (int64_t c = c_lo; c < c_hi; ++c) {
       for (int32_t q = S.chead[c]; q < S.ccnt[c]; ++q) {
         const Node<D>& nd = nodes[c * kChunk + q];
@@ -1139,8 +1143,8 @@ __device__ void process_ray(const FieldArgs& A, Shared<D>& sh, const RayStore& S
           const int i0 = (int)floorf(x);
           const int i1 = min(i0 + 1, ntf - 1);
           const float f = x - (float)i0;
-          const float* p0 = A.tf + 4 * i0;
-          const float* p1 = A.tf + 4 * i1;
+          const float* p0 = tfp + 4 * i0;
+          const float* p1 = tfp + 4 * i1;
           const float er = (1.f - f) * p0[0] + f * p1[0];
           const float eg = (1.f - f) * p0[1] + f * p1[1];
           const float eb = (1.f - f) * p0[2] + f * p1[2];
@@ -1185,7 +1189,8 @@ __global__ void __launch_bounds__(kFieldThreads) k_field(FieldArgs A) {
   __shared__ Shared<D> sh;
   char* slab = A.slab + (int64_t)blockIdx.x * A.slab_stride;
   Node<D>* nodes = (Node<D>*)slab;
-  char* gstore = slab + align8((int64_t)sizeof(Node<D>) * ((A.max_knots + kChunk - 1) / kChunk) * kChunk);
+  uint64_t* gjmp = (uint64_t*)(slab + A.slab_jmp);
+  char* gstore = slab + A.slab_store;
   for (;;) {
     if (threadIdx.x == 0) sh.ray = (int64_t)atomicAdd(A.queue, 1u);
     __syncthreads();
@@ -1207,15 +1212,14 @@ __global__ void __launch_bounds__(kFieldThreads) k_field(FieldArgs A) {
         }
       }
     } else {
+      // the whole layout in LDS if it fits, else the keys in LDS and the jump rows in device
+      // memory, else everything in device memory (the arithmetic is the same on every path)
       const int64_t nk = nh * (A.mc.K + 1);
-      if (nh <= A.hn_lds) {
-        const RayStore S = carve(lds, nh, nk);
-        process_ray<D, RENDER>(A, sh, S, nodes, r, nh);
-      } else {
-        if (threadIdx.x == 0) atomicAdd(&A.counters[3], 1ull);
-        const RayStore S = carve(gstore, nh, nk);
-        process_ray<D, RENDER>(A, sh, S, nodes, r, nh);
-      }
+      const bool all_lds = ray_store_bytes(nh, nk, A.nj, true) <= A.lds_bytes;
+      const bool keys_lds = ray_store_bytes(nh, nk, A.nj, false) <= A.lds_bytes;
+      if (threadIdx.x == 0 && !all_lds) atomicAdd(&A.counters[keys_lds ? 4 : 3], 1ull);
+      const RayStore S = carve(keys_lds ? lds : gstore, nh, nk, A.nj, (keys_lds && !all_lds) ? gjmp : nullptr);
+      process_ray<D, RENDER>(A, sh, S, nodes, r, nh);
     }
     __syncthreads();
   }
@@ -1564,24 +1568,31 @@ void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam,
   A.counters = ctr;
   const int64_t max_knots = std::max<int64_t>(1, (int64_t)mh * (K + 1));
   A.max_knots = max_knots;
-  // LDS layout capacity
+  // LDS layout capacity: the largest ray's whole layout, within the LDS left by the static part
+  const int nj = jump_values_per_hit(P, (K % 2 == 0) ? 1 : 0, D);
+  A.nj = nj;
   const size_t lds_static = static_lds(D);
-  const size_t lds_limit = 160 * 1024 - lds_static - 1024;
-  int64_t hn = std::max<int64_t>(1, (int64_t)mh);
-  while (hn > 1 && (size_t)ray_store_bytes(hn, hn * (K + 1)) > lds_limit) hn = hn * 7 / 8;
-  // test hook: a smaller LDS capacity sends more rays down the device-memory path
-  if (const char* cap = std::getenv("SPH_HOA_MAX_LDS_HITS")) hn = std::max<int64_t>(1, std::min<int64_t>(hn, std::atoll(cap)));
-  A.hn_lds = (int)hn;
-  const size_t lds = (size_t)ray_store_bytes(hn, hn * (K + 1));
+  const int64_t lds_limit = 160 * 1024 - (int64_t)lds_static - 1024;
+  int64_t lds = std::min<int64_t>(lds_limit, ray_store_bytes(std::max<int64_t>(1, (int64_t)mh), max_knots, nj, true));
+  // test hook: a smaller LDS capacity (in hits) sends more rays down the device-memory paths
+  if (const char* cap = std::getenv("SPH_HOA_MAX_LDS_HITS")) {
+    const int64_t ch = std::max<int64_t>(1, std::atoll(cap));
+    lds = std::min<int64_t>(lds, ray_store_bytes(ch, ch * (K + 1), nj, true));
+  }
+  A.lds_bytes = lds;
   int per_cu = 0;
   hipDeviceProp_t prop;
   int dev = 0;
   hip_check(hipGetDevice(&dev), "device");
   hip_check(hipGetDeviceProperties(&prop, dev), "props");
-  per_cu = (int)std::max<size_t>(1, std::min<size_t>(8, (160 * 1024) / (lds + lds_static + 1)));
+  per_cu = (int)std::max<int64_t>(1, std::min<int64_t>(8, (160 * 1024) / (lds + (int64_t)lds_static + 1)));
   const int grid = (int)std::min<int64_t>((int64_t)prop.multiProcessorCount * per_cu, n_rays);
-  const int64_t heavy = ((int64_t)mh > hn) ? ray_store_bytes((int64_t)mh, max_knots) : 0;
-  A.slab_stride = align8((int64_t)node_bytes(D) * ((max_knots + kChunk - 1) / kChunk) * kChunk) + align8(heavy) + 64;
+  const int64_t mh1 = std::max<int64_t>(1, (int64_t)mh);
+  const bool jumps_out = ray_store_bytes(mh1, max_knots, nj, true) > lds;
+  const bool all_out = ray_store_bytes(mh1, max_knots, nj, false) > lds;
+  A.slab_jmp = align8((int64_t)node_bytes(D) * ((max_knots + kChunk - 1) / kChunk) * kChunk);
+  A.slab_store = A.slab_jmp + (jumps_out ? align8(8 * (int64_t)nj * mh1) : 0);
+  A.slab_stride = A.slab_store + (all_out ? align8(ray_store_bytes(mh1, max_knots, nj, true)) : 0) + 64;
   ix.slab.ensure((size_t)A.slab_stride * grid);
   A.slab = ix.slab.as<char>();
   const bool render = (out.rgba != nullptr);
@@ -1593,7 +1604,7 @@ void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam,
     A.tf_step = (double)out.tf->step;
     A.rgba = out.rgba;
     if (ix.timing) hip_check(hipEventRecord(ix.ev[4], st), "event");
-    dispatch_field<true>(D, A, grid, lds, st);
+    dispatch_field<true>(D, A, grid, (size_t)lds, st);
     if (ix.timing) {
       hip_check(hipEventRecord(ix.ev[5], st), "event");
       ix.timing_pending = true;
@@ -1630,7 +1641,7 @@ void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam,
                   "copy");
     }
     if (ix.timing) hip_check(hipEventRecord(ix.ev[4], st), "event");
-    dispatch_field<false>(D, A, grid, lds, st);
+    dispatch_field<false>(D, A, grid, (size_t)lds, st);
     if (ix.timing) {
       hip_check(hipEventRecord(ix.ev[5], st), "event");
       ix.timing_pending = true;
@@ -1641,7 +1652,7 @@ void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam,
     k_ray_counts<<<blocks_for(n_rays, 256), 256, 0, st>>>(A.ray_out, n_rays, cnt.as<int64_t>());
     device_exclusive_scan_i64(cnt.as<int64_t>(), f->ray_offsets, n_rays, ix.scan_tmp, st);
     k_set_last<<<1, 1, 0, st>>>(f->ray_offsets, cnt.as<int64_t>(), n_rays);
-    unsigned long long c4[4];
+    unsigned long long c4[5];
     hip_check(hipMemcpyAsync(c4, ctr, sizeof(c4), hipMemcpyDeviceToHost, st), "copy");
     hip_check(hipMemcpyAsync(&fl, flags, 4, hipMemcpyDeviceToHost, st), "copy");
     hip_check(hipStreamSynchronize(st), "sync");
@@ -1651,6 +1662,7 @@ void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam,
     f->n_knots = total_pairs * (K + 1);
     ix.stats.n_pieces = (int64_t)c4[0];
     ix.stats.rays_global = (int64_t)c4[3];
+    ix.stats.rays_jumps_device = (int64_t)c4[4];
     if (fl & kFlagPosRange) throw Error(SPH_HOA_E_OVERFLOW, "a quantized knot position left the int32 range");
     if (fl & kFlagCoefRange) throw Error(SPH_HOA_E_OVERFLOW, "a quantized coefficient left the int64 range");
     if (fl & kFlagTail) throw Error(SPH_HOA_E_INTERNAL, "a ray's knots did not cancel exactly");

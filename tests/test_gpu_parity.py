@@ -202,15 +202,18 @@ def test_device_memory_path_is_identical():
     o, v = synth.ortho_rays()
     o, v = o[:300], v[:300]
     a = _approx(sc, o, v, 0.0, 1.4)
-    os.environ["SPH_HOA_MAX_LDS_HITS"] = "16"
-    try:
-        b = _approx(sc, o, v, 0.0, 1.4)
-        st = sc.index().stats()
-    finally:
-        del os.environ["SPH_HOA_MAX_LDS_HITS"]
-    assert st["rays_global"] > 100
-    for k in ("ray_offsets", "t_start", "t_end", "coef", "ray_peak", "exact_t", "exact_coef", "knot_t", "knot_pid"):
-        assert torch.equal(a[k], b[k]), k
+    # 16 hits: most rays keep everything in device memory; 40 hits: most keep their keys in LDS
+    # and the per-hit jump rows in device memory
+    for cap, stat in (("16", "rays_global"), ("40", "rays_jumps_device")):
+        os.environ["SPH_HOA_MAX_LDS_HITS"] = cap
+        try:
+            b = _approx(sc, o, v, 0.0, 1.4)
+            st = sc.index().stats()
+        finally:
+            del os.environ["SPH_HOA_MAX_LDS_HITS"]
+        assert st[stat] > 100, (cap, st)
+        for k in ("ray_offsets", "t_start", "t_end", "coef", "ray_peak", "exact_t", "exact_coef", "knot_t", "knot_pid"):
+            assert torch.equal(a[k], b[k]), (cap, k)
 
 
 def test_deterministic():
