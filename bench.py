@@ -45,6 +45,9 @@ def parse():
     ap.add_argument("--size", type=int, default=512)
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="budget of the oracle baseline")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="instead of the benchmark, run 5 plain device copies of MIB MiB each (the "
+                         "reference kernel for scaling the HBM byte counters) and exit")
     return ap.parse_args()
 
 
@@ -77,6 +80,33 @@ def _run_batch(rays):
     return oracle_worker((rays, _STATE))
 
 
+def kernel_source_digest():
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in ("raycast.hip", "device.h", "impl.h"):
+        with open(os.path.join(ROOT, "paper_2401_02896_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def committed_traffic():
+    """HBM bytes per k_field launch from the committed counter summary, or None when that summary
+    was taken on a different kernel source (or is absent)."""
+    path = os.path.join(ROOT, "profiles", "k_field_plain_1M_512_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256") != kernel_source_digest():
+        return None
+    return float(vals["traffic_bytes_per_launch"])
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -84,6 +114,17 @@ def main():
               "split the image; this build measures the one-GPU share.", file=sys.stderr)
         sys.exit(2)
     import torch
+
+    if a.calibrate_copy:
+        assert torch.cuda.is_available(), "bench.py needs the GPU"
+        n = a.calibrate_copy * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": n * 4, "copies": 5}), flush=True)
+        return
 
     import paper_2401_02896_amd as L
     import synth
@@ -127,20 +168,16 @@ def main():
     lat_ms = np.array(lat) * 1e3
     field_ms = st["ms_field"] / max(1, st["timed_calls"])
     gather_ms = st["ms_gather"] / max(1, st["timed_calls"])
-    # Roofline of the field kernel (ALU bound, integer multiplies): per contribution the
-    # knots of one particle are accumulated three times (aggregate, peak, pieces) with a
-    # D(D+1)/2-step Taylor shift per knot, each step one 64x32-bit multiply = two 32-bit
-    # multiplies; the closure of the middle knot adds sum_{d odd} P * (D - d + 1) 64-bit
-    # multiply-adds (three 32-bit multiplies each), also three times.
-    P = (K + 1) // 2
-    knots = K + 1
-    shift_mul32 = 2 * (D * (D + 1) // 2)
-    closure_mul32 = 3 * sum(P * (D - d + 1) * 2 for d in range(1, D + 1, 2))
-    mul32_per_pair = 3 * (knots * shift_mul32 + closure_mul32)
+    # Roofline of the field kernel (ALU bound).  Algorithmic work per contribution: the integer
+    # multiplies of the accumulation rule applied once to each of the particle's K + 1 knots,
+    # D(D+1)/2 products of a 64-bit coefficient by a 32-bit distance, 3 32-bit multiplies each.
+    # (The kernel applies the rule three times per knot - aggregate, peak, pieces - and adds the
+    # float64 merge, so the fraction also measures that overhead.)
+    mul32_per_pair = (K + 1) * (D * (D + 1) // 2) * 3
     achieved = mul32_per_pair * pairs_per_frame / (field_ms * 1e-3) / 1e12
     peak = INT32_MUL_PER_S / 1e12
     roofline = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tmul32/s",
-                "frac": achieved / peak, "traffic": None, "kernel": "k_field",
+                "frac": achieved / peak, "traffic": committed_traffic(), "kernel": "k_field",
                 "kernel_ms": field_ms, "gather_ms": gather_ms,
                 "algorithmic_mul32_per_pair": mul32_per_pair}
     result = {

@@ -129,7 +129,7 @@ typedef struct {
   const float* rgba;  /* device [n][4] */
   int32_t n;          /* >= 2 */
   float v_min, v_max; /* v_max > v_min */
-  float step;         /* sampling step along the ray (world units), > 0 */
+  float step;         /* sampling step along the ray (world units), > 0, (t_max - t_min) / step < 2^30 */
 } sph_hoa_tf;
 
 /* Counters of the last approx_rays / render on an index (host struct). */

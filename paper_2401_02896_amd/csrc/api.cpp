@@ -239,6 +239,8 @@ sph_hoa_status sph_hoa_render(sph_hoa_index idx, const sph_hoa_camera* cam, cons
     require(tf->rgba && tf->n >= 2, "transfer function needs >= 2 control points");
     require(std::isfinite(tf->v_min) && std::isfinite(tf->v_max) && tf->v_max > tf->v_min, "need v_min < v_max");
     require(std::isfinite(tf->step) && tf->step > 0, "step must be > 0");
+    require(((double)cam->t_max - (double)cam->t_min) / (double)tf->step < 1073741824.0,
+            "step too small: more than 2^30 samples per ray");
     sph::Index& ix = idx->ix;
     const double span = std::max(std::fabs((double)cam->t_min), std::fabs((double)cam->t_max)) +
                         ix.grid.lv[ix.grid.n_levels - 1].c;

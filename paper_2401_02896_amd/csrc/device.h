@@ -1,4 +1,4 @@
-// Device helpers: wave/work-group scans and an in-LDS bitonic sort.
+// Device helpers: wave/work-group scans and the in-LDS radix sort of a ray's knot keys.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -18,6 +18,19 @@ __device__ __forceinline__ T wave_incl_scan(T v) {
     T n = __shfl_up(v, o, 64);
     if (l >= o) v += n;
   }
+  return v;
+}
+
+// inclusive scan of a uint32 over the 64 lanes of a wave with DPP lane moves (no LDS):
+// Hillis-Steele within each row of 16 lanes, then row 0's total into row 1 and row 2's into row 3
+// (row_bcast:15), then the total of rows 0-1 into rows 2-3 (row_bcast:31)
+__device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t v) {
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false);  // row_shr:1
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false);  // row_shr:2
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false);  // row_shr:4
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false);  // row_shr:8
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false);  // row_bcast:15
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false);  // row_bcast:31
   return v;
 }
 
@@ -60,101 +73,100 @@ __device__ int64_t block_excl_scan_i64(int64_t v, int64_t* wtot, int tid, int64_
   return pre + incl - v;
 }
 
-__device__ __forceinline__ int next_pow2(int n) {
-  int p = 1;
-  while (p < n) p <<= 1;
-  return p;
-}
-
-// Ascending sort of a[0..n) (any n) by all threads of the work-group, using the
-// bitonic network with the "flip" first stage of every merge so that the
-// missing elements n..next_pow2(n) behave as +infinity and never move.
-// Caller guarantees a barrier before (data ready); ends with a barrier.
-template <class T>
-__device__ void bitonic_sort(T* a, int n, int tid, int nthreads) {
-  const int np2 = next_pow2(n);
-  const int half = np2 >> 1;
-  for (int k = 2; k <= np2; k <<= 1) {
-    const int hk = k >> 1;
-    for (int c = tid; c < half; c += nthreads) {
-      const int blk = c / hk, j = c - blk * hk;
-      const int lo = blk * k + j, hi = blk * k + k - 1 - j;
-      if (hi < n) {
-        T x = a[lo], y = a[hi];
-        if (y < x) {
-          a[lo] = y;
-          a[hi] = x;
-        }
-      }
-    }
-    __syncthreads();
-    for (int s = hk >> 1; s >= 1; s >>= 1) {
-      for (int c = tid; c < half; c += nthreads) {
-        const int blk = c / s, j = c - blk * s;
-        const int lo = blk * 2 * s + j, hi = lo + s;
-        if (hi < n) {
-          T x = a[lo], y = a[hi];
-          if (y < x) {
-            a[lo] = y;
-            a[hi] = x;
-          }
-        }
-      }
-      __syncthreads();
-    }
-  }
-}
-
 // Stable LSD radix sort of a[0..n) by bits [lo_bit, lo_bit + nbits) with 4-bit digits, by all
-// NT threads of the work-group.  Thread t owns the contiguous block [t m, (t+1) m), m = ceil(n/NT),
-// counts its digits in packed 16-bit register fields, and scatters its block in order after a
-// work-group scan of the (digit, thread) counts, so equal digits keep their order.
-// tmp: n elements of scratch; hist: 16 * NT uint32 (LDS); wsum: NT / 64 + 1 uint32 (LDS).
-// The result ends in `a`.  Caller guarantees a barrier before; ends with a barrier.
-template <int NT>
-__device__ void radix_sort_u64(uint64_t* a, uint64_t* tmp, int n, int lo_bit, int nbits, uint32_t* hist,
-                               uint32_t* wsum, int tid) {
-  const int m = (n + NT - 1) / NT;
+// NT threads of the work-group, n <= 1023 NT.  Thread t owns the contiguous block [t m, (t+1) m),
+// m = ceil(n / NT) rounded up to odd (an odd stride of 8-byte elements spreads a wave's reads over
+// the LDS banks).  Per pass a thread loads its keys in batches of 16 into registers and counts
+// its digits in packed 16-bit fields; a wave scan of the packed fields gives each lane its rank
+// among the wave's equal digits, and a 16 x (NT/64) table in LDS gives each (wave, digit) its
+// base, so the scatter keeps equal digits in order with no read-modify-write of shared counters.
+// tab: 32 * (NT / 64) uint32 of LDS.  The result ends in `a`; with PAD_OUT it is stored with one
+// unused slot after every 16 elements (element i at i + i / 16; a and tmp then hold
+// n + n / 16 + 1 elements).  Caller guarantees a barrier before; ends with a barrier.
+template <int NT, bool PAD_OUT>
+__device__ void radix_sort_u64(uint64_t* a, uint64_t* tmp, int n, int lo_bit, int nbits, uint32_t* tab, int tid) {
+  constexpr int W = NT / 64;
+  constexpr int E = (16 * W + 63) / 64;  // table entries per lane of the scanning wave
+  constexpr int MB = 16;
+  uint32_t* cnt = tab;             // [W][16] digit counts per wave
+  uint32_t* wbase = tab + 16 * W;  // [W][16] first output slot per (wave, digit)
+  const int m = ((n + NT - 1) / NT) | 1;
   const int b0 = min(tid * m, n), b1 = min(b0 + m, n);
+  const int w = tid >> 6, lane = tid & 63;
   uint64_t* src = a;
   uint64_t* dst = tmp;
   for (int shift = lo_bit; shift < lo_bit + nbits; shift += 4) {
+    const bool last = shift + 4 >= lo_bit + nbits;
     uint64_t c[4] = {0, 0, 0, 0};  // 16 counters of 16 bits
-    for (int i = b0; i < b1; ++i) {
-      const uint32_t d = (uint32_t)(src[i] >> shift) & 15u;
-      const uint64_t inc = 1ull << (16 * (d & 3));
-      const uint32_t q = d >> 2;
-      c[0] += (q == 0) ? inc : 0ull;
-      c[1] += (q == 1) ? inc : 0ull;
-      c[2] += (q == 2) ? inc : 0ull;
-      c[3] += (q == 3) ? inc : 0ull;
+    for (int i0 = b0; i0 < b1; i0 += MB) {
+      uint64_t kv[MB];
+#pragma unroll
+      for (int k = 0; k < MB; ++k) kv[k] = (i0 + k < b1) ? src[i0 + k] : 0ull;
+#pragma unroll
+      for (int k = 0; k < MB; ++k) {
+        const uint32_t d = (uint32_t)(kv[k] >> shift) & 15u;
+        const uint64_t inc = (i0 + k < b1) ? (1ull << (16 * (d & 3))) : 0ull;
+        const uint32_t q = d >> 2;
+        c[0] += (q == 0) ? inc : 0ull;
+        c[1] += (q == 1) ? inc : 0ull;
+        c[2] += (q == 2) ? inc : 0ull;
+        c[3] += (q == 3) ? inc : 0ull;
+      }
     }
+    // rank of this lane's first key of each digit among the wave's keys of that digit (the packed
+    // fields stay below 2^16, so the two 32-bit halves scan independently)
+    uint64_t pre[4];
 #pragma unroll
-    for (int d = 0; d < 16; ++d) hist[d * NT + tid] = (uint32_t)((c[d >> 2] >> (16 * (d & 3))) & 0xffffu);
-    __syncthreads();
-    // exclusive scan of hist[0 .. 16 NT) in memory order: thread t takes entries [16 t, 16 t + 16)
-    uint32_t loc[16];
-    uint32_t s = 0;
+    for (int q = 0; q < 4; ++q) {
+      const uint32_t il = wave_incl_scan_u32((uint32_t)c[q]);
+      const uint32_t ih = wave_incl_scan_u32((uint32_t)(c[q] >> 32));
+      const uint64_t incl = ((uint64_t)ih << 32) | il;
+      pre[q] = incl - c[q];
+      if (lane == 63) {
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-      loc[k] = s;
-      s += hist[tid * 16 + k];
+        for (int f = 0; f < 4; ++f) cnt[w * 16 + 4 * q + f] = (uint32_t)((incl >> (16 * f)) & 0xffffu);
+      }
     }
-    const uint32_t incl = wave_incl_scan(s);
-    const int w = tid >> 6;
-    if ((tid & 63) == 63) wsum[w] = incl;
     __syncthreads();
-    uint32_t pre = incl - s;
-    for (int i = 0; i < w; ++i) pre += wsum[i];
+    if (w == 0) {
+      // entry (wave ww, digit d) = all keys of smaller digits plus this digit's keys of earlier
+      // waves: one exclusive scan over the entries in digit-major order e = d * W + ww, E
+      // consecutive entries per lane
+      uint32_t x[E], sum = 0;
 #pragma unroll
-    for (int k = 0; k < 16; ++k) hist[tid * 16 + k] = loc[k] + pre;
+      for (int j = 0; j < E; ++j) {
+        const int e = lane * E + j, d = e / W, ww = e % W;
+        x[j] = (e < 16 * W) ? cnt[ww * 16 + d] : 0u;
+        sum += x[j];
+      }
+      uint32_t run = wave_incl_scan_u32(sum) - sum;
+#pragma unroll
+      for (int j = 0; j < E; ++j) {
+        const int e = lane * E + j, d = e / W, ww = e % W;
+        if (e < 16 * W) wbase[ww * 16 + d] = run;
+        run += x[j];
+      }
+    }
     __syncthreads();
-    for (int i = b0; i < b1; ++i) {
-      const uint64_t v = src[i];
-      const uint32_t d = (uint32_t)(v >> shift) & 15u;
-      const uint32_t p = hist[d * NT + tid];
-      hist[d * NT + tid] = p + 1;
-      dst[p] = v;
+    for (int i0 = b0; i0 < b1; i0 += MB) {
+      uint64_t kv[MB];
+#pragma unroll
+      for (int k = 0; k < MB; ++k) kv[k] = (i0 + k < b1) ? src[i0 + k] : 0ull;
+#pragma unroll
+      for (int k = 0; k < MB; ++k) {
+        if (i0 + k < b1) {
+          const uint32_t d = (uint32_t)(kv[k] >> shift) & 15u;
+          const uint32_t q = d >> 2, sh = 16 * (d & 3);
+          const uint64_t pq = (q == 0) ? pre[0] : ((q == 1) ? pre[1] : ((q == 2) ? pre[2] : pre[3]));
+          const uint32_t p = min(wbase[w * 16 + d] + (uint32_t)((pq >> sh) & 0xffffu), (uint32_t)(n - 1));
+          const uint64_t inc = 1ull << sh;
+          pre[0] += (q == 0) ? inc : 0ull;
+          pre[1] += (q == 1) ? inc : 0ull;
+          pre[2] += (q == 2) ? inc : 0ull;
+          pre[3] += (q == 3) ? inc : 0ull;
+          dst[(PAD_OUT && last) ? p + (p >> 4) : p] = kv[k];
+        }
+      }
     }
     __syncthreads();
     uint64_t* t = src;
@@ -162,7 +174,8 @@ __device__ void radix_sort_u64(uint64_t* a, uint64_t* tmp, int n, int lo_bit, in
     dst = t;
   }
   if (src != a) {
-    for (int i = tid; i < n; i += NT) a[i] = src[i];
+    const int np = PAD_OUT ? n + (n >> 4) : n;
+    for (int i = tid; i < np; i += NT) a[i] = src[i];
     __syncthreads();
   }
 }

@@ -450,9 +450,21 @@ struct FieldArgs {
 template <int D>
 struct Node {
   int32_t a, b;
-  double g[D + 1];
-  double r;
+  double g[D + 1];  // Legendre coefficients of the projection on [a, b] (in u = (t - a) / (b - a))
+  double r;         // accumulated squared L2 residual of the projection
+  double e;         // mean square of the projection over [a, b]: sum_j g_j^2 / (2j + 1)
 };
+
+template <int D>
+__device__ __forceinline__ double mean_square(const double* g) {
+  double e = 0.0;
+#pragma unroll
+  for (int j = 0; j <= D; ++j) {
+    constexpr double one = 1.0;
+    e += g[j] * g[j] * (one / (2 * j + 1));
+  }
+  return e;
+}
 
 __device__ __forceinline__ int64_t rint_i64(double x, uint32_t* flags) {
   if (!(fabs(x) < 4.6e18)) {
@@ -485,12 +497,13 @@ __host__ __device__ inline int jump_values_per_hit(int P, int even_k, int D) { r
 //   row k-1, k = 1..P: the knot at +theta_k; the knot at -theta_k mirrors it (even orders negated);
 //   odd K: row 0 is the knot at +theta_1, whose odd orders come from the closure;
 //   even K: row P is the middle knot (odd orders from the closure, even orders zero).
-// The knot pairs are visited one at a time, keeping only the closure sums live.  Computed once per
+// sr[m][d-1]: the table's projection jump of order d at +theta_{m+1} (s-hat, Sec. 3.1).  The
+// knot pairs are visited one at a time, keeping only the closure sums live.  Computed once per
 // hit, so the scans over the sorted knots only look values up.  Returns false if a quantized
 // coefficient left the int64 range.
 template <int D>
-__device__ bool hit_jumps(const MethodConsts& mc, const double* shat_row, double base, double u, const int32_t* off,
-                          uint64_t* rows) {
+__device__ bool hit_jumps(const MethodConsts& mc, const double (&sr)[kMaxP][D], double base, double u,
+                          const int32_t* off, uint64_t* rows) {
   const int P = mc.P;
   constexpr int ND = (D + 1) / 2;  // odd orders 1, 3, ...
   uint64_t acc[ND];
@@ -504,7 +517,7 @@ __device__ bool hit_jumps(const MethodConsts& mc, const double* shat_row, double
     for (int d = 1; d <= D; ++d) {
       p = p * u;
       const double scale = base * p;
-      const double x = shat_row[m * (D + 1) + d] * scale;
+      const double x = sr[m][d - 1] * scale;
       ok = ok && (fabs(x) < 4.6e18);
       const uint64_t j = (fabs(x) < 4.6e18) ? (uint64_t)(int64_t)rint(x) : 0ull;
       left[d] = (d % 2 == 0) ? (uint64_t)0 - j : j;
@@ -512,7 +525,9 @@ __device__ bool hit_jumps(const MethodConsts& mc, const double* shat_row, double
   };
   // knot pairs whose table jumps enter the closure sums directly: all of them for even K
   // (middle knot), m = 1..P-1 for odd K (the pair +-theta_1 is solved for below)
-  for (int m = mc.even_k ? 0 : 1; m < P; ++m) {
+#pragma unroll
+  for (int m = 0; m < kMaxP; ++m) {
+    if (m >= P || (m == 0 && !mc.even_k)) continue;
     uint64_t left[D + 1];
     table_left(m, left);
     uint64_t pw[D + 1];
@@ -595,14 +610,18 @@ __device__ __forceinline__ Node<D> make_leaf(const MergeTables& mt, int32_t ta, 
     for (int d = 0; d <= D; ++d) s += mt.pow2leg[j][d] * beta[d];
     n.g[j] = s;
   }
+  n.e = mean_square<D>(n.g);
   return n;
 }
 
-// Union of adjacent nodes A = [a, b], B = [b, c]: projection and residual (exact from the parts).
+// Union of adjacent nodes A = [a, b], B = [b, c]: projection and residual, exact from the parts.
+// The residual added by the union is the squared distance of the parts' projections from the
+// union's projection; by orthogonality it equals la e_A + lb e_B - (la + lb) e_U (lengths times mean
+// squares).  That difference cancels when the parts are nearly one polynomial, so when it lies
+// within its rounding bound of the merge threshold thr2 * length the distance is integrated
+// directly instead (a second Gauss-Legendre sweep, exact for the degree 2D integrand).
 template <int D>
-__device__ Node<D> combine(const MergeTables& mt, const Node<D>& A, const Node<D>& B, double tau) {
-  // two sweeps over the D + 1 Gauss-Legendre nodes of each part, recomputing the Legendre values
-  // instead of keeping (D + 1)^2 of them live (register pressure)
+__device__ Node<D> combine(const MergeTables& mt, const Node<D>& A, const Node<D>& B, double tau, double thr2) {
   Node<D> U;
   U.a = A.a;
   U.b = B.b;
@@ -611,7 +630,7 @@ __device__ Node<D> combine(const MergeTables& mt, const Node<D>& A, const Node<D
   double g[D + 1];
 #pragma unroll
   for (int j = 0; j <= D; ++j) g[j] = 0.0;
-#pragma unroll 1
+#pragma unroll
   for (int i = 0; i <= D; ++i) {
     double fa = 0.0, fb = 0.0;
 #pragma unroll
@@ -628,29 +647,37 @@ __device__ Node<D> combine(const MergeTables& mt, const Node<D>& A, const Node<D
   }
 #pragma unroll
   for (int j = 0; j <= D; ++j) U.g[j] = (2.0 * j + 1.0) * g[j];
-  double ra = 0.0, rb = 0.0;
-#pragma unroll 1
-  for (int i = 0; i <= D; ++i) {
-    double fa = 0.0, fb = 0.0;
+  U.e = mean_square<D>(U.g);
+  const double parts = la * A.e + lb * B.e;
+  double rloc = fmax(0.0, (parts - (la + lb) * U.e) * tau);
+  const double rin = A.r + B.r;
+  const double bound = 1e-13 * parts * tau + 1e-13 * rin;
+  if (fabs(rin + rloc - thr2 * ((la + lb) * tau)) <= bound) {
+    double ra = 0.0, rb = 0.0;
 #pragma unroll
-    for (int j = 0; j <= D; ++j) {
-      fa += A.g[j] * mt.leg_at_node[j][i];
-      fb += B.g[j] * mt.leg_at_node[j][i];
-    }
-    double pa[D + 1], pb[D + 1];
-    legendre_at<D>(lam * mt.node[i], pa);
-    legendre_at<D>(lam + (1.0 - lam) * mt.node[i], pb);
-    double ua = 0.0, ub = 0.0;
+    for (int i = 0; i <= D; ++i) {
+      double fa = 0.0, fb = 0.0;
 #pragma unroll
-    for (int j = 0; j <= D; ++j) {
-      ua += U.g[j] * pa[j];
-      ub += U.g[j] * pb[j];
+      for (int j = 0; j <= D; ++j) {
+        fa += A.g[j] * mt.leg_at_node[j][i];
+        fb += B.g[j] * mt.leg_at_node[j][i];
+      }
+      double pa[D + 1], pb[D + 1];
+      legendre_at<D>(lam * mt.node[i], pa);
+      legendre_at<D>(lam + (1.0 - lam) * mt.node[i], pb);
+      double ua = 0.0, ub = 0.0;
+#pragma unroll
+      for (int j = 0; j <= D; ++j) {
+        ua += U.g[j] * pa[j];
+        ub += U.g[j] * pb[j];
+      }
+      const double da = fa - ua, db = fb - ub;
+      ra += mt.wgt[i] * da * da;
+      rb += mt.wgt[i] * db * db;
     }
-    const double da = fa - ua, db = fb - ub;
-    ra += mt.wgt[i] * da * da;
-    rb += mt.wgt[i] * db * db;
+    rloc = la * tau * ra + lb * tau * rb;
   }
-  U.r = A.r + B.r + la * tau * ra + lb * tau * rb;
+  U.r = rin + rloc;
   return U;
 }
 
@@ -692,13 +719,10 @@ __device__ __forceinline__ void agg_combine(const Agg<D>& x, const Agg<D>& y, Ag
 
 template <int D>
 struct Shared {
-  union {
-    Agg<D> agg[kFieldThreads];
-    uint32_t hist[16 * kFieldThreads];  // radix sort counters
-  };
+  Agg<D> hs[kFieldThreads];                  // scan of the thread aggregates
+  uint32_t rtab[32 * (kFieldThreads / 64)];  // radix sort tables
   float part[kFieldThreads][4];
   int64_t wtot[kFieldThreads / 64];
-  uint32_t wsum[kFieldThreads / 64 + 1];
   unsigned long long peak;
   int64_t ray;
   int64_t base_out, base_ex;
@@ -719,10 +743,15 @@ struct RayStore {
 
 __host__ __device__ inline int64_t align8(int64_t x) { return (x + 7) & ~int64_t(7); }
 
+// The sorted knot keys are stored with one unused slot after every 16 (position i at
+// kpad(i)), so that threads walking consecutive 16-knot chunks read different LDS banks.
+__host__ __device__ inline int64_t kpad(int64_t i) { return i + (i >> 4); }
+__host__ __device__ inline int64_t kpad_size(int64_t n) { return n + (n >> 4) + 1; }
+
 // bytes of the per-ray layout for nh hits and nk knots (with_jumps: the jump rows included)
 __host__ __device__ inline int64_t ray_store_bytes(int64_t nh, int64_t nk, int nj, bool with_jumps) {
   const int64_t nc = (nk + kChunk - 1) / kChunk;
-  return 8 * nk + 8 * nk + (with_jumps ? 8 * (int64_t)nj * nh : 0) + 4 * align8(4 * nc);
+  return 16 * kpad_size(nk) + (with_jumps ? 8 * (int64_t)nj * nh : 0) + 4 * align8(4 * nc);
 }
 
 // jmp_ext: jump rows kept elsewhere (device memory) instead of in this layout
@@ -731,9 +760,9 @@ __device__ inline RayStore carve(char* p, int64_t nh, int64_t nk, int nj, uint64
   const int64_t nc = (nk + kChunk - 1) / kChunk;
   s.nj = nj;
   s.kkey = (uint64_t*)p;
-  p += 8 * nk;
+  p += 8 * kpad_size(nk);
   s.kkey2 = (uint64_t*)p;
-  p += 8 * nk;
+  p += 8 * kpad_size(nk);
   if (jmp_ext) {
     s.jmp = jmp_ext;
   } else {
@@ -788,38 +817,84 @@ __device__ void process_ray(const FieldArgs& A, Shared<D>& sh, const RayStore& S
   int32_t* park = reinterpret_cast<int32_t*>(S.kkey);
   const int64_t span32 = 2 * (int64_t)(K + 1);
   int32_t my_lo = 0x7fffffff, my_hi = (int32_t)0x80000000;
+  // hits are taken RB at a time per thread and every level of dependent loads (hit index,
+  // particle, table rows) is issued for the whole batch before it is used
+  constexpr int RB = 4;
 #pragma unroll 1
-  for (int64_t s = tid; s < nh; s += kFieldThreads) {
-    const uint32_t j = A.hits[hoff + s];
-    const float4 p = A.pos4[j];
-    const double dxx = (double)p.x - o[0], dxy = (double)p.y - o[1], dxz = (double)p.z - o[2];
-    const double cx = dxy * v[2] - dxz * v[1];
-    const double cy = dxz * v[0] - dxx * v[2];
-    const double cz = dxx * v[1] - dxy * v[0];
-    const double z = (double)p.w;
-    const double lam2 = (cx * cx + cy * cy + cz * cz) / (z * z);
-    const double tchi = dxx * v[0] + dxy * v[1] + dxz * v[2];
-    const double lam = sqrt(lam2);
-    int li = (int)floor(lam * (double)A.mc.n_lut / kSupport);
-    li = li < 0 ? 0 : (li > A.mc.n_lut - 1 ? A.mc.n_lut - 1 : li);
-    const double t0d = rint(tchi / tau);
-    bool bad = !(fabs(t0d) < 2.0e9);
-    const int32_t t0 = bad ? 0 : (int32_t)t0d;
-    int32_t offs[kMaxP] = {0, 0, 0};
-    for (int m = 0; m < P; ++m) {
-      const double od = rint(z * A.theta[(int64_t)li * P + m] / tau);
-      if (!(od < 2.0e9) || !(fabs(t0d) + od < 2147483647.0)) bad = true;
-      offs[m] = bad ? 0 : (int32_t)od;
+  for (int64_t s0 = tid; s0 < nh; s0 += RB * kFieldThreads) {
+    uint32_t jb[RB];
+#pragma unroll
+    for (int b = 0; b < RB; ++b) {
+      const int64_t s = s0 + (int64_t)b * kFieldThreads;
+      jb[b] = (s < nh) ? A.hits[hoff + s] : 0u;
     }
-    if (bad) atomicOr(A.flags, kFlagPosRange);
-    park[s * span32] = t0;
-    for (int m = 0; m < P; ++m) park[s * span32 + 1 + m] = offs[m];
-    const double base = (double)A.val[j] / (sigma * (z * z * z));
-    const double u = tau / z;
-    if (!hit_jumps<D>(A.mc, A.shat + (int64_t)li * P * (D + 1), base, u, offs, S.jmp + s * S.nj))
-      atomicOr(A.flags, kFlagCoefRange);
-    my_lo = min(my_lo, t0 - offs[P - 1]);
-    my_hi = max(my_hi, t0 + offs[P - 1]);
+    float4 pb[RB];
+    float vb[RB];
+#pragma unroll
+    for (int b = 0; b < RB; ++b) {
+      const bool in = s0 + (int64_t)b * kFieldThreads < nh;
+      pb[b] = in ? A.pos4[jb[b]] : make_float4(0.f, 0.f, 0.f, 1.f);
+      vb[b] = in ? A.val[jb[b]] : 0.f;
+    }
+    int lib[RB];
+    double t0db[RB];
+#pragma unroll
+    for (int b = 0; b < RB; ++b) {
+      const float4 p = pb[b];
+      const double dxx = (double)p.x - o[0], dxy = (double)p.y - o[1], dxz = (double)p.z - o[2];
+      const double cx = dxy * v[2] - dxz * v[1];
+      const double cy = dxz * v[0] - dxx * v[2];
+      const double cz = dxx * v[1] - dxy * v[0];
+      const double z = (double)p.w;
+      const double lam2 = (cx * cx + cy * cy + cz * cz) / (z * z);
+      const double tchi = dxx * v[0] + dxy * v[1] + dxz * v[2];
+      const double lam = sqrt(lam2);
+      int li = (int)floor(lam * (double)A.mc.n_lut / kSupport);
+      lib[b] = li < 0 ? 0 : (li > A.mc.n_lut - 1 ? A.mc.n_lut - 1 : li);
+      t0db[b] = rint(tchi / tau);
+    }
+    double thb[RB][kMaxP];
+    double srb[RB][kMaxP][D];
+#pragma unroll
+    for (int b = 0; b < RB; ++b) {
+      const bool in = s0 + (int64_t)b * kFieldThreads < nh;
+#pragma unroll
+      for (int m = 0; m < kMaxP; ++m) {
+        const bool use = in && m < P;
+        thb[b][m] = use ? A.theta[(int64_t)lib[b] * P + m] : 0.0;
+#pragma unroll
+        for (int d = 1; d <= D; ++d)
+          srb[b][m][d - 1] = use ? A.shat[((int64_t)lib[b] * P + m) * (D + 1) + d] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < RB; ++b) {
+      const int64_t s = s0 + (int64_t)b * kFieldThreads;
+      if (s >= nh) continue;
+      const double z = (double)pb[b].w;
+      const double t0d = t0db[b];
+      bool bad = !(fabs(t0d) < 2.0e9);
+      const int32_t t0 = bad ? 0 : (int32_t)t0d;
+      int32_t offs[kMaxP] = {0, 0, 0};
+#pragma unroll
+      for (int m = 0; m < kMaxP; ++m) {
+        if (m >= P) continue;
+        const double od = rint(z * thb[b][m] / tau);
+        if (!(od < 2.0e9) || !(fabs(t0d) + od < 2147483647.0)) bad = true;
+        offs[m] = bad ? 0 : (int32_t)od;
+      }
+      if (bad) atomicOr(A.flags, kFlagPosRange);
+      park[s * span32] = t0;
+#pragma unroll
+      for (int m = 0; m < kMaxP; ++m)
+        if (m < P) park[s * span32 + 1 + m] = offs[m];
+      const double base = (double)vb[b] / (sigma * (z * z * z));
+      const double u = tau / z;
+      if (!hit_jumps<D>(A.mc, srb[b], base, u, offs, S.jmp + s * S.nj)) atomicOr(A.flags, kFlagCoefRange);
+      const int32_t oP = (P == 1) ? offs[0] : ((P == 2) ? offs[1] : offs[2]);
+      my_lo = min(my_lo, t0 - oP);
+      my_hi = max(my_hi, t0 + oP);
+    }
   }
   atomicMin(&sh.t_lo, my_lo);
   atomicMax(&sh.t_hi, my_hi);
@@ -851,7 +926,7 @@ __device__ void process_ray(const FieldArgs& A, Shared<D>& sh, const RayStore& S
     const uint32_t range = (uint32_t)sh.t_hi - (uint32_t)t_lo;
     int nbits = 4;
     while (nbits < 32 && (range >> nbits) != 0) nbits += 4;
-    radix_sort_u64<kFieldThreads>(S.kkey, S.kkey2, (int)nk, 32, nbits, sh.hist, sh.wsum, tid);
+    radix_sort_u64<kFieldThreads, true>(S.kkey, S.kkey2, (int)nk, 32, nbits, sh.rtab, tid);
   }
   // ---- thread ranges of chunks
   const int64_t n_chunks = (nk + kChunk - 1) / kChunk;
@@ -859,13 +934,14 @@ __device__ void process_ray(const FieldArgs& A, Shared<D>& sh, const RayStore& S
   const int64_t c_lo = min((int64_t)tid * per, n_chunks), c_hi = min(c_lo + per, n_chunks);
   const int64_t k_lo = c_lo * kChunk, k_hi = min(c_hi * kChunk, nk);
   // ---- pass A: aggregate of this thread's knots
+  Agg<D> agg_mine;
   {
     Agg<D> g;
     g.valid = 0;
     g.t = 0;
     for (int d = 0; d <= D; ++d) g.a[d] = 0;
     for (int64_t i = k_lo; i < k_hi; ++i) {
-      const uint64_t key = S.kkey[i];
+      const uint64_t key = S.kkey[kpad(i)];
       const int64_t t = key_t(key);
       uint64_t jmp[D + 1];
       jump_of<D>(A.mc, S, key, jmp);
@@ -874,23 +950,24 @@ __device__ void process_ray(const FieldArgs& A, Shared<D>& sh, const RayStore& S
       g.t = t;
       g.valid = 1;
     }
-    sh.agg[tid] = g;
+    agg_mine = g;
   }
+  // inclusive Hillis-Steele scan of the thread aggregates in thread order
+  sh.hs[tid] = agg_mine;
   __syncthreads();
-  // inclusive Hillis-Steele scan over the thread aggregates
   for (int ofs = 1; ofs < kFieldThreads; ofs <<= 1) {
-    Agg<D> mine = sh.agg[tid];
+    Agg<D> mine = sh.hs[tid];
     Agg<D> res = mine;
     if (tid >= ofs) {
-      Agg<D> prev = sh.agg[tid - ofs];
+      Agg<D> prev = sh.hs[tid - ofs];
       agg_combine<D>(prev, mine, res);
     }
     __syncthreads();
-    sh.agg[tid] = res;
+    sh.hs[tid] = res;
     __syncthreads();
   }
   Agg<D> carry;
-  if (tid > 0) carry = sh.agg[tid - 1];
+  if (tid > 0) carry = sh.hs[tid - 1];
   else {
     carry.valid = 0;
     carry.t = 0;
@@ -904,7 +981,7 @@ __device__ void process_ray(const FieldArgs& A, Shared<D>& sh, const RayStore& S
   {
     Agg<D> st = carry;
     for (int64_t i = k_lo; i < k_hi; ++i) {
-      const uint64_t key = S.kkey[i];
+      const uint64_t key = S.kkey[kpad(i)];
       const int64_t t = key_t(key);
       uint64_t jmp[D + 1];
       jump_of<D>(A.mc, S, key, jmp);
@@ -913,7 +990,7 @@ __device__ void process_ray(const FieldArgs& A, Shared<D>& sh, const RayStore& S
       st.t = t;
       st.valid = 1;
       const bool last = (i + 1 == nk);
-      if (!last && key_t(S.kkey[i + 1]) != t) {
+      if (!last && key_t(S.kkey[kpad(i + 1)]) != t) {
         const int64_t a0 = (int64_t)st.a[0];
         const unsigned long long m = (unsigned long long)(a0 < 0 ? -a0 : a0);
         pk = pk > m ? pk : m;
@@ -959,7 +1036,7 @@ __device__ void process_ray(const FieldArgs& A, Shared<D>& sh, const RayStore& S
     };
     for (int64_t c = c_lo; c < c_hi; ++c) S.ccnt[c] = 0;
     for (int64_t i = k_lo; i < k_hi; ++i) {
-      const uint64_t key = S.kkey[i];
+      const uint64_t key = S.kkey[kpad(i)];
       const int64_t t = key_t(key);
       uint64_t jmp[D + 1];
       jump_of<D>(A.mc, S, key, jmp);
@@ -977,7 +1054,7 @@ __device__ void process_ray(const FieldArgs& A, Shared<D>& sh, const RayStore& S
         emitted = 0;
       }
       if (i + 1 < nk) {
-        const int32_t tn = key_t(S.kkey[i + 1]);
+        const int32_t tn = key_t(S.kkey[kpad(i + 1)]);
         if (tn != (int32_t)t) {
           if (A.exact) {
             const int64_t e = sh.base_ex + ex_pos;
@@ -993,7 +1070,7 @@ __device__ void process_ray(const FieldArgs& A, Shared<D>& sh, const RayStore& S
             cur = leaf;
             have = true;
           } else if (tol > 0.0) {
-            Node<D> cand = combine<D>(A.mt, cur, leaf, tau);
+            Node<D> cand = combine<D>(A.mt, cur, leaf, tau, thr2);
             if (passes<D>(cand, thr2, tau)) cur = cand;
             else {
               flush(chunk);
@@ -1031,7 +1108,7 @@ __device__ void process_ray(const FieldArgs& A, Shared<D>& sh, const RayStore& S
         int32_t nf = lf >= 0 ? lf : rf;
         int32_t nl = rl >= 0 ? rl : ll;
         if (ll >= 0 && rf >= 0) {
-          Node<D> cand = combine<D>(A.mt, nodes[ll], nodes[rf], tau);
+          Node<D> cand = combine<D>(A.mt, nodes[ll], nodes[rf], tau, thr2);
           if (passes<D>(cand, thr2, tau)) {
             nodes[ll] = cand;
             const int64_t rc = rf / kChunk;
@@ -1085,7 +1162,7 @@ __device__ void process_ray(const FieldArgs& A, Shared<D>& sh, const RayStore& S
       // sorted knot list in the canonical order (position, particle input index, kidx)
       __syncthreads();
       for (int64_t i = tid; i < nk; i += kFieldThreads) {
-        const uint64_t key = S.kkey[i];
+        const uint64_t key = S.kkey[kpad(i)];
         S.kkey2[i] = (key & 0xffffffff00000000ull) | ((uint64_t)(uint32_t)A.orig[A.hits[hoff + key_slot(key)]] << 3) |
                      (uint64_t)key_kidx(key);
       }
@@ -1093,7 +1170,7 @@ __device__ void process_ray(const FieldArgs& A, Shared<D>& sh, const RayStore& S
       const uint32_t range = (uint32_t)sh.t_hi - (uint32_t)t_lo;
       int nbits = 36;
       while (nbits < 64 && (range >> (nbits - 32)) != 0) nbits += 4;
-      radix_sort_u64<kFieldThreads>(S.kkey2, S.kkey, (int)nk, 0, nbits, sh.hist, sh.wsum, tid);
+      radix_sort_u64<kFieldThreads, false>(S.kkey2, S.kkey, (int)nk, 0, nbits, sh.rtab, tid);
       for (int64_t i = tid; i < nk; i += kFieldThreads) {
         const uint64_t key = S.kkey2[i];
         const int64_t ko = A.knot_off[r] + i;
@@ -1105,21 +1182,58 @@ __device__ void process_ray(const FieldArgs& A, Shared<D>& sh, const RayStore& S
       }
     }
   } else {
-    // classification and front-to-back compositing of this thread's nodes
-    float C0 = 0.f, C1 = 0.f, C2 = 0.f, T = 1.f;
+    // classification and front-to-back compositing.  The samples of the ray's live nodes are
+    // numbered in order and split evenly over the threads (merged nodes can be long, so per-node
+    // work is uneven); a thread finds its first node by binary search in an index of the nodes'
+    // first sample numbers.
     const float vmin = A.tf_vmin, vr = A.tf_vmax - A.tf_vmin;
     const int ntf = A.tf_n;
-    // the transfer function is read once per sample: stage it in the (now free) sort scratch
+    auto sample_count = [&](const Node<D>& nd) -> int64_t {
+      const double ta = (double)nd.a * tau, tb = (double)nd.b * tau;
+      const double a = fmax(ta, A.t_min), b = fmin(tb, A.t_max);
+      return (b > a) ? (int64_t)fmax(1.0, ceil((b - a) / A.tf_step)) : 0;
+    };
+    int64_t my_samples = 0;
+    for (int64_t c = c_lo; c < c_hi; ++c)
+      for (int32_t q = S.chead[c]; q < S.ccnt[c]; ++q) my_samples += sample_count(nodes[c * kChunk + q]);
+    int64_t n_samp = 0;
+    const int64_t samp_first = block_excl_scan_i64<kFieldThreads>(my_samples, sh.wtot, tid, &n_samp);
+    // node index in the sort scratch: first sample number and node slot of each live node
+    int32_t* ist = reinterpret_cast<int32_t*>(S.kkey2);
+    int32_t* iref = ist + n_live;
+    {
+      int64_t pos = live_first, sp = samp_first;
+      for (int64_t c = c_lo; c < c_hi; ++c)
+        for (int32_t q = S.chead[c]; q < S.ccnt[c]; ++q) {
+          ist[pos] = (int32_t)sp;
+          iref[pos] = (int32_t)(c * kChunk + q);
+          sp += sample_count(nodes[c * kChunk + q]);
+          ++pos;
+        }
+    }
+    // the transfer function is read once per sample: stage it in the key array (free now)
     const float* tfp = A.tf;
-    if ((int64_t)ntf * 16 <= 8 * nk) {
-      float* t = reinterpret_cast<float*>(S.kkey2);
+    if ((int64_t)ntf * 16 <= 8 * kpad_size(nk)) {
+      float* t = reinterpret_cast<float*>(S.kkey);
       for (int i = tid; i < 4 * ntf; i += kFieldThreads) t[i] = A.tf[i];
-      __syncthreads();
       tfp = t;
     }
-    for (int64_t c = c_lo; c < c_hi; ++c) {
-      for (int32_t q = S.chead[c]; q < S.ccnt[c]; ++q) {
-        const Node<D>& nd = nodes[c * kChunk + q];
+    __syncthreads();
+    float C0 = 0.f, C1 = 0.f, C2 = 0.f, T = 1.f;
+    const int64_t share = (n_samp + kFieldThreads - 1) / kFieldThreads;
+    const int64_t g0 = min((int64_t)tid * share, n_samp), g1 = min(g0 + share, n_samp);
+    if (g0 < g1) {
+      // last node whose first sample number is <= g0 (nodes without samples share the number of
+      // the next node, so the search never stops on one of them)
+      int64_t lo = 0, hi = n_live - 1;
+      while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) >> 1;
+        if ((int64_t)ist[mid] <= g0) lo = mid;
+        else hi = mid - 1;
+      }
+      int64_t g = g0;
+      for (int64_t n = lo; g < g1; ++n) {
+        const Node<D>& nd = nodes[iref[n]];
         const double ta = (double)nd.a * tau, tb = (double)nd.b * tau;
         const double a = fmax(ta, A.t_min), b = fmin(tb, A.t_max);
         if (!(b > a)) continue;
@@ -1128,13 +1242,15 @@ __device__ void process_ray(const FieldArgs& A, Shared<D>& sh, const RayStore& S
         const double delta = (b - a) / Sd;
         float cf[D + 1];
         for (int d = 0; d <= D; ++d) {
-          double s = 0.0;
-          for (int j = 0; j <= D; ++j) s += nd.g[j] * A.mt.leg2pow[j][d];
-          cf[d] = (float)s;
+          double sacc = 0.0;
+          for (int j = 0; j <= D; ++j) sacc += nd.g[j] * A.mt.leg2pow[j][d];
+          cf[d] = (float)sacc;
         }
         const float u0 = (float)((a - ta) / (tb - ta)), du = (float)(delta / (tb - ta));
         const float dl = (float)delta;
-        for (int64_t j = 0; j < S_n; ++j) {
+        const int64_t first = ist[n];
+        const int64_t j1 = min(S_n, g1 - first);
+        for (int64_t j = g - first; j < j1; ++j) {
           const float uu = u0 + ((float)j + 0.5f) * du;
           float val = cf[D];
           for (int d = D - 1; d >= 0; --d) val = val * uu + cf[d];
@@ -1156,6 +1272,7 @@ __device__ void process_ray(const FieldArgs& A, Shared<D>& sh, const RayStore& S
           C2 += T * eb * frac;
           T *= expf(-xx);
         }
+        g = first + j1;
       }
     }
     sh.part[tid][0] = C0;
@@ -1215,11 +1332,16 @@ __global__ void __launch_bounds__(kFieldThreads) k_field(FieldArgs A) {
       // the whole layout in LDS if it fits, else the keys in LDS and the jump rows in device
       // memory, else everything in device memory (the arithmetic is the same on every path)
       const int64_t nk = nh * (A.mc.K + 1);
-      const bool all_lds = ray_store_bytes(nh, nk, A.nj, true) <= A.lds_bytes;
-      const bool keys_lds = ray_store_bytes(nh, nk, A.nj, false) <= A.lds_bytes;
-      if (threadIdx.x == 0 && !all_lds) atomicAdd(&A.counters[keys_lds ? 4 : 3], 1ull);
-      const RayStore S = carve(keys_lds ? lds : gstore, nh, nk, A.nj, (keys_lds && !all_lds) ? gjmp : nullptr);
-      process_ray<D, RENDER>(A, sh, S, nodes, r, nh);
+      if (ray_store_bytes(nh, nk, A.nj, true) <= A.lds_bytes) {
+        // common case, its own inlined copy so that every access compiles to LDS instructions
+        const RayStore S = carve(lds, nh, nk, A.nj, nullptr);
+        process_ray<D, RENDER>(A, sh, S, nodes, r, nh);
+      } else {
+        const bool keys_lds = ray_store_bytes(nh, nk, A.nj, false) <= A.lds_bytes;
+        if (threadIdx.x == 0) atomicAdd(&A.counters[keys_lds ? 4 : 3], 1ull);
+        const RayStore S = carve(keys_lds ? lds : gstore, nh, nk, A.nj, keys_lds ? gjmp : nullptr);
+        process_ray<D, RENDER>(A, sh, S, nodes, r, nh);
+      }
     }
     __syncthreads();
   }
@@ -1355,7 +1477,7 @@ void dispatch_field(int D, FieldArgs& A, int grid, size_t lds, hipStream_t st) {
   }
 }
 
-size_t node_bytes(int D) { return 8 + 8 * (size_t)(D + 2); }
+size_t node_bytes(int D) { return 8 + 8 * (size_t)(D + 3); }
 
 size_t static_lds(int D) {
   switch (D) {
@@ -1531,8 +1653,9 @@ void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam,
   ix.stats.n_pairs = total_pairs;
   ix.stats.max_hits = (int64_t)mh;
   ix.stats.n_knots = total_pairs * (K + 1);
-  if ((int64_t)mh * (K + 1) >= (int64_t(1) << 29))
-    throw Error(SPH_HOA_E_UNSUPPORTED, "more than 2^29 knots on one ray");
+  // the per-ray sort ranks a wave's keys in 16-bit fields: at most 1023 keys per thread
+  if ((int64_t)mh * (K + 1) > (int64_t)1023 * kFieldThreads)
+    throw Error(SPH_HOA_E_UNSUPPORTED, "more than 1023 * 256 knots on one ray");
   ix.hits.ensure(sizeof(uint32_t) * std::max<int64_t>(1, total_pairs));
   G.off = ix.hit_off.as<int64_t>();
   G.hits = ix.hits.as<uint32_t>();
