@@ -189,7 +189,11 @@ def main():
         "config": {"workload": f"plain GPU path: {a.particles} clustered particles (16 Gaussians + 10% uniform, "
                                f"h=r32/2, SPH density), Wendland C2, K=4, D=3, tol 1e-3, {a.size}x{a.size} "
                                "perspective rays, render", "pairs_per_frame": pairs_per_frame,
-                   "max_hits_per_ray": st["max_hits"], "rays_device_memory": st["rays_global"],
+                   "max_hits_per_ray": st["max_hits"],
+                   "rays_by_layout": {"lds": st["n_rays"] - st["rays_jumps_device"] - st["rays_scratch_device"]
+                                      - st["rays_global"], "jump_rows_in_hbm": st["rays_jumps_device"],
+                                      "jump_rows_and_sort_scratch_in_hbm": st["rays_scratch_device"],
+                                      "all_in_hbm": st["rays_global"]},
                    "tau": info["tau"], "sigma": info["sigma"], "index_build_s": index_s, "generate_s": gen_s},
         "roofline": roofline,
     }

@@ -139,8 +139,9 @@ typedef struct {
   int64_t n_knots;
   int64_t n_pieces;       /* merged pieces (render: pieces composited) */
   int64_t max_hits;       /* largest number of contributions on one ray */
-  int64_t rays_global;    /* approx_rays: rays whose whole per-ray layout was in device memory */
-  int64_t rays_jumps_device; /* approx_rays: rays with keys in LDS, per-hit jump rows in device memory */
+  int64_t rays_global;    /* rays whose whole per-ray layout was in device memory instead of LDS */
+  int64_t rays_jumps_device; /* rays with keys in LDS, per-hit jump rows in device memory */
+  int64_t rays_scratch_device; /* rays with keys in LDS, jump rows and sort scratch in device memory */
   /* with timing enabled (sph_hoa_index_set_timing): device time summed over the timed calls
    * since timing was (re-)enabled, from hipEvents recorded on the call's stream */
   int64_t timed_calls;

@@ -73,7 +73,7 @@ class TF(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [("n_rays", ctypes.c_int64), ("n_pairs", ctypes.c_int64), ("n_knots", ctypes.c_int64),
                 ("n_pieces", ctypes.c_int64), ("max_hits", ctypes.c_int64), ("rays_global", ctypes.c_int64),
-                ("rays_jumps_device", ctypes.c_int64),
+                ("rays_jumps_device", ctypes.c_int64), ("rays_scratch_device", ctypes.c_int64),
                 ("timed_calls", ctypes.c_int64), ("ms_gather", ctypes.c_double), ("ms_field", ctypes.c_double)]
 
 

@@ -297,9 +297,19 @@ sph_hoa_status sph_hoa_index_get_grid(sph_hoa_index idx, uint64_t* morton, int32
 sph_hoa_status sph_hoa_index_get_stats(sph_hoa_index idx, sph_hoa_stats* stats) {
   return guarded([&]() {
     require(idx && stats, "NULL argument");
-    if (idx->ix.last_stream) sph::hip_check(hipStreamSynchronize(idx->ix.last_stream), "sync");
-    idx->ix.collect_timing();
-    *stats = idx->ix.stats;
+    sph::Index& ix = idx->ix;
+    if (ix.last_stream) sph::hip_check(hipStreamSynchronize(ix.last_stream), "sync");
+    ix.collect_timing();
+    if (ix.render_stats_pending) {
+      // a render does not wait for its kernels; its placement counters are read back here
+      unsigned long long c[6];
+      sph::hip_check(hipMemcpy(c, ix.counters.p, sizeof(c), hipMemcpyDeviceToHost), "copy");
+      ix.stats.rays_global = (int64_t)c[3];
+      ix.stats.rays_jumps_device = (int64_t)c[4];
+      ix.stats.rays_scratch_device = (int64_t)c[5];
+      ix.render_stats_pending = false;
+    }
+    *stats = ix.stats;
     stats->timed_calls = idx->ix.timed_calls;
     stats->ms_gather = idx->ix.ms_gather;
     stats->ms_field = idx->ix.ms_field;

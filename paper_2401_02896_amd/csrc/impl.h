@@ -18,6 +18,8 @@ constexpr int kMaxD = 6;
 constexpr int kMaxP = 3;
 constexpr int kChunk = 16;          // knots per merge chunk
 constexpr int kFieldThreads = 256;  // threads per ray work-group
+constexpr int kFieldWgPerCu = 2;    // ray work-groups resident per CU
+constexpr int64_t kLdsPerCu = 160 * 1024;
 constexpr int64_t kMaxAxisCells = int64_t(1) << 19;
 constexpr int64_t kMaxLevel0Cells = int64_t(1) << 24;
 constexpr double kAmaxMargin = 1.25;
@@ -114,6 +116,7 @@ struct Index {
   DevBuf ray_meta;              // per-ray outputs of the field kernel
   DevBuf out_stage, exact_stage;
   sph_hoa_stats stats{};
+  bool render_stats_pending = false;  // placement counters of the last render not read back yet
   hipStream_t last_stream = nullptr;
   // optional event timing of the kernels (sph_hoa_index_set_timing)
   bool timing = false;

@@ -416,10 +416,12 @@ struct FieldArgs {
   int64_t slab_stride;  // bytes per work-group
   int64_t max_knots;    // largest knot count of any ray (sizes the slab)
   int64_t slab_jmp;     // offset of the jump rows in a work-group's slab
+  int64_t slab_scratch; // offset of the sort scratch in a work-group's slab
   int64_t slab_store;   // offset of the whole per-ray layout in a work-group's slab
   uint32_t* flags;
   unsigned long long* counters;  // [0] merged pieces (bump), [1] exact pieces (bump), [2] pieces total,
-                                 // [3] rays in device memory, [4] rays with jump rows in device memory
+                                 // [3] rays in device memory, [4] rays with jump rows in device memory,
+                                 // [5] rays with jump rows and sort scratch in device memory
   // approx outputs (staging, bump-allocated)
   int64_t out_cap;
   float* st_t0;
@@ -748,21 +750,37 @@ __host__ __device__ inline int64_t align8(int64_t x) { return (x + 7) & ~int64_t
 __host__ __device__ inline int64_t kpad(int64_t i) { return i + (i >> 4); }
 __host__ __device__ inline int64_t kpad_size(int64_t n) { return n + (n >> 4) + 1; }
 
-// bytes of the per-ray layout for nh hits and nk knots (with_jumps: the jump rows included)
-__host__ __device__ inline int64_t ray_store_bytes(int64_t nh, int64_t nk, int nj, bool with_jumps) {
+// bytes of the per-ray layout for nh hits and nk knots, with or without the jump rows and the
+// sort scratch (those two can live in the work-group's device-memory slab instead)
+__host__ __device__ inline int64_t ray_store_bytes(int64_t nh, int64_t nk, int nj, bool with_jumps,
+                                                   bool with_scratch = true) {
   const int64_t nc = (nk + kChunk - 1) / kChunk;
-  return 16 * kpad_size(nk) + (with_jumps ? 8 * (int64_t)nj * nh : 0) + 4 * align8(4 * nc);
+  return (with_scratch ? 16 : 8) * kpad_size(nk) + (with_jumps ? 8 * (int64_t)nj * nh : 0) + 4 * align8(4 * nc);
 }
 
-// jmp_ext: jump rows kept elsewhere (device memory) instead of in this layout
-__device__ inline RayStore carve(char* p, int64_t nh, int64_t nk, int nj, uint64_t* jmp_ext) {
+// Placement tiers of a ray's layout: 0 all in LDS; 1 jump rows in device memory; 2 jump rows and
+// sort scratch in device memory; 3 everything in device memory.
+__host__ __device__ inline int ray_tier(int64_t nh, int64_t nk, int nj, int64_t lds_bytes) {
+  if (ray_store_bytes(nh, nk, nj, true, true) <= lds_bytes) return 0;
+  if (ray_store_bytes(nh, nk, nj, false, true) <= lds_bytes) return 1;
+  if (ray_store_bytes(nh, nk, nj, false, false) <= lds_bytes) return 2;
+  return 3;
+}
+
+// jmp_ext / scratch_ext: jump rows / sort scratch kept in device memory instead of in this layout
+__device__ inline RayStore carve(char* p, int64_t nh, int64_t nk, int nj, uint64_t* jmp_ext,
+                                 uint64_t* scratch_ext = nullptr) {
   RayStore s;
   const int64_t nc = (nk + kChunk - 1) / kChunk;
   s.nj = nj;
   s.kkey = (uint64_t*)p;
   p += 8 * kpad_size(nk);
-  s.kkey2 = (uint64_t*)p;
-  p += 8 * kpad_size(nk);
+  if (scratch_ext) {
+    s.kkey2 = scratch_ext;
+  } else {
+    s.kkey2 = (uint64_t*)p;
+    p += 8 * kpad_size(nk);
+  }
   if (jmp_ext) {
     s.jmp = jmp_ext;
   } else {
@@ -817,84 +835,52 @@ __device__ void process_ray(const FieldArgs& A, Shared<D>& sh, const RayStore& S
   int32_t* park = reinterpret_cast<int32_t*>(S.kkey);
   const int64_t span32 = 2 * (int64_t)(K + 1);
   int32_t my_lo = 0x7fffffff, my_hi = (int32_t)0x80000000;
-  // hits are taken RB at a time per thread and every level of dependent loads (hit index,
-  // particle, table rows) is issued for the whole batch before it is used
-  constexpr int RB = 4;
 #pragma unroll 1
-  for (int64_t s0 = tid; s0 < nh; s0 += RB * kFieldThreads) {
-    uint32_t jb[RB];
+  for (int64_t s = tid; s < nh; s += kFieldThreads) {
+    const uint32_t j = A.hits[hoff + s];
+    const float4 p = A.pos4[j];
+    const float vj = A.val[j];
+    const double dxx = (double)p.x - o[0], dxy = (double)p.y - o[1], dxz = (double)p.z - o[2];
+    const double cx = dxy * v[2] - dxz * v[1];
+    const double cy = dxz * v[0] - dxx * v[2];
+    const double cz = dxx * v[1] - dxy * v[0];
+    const double z = (double)p.w;
+    const double lam2 = (cx * cx + cy * cy + cz * cz) / (z * z);
+    const double tchi = dxx * v[0] + dxy * v[1] + dxz * v[2];
+    const double lam = sqrt(lam2);
+    int li = (int)floor(lam * (double)A.mc.n_lut / kSupport);
+    li = li < 0 ? 0 : (li > A.mc.n_lut - 1 ? A.mc.n_lut - 1 : li);
+    // the table row (knots and projection jumps) is loaded in one go before it is used
+    double th[kMaxP];
+    double sr[kMaxP][D];
 #pragma unroll
-    for (int b = 0; b < RB; ++b) {
-      const int64_t s = s0 + (int64_t)b * kFieldThreads;
-      jb[b] = (s < nh) ? A.hits[hoff + s] : 0u;
+    for (int m = 0; m < kMaxP; ++m) {
+      th[m] = (m < P) ? A.theta[(int64_t)li * P + m] : 0.0;
+#pragma unroll
+      for (int d = 1; d <= D; ++d) sr[m][d - 1] = (m < P) ? A.shat[((int64_t)li * P + m) * (D + 1) + d] : 0.0;
     }
-    float4 pb[RB];
-    float vb[RB];
+    const double t0d = rint(tchi / tau);
+    bool bad = !(fabs(t0d) < 2.0e9);
+    const int32_t t0 = bad ? 0 : (int32_t)t0d;
+    int32_t offs[kMaxP] = {0, 0, 0};
 #pragma unroll
-    for (int b = 0; b < RB; ++b) {
-      const bool in = s0 + (int64_t)b * kFieldThreads < nh;
-      pb[b] = in ? A.pos4[jb[b]] : make_float4(0.f, 0.f, 0.f, 1.f);
-      vb[b] = in ? A.val[jb[b]] : 0.f;
+    for (int m = 0; m < kMaxP; ++m) {
+      if (m >= P) continue;
+      const double od = rint(z * th[m] / tau);
+      if (!(od < 2.0e9) || !(fabs(t0d) + od < 2147483647.0)) bad = true;
+      offs[m] = bad ? 0 : (int32_t)od;
     }
-    int lib[RB];
-    double t0db[RB];
+    if (bad) atomicOr(A.flags, kFlagPosRange);
+    park[s * span32] = t0;
 #pragma unroll
-    for (int b = 0; b < RB; ++b) {
-      const float4 p = pb[b];
-      const double dxx = (double)p.x - o[0], dxy = (double)p.y - o[1], dxz = (double)p.z - o[2];
-      const double cx = dxy * v[2] - dxz * v[1];
-      const double cy = dxz * v[0] - dxx * v[2];
-      const double cz = dxx * v[1] - dxy * v[0];
-      const double z = (double)p.w;
-      const double lam2 = (cx * cx + cy * cy + cz * cz) / (z * z);
-      const double tchi = dxx * v[0] + dxy * v[1] + dxz * v[2];
-      const double lam = sqrt(lam2);
-      int li = (int)floor(lam * (double)A.mc.n_lut / kSupport);
-      lib[b] = li < 0 ? 0 : (li > A.mc.n_lut - 1 ? A.mc.n_lut - 1 : li);
-      t0db[b] = rint(tchi / tau);
-    }
-    double thb[RB][kMaxP];
-    double srb[RB][kMaxP][D];
-#pragma unroll
-    for (int b = 0; b < RB; ++b) {
-      const bool in = s0 + (int64_t)b * kFieldThreads < nh;
-#pragma unroll
-      for (int m = 0; m < kMaxP; ++m) {
-        const bool use = in && m < P;
-        thb[b][m] = use ? A.theta[(int64_t)lib[b] * P + m] : 0.0;
-#pragma unroll
-        for (int d = 1; d <= D; ++d)
-          srb[b][m][d - 1] = use ? A.shat[((int64_t)lib[b] * P + m) * (D + 1) + d] : 0.0;
-      }
-    }
-#pragma unroll
-    for (int b = 0; b < RB; ++b) {
-      const int64_t s = s0 + (int64_t)b * kFieldThreads;
-      if (s >= nh) continue;
-      const double z = (double)pb[b].w;
-      const double t0d = t0db[b];
-      bool bad = !(fabs(t0d) < 2.0e9);
-      const int32_t t0 = bad ? 0 : (int32_t)t0d;
-      int32_t offs[kMaxP] = {0, 0, 0};
-#pragma unroll
-      for (int m = 0; m < kMaxP; ++m) {
-        if (m >= P) continue;
-        const double od = rint(z * thb[b][m] / tau);
-        if (!(od < 2.0e9) || !(fabs(t0d) + od < 2147483647.0)) bad = true;
-        offs[m] = bad ? 0 : (int32_t)od;
-      }
-      if (bad) atomicOr(A.flags, kFlagPosRange);
-      park[s * span32] = t0;
-#pragma unroll
-      for (int m = 0; m < kMaxP; ++m)
-        if (m < P) park[s * span32 + 1 + m] = offs[m];
-      const double base = (double)vb[b] / (sigma * (z * z * z));
-      const double u = tau / z;
-      if (!hit_jumps<D>(A.mc, srb[b], base, u, offs, S.jmp + s * S.nj)) atomicOr(A.flags, kFlagCoefRange);
-      const int32_t oP = (P == 1) ? offs[0] : ((P == 2) ? offs[1] : offs[2]);
-      my_lo = min(my_lo, t0 - oP);
-      my_hi = max(my_hi, t0 + oP);
-    }
+    for (int m = 0; m < kMaxP; ++m)
+      if (m < P) park[s * span32 + 1 + m] = offs[m];
+    const double base = (double)vj / (sigma * (z * z * z));
+    const double u = tau / z;
+    if (!hit_jumps<D>(A.mc, sr, base, u, offs, S.jmp + s * S.nj)) atomicOr(A.flags, kFlagCoefRange);
+    const int32_t oP = (P == 1) ? offs[0] : ((P == 2) ? offs[1] : offs[2]);
+    my_lo = min(my_lo, t0 - oP);
+    my_hi = max(my_hi, t0 + oP);
   }
   atomicMin(&sh.t_lo, my_lo);
   atomicMax(&sh.t_hi, my_hi);
@@ -1301,12 +1287,13 @@ __device__ void process_ray(const FieldArgs& A, Shared<D>& sh, const RayStore& S
 }
 
 template <int D, bool RENDER>
-__global__ void __launch_bounds__(kFieldThreads) k_field(FieldArgs A) {
+__global__ void __launch_bounds__(kFieldThreads, kFieldWgPerCu) k_field(FieldArgs A) {
   extern __shared__ __align__(16) char lds[];
   __shared__ Shared<D> sh;
   char* slab = A.slab + (int64_t)blockIdx.x * A.slab_stride;
   Node<D>* nodes = (Node<D>*)slab;
   uint64_t* gjmp = (uint64_t*)(slab + A.slab_jmp);
+  uint64_t* gscratch = (uint64_t*)(slab + A.slab_scratch);
   char* gstore = slab + A.slab_store;
   for (;;) {
     if (threadIdx.x == 0) sh.ray = (int64_t)atomicAdd(A.queue, 1u);
@@ -1329,17 +1316,18 @@ __global__ void __launch_bounds__(kFieldThreads) k_field(FieldArgs A) {
         }
       }
     } else {
-      // the whole layout in LDS if it fits, else the keys in LDS and the jump rows in device
-      // memory, else everything in device memory (the arithmetic is the same on every path)
+      // the whole layout in LDS if it fits, else the jump rows, then also the sort scratch, then
+      // everything in the work-group's device memory (the arithmetic is the same on every path)
       const int64_t nk = nh * (A.mc.K + 1);
-      if (ray_store_bytes(nh, nk, A.nj, true) <= A.lds_bytes) {
+      const int tier = ray_tier(nh, nk, A.nj, A.lds_bytes);
+      if (tier == 0) {
         // common case, its own inlined copy so that every access compiles to LDS instructions
         const RayStore S = carve(lds, nh, nk, A.nj, nullptr);
         process_ray<D, RENDER>(A, sh, S, nodes, r, nh);
       } else {
-        const bool keys_lds = ray_store_bytes(nh, nk, A.nj, false) <= A.lds_bytes;
-        if (threadIdx.x == 0) atomicAdd(&A.counters[keys_lds ? 4 : 3], 1ull);
-        const RayStore S = carve(keys_lds ? lds : gstore, nh, nk, A.nj, keys_lds ? gjmp : nullptr);
+        if (threadIdx.x == 0) atomicAdd(&A.counters[tier == 1 ? 4 : (tier == 2 ? 5 : 3)], 1ull);
+        const RayStore S = carve(tier < 3 ? lds : gstore, nh, nk, A.nj, tier < 3 ? gjmp : nullptr,
+                                 tier == 2 ? gscratch : nullptr);
         process_ray<D, RENDER>(A, sh, S, nodes, r, nh);
       }
     }
@@ -1513,6 +1501,7 @@ void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam,
               FieldOut& out, hipStream_t st) {
   const int D = ix.D, K = ix.K, P = ix.P;
   ix.collect_timing();
+  ix.render_stats_pending = false;
   ix.stats = sph_hoa_stats{};
   ix.stats.n_rays = n_rays;
   ix.counters.ensure(256);
@@ -1691,31 +1680,33 @@ void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam,
   A.counters = ctr;
   const int64_t max_knots = std::max<int64_t>(1, (int64_t)mh * (K + 1));
   A.max_knots = max_knots;
-  // LDS layout capacity: the largest ray's whole layout, within the LDS left by the static part
+  // LDS per work-group: two work-groups share a CU (two waves per SIMD hide the latency of the
+  // dependent integer and float64 chains; the kernel is register-capped for it), so a ray's layout
+  // gets half the CU's LDS less the static part; it is sized down to the frame's longest ray
   const int nj = jump_values_per_hit(P, (K % 2 == 0) ? 1 : 0, D);
   A.nj = nj;
   const size_t lds_static = static_lds(D);
-  const int64_t lds_limit = 160 * 1024 - (int64_t)lds_static - 1024;
-  int64_t lds = std::min<int64_t>(lds_limit, ray_store_bytes(std::max<int64_t>(1, (int64_t)mh), max_knots, nj, true));
+  const int64_t mh1 = std::max<int64_t>(1, (int64_t)mh);
+  const int64_t lds_budget = kLdsPerCu / kFieldWgPerCu - (int64_t)lds_static - 512;
+  int64_t lds = std::min<int64_t>(lds_budget, ray_store_bytes(mh1, max_knots, nj, true));
   // test hook: a smaller LDS capacity (in hits) sends more rays down the device-memory paths
   if (const char* cap = std::getenv("SPH_HOA_MAX_LDS_HITS")) {
     const int64_t ch = std::max<int64_t>(1, std::atoll(cap));
     lds = std::min<int64_t>(lds, ray_store_bytes(ch, ch * (K + 1), nj, true));
   }
   A.lds_bytes = lds;
-  int per_cu = 0;
   hipDeviceProp_t prop;
   int dev = 0;
   hip_check(hipGetDevice(&dev), "device");
   hip_check(hipGetDeviceProperties(&prop, dev), "props");
-  per_cu = (int)std::max<int64_t>(1, std::min<int64_t>(8, (160 * 1024) / (lds + (int64_t)lds_static + 1)));
+  const int per_cu = (int)std::max<int64_t>(
+      1, std::min<int64_t>(kFieldWgPerCu, kLdsPerCu / (lds + (int64_t)lds_static + 512)));
   const int grid = (int)std::min<int64_t>((int64_t)prop.multiProcessorCount * per_cu, n_rays);
-  const int64_t mh1 = std::max<int64_t>(1, (int64_t)mh);
-  const bool jumps_out = ray_store_bytes(mh1, max_knots, nj, true) > lds;
-  const bool all_out = ray_store_bytes(mh1, max_knots, nj, false) > lds;
+  const int max_tier = ray_tier(mh1, max_knots, nj, lds);
   A.slab_jmp = align8((int64_t)node_bytes(D) * ((max_knots + kChunk - 1) / kChunk) * kChunk);
-  A.slab_store = A.slab_jmp + (jumps_out ? align8(8 * (int64_t)nj * mh1) : 0);
-  A.slab_stride = A.slab_store + (all_out ? align8(ray_store_bytes(mh1, max_knots, nj, true)) : 0) + 64;
+  A.slab_scratch = A.slab_jmp + (max_tier >= 1 ? align8(8 * (int64_t)nj * mh1) : 0);
+  A.slab_store = A.slab_scratch + (max_tier >= 2 ? align8(8 * kpad_size(max_knots)) : 0);
+  A.slab_stride = A.slab_store + (max_tier >= 3 ? align8(ray_store_bytes(mh1, max_knots, nj, true)) : 0) + 64;
   ix.slab.ensure((size_t)A.slab_stride * grid);
   A.slab = ix.slab.as<char>();
   const bool render = (out.rgba != nullptr);
@@ -1728,6 +1719,7 @@ void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam,
     A.rgba = out.rgba;
     if (ix.timing) hip_check(hipEventRecord(ix.ev[4], st), "event");
     dispatch_field<true>(D, A, grid, (size_t)lds, st);
+    ix.render_stats_pending = true;
     if (ix.timing) {
       hip_check(hipEventRecord(ix.ev[5], st), "event");
       ix.timing_pending = true;
@@ -1775,7 +1767,7 @@ void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam,
     k_ray_counts<<<blocks_for(n_rays, 256), 256, 0, st>>>(A.ray_out, n_rays, cnt.as<int64_t>());
     device_exclusive_scan_i64(cnt.as<int64_t>(), f->ray_offsets, n_rays, ix.scan_tmp, st);
     k_set_last<<<1, 1, 0, st>>>(f->ray_offsets, cnt.as<int64_t>(), n_rays);
-    unsigned long long c4[5];
+    unsigned long long c4[6];
     hip_check(hipMemcpyAsync(c4, ctr, sizeof(c4), hipMemcpyDeviceToHost, st), "copy");
     hip_check(hipMemcpyAsync(&fl, flags, 4, hipMemcpyDeviceToHost, st), "copy");
     hip_check(hipStreamSynchronize(st), "sync");
@@ -1786,6 +1778,7 @@ void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam,
     ix.stats.n_pieces = (int64_t)c4[0];
     ix.stats.rays_global = (int64_t)c4[3];
     ix.stats.rays_jumps_device = (int64_t)c4[4];
+    ix.stats.rays_scratch_device = (int64_t)c4[5];
     if (fl & kFlagPosRange) throw Error(SPH_HOA_E_OVERFLOW, "a quantized knot position left the int32 range");
     if (fl & kFlagCoefRange) throw Error(SPH_HOA_E_OVERFLOW, "a quantized coefficient left the int64 range");
     if (fl & kFlagTail) throw Error(SPH_HOA_E_INTERNAL, "a ray's knots did not cancel exactly");

@@ -202,9 +202,10 @@ def test_device_memory_path_is_identical():
     o, v = synth.ortho_rays()
     o, v = o[:300], v[:300]
     a = _approx(sc, o, v, 0.0, 1.4)
-    # 16 hits: most rays keep everything in device memory; 40 hits: most keep their keys in LDS
-    # and the per-hit jump rows in device memory
-    for cap, stat in (("16", "rays_global"), ("40", "rays_jumps_device")):
+    # 16 hits: most rays keep everything in device memory; 24 hits: most keep their keys in LDS
+    # and the jump rows and sort scratch in device memory; 40 hits: most keep keys and scratch in
+    # LDS and the per-hit jump rows in device memory
+    for cap, stat in (("16", "rays_global"), ("24", "rays_scratch_device"), ("40", "rays_jumps_device")):
         os.environ["SPH_HOA_MAX_LDS_HITS"] = cap
         try:
             b = _approx(sc, o, v, 0.0, 1.4)
