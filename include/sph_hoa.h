@@ -181,6 +181,18 @@ sph_hoa_status sph_hoa_approx_rays(sph_hoa_index idx, const sph_hoa_rays* rays, 
 sph_hoa_status sph_hoa_render(sph_hoa_index idx, const sph_hoa_camera* cam, const sph_hoa_tf* tf,
                               float* rgba_out, void* stream);
 
+/*
+ * Render a batch of cameras (each with its own size, frame and t range) with one launch chain:
+ * all their rays are generated, gathered (grid walk), scheduled longest first and processed
+ * together, so many small images share the GPU.  Each image equals the one sph_hoa_render gives
+ * for that camera (same hit sets, fields and compositing arithmetic).
+ * cams: HOST array [n_cams] (0 <= n_cams <= 2^20), copied.  rgba_out: device float32, the images
+ * concatenated in camera order, each [height][width][4]; at most 2^32 rays in total.
+ * Synchronises `stream` once (per-frame hit counts); NULL cams / rgba_out allowed when n_cams = 0.
+ */
+sph_hoa_status sph_hoa_render_batch(sph_hoa_index idx, const sph_hoa_camera* cams, int32_t n_cams,
+                                    const sph_hoa_tf* tf, float* rgba_out, void* stream);
+
 sph_hoa_status sph_hoa_index_free(sph_hoa_index idx);
 
 /* Host copy of the index parameters. */

@@ -77,7 +77,8 @@ class Stats(ctypes.Structure):
                 ("timed_calls", ctypes.c_int64), ("ms_gather", ctypes.c_double), ("ms_field", ctypes.c_double)]
 
 
-EXPORTS = ["sph_hoa_build_index", "sph_hoa_approx_rays", "sph_hoa_render", "sph_hoa_index_free",
+EXPORTS = ["sph_hoa_build_index", "sph_hoa_approx_rays", "sph_hoa_render", "sph_hoa_render_batch",
+           "sph_hoa_index_free",
            "sph_hoa_index_get_info", "sph_hoa_index_get_lut", "sph_hoa_index_get_grid", "sph_hoa_index_get_stats",
            "sph_hoa_index_set_timing",
            "sph_hoa_optimal_knots", "sph_hoa_knot_table", "sph_hoa_lut_coefficients",
@@ -98,6 +99,7 @@ def lib():
     L.sph_hoa_build_index.argtypes = [vp, vp, vp, i64, ctypes.c_int, ctypes.POINTER(Params), vp, ctypes.POINTER(vp)]
     L.sph_hoa_approx_rays.argtypes = [vp, ctypes.POINTER(Rays), ctypes.POINTER(Field), u32, vp]
     L.sph_hoa_render.argtypes = [vp, ctypes.POINTER(Camera), ctypes.POINTER(TF), vp, vp]
+    L.sph_hoa_render_batch.argtypes = [vp, ctypes.POINTER(Camera), i32, ctypes.POINTER(TF), vp, vp]
     L.sph_hoa_index_free.argtypes = [vp]
     L.sph_hoa_index_get_info.argtypes = [vp, ctypes.POINTER(IndexInfo)]
     L.sph_hoa_index_get_lut.argtypes = [vp, vp, vp, vp]
@@ -308,6 +310,29 @@ def sph_hoa_render(index, camera: dict, tf_rgba, v_min, v_max, step, out=None):
     t = TF(_ptr(tf).value, tf.shape[0], v_min, v_max, step)
     _check(lib().sph_hoa_render(index.handle, ctypes.byref(c), ctypes.byref(t), _ptr(out), _stream()))
     return out
+
+
+def sph_hoa_render_batch(index, cameras, tf_rgba, v_min, v_max, step, out=None):
+    """Render a batch of cameras in one launch chain (sph_hoa_render_batch).  Returns the flat
+    float32 device tensor of all images (camera order) and the list of [height, width, 4] views."""
+    import torch
+
+    cs = (Camera * max(1, len(cameras)))()
+    sizes = []
+    for i, cam in enumerate(cameras):
+        cs[i] = make_camera(cam)
+        sizes.append((cs[i].height, cs[i].width))
+    n = sum(h * w for h, w in sizes)
+    tf = _dev_f32(tf_rgba).reshape(-1, 4)
+    if out is None:
+        out = torch.empty((max(1, n), 4), dtype=torch.float32, device="cuda")
+    t = TF(_ptr(tf).value, tf.shape[0], v_min, v_max, step)
+    _check(lib().sph_hoa_render_batch(index.handle, cs, len(cameras), ctypes.byref(t), _ptr(out), _stream()))
+    views, o = [], 0
+    for h, w in sizes:
+        views.append(out[o:o + h * w].view(h, w, 4))
+        o += h * w
+    return out, views
 
 
 def sph_hoa_optimal_knots(kernel, pieces, degree, lam):

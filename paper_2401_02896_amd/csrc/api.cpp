@@ -216,40 +216,73 @@ sph_hoa_status sph_hoa_approx_rays(sph_hoa_index idx, const sph_hoa_rays* rays, 
   });
 }
 
+namespace {
+
+void check_camera(const sph::Index& ix, const sph_hoa_camera* cam, const sph_hoa_tf* tf) {
+  require(cam->width > 0 && cam->height > 0 && (int64_t)cam->width * cam->height < (int64_t(1) << 31),
+          "bad image size");
+  require(std::isfinite(cam->t_min) && std::isfinite(cam->t_max) && cam->t_min < cam->t_max,
+          "need finite t_min < t_max");
+  for (int k = 0; k < 3; ++k)
+    require(std::isfinite(cam->eye[k]) && std::isfinite(cam->look_at[k]) && std::isfinite(cam->up[k]),
+            "camera vectors must be finite");
+  if (cam->ortho)
+    require(std::isfinite(cam->ortho_half_extent) && cam->ortho_half_extent > 0, "ortho_half_extent must be > 0");
+  else
+    require(cam->fov_y_deg > 0 && cam->fov_y_deg < 180, "fov_y_deg must be in (0, 180)");
+  const double fx = (double)cam->look_at[0] - cam->eye[0], fy = (double)cam->look_at[1] - cam->eye[1],
+               fz = (double)cam->look_at[2] - cam->eye[2];
+  const double cx = fy * cam->up[2] - fz * cam->up[1], cy = fz * cam->up[0] - fx * cam->up[2],
+               cz = fx * cam->up[1] - fy * cam->up[0];
+  require(fx * fx + fy * fy + fz * fz > 0 && cx * cx + cy * cy + cz * cz > 0, "degenerate camera frame");
+  require(((double)cam->t_max - (double)cam->t_min) / (double)tf->step < 1073741824.0,
+          "step too small: more than 2^30 samples per ray");
+  const double span = std::max(std::fabs((double)cam->t_min), std::fabs((double)cam->t_max)) +
+                      ix.grid.lv[ix.grid.n_levels - 1].c;
+  if (!(span / ix.tau < 2.1e9))
+    throw sph::Error(SPH_HOA_E_OVERFLOW, "ray segment too long for int32 positions (|t| + q h_max >= 2^31 tau)");
+}
+
+void check_tf(const sph_hoa_tf* tf) {
+  require(tf->rgba && tf->n >= 2, "transfer function needs >= 2 control points");
+  require(std::isfinite(tf->v_min) && std::isfinite(tf->v_max) && tf->v_max > tf->v_min, "need v_min < v_max");
+  require(std::isfinite(tf->step) && tf->step > 0, "step must be > 0");
+}
+
+}  // namespace
+
 sph_hoa_status sph_hoa_render(sph_hoa_index idx, const sph_hoa_camera* cam, const sph_hoa_tf* tf, float* rgba_out,
                               void* stream) {
   return guarded([&]() {
     require(idx && cam && tf && rgba_out, "NULL argument");
-    require(cam->width > 0 && cam->height > 0 && (int64_t)cam->width * cam->height < (int64_t(1) << 31),
-            "bad image size");
-    require(std::isfinite(cam->t_min) && std::isfinite(cam->t_max) && cam->t_min < cam->t_max,
-            "need finite t_min < t_max");
-    for (int k = 0; k < 3; ++k)
-      require(std::isfinite(cam->eye[k]) && std::isfinite(cam->look_at[k]) && std::isfinite(cam->up[k]),
-              "camera vectors must be finite");
-    if (cam->ortho)
-      require(std::isfinite(cam->ortho_half_extent) && cam->ortho_half_extent > 0, "ortho_half_extent must be > 0");
-    else
-      require(cam->fov_y_deg > 0 && cam->fov_y_deg < 180, "fov_y_deg must be in (0, 180)");
-    const double fx = (double)cam->look_at[0] - cam->eye[0], fy = (double)cam->look_at[1] - cam->eye[1],
-                 fz = (double)cam->look_at[2] - cam->eye[2];
-    const double cx = fy * cam->up[2] - fz * cam->up[1], cy = fz * cam->up[0] - fx * cam->up[2],
-                 cz = fx * cam->up[1] - fy * cam->up[0];
-    require(fx * fx + fy * fy + fz * fz > 0 && cx * cx + cy * cy + cz * cz > 0, "degenerate camera frame");
-    require(tf->rgba && tf->n >= 2, "transfer function needs >= 2 control points");
-    require(std::isfinite(tf->v_min) && std::isfinite(tf->v_max) && tf->v_max > tf->v_min, "need v_min < v_max");
-    require(std::isfinite(tf->step) && tf->step > 0, "step must be > 0");
-    require(((double)cam->t_max - (double)cam->t_min) / (double)tf->step < 1073741824.0,
-            "step too small: more than 2^30 samples per ray");
     sph::Index& ix = idx->ix;
-    const double span = std::max(std::fabs((double)cam->t_min), std::fabs((double)cam->t_max)) +
-                        ix.grid.lv[ix.grid.n_levels - 1].c;
-    if (!(span / ix.tau < 2.1e9))
-      throw sph::Error(SPH_HOA_E_OVERFLOW, "ray segment too long for int32 positions (|t| + q h_max >= 2^31 tau)");
+    check_tf(tf);
+    check_camera(ix, cam, tf);
     hipStream_t st = (hipStream_t)stream;
     ix.last_stream = st;
     sph::FieldOut fo{nullptr, rgba_out, tf, false};
     sph::run_rays(ix, (int64_t)cam->width * cam->height, true, cam, nullptr, fo, st);
+  });
+}
+
+sph_hoa_status sph_hoa_render_batch(sph_hoa_index idx, const sph_hoa_camera* cams, int32_t n_cams,
+                                    const sph_hoa_tf* tf, float* rgba_out, void* stream) {
+  return guarded([&]() {
+    require(idx && tf && (n_cams == 0 || (cams && rgba_out)), "NULL argument");
+    require(n_cams >= 0 && n_cams <= (1 << 20), "n_cams must be in [0, 2^20]");
+    sph::Index& ix = idx->ix;
+    check_tf(tf);
+    int64_t n = 0;
+    for (int32_t c = 0; c < n_cams; ++c) {
+      check_camera(ix, &cams[c], tf);
+      n += (int64_t)cams[c].width * cams[c].height;
+    }
+    require(n < (int64_t(1) << 32), "more than 2^32 rays in one batch");
+    hipStream_t st = (hipStream_t)stream;
+    ix.last_stream = st;
+    if (n == 0) return;
+    sph::FieldOut fo{nullptr, rgba_out, tf, false};
+    sph::run_rays(ix, n, false, nullptr, nullptr, fo, st, cams, n_cams);
   });
 }
 

@@ -115,6 +115,9 @@ struct Index {
   DevBuf slab;                  // per-work-group node / heavy-ray storage
   DevBuf ray_meta;              // per-ray outputs of the field kernel
   DevBuf out_stage, exact_stage;
+  DevBuf cams_dev, ray_tr;          // camera batches: frames, ray offsets, per-ray segments
+  DevBuf order_keys, order;         // processing order of arbitrary rays and batches
+  DevBuf sort_hist, sort_offs;
   sph_hoa_stats stats{};
   bool render_stats_pending = false;  // placement counters of the last render not read back yet
   hipStream_t last_stream = nullptr;
@@ -142,10 +145,14 @@ struct FieldOut {
   const sph_hoa_tf* tf;
   bool exact;
 };
+// n_batch > 0: render the cameras batch[0..n_batch) together (rays concatenated in camera order)
 void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam, const sph_hoa_rays* rays,
-              FieldOut& out, hipStream_t st);
+              FieldOut& out, hipStream_t st, const sph_hoa_camera* batch = nullptr, int n_batch = 0);
 
 // small device utilities (util.hip)
 void device_exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, DevBuf& tmp, hipStream_t st);
+// device radix sort of n uint64 keys by their low `bits` bits (index.hip); true if the result is in alt
+bool device_sort_u64(uint64_t* keys, uint64_t* alt, int64_t n, int bits, DevBuf& hist, DevBuf& offs, DevBuf& tmp,
+                     hipStream_t st);
 
 }  // namespace sph

@@ -319,6 +319,11 @@ unsigned grid_for(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<in
 
 }  // namespace
 
+bool device_sort_u64(uint64_t* keys, uint64_t* alt, int64_t n, int bits, DevBuf& hist, DevBuf& offs, DevBuf& tmp,
+                     hipStream_t st) {
+  return radix_sort<uint64_t>(keys, nullptr, alt, nullptr, n, bits, hist, offs, tmp, st);
+}
+
 void build_index_device(Index& ix, const float* xyz, const float* h, const float* value, hipStream_t st) {
   const int64_t n = ix.n;
   DevBuf small;

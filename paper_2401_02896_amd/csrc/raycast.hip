@@ -28,30 +28,66 @@ struct CamDev {
   double eye[3], f[3], r[3], u[3];
   double g, aspect, half;  // tan(fov/2), W/H, ortho half extent
   int W, H, ortho;
+  float t_min, t_max;
 };
 
-__global__ void k_camera_rays(CamDev c, int64_t n, double* o, double* v) {
-  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
-    const double col = (double)(p % c.W), row = (double)(p / c.W);
-    const double a = (2.0 * col + 1.0) / (double)c.W - 1.0;
-    const double b = 1.0 - (2.0 * row + 1.0) / (double)c.H;
-    if (c.ortho) {
-      const double sa = a * c.half * c.aspect, sb = b * c.half;
-      for (int k = 0; k < 3; ++k) {
-        o[3 * p + k] = c.eye[k] + sa * c.r[k] + sb * c.u[k];
-        v[3 * p + k] = c.f[k];
-      }
-    } else {
-      const double sa = a * c.g * c.aspect, sb = b * c.g;
-      const double dx = c.f[0] + sa * c.r[0] + sb * c.u[0];
-      const double dy = c.f[1] + sa * c.r[1] + sb * c.u[1];
-      const double dz = c.f[2] + sa * c.r[2] + sb * c.u[2];
-      const double nrm = sqrt(dx * dx + dy * dy + dz * dz);
-      v[3 * p] = dx / nrm;
-      v[3 * p + 1] = dy / nrm;
-      v[3 * p + 2] = dz / nrm;
-      for (int k = 0; k < 3; ++k) o[3 * p + k] = c.eye[k];
+// Ray of pixel p (row-major, row 0 at the top) through the pixel centre.
+__device__ __forceinline__ void camera_ray(const CamDev& c, int64_t p, double* o, double* v) {
+  const double col = (double)(p % c.W), row = (double)(p / c.W);
+  const double a = (2.0 * col + 1.0) / (double)c.W - 1.0;
+  const double b = 1.0 - (2.0 * row + 1.0) / (double)c.H;
+  if (c.ortho) {
+    const double sa = a * c.half * c.aspect, sb = b * c.half;
+    for (int k = 0; k < 3; ++k) {
+      o[k] = c.eye[k] + sa * c.r[k] + sb * c.u[k];
+      v[k] = c.f[k];
     }
+  } else {
+    const double sa = a * c.g * c.aspect, sb = b * c.g;
+    const double dx = c.f[0] + sa * c.r[0] + sb * c.u[0];
+    const double dy = c.f[1] + sa * c.r[1] + sb * c.u[1];
+    const double dz = c.f[2] + sa * c.r[2] + sb * c.u[2];
+    const double nrm = sqrt(dx * dx + dy * dy + dz * dz);
+    v[0] = dx / nrm;
+    v[1] = dy / nrm;
+    v[2] = dz / nrm;
+    for (int k = 0; k < 3; ++k) o[k] = c.eye[k];
+  }
+}
+
+__global__ void k_camera_rays(CamDev c, int64_t n, double* o, double* v) {
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x)
+    camera_ray(c, p, o + 3 * p, v + 3 * p);
+}
+
+// Rays of a batch of cameras, concatenated in camera order (offs: first ray of each camera, n_cams + 1
+// entries), with each ray's own segment [t_min, t_max] in tr.
+__global__ void k_camera_rays_batch(const CamDev* cams, const int64_t* offs, int n_cams, int64_t n, double* o,
+                                    double* v, float* tr) {
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
+    int lo = 0, hi = n_cams - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (offs[mid] <= p) lo = mid;
+      else hi = mid - 1;
+    }
+    const CamDev& c = cams[lo];
+    camera_ray(c, p - offs[lo], o + 3 * p, v + 3 * p);
+    tr[2 * p] = c.t_min;
+    tr[2 * p + 1] = c.t_max;
+  }
+}
+
+__global__ void k_low32(const uint64_t* keys, int64_t n, uint32_t* out) {
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x)
+    out[p] = (uint32_t)keys[p];
+}
+
+// Longest rays first: key = (2^32 - 1 - hits) << 32 | ray, sorted ascending.
+__global__ void k_order_keys(const int64_t* count, int64_t n, uint64_t* keys) {
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t c = (uint64_t)min(count[p], (int64_t)0xffffffff);
+    keys[p] = ((0xffffffffull - c) << 32) | (uint64_t)p;
   }
 }
 
@@ -79,6 +115,7 @@ struct GatherArgs {
   const double* v;
   int64_t n_rays;
   double t_min, t_max;
+  const float* tr;      // optional per-ray [t_min, t_max] (batches); else the scalars above
   const float4* pos4;
   const uint32_t* cbeg;
   const uint32_t* cend;
@@ -117,6 +154,7 @@ __global__ void __launch_bounds__(kGatherThreads) k_gather(GatherArgs A) {
     o[k] = A.o[3 * r + k];
     v[k] = A.v[3 * r + k];
   }
+  const double t_min = A.tr ? (double)A.tr[2 * r] : A.t_min, t_max = A.tr ? (double)A.tr[2 * r + 1] : A.t_max;
   int64_t* ex = s_excl + w * 64;
   uint32_t* bg = s_beg + w * 64;
   int64_t found = 0;
@@ -131,7 +169,7 @@ __global__ void __launch_bounds__(kGatherThreads) k_gather(GatherArgs A) {
     if (L.n_particles == 0) continue;
     const double c = L.c, ic = L.inv_c, eps = c * 1e-7;
     // clip the segment to the box in which it can reach this level's particles
-    double ta = A.t_min, tb = A.t_max;
+    double ta = t_min, tb = t_max;
     bool empty = false;
     for (int a = 0; a < 3; ++a) {
       const double bmin = A.g.lo[a] - c - eps, bmax = A.g.lo[a] + (double)(L.n[a] + 1) * c + eps;
@@ -214,7 +252,7 @@ __global__ void __launch_bounds__(kGatherThreads) k_gather(GatherArgs A) {
             else hi = mid - 1;
           }
           j = bg[lo] + (uint32_t)(ci - ex[lo]);
-          hit = pair_hit(o, v, A.pos4[j], A.t_min, A.t_max);
+          hit = pair_hit(o, v, A.pos4[j], t_min, t_max);
         }
         const uint64_t m = __ballot(hit);
         if (FILL && hit) {
@@ -395,6 +433,8 @@ struct FieldArgs {
   const double* v;
   int64_t n_rays;
   double t_min, t_max;
+  const float* tr;         // optional per-ray [t_min, t_max] (batches)
+  const uint32_t* order;   // optional processing order of the rays (longest first)
   // hits
   const int64_t* hit_count;
   const int64_t* hit_off;
@@ -1174,9 +1214,10 @@ __device__ void process_ray(const FieldArgs& A, Shared<D>& sh, const RayStore& S
     // first sample numbers.
     const float vmin = A.tf_vmin, vr = A.tf_vmax - A.tf_vmin;
     const int ntf = A.tf_n;
+    const double ray_tmin = A.tr ? (double)A.tr[2 * r] : A.t_min, ray_tmax = A.tr ? (double)A.tr[2 * r + 1] : A.t_max;
     auto sample_count = [&](const Node<D>& nd) -> int64_t {
       const double ta = (double)nd.a * tau, tb = (double)nd.b * tau;
-      const double a = fmax(ta, A.t_min), b = fmin(tb, A.t_max);
+      const double a = fmax(ta, ray_tmin), b = fmin(tb, ray_tmax);
       return (b > a) ? (int64_t)fmax(1.0, ceil((b - a) / A.tf_step)) : 0;
     };
     int64_t my_samples = 0;
@@ -1221,7 +1262,7 @@ __device__ void process_ray(const FieldArgs& A, Shared<D>& sh, const RayStore& S
       for (int64_t n = lo; g < g1; ++n) {
         const Node<D>& nd = nodes[iref[n]];
         const double ta = (double)nd.a * tau, tb = (double)nd.b * tau;
-        const double a = fmax(ta, A.t_min), b = fmin(tb, A.t_max);
+        const double a = fmax(ta, ray_tmin), b = fmin(tb, ray_tmax);
         if (!(b > a)) continue;
         const double Sd = fmax(1.0, ceil((b - a) / A.tf_step));
         const int64_t S_n = (int64_t)Sd;
@@ -1296,7 +1337,10 @@ __global__ void __launch_bounds__(kFieldThreads, kFieldWgPerCu) k_field(FieldArg
   uint64_t* gscratch = (uint64_t*)(slab + A.slab_scratch);
   char* gstore = slab + A.slab_store;
   for (;;) {
-    if (threadIdx.x == 0) sh.ray = (int64_t)atomicAdd(A.queue, 1u);
+    if (threadIdx.x == 0) {
+      const int64_t q = (int64_t)atomicAdd(A.queue, 1u);
+      sh.ray = (q < A.n_rays && A.order) ? (int64_t)A.order[q] : q;
+    }
     __syncthreads();
     const int64_t r = sh.ray;
     if (r >= A.n_rays) break;
@@ -1484,6 +1528,45 @@ unsigned blocks_for(int64_t n, int t) {
 
 }  // namespace
 
+// Camera frame of an sph_hoa_camera (float inputs widened to float64).
+CamDev make_cam(const sph_hoa_camera* cam) {
+  CamDev c{};
+  double e[3], la[3], up[3];
+  for (int k = 0; k < 3; ++k) {
+    e[k] = (double)cam->eye[k];
+    la[k] = (double)cam->look_at[k];
+    up[k] = (double)cam->up[k];
+  }
+  auto norm3 = [](double& x, double& y, double& z) {
+    const double nn = std::sqrt(x * x + y * y + z * z);
+    x = x / nn;
+    y = y / nn;
+    z = z / nn;
+  };
+  double fx = la[0] - e[0], fy = la[1] - e[1], fz = la[2] - e[2];
+  norm3(fx, fy, fz);
+  double rx = fy * up[2] - fz * up[1], ry = fz * up[0] - fx * up[2], rz = fx * up[1] - fy * up[0];
+  norm3(rx, ry, rz);
+  const double ux = ry * fz - rz * fy, uy = rz * fx - rx * fz, uz = rx * fy - ry * fx;
+  const double f[3] = {fx, fy, fz}, rr[3] = {rx, ry, rz}, uu[3] = {ux, uy, uz};
+  for (int k = 0; k < 3; ++k) {
+    c.eye[k] = e[k];
+    c.f[k] = f[k];
+    c.r[k] = rr[k];
+    c.u[k] = uu[k];
+  }
+  const double fov = (double)cam->fov_y_deg;
+  c.g = std::tan(fov * 3.14159265358979323846 / 180.0 / 2.0);
+  c.aspect = (double)cam->width / (double)cam->height;
+  c.half = (double)cam->ortho_half_extent;
+  c.W = cam->width;
+  c.H = cam->height;
+  c.ortho = cam->ortho;
+  c.t_min = cam->t_min;
+  c.t_max = cam->t_max;
+  return c;
+}
+
 void Index::collect_timing() {
   if (!timing_pending) return;
   timing_pending = false;
@@ -1498,7 +1581,7 @@ void Index::collect_timing() {
 }
 
 void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam, const sph_hoa_rays* rays,
-              FieldOut& out, hipStream_t st) {
+              FieldOut& out, hipStream_t st, const sph_hoa_camera* batch, int n_batch) {
   const int D = ix.D, K = ix.K, P = ix.P;
   ix.collect_timing();
   ix.render_stats_pending = false;
@@ -1513,42 +1596,31 @@ void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam,
   if (n_rays == 0) return;
   ix.rays_o.ensure(sizeof(double) * 3 * n_rays);
   ix.rays_v.ensure(sizeof(double) * 3 * n_rays);
-  double t_min, t_max;
+  double t_min = 0.0, t_max = 0.0;
   CamDev cam_dev{};
-  if (camera) {
-    CamDev& c = cam_dev;
-    double e[3], la[3], up[3];
-    for (int k = 0; k < 3; ++k) {
-      e[k] = (double)cam->eye[k];
-      la[k] = (double)cam->look_at[k];
-      up[k] = (double)cam->up[k];
+  const float* ray_tr = nullptr;
+  if (n_batch > 0) {
+    // batch of cameras: all rays generated and processed together, each with its camera's segment
+    std::vector<CamDev> cd((size_t)n_batch);
+    std::vector<int64_t> offs((size_t)n_batch + 1, 0);
+    for (int c = 0; c < n_batch; ++c) {
+      cd[c] = make_cam(&batch[c]);
+      offs[c + 1] = offs[c] + (int64_t)batch[c].width * batch[c].height;
     }
-    auto norm3 = [](double& x, double& y, double& z) {
-      const double nn = std::sqrt(x * x + y * y + z * z);
-      x = x / nn;
-      y = y / nn;
-      z = z / nn;
-    };
-    double fx = la[0] - e[0], fy = la[1] - e[1], fz = la[2] - e[2];
-    norm3(fx, fy, fz);
-    double rx = fy * up[2] - fz * up[1], ry = fz * up[0] - fx * up[2], rz = fx * up[1] - fy * up[0];
-    norm3(rx, ry, rz);
-    const double ux = ry * fz - rz * fy, uy = rz * fx - rx * fz, uz = rx * fy - ry * fx;
-    const double f[3] = {fx, fy, fz}, rr[3] = {rx, ry, rz}, uu[3] = {ux, uy, uz};
-    for (int k = 0; k < 3; ++k) {
-      c.eye[k] = e[k];
-      c.f[k] = f[k];
-      c.r[k] = rr[k];
-      c.u[k] = uu[k];
-    }
-    const double fov = (double)cam->fov_y_deg;
-    c.g = std::tan(fov * 3.14159265358979323846 / 180.0 / 2.0);
-    c.aspect = (double)cam->width / (double)cam->height;
-    c.half = (double)cam->ortho_half_extent;
-    c.W = cam->width;
-    c.H = cam->height;
-    c.ortho = cam->ortho;
-    k_camera_rays<<<blocks_for(n_rays, 256), 256, 0, st>>>(c, n_rays, ix.rays_o.as<double>(), ix.rays_v.as<double>());
+    ix.cams_dev.ensure(sizeof(CamDev) * n_batch + sizeof(int64_t) * (n_batch + 1));
+    CamDev* cdev = ix.cams_dev.as<CamDev>();
+    int64_t* odev = reinterpret_cast<int64_t*>(cdev + n_batch);
+    hip_check(hipMemcpyAsync(cdev, cd.data(), sizeof(CamDev) * n_batch, hipMemcpyHostToDevice, st), "copy");
+    hip_check(hipMemcpyAsync(odev, offs.data(), sizeof(int64_t) * (n_batch + 1), hipMemcpyHostToDevice, st), "copy");
+    ix.ray_tr.ensure(sizeof(float) * 2 * n_rays);
+    k_camera_rays_batch<<<blocks_for(n_rays, 256), 256, 0, st>>>(cdev, odev, n_batch, n_rays, ix.rays_o.as<double>(),
+                                                                 ix.rays_v.as<double>(), ix.ray_tr.as<float>());
+    ray_tr = ix.ray_tr.as<float>();
+    // staged host copies must outlive the asynchronous copies
+    hip_check(hipStreamSynchronize(st), "sync");
+  } else if (camera) {
+    cam_dev = make_cam(cam);
+    k_camera_rays<<<blocks_for(n_rays, 256), 256, 0, st>>>(cam_dev, n_rays, ix.rays_o.as<double>(), ix.rays_v.as<double>());
     t_min = (double)cam->t_min;
     t_max = (double)cam->t_max;
   } else {
@@ -1574,11 +1646,12 @@ void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam,
   G.count = ix.hit_count.as<int64_t>();
   G.max_hits = max_hits;
   G.flags = flags;
+  G.tr = ray_tr;
   const unsigned gblocks = (unsigned)((n_rays + 3) / 4);
   BinArgs B{};
   TileHitArgs TH{};
   int64_t n_tiles = 0;
-  if (camera) {
+  if (camera && n_batch == 0) {
     // bin particles into screen tiles, then count hits per pixel ray from the tile lists
     B.pos4 = ix.pos4.as<float4>();
     B.n = ix.n;
@@ -1649,7 +1722,7 @@ void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam,
   G.off = ix.hit_off.as<int64_t>();
   G.hits = ix.hits.as<uint32_t>();
   if (ix.timing) hip_check(hipEventRecord(ix.ev[2], st), "event");
-  if (camera) {
+  if (camera && n_batch == 0) {
     TH.off = G.off;
     TH.hits = G.hits;
     k_tile_hits<true><<<(unsigned)n_tiles, 64, 0, st>>>(TH);
@@ -1665,6 +1738,20 @@ void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam,
   A.n_rays = n_rays;
   A.t_min = t_min;
   A.t_max = t_max;
+  A.tr = ray_tr;
+  A.order = nullptr;
+  if (n_batch > 0 || !camera) {
+    // arbitrary rays and batches can be heavy-tailed: process the longest rays first so that the
+    // persistent work-groups finish together
+    ix.order_keys.ensure(sizeof(uint64_t) * 2 * n_rays);
+    uint64_t* k0 = ix.order_keys.as<uint64_t>();
+    uint64_t* k1 = k0 + n_rays;
+    k_order_keys<<<blocks_for(n_rays, 256), 256, 0, st>>>(ix.hit_count.as<int64_t>(), n_rays, k0);
+    const bool alt = device_sort_u64(k0, k1, n_rays, 64, ix.sort_hist, ix.sort_offs, ix.scan_tmp, st);
+    ix.order.ensure(sizeof(uint32_t) * n_rays);
+    k_low32<<<blocks_for(n_rays, 256), 256, 0, st>>>(alt ? k1 : k0, n_rays, ix.order.as<uint32_t>());
+    A.order = ix.order.as<uint32_t>();
+  }
   A.hit_count = ix.hit_count.as<int64_t>();
   A.hit_off = ix.hit_off.as<int64_t>();
   A.hits = ix.hits.as<uint32_t>();

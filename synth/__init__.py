@@ -69,6 +69,35 @@ def clustered_particles(seed: int = 2, n: int = 1_000_000, clusters: int = 16, b
     return xyz, h, val
 
 
+def cluster_centres(seed: int = 2, clusters: int = 16):
+    """The Gaussian centres clustered_particles(seed, ..., clusters) draws first."""
+    return np.random.default_rng(seed).uniform(0.2, 0.8, (clusters, 3))
+
+
+def batch_cameras(seed: int = 4, n: int = 256, centres=None, core_fraction: float = 0.5):
+    """Ray bundles of the batching workload: square images of side 2^k, k uniform in 5..9
+    (32..512, log-uniform), eyes uniform on the sphere of radius 2 about the cube centre, t in
+    [1, 3].  A fraction of the bundles look at a cluster centre with a narrow field of view, so
+    their rays run through the dense cores (the heavy tail of hits per ray); the others see the
+    whole cube."""
+    rng = np.random.default_rng(seed)
+    cams = []
+    for _ in range(n):
+        side = int(2 ** int(rng.integers(5, 10)))
+        d = rng.standard_normal(3)
+        d /= np.linalg.norm(d)
+        eye = 0.5 + 2.0 * d
+        core = centres is not None and rng.random() < core_fraction
+        target = centres[int(rng.integers(len(centres)))] if core else np.array([0.5, 0.5, 0.5])
+        fwd = target - eye
+        fwd /= np.linalg.norm(fwd)
+        up = [0.0, 1.0, 0.0] if abs(fwd[1]) < 0.9 else [1.0, 0.0, 0.0]
+        cams.append({"eye": [float(x) for x in eye], "look_at": [float(x) for x in target], "up": up,
+                     "fov_y_deg": 6.0 if core else 30.0, "ortho": 0, "ortho_half_extent": 0.0,
+                     "width": side, "height": side, "t_min": 1.0, "t_max": 3.0})
+    return cams
+
+
 def plain_camera(width: int = 512, height: int = 512):
     return {"eye": [0.5, 0.5, -1.5], "look_at": [0.5, 0.5, 0.5], "up": [0.0, 1.0, 0.0], "fov_y_deg": 30.0,
             "ortho": 0, "ortho_half_extent": 0.0, "width": width, "height": height, "t_min": 1.0, "t_max": 3.0}

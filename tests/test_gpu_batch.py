@@ -1,0 +1,95 @@
+"""Batched rendering (sph_hoa_render_batch): many cameras in one launch chain.
+
+Each image of a batch must equal, bit for bit, the image sph_hoa_render gives for that camera
+alone: the hit sets are the same exact float64 tests, the field and merge do not depend on the
+order of hits or on where a ray's layout is placed, and the compositing arithmetic is per ray.
+Sampled pixels are also checked against the oracle (1e-4 RGBA).
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import geometry
+from tests import gpu_helpers as H
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - only on the GPU machine
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_2401_02896_amd as L  # noqa: E402
+
+
+def _tiny_cams():
+    base = synth.tiny_camera()
+    cams = [dict(base, width=16, height=16), dict(base, width=48, height=24),
+            dict(base, width=7, height=5), synth.tiny_camera(64, 64)]
+    persp = {"eye": [0.5, 0.5, -1.0], "look_at": [0.5, 0.5, 0.5], "up": [0.0, 1.0, 0.0], "fov_y_deg": 40.0,
+             "ortho": 0, "ortho_half_extent": 0.0, "width": 40, "height": 32, "t_min": 0.5, "t_max": 2.5}
+    cams.append(persp)
+    # a narrow bundle through the middle of the cube (long rays next to short ones)
+    cams.append(dict(persp, fov_y_deg=3.0, width=8, height=8))
+    cams.append(dict(base, eye=[-0.2, 0.5, 0.5], look_at=[1.0, 0.5, 0.5], width=20, height=20))
+    return cams
+
+
+def test_batch_images_equal_single_renders():
+    sc = H.tiny_scene()
+    tf = synth.transfer_function()
+    vmax, step = 4.0e4, 1.4 / 256
+    cams = _tiny_cams()
+    flat, imgs = L.sph_hoa_render_batch(sc.index(), cams, tf, 0.0, vmax, step)
+    torch.cuda.synchronize()
+    assert flat.shape[0] == sum(c["width"] * c["height"] for c in cams)
+    for cam, img in zip(cams, imgs):
+        ref = L.sph_hoa_render(sc.index(), cam, tf, 0.0, vmax, step)
+        assert torch.equal(img, ref), cam
+
+
+def test_batch_pixels_match_oracle():
+    sc = H.tiny_scene()
+    tf = synth.transfer_function()
+    vmax, step = 4.0e4, 1.4 / 256
+    cams = _tiny_cams()
+    _, imgs = L.sph_hoa_render_batch(sc.index(), cams, tf, 0.0, vmax, step)
+    rng = np.random.default_rng(9)
+    checked = 0
+    for cam, img in zip(cams, imgs):
+        im = img.cpu().numpy().reshape(-1, 4)
+        oo, vv = geometry.camera_rays(cam)
+        for r in rng.integers(0, cam["width"] * cam["height"], 4):
+            f = sc.oracle_ray(oo[r], vv[r], cam["t_min"], cam["t_max"])
+            if f["margin"] <= 1e-6:
+                continue
+            px = H.oracle_pixel(sc, f, cam["t_min"], cam["t_max"], tf.astype(np.float64), 0.0, vmax, step)
+            assert np.max(np.abs(im[r] - px)) <= 1e-4, (cam, int(r), im[r], px)
+            checked += 1
+    assert checked >= 20
+
+
+def test_empty_batch_and_errors():
+    sc = H.tiny_scene()
+    tf = synth.transfer_function()
+    flat, imgs = L.sph_hoa_render_batch(sc.index(), [], tf, 0.0, 1.0, 0.01)
+    assert imgs == []
+    bad = dict(synth.tiny_camera(), t_min=2.0, t_max=1.0)
+    with pytest.raises(L.SphHoaError):
+        L.sph_hoa_render_batch(sc.index(), [synth.tiny_camera(8, 8), bad], tf, 0.0, 1.0, 0.01)
+
+
+def test_heavy_tailed_batch_equals_single_renders():
+    """Clustered particles, bundles aimed through cluster cores next to wide views (hits per ray
+    from 0 to the thousands), scheduled longest first."""
+    xyz, h, val = synth.clustered_particles(seed=5, n=200_000)
+    idx = L.sph_hoa_build_index(xyz, h, val, kernel=L.KERNEL_WENDLAND_C2, degree=3, pieces=4, merge_tol=1e-3)
+    cams = synth.batch_cameras(seed=4, n=6, centres=synth.cluster_centres(seed=5))
+    cams = [dict(c, width=min(c["width"], 64), height=min(c["height"], 64)) for c in cams]
+    tf = synth.transfer_function()
+    _, imgs = L.sph_hoa_render_batch(idx, cams, tf, 0.0, 300.0, 2.0 / 512)
+    st = idx.stats()
+    assert st["max_hits"] > 500
+    for cam, img in zip(cams, imgs):
+        ref = L.sph_hoa_render(idx, cam, tf, 0.0, 300.0, 2.0 / 512)
+        assert torch.equal(img, ref), cam
+    idx.free()
