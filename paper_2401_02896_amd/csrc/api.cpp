@@ -333,6 +333,7 @@ sph_hoa_status sph_hoa_index_get_stats(sph_hoa_index idx, sph_hoa_stats* stats) 
     sph::Index& ix = idx->ix;
     if (ix.last_stream) sph::hip_check(hipStreamSynchronize(ix.last_stream), "sync");
     ix.collect_timing();
+    ix.tuner.collect();
     if (ix.render_stats_pending) {
       // a render does not wait for its kernels; its placement counters are read back here
       unsigned long long c[6];

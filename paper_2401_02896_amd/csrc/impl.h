@@ -6,6 +6,7 @@
 #include <cstdint>
 #include <stdexcept>
 #include <string>
+#include <map>
 #include <vector>
 
 #include "../../include/sph_hoa.h"
@@ -18,7 +19,6 @@ constexpr int kMaxD = 6;
 constexpr int kMaxP = 3;
 constexpr int kChunk = 16;          // knots per merge chunk
 constexpr int kFieldThreads = 256;  // threads per ray work-group
-constexpr int kFieldWgPerCu = 2;    // ray work-groups resident per CU
 constexpr int64_t kLdsPerCu = 160 * 1024;
 constexpr int64_t kMaxAxisCells = int64_t(1) << 19;
 constexpr int64_t kMaxLevel0Cells = int64_t(1) << 24;
@@ -89,6 +89,39 @@ struct MethodConsts {
   double tau, sigma, q, merge_tol;
 };
 
+// Online choice of the field kernel's work-groups per CU (1 or 2) per workload signature (degree,
+// mode, log2 of the mean and of the largest hits per ray): each candidate is timed once on a real
+// call (its output is identical), then the faster is kept.
+struct FieldTuner {
+  struct Key {
+    int D, render, mean_bucket, max_bucket;
+    bool operator<(const Key& o) const {
+      if (D != o.D) return D < o.D;
+      if (render != o.render) return render < o.render;
+      if (mean_bucket != o.mean_bucket) return mean_bucket < o.mean_bucket;
+      return max_bucket < o.max_bucket;
+    }
+  };
+  struct Entry {
+    double ms_per_pair[2] = {-1.0, -1.0};  // two work-groups per CU, one
+  };
+  std::map<Key, Entry> table;
+  bool pending = false;
+  Key pend_key{};
+  int pend_slot = 0;
+  int64_t pend_pairs = 0;
+  hipEvent_t ev[2] = {};
+  static Key key_of(int D, bool render, int64_t pairs, int64_t rays, int64_t max_hits);
+  int choose(const Key& k);
+  void begin(const Key& k, int wgs, int64_t pairs, hipStream_t st);
+  void end(hipStream_t st);
+  void collect();
+  FieldTuner() = default;
+  FieldTuner(const FieldTuner&) = delete;
+  FieldTuner& operator=(const FieldTuner&) = delete;
+  ~FieldTuner();
+};
+
 struct Index {
   int64_t n = 0;
   Kernel kernel = Kernel::Cubic;
@@ -119,6 +152,7 @@ struct Index {
   DevBuf order_keys, order;         // processing order of arbitrary rays and batches
   DevBuf sort_hist, sort_offs;
   sph_hoa_stats stats{};
+  FieldTuner tuner;
   bool render_stats_pending = false;  // placement counters of the last render not read back yet
   hipStream_t last_stream = nullptr;
   // optional event timing of the kernels (sph_hoa_index_set_timing)

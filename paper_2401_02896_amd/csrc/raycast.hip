@@ -55,12 +55,7 @@ __device__ __forceinline__ void camera_ray(const CamDev& c, int64_t p, double* o
   }
 }
 
-__global__ void k_camera_rays(CamDev c, int64_t n, double* o, double* v) {
-  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x)
-    camera_ray(c, p, o + 3 * p, v + 3 * p);
-}
-
-// Rays of a batch of cameras, concatenated in camera order (offs: first ray of each camera, n_cams + 1
+// Rays of one or more cameras, concatenated in camera order (offs: first ray of each camera, n_cams + 1
 // entries), with each ray's own segment [t_min, t_max] in tr.
 __global__ void k_camera_rays_batch(const CamDev* cams, const int64_t* offs, int n_cams, int64_t n, double* o,
                                     double* v, float* tr) {
@@ -283,18 +278,18 @@ constexpr int kTile = 8;
 struct BinArgs {
   const float4* pos4;
   int64_t n;
-  CamDev c;
-  int tiles_x, tiles_y;
-  double t_min, t_max;
+  const CamDev* cams;       // [n_cams]
+  const int64_t* tile_base; // [n_cams + 1] first tile of each camera in the concatenated tile index
+  int n_cams;
   unsigned int* tile_count;
   const int64_t* tile_off;
   unsigned int* tile_cursor;
   uint32_t* items;
 };
 
-// pixel range [c0, c1] x [r0, r1] covered by the projection of the particle's support sphere
-__device__ bool particle_pixels(const BinArgs& B, float4 p, int* c0, int* c1, int* r0, int* r1) {
-  const CamDev& c = B.c;
+// pixel range [c0, c1] x [r0, r1] of camera c covered by the projection of the particle's support sphere
+__device__ bool particle_pixels(const CamDev& c, float4 p, int* c0, int* c1, int* r0, int* r1) {
+  const double t_min = (double)c.t_min, t_max = (double)c.t_max;
   const double dx = (double)p.x - c.eye[0], dy = (double)p.y - c.eye[1], dz = (double)p.z - c.eye[2];
   const double z = dx * c.f[0] + dy * c.f[1] + dz * c.f[2];
   const double x = dx * c.r[0] + dy * c.r[1] + dz * c.r[2];
@@ -302,14 +297,14 @@ __device__ bool particle_pixels(const BinArgs& B, float4 p, int* c0, int* c1, in
   const double R = kSupport * (double)p.w * (1.0 + 1e-6) + 1e-12;
   double a0, a1, b0, b1;
   if (c.ortho) {
-    if (z + R < B.t_min || z - R > B.t_max) return false;
+    if (z + R < t_min || z - R > t_max) return false;
     a0 = (x - R) / (c.half * c.aspect);
     a1 = (x + R) / (c.half * c.aspect);
     b0 = (y - R) / c.half;
     b1 = (y + R) / c.half;
   } else {
     const double dist = sqrt(dx * dx + dy * dy + dz * dz);
-    if (dist - R >= B.t_max || dist + R <= B.t_min) return false;
+    if (dist - R >= t_max || dist + R <= t_min) return false;
     if (z <= R * 1.0001) {
       a0 = b0 = -1e30;
       a1 = b1 = 1e30;
@@ -337,17 +332,24 @@ __device__ bool particle_pixels(const BinArgs& B, float4 p, int* c0, int* c1, in
   return *c0 <= *c1 && *r0 <= *r1;
 }
 
+// (camera, particle) pairs, camera-major so that consecutive threads read consecutive particles
 template <bool FILL>
 __global__ void __launch_bounds__(256) k_bin(BinArgs B) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < B.n; i += (int64_t)gridDim.x * blockDim.x) {
+  const int64_t total = B.n * (int64_t)B.n_cams;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int cam = (int)(i / B.n);
+    const int64_t j = i - (int64_t)cam * B.n;
+    const CamDev& c = B.cams[cam];
     int c0, c1, r0, r1;
-    if (!particle_pixels(B, B.pos4[i], &c0, &c1, &r0, &r1)) continue;
+    if (!particle_pixels(c, B.pos4[j], &c0, &c1, &r0, &r1)) continue;
+    const int tiles_x = (c.W + kTile - 1) / kTile;
+    const int64_t tb = B.tile_base[cam];
     for (int ty = r0 / kTile; ty <= r1 / kTile; ++ty)
       for (int tx = c0 / kTile; tx <= c1 / kTile; ++tx) {
-        const int64_t t = (int64_t)ty * B.tiles_x + tx;
+        const int64_t t = tb + (int64_t)ty * tiles_x + tx;
         if (FILL) {
           const unsigned int k = atomicAdd(&B.tile_cursor[t], 1u);
-          B.items[B.tile_off[t] + k] = (uint32_t)i;
+          B.items[B.tile_off[t] + k] = (uint32_t)j;
         } else {
           atomicAdd(&B.tile_count[t], 1u);
         }
@@ -363,8 +365,10 @@ __global__ void k_u32_to_i64_n(const unsigned int* a, int64_t* b, int64_t n) {
 struct TileHitArgs {
   const double* o;
   const double* v;
-  int W, H, tiles_x;
-  double t_min, t_max;
+  const CamDev* cams;
+  const int64_t* tile_base;  // [n_cams + 1]
+  const int64_t* ray_base;   // [n_cams + 1] first ray of each camera
+  int n_cams;
   const float4* pos4;
   const int64_t* tile_off;
   const uint32_t* items;
@@ -379,11 +383,22 @@ template <bool FILL>
 __global__ void __launch_bounds__(64) k_tile_hits(TileHitArgs T) {
   __shared__ float4 cp[64];
   __shared__ uint32_t cj[64];
-  const int tile = blockIdx.x, lane = threadIdx.x;
-  const int tx = tile % T.tiles_x, ty = tile / T.tiles_x;
+  const int64_t tile = blockIdx.x;
+  const int lane = threadIdx.x;
+  int lo = 0, hi = T.n_cams - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (T.tile_base[mid] <= tile) lo = mid;
+    else hi = mid - 1;
+  }
+  const CamDev& c = T.cams[lo];
+  const double t_min = (double)c.t_min, t_max = (double)c.t_max;
+  const int64_t lt = tile - T.tile_base[lo];
+  const int tiles_x = (c.W + kTile - 1) / kTile;
+  const int tx = (int)(lt % tiles_x), ty = (int)(lt / tiles_x);
   const int col = tx * kTile + (lane % kTile), row = ty * kTile + (lane / kTile);
-  const bool valid = col < T.W && row < T.H;
-  const int64_t r = valid ? (int64_t)row * T.W + col : 0;
+  const bool valid = col < c.W && row < c.H;
+  const int64_t r = valid ? T.ray_base[lo] + (int64_t)row * c.W + col : 0;
   double o[3] = {0, 0, 0}, v[3] = {0, 0, 1};
   if (valid)
     for (int k = 0; k < 3; ++k) {
@@ -404,7 +419,7 @@ __global__ void __launch_bounds__(64) k_tile_hits(TileHitArgs T) {
     const int m = (int)min((int64_t)64, e - base);
     if (valid) {
       for (int q = 0; q < m; ++q) {
-        if (pair_hit(o, v, cp[q], T.t_min, T.t_max)) {
+        if (pair_hit(o, v, cp[q], t_min, t_max)) {
           if (FILL) T.hits[out0 + cnt] = cj[q];
           ++cnt;
         }
@@ -1327,8 +1342,10 @@ __device__ void process_ray(const FieldArgs& A, Shared<D>& sh, const RayStore& S
   }
 }
 
-template <int D, bool RENDER>
-__global__ void __launch_bounds__(kFieldThreads, kFieldWgPerCu) k_field(FieldArgs A) {
+// WGS: ray work-groups meant to share a CU (registers capped accordingly; the host sizes the
+// dynamic LDS to 1 / WGS of the CU)
+template <int D, bool RENDER, int WGS>
+__global__ void __launch_bounds__(kFieldThreads, WGS) k_field(FieldArgs A) {
   extern __shared__ __align__(16) char lds[];
   __shared__ Shared<D> sh;
   char* slab = A.slab + (int64_t)blockIdx.x * A.slab_stride;
@@ -1488,25 +1505,32 @@ size_t shared_static_bytes() {
   return sizeof(Shared<D>);
 }
 
-template <int D, bool RENDER>
+template <int D, bool RENDER, int WGS>
 void launch_field(FieldArgs& A, int grid, size_t lds, hipStream_t st) {
-  hip_check(hipFuncSetAttribute((const void*)k_field<D, RENDER>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds),
+  hip_check(hipFuncSetAttribute((const void*)k_field<D, RENDER, WGS>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)lds),
             "set lds");
-  k_field<D, RENDER><<<grid, kFieldThreads, lds, st>>>(A);
+  k_field<D, RENDER, WGS><<<grid, kFieldThreads, lds, st>>>(A);
   hip_check(hipGetLastError(), "field launch");
 }
 
-template <bool RENDER>
-void dispatch_field(int D, FieldArgs& A, int grid, size_t lds, hipStream_t st) {
+template <bool RENDER, int WGS>
+void dispatch_field_wgs(int D, FieldArgs& A, int grid, size_t lds, hipStream_t st) {
   switch (D) {
-    case 1: launch_field<1, RENDER>(A, grid, lds, st); break;
-    case 2: launch_field<2, RENDER>(A, grid, lds, st); break;
-    case 3: launch_field<3, RENDER>(A, grid, lds, st); break;
-    case 4: launch_field<4, RENDER>(A, grid, lds, st); break;
-    case 5: launch_field<5, RENDER>(A, grid, lds, st); break;
-    case 6: launch_field<6, RENDER>(A, grid, lds, st); break;
+    case 1: launch_field<1, RENDER, WGS>(A, grid, lds, st); break;
+    case 2: launch_field<2, RENDER, WGS>(A, grid, lds, st); break;
+    case 3: launch_field<3, RENDER, WGS>(A, grid, lds, st); break;
+    case 4: launch_field<4, RENDER, WGS>(A, grid, lds, st); break;
+    case 5: launch_field<5, RENDER, WGS>(A, grid, lds, st); break;
+    case 6: launch_field<6, RENDER, WGS>(A, grid, lds, st); break;
     default: throw Error(SPH_HOA_E_UNSUPPORTED, "degree");
   }
+}
+
+template <bool RENDER>
+void dispatch_field(int D, int wgs, FieldArgs& A, int grid, size_t lds, hipStream_t st) {
+  if (wgs == 1) dispatch_field_wgs<RENDER, 1>(D, A, grid, lds, st);
+  else dispatch_field_wgs<RENDER, 2>(D, A, grid, lds, st);
 }
 
 size_t node_bytes(int D) { return 8 + 8 * (size_t)(D + 3); }
@@ -1567,6 +1591,56 @@ CamDev make_cam(const sph_hoa_camera* cam) {
   return c;
 }
 
+FieldTuner::Key FieldTuner::key_of(int D, bool render, int64_t pairs, int64_t rays, int64_t max_hits) {
+  auto lg = [](int64_t x) {
+    int b = 0;
+    while (x > 1) {
+      x >>= 1;
+      ++b;
+    }
+    return b;
+  };
+  return Key{D, render ? 1 : 0, lg(1 + pairs / std::max<int64_t>(1, rays)), lg(1 + max_hits)};
+}
+
+int FieldTuner::choose(const Key& k) {
+  Entry& e = table[k];
+  if (e.ms_per_pair[0] < 0) return 2;  // measure two work-groups per CU first, then one
+  if (e.ms_per_pair[1] < 0) return 1;
+  return e.ms_per_pair[1] < e.ms_per_pair[0] ? 1 : 2;
+}
+
+void FieldTuner::begin(const Key& k, int wgs, int64_t pairs, hipStream_t st) {
+  Entry& e = table[k];
+  const int slot = wgs == 2 ? 0 : 1;
+  pending = (e.ms_per_pair[slot] < 0 && pairs > 0);
+  if (!pending) return;
+  for (auto& v : ev)
+    if (!v) hip_check(hipEventCreate(&v), "event");
+  pend_key = k;
+  pend_slot = slot;
+  pend_pairs = pairs;
+  hip_check(hipEventRecord(ev[0], st), "event");
+}
+
+void FieldTuner::end(hipStream_t st) {
+  if (pending) hip_check(hipEventRecord(ev[1], st), "event");
+}
+
+void FieldTuner::collect() {
+  if (!pending) return;
+  pending = false;
+  hip_check(hipEventSynchronize(ev[1]), "event sync");
+  float ms = 0.f;
+  hip_check(hipEventElapsedTime(&ms, ev[0], ev[1]), "elapsed");
+  table[pend_key].ms_per_pair[pend_slot] = (double)ms / (double)pend_pairs;
+}
+
+FieldTuner::~FieldTuner() {
+  for (auto& v : ev)
+    if (v) (void)hipEventDestroy(v);
+}
+
 void Index::collect_timing() {
   if (!timing_pending) return;
   timing_pending = false;
@@ -1584,6 +1658,7 @@ void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam,
               FieldOut& out, hipStream_t st, const sph_hoa_camera* batch, int n_batch) {
   const int D = ix.D, K = ix.K, P = ix.P;
   ix.collect_timing();
+  ix.tuner.collect();
   ix.render_stats_pending = false;
   ix.stats = sph_hoa_stats{};
   ix.stats.n_rays = n_rays;
@@ -1597,32 +1672,38 @@ void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam,
   ix.rays_o.ensure(sizeof(double) * 3 * n_rays);
   ix.rays_v.ensure(sizeof(double) * 3 * n_rays);
   double t_min = 0.0, t_max = 0.0;
-  CamDev cam_dev{};
   const float* ray_tr = nullptr;
-  if (n_batch > 0) {
-    // batch of cameras: all rays generated and processed together, each with its camera's segment
-    std::vector<CamDev> cd((size_t)n_batch);
-    std::vector<int64_t> offs((size_t)n_batch + 1, 0);
-    for (int c = 0; c < n_batch; ++c) {
-      cd[c] = make_cam(&batch[c]);
-      offs[c + 1] = offs[c] + (int64_t)batch[c].width * batch[c].height;
+  const int n_cams = (n_batch > 0) ? n_batch : (camera ? 1 : 0);
+  const sph_hoa_camera* cam_list = (n_batch > 0) ? batch : cam;
+  CamDev* cdev = nullptr;
+  int64_t *ray_base = nullptr, *tile_base = nullptr;
+  int64_t n_tiles = 0;
+  if (n_cams > 0) {
+    // cameras (one, or a batch rendered together): frames, first ray and first screen tile of each
+    std::vector<CamDev> cd((size_t)n_cams);
+    std::vector<int64_t> rb((size_t)n_cams + 1, 0), tb((size_t)n_cams + 1, 0);
+    for (int c = 0; c < n_cams; ++c) {
+      const sph_hoa_camera& sc = cam_list[c];
+      cd[c] = make_cam(&sc);
+      rb[c + 1] = rb[c] + (int64_t)sc.width * sc.height;
+      tb[c + 1] = tb[c] + (int64_t)((sc.width + kTile - 1) / kTile) * ((sc.height + kTile - 1) / kTile);
     }
-    ix.cams_dev.ensure(sizeof(CamDev) * n_batch + sizeof(int64_t) * (n_batch + 1));
-    CamDev* cdev = ix.cams_dev.as<CamDev>();
-    int64_t* odev = reinterpret_cast<int64_t*>(cdev + n_batch);
-    hip_check(hipMemcpyAsync(cdev, cd.data(), sizeof(CamDev) * n_batch, hipMemcpyHostToDevice, st), "copy");
-    hip_check(hipMemcpyAsync(odev, offs.data(), sizeof(int64_t) * (n_batch + 1), hipMemcpyHostToDevice, st), "copy");
+    n_tiles = tb[n_cams];
+    ix.cams_dev.ensure(sizeof(CamDev) * n_cams + sizeof(int64_t) * 2 * (n_cams + 1));
+    cdev = ix.cams_dev.as<CamDev>();
+    ray_base = reinterpret_cast<int64_t*>(cdev + n_cams);
+    tile_base = ray_base + (n_cams + 1);
+    hip_check(hipMemcpyAsync(cdev, cd.data(), sizeof(CamDev) * n_cams, hipMemcpyHostToDevice, st), "copy");
+    hip_check(hipMemcpyAsync(ray_base, rb.data(), sizeof(int64_t) * (n_cams + 1), hipMemcpyHostToDevice, st), "copy");
+    hip_check(hipMemcpyAsync(tile_base, tb.data(), sizeof(int64_t) * (n_cams + 1), hipMemcpyHostToDevice, st), "copy");
     ix.ray_tr.ensure(sizeof(float) * 2 * n_rays);
-    k_camera_rays_batch<<<blocks_for(n_rays, 256), 256, 0, st>>>(cdev, odev, n_batch, n_rays, ix.rays_o.as<double>(),
+    k_camera_rays_batch<<<blocks_for(n_rays, 256), 256, 0, st>>>(cdev, ray_base, n_cams, n_rays, ix.rays_o.as<double>(),
                                                                  ix.rays_v.as<double>(), ix.ray_tr.as<float>());
     ray_tr = ix.ray_tr.as<float>();
-    // staged host copies must outlive the asynchronous copies
+    t_min = (double)cam_list[0].t_min;
+    t_max = (double)cam_list[0].t_max;
+    // the staged host vectors must outlive the copies
     hip_check(hipStreamSynchronize(st), "sync");
-  } else if (camera) {
-    cam_dev = make_cam(cam);
-    k_camera_rays<<<blocks_for(n_rays, 256), 256, 0, st>>>(cam_dev, n_rays, ix.rays_o.as<double>(), ix.rays_v.as<double>());
-    t_min = (double)cam->t_min;
-    t_max = (double)cam->t_max;
   } else {
     k_widen_rays<<<blocks_for(n_rays, 256), 256, 0, st>>>(rays->origin, rays->dir, n_rays, ix.rays_o.as<double>(),
                                                           ix.rays_v.as<double>(), flags);
@@ -1650,17 +1731,14 @@ void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam,
   const unsigned gblocks = (unsigned)((n_rays + 3) / 4);
   BinArgs B{};
   TileHitArgs TH{};
-  int64_t n_tiles = 0;
-  if (camera && n_batch == 0) {
+  const int64_t n_pairs_bin = ix.n * (int64_t)n_cams;
+  if (n_cams > 0) {
     // bin particles into screen tiles, then count hits per pixel ray from the tile lists
     B.pos4 = ix.pos4.as<float4>();
     B.n = ix.n;
-    B.c = cam_dev;
-    B.tiles_x = (cam->width + kTile - 1) / kTile;
-    B.tiles_y = (cam->height + kTile - 1) / kTile;
-    B.t_min = t_min;
-    B.t_max = t_max;
-    n_tiles = (int64_t)B.tiles_x * B.tiles_y;
+    B.cams = cdev;
+    B.tile_base = tile_base;
+    B.n_cams = n_cams;
     ix.tile_count.ensure(sizeof(unsigned int) * (n_tiles + 1) * 2);
     ix.tile_off.ensure(sizeof(int64_t) * (n_tiles + 1) * 2);
     unsigned int* tcount = ix.tile_count.as<unsigned int>();
@@ -1671,7 +1749,7 @@ void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam,
     B.tile_off = ix.tile_off.as<int64_t>();
     if (ix.timing) hip_check(hipEventRecord(ix.ev[0], st), "event");
     hip_check(hipMemsetAsync(tcount, 0, sizeof(unsigned int) * (n_tiles + 1) * 2, st), "memset");
-    k_bin<false><<<blocks_for(ix.n, 256), 256, 0, st>>>(B);
+    k_bin<false><<<blocks_for(n_pairs_bin, 256), 256, 0, st>>>(B);
     k_u32_to_i64_n<<<blocks_for(n_tiles, 256), 256, 0, st>>>(tcount, tcnt64, n_tiles);
     device_exclusive_scan_i64(tcnt64, ix.tile_off.as<int64_t>(), n_tiles, ix.scan_tmp, st);
     k_set_last<<<1, 1, 0, st>>>(ix.tile_off.as<int64_t>(), tcnt64, n_tiles);
@@ -1680,14 +1758,13 @@ void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam,
     hip_check(hipStreamSynchronize(st), "sync");
     ix.tile_items.ensure(sizeof(uint32_t) * std::max<int64_t>(1, n_items));
     B.items = ix.tile_items.as<uint32_t>();
-    k_bin<true><<<blocks_for(ix.n, 256), 256, 0, st>>>(B);
+    k_bin<true><<<blocks_for(n_pairs_bin, 256), 256, 0, st>>>(B);
     TH.o = G.o;
     TH.v = G.v;
-    TH.W = cam->width;
-    TH.H = cam->height;
-    TH.tiles_x = B.tiles_x;
-    TH.t_min = t_min;
-    TH.t_max = t_max;
+    TH.cams = cdev;
+    TH.tile_base = tile_base;
+    TH.ray_base = ray_base;
+    TH.n_cams = n_cams;
     TH.pos4 = B.pos4;
     TH.tile_off = B.tile_off;
     TH.items = B.items;
@@ -1722,7 +1799,7 @@ void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam,
   G.off = ix.hit_off.as<int64_t>();
   G.hits = ix.hits.as<uint32_t>();
   if (ix.timing) hip_check(hipEventRecord(ix.ev[2], st), "event");
-  if (camera && n_batch == 0) {
+  if (n_cams > 0) {
     TH.off = G.off;
     TH.hits = G.hits;
     k_tile_hits<true><<<(unsigned)n_tiles, 64, 0, st>>>(TH);
@@ -1740,7 +1817,7 @@ void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam,
   A.t_max = t_max;
   A.tr = ray_tr;
   A.order = nullptr;
-  if (n_batch > 0 || !camera) {
+  if (n_cams != 1) {
     // arbitrary rays and batches can be heavy-tailed: process the longest rays first so that the
     // persistent work-groups finish together
     ix.order_keys.ensure(sizeof(uint64_t) * 2 * n_rays);
@@ -1767,14 +1844,20 @@ void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam,
   A.counters = ctr;
   const int64_t max_knots = std::max<int64_t>(1, (int64_t)mh * (K + 1));
   A.max_knots = max_knots;
-  // LDS per work-group: two work-groups share a CU (two waves per SIMD hide the latency of the
-  // dependent integer and float64 chains; the kernel is register-capped for it), so a ray's layout
-  // gets half the CU's LDS less the static part; it is sized down to the frame's longest ray
+  // Work-groups per CU: two (two waves per SIMD hide the latency of the dependent integer and
+  // float64 chains; registers capped for it, half the CU's LDS per ray) or one (the whole LDS, so
+  // long rays keep more of their layout on chip).  Chosen per workload signature by measuring
+  // both (FieldTuner); a ray's layout gets 1 / wgs of the CU's LDS less the static part, sized
+  // down to the frame's longest ray.
   const int nj = jump_values_per_hit(P, (K % 2 == 0) ? 1 : 0, D);
   A.nj = nj;
   const size_t lds_static = static_lds(D);
   const int64_t mh1 = std::max<int64_t>(1, (int64_t)mh);
-  const int64_t lds_budget = kLdsPerCu / kFieldWgPerCu - (int64_t)lds_static - 512;
+  const bool render_mode = (out.rgba != nullptr);
+  const FieldTuner::Key tkey = FieldTuner::key_of(D, render_mode, total_pairs, n_rays, (int64_t)mh);
+  int wgs = ix.tuner.choose(tkey);
+  if (const char* f = std::getenv("SPH_HOA_FIELD_WGS")) wgs = (std::atoi(f) == 1) ? 1 : 2;  // test hook
+  const int64_t lds_budget = kLdsPerCu / wgs - (int64_t)lds_static - 512;
   int64_t lds = std::min<int64_t>(lds_budget, ray_store_bytes(mh1, max_knots, nj, true));
   // test hook: a smaller LDS capacity (in hits) sends more rays down the device-memory paths
   if (const char* cap = std::getenv("SPH_HOA_MAX_LDS_HITS")) {
@@ -1786,8 +1869,7 @@ void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam,
   int dev = 0;
   hip_check(hipGetDevice(&dev), "device");
   hip_check(hipGetDeviceProperties(&prop, dev), "props");
-  const int per_cu = (int)std::max<int64_t>(
-      1, std::min<int64_t>(kFieldWgPerCu, kLdsPerCu / (lds + (int64_t)lds_static + 512)));
+  const int per_cu = (int)std::max<int64_t>(1, std::min<int64_t>(wgs, kLdsPerCu / (lds + (int64_t)lds_static + 512)));
   const int grid = (int)std::min<int64_t>((int64_t)prop.multiProcessorCount * per_cu, n_rays);
   const int max_tier = ray_tier(mh1, max_knots, nj, lds);
   A.slab_jmp = align8((int64_t)node_bytes(D) * ((max_knots + kChunk - 1) / kChunk) * kChunk);
@@ -1796,8 +1878,7 @@ void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam,
   A.slab_stride = A.slab_store + (max_tier >= 3 ? align8(ray_store_bytes(mh1, max_knots, nj, true)) : 0) + 64;
   ix.slab.ensure((size_t)A.slab_stride * grid);
   A.slab = ix.slab.as<char>();
-  const bool render = (out.rgba != nullptr);
-  if (render) {
+  if (render_mode) {
     A.tf = out.tf->rgba;
     A.tf_n = out.tf->n;
     A.tf_vmin = out.tf->v_min;
@@ -1805,7 +1886,9 @@ void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam,
     A.tf_step = (double)out.tf->step;
     A.rgba = out.rgba;
     if (ix.timing) hip_check(hipEventRecord(ix.ev[4], st), "event");
-    dispatch_field<true>(D, A, grid, (size_t)lds, st);
+    ix.tuner.begin(tkey, wgs, total_pairs, st);
+    dispatch_field<true>(D, wgs, A, grid, (size_t)lds, st);
+    ix.tuner.end(st);
     ix.render_stats_pending = true;
     if (ix.timing) {
       hip_check(hipEventRecord(ix.ev[5], st), "event");
@@ -1843,7 +1926,9 @@ void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam,
                   "copy");
     }
     if (ix.timing) hip_check(hipEventRecord(ix.ev[4], st), "event");
-    dispatch_field<false>(D, A, grid, (size_t)lds, st);
+    ix.tuner.begin(tkey, wgs, total_pairs, st);
+    dispatch_field<false>(D, wgs, A, grid, (size_t)lds, st);
+    ix.tuner.end(st);
     if (ix.timing) {
       hip_check(hipEventRecord(ix.ev[5], st), "event");
       ix.timing_pending = true;

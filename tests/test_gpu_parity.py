@@ -217,6 +217,29 @@ def test_device_memory_path_is_identical():
             assert torch.equal(a[k], b[k]), (cap, k)
 
 
+def test_field_kernel_configurations_identical():
+    """One or two ray work-groups per CU (the tuner's two choices) give the same bits."""
+    sc = H.tiny_scene()
+    o, v = synth.ortho_rays()
+    o, v = o[:700], v[:700]
+    cam = synth.tiny_camera(48, 40)
+    tf = synth.transfer_function()
+    res = []
+    for wgs in ("1", "2"):
+        os.environ["SPH_HOA_FIELD_WGS"] = wgs
+        try:
+            a = _approx(sc, o, v, 0.0, 1.4)
+            img = L.sph_hoa_render(sc.index(), cam, tf, 0.0, 4.0e4, 1.4 / 256)
+            torch.cuda.synchronize()
+        finally:
+            del os.environ["SPH_HOA_FIELD_WGS"]
+        res.append((a, img))
+    (a1, i1), (a2, i2) = res
+    for k in ("ray_offsets", "t_start", "t_end", "coef", "ray_peak", "exact_t", "exact_coef", "knot_t", "knot_pid"):
+        assert torch.equal(a1[k], a2[k]), k
+    assert torch.equal(i1, i2)
+
+
 def test_deterministic():
     sc = H.tiny_scene()
     o, v = synth.ortho_rays()
