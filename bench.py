@@ -45,9 +45,13 @@ def parse():
     ap.add_argument("--size", type=int, default=512)
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="budget of the oracle baseline")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", choices=("plain", "batch"), default="plain",
+    ap.add_argument("--rate", type=float, default=20.0, help="serve workload: Poisson arrival rate (requests/s)")
+    ap.add_argument("--duration", type=float, default=8.0, help="serve workload: seconds of arrivals")
+    ap.add_argument("--sides", default="64,128,256", help="serve workload: image sides (uniform choice)")
+    ap.add_argument("--workload", choices=("plain", "batch", "serve"), default="plain",
                     help="plain: the 1M-particle 512x512 frame (the reported metric); batch: camera bundles "
-                         "of 32^2..512^2 rendered with one sph_hoa_render_batch call")
+                         "of 32^2..512^2 rendered with one sph_hoa_render_batch call; serve: Poisson render "
+                         "requests to the native render server")
     ap.add_argument("--batch-cams", type=int, default=64, help="cameras per batch (batch workload)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="instead of the benchmark, run 5 plain device copies of MIB MiB each (the "
@@ -146,6 +150,64 @@ def run_batch(a, torch, L, synth):
     print(json.dumps(result), flush=True)
 
 
+def run_serve(a, torch, L, synth):
+    """Serving workload: render requests arrive as a Poisson stream (a.rate per second for
+    a.duration seconds) at the native render server holding a resident clustered set (default 2M
+    particles, Wendland C2, K = 4, D = 3); each request is one camera on the radius-2 sphere (half
+    of them narrow views through cluster cores) with a square image of a side drawn from a.sides.
+    Reports latency (submit to completion) and the sustained contribution rate."""
+    import threading
+
+    n = a.particles if a.particles != 1_000_000 else 2_000_000
+    xyz, h, val = synth.clustered_particles(seed=2, n=n)
+    idx = L.sph_hoa_build_index(xyz, h, val, kernel=L.KERNEL_WENDLAND_C2, degree=3, pieces=4, lut_entries=4096,
+                                merge_tol=1e-3)
+    tf = torch.as_tensor(synth.transfer_function(), device="cuda")
+    rng = np.random.default_rng(5)
+    sides = [int(x) for x in a.sides.split(",")]
+    n_req = int(rng.poisson(a.rate * a.duration))
+    arrivals = np.sort(rng.uniform(0.0, a.duration, n_req))
+    cams = synth.batch_cameras(seed=5, n=n_req, centres=synth.cluster_centres(seed=2))
+    for c in cams:
+        side = int(sides[int(rng.integers(len(sides)))])
+        c["width"] = c["height"] = side
+    srv = L.Server(hbm_budget_bytes=32 << 30)
+    slot = srv.add_index(idx)
+    # warm-up: one request of each size, not counted
+    for sd in sides:
+        rid, _ = srv.submit(slot, dict(cams[0], width=sd, height=sd), tf, 0.0, 300.0, 2.0 / 512)
+        srv.wait(rid)
+    st0 = srv.stats()
+    ids = []
+    t0 = time.perf_counter()
+    for i, c in enumerate(cams):
+        dt = arrivals[i] - (time.perf_counter() - t0)
+        if dt > 0:
+            time.sleep(dt)
+        ids.append(srv.submit(slot, c, tf, 0.0, 300.0, 2.0 / 512)[0])
+    lat = [srv.wait(rid)[1] for rid in ids]
+    wall = time.perf_counter() - t0
+    st = srv.stats()
+    srv.close()
+    lat = np.array(lat)
+    pairs = st["n_pairs"] - st0["n_pairs"]
+    batches = st["batches"] - st0["batches"]
+    result = {
+        "metric": "particle-ray contributions/s at rel err <=1e-5; p50/p99 frame latency",
+        "value": pairs / wall, "unit": "contributions/s", "n_gpus": 1, "steps": n_req, "warmup": len(sides),
+        "ms_per_step": wall / max(1, n_req) * 1e3, "p50_ms": float(np.percentile(lat, 50)) if n_req else None,
+        "p99_ms": float(np.percentile(lat, 99)) if n_req else None, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+        "config": {"workload": f"serve: Poisson requests at {a.rate}/s for {a.duration} s, sides {sides}, resident "
+                               f"{n} clustered particles, Wendland C2, K=4, D=3, tol 1e-3, native render server",
+                   "requests": n_req, "batches": batches, "mean_requests_per_batch": n_req / max(1, batches),
+                   "offered_rays_per_s": sum(c["width"] * c["height"] for c in cams) / a.duration,
+                   "served_rays": st["n_rays"] - st0["n_rays"], "pairs": pairs, "wall_s": wall,
+                   "worker_busy_s": st["busy_s"] - st0["busy_s"], "max_latency_ms": float(lat.max()) if n_req else None},
+    }
+    print(json.dumps(result), flush=True)
+
+
 def kernel_source_digest():
     import hashlib
 
@@ -199,6 +261,8 @@ def main():
     L.lib()
     if a.workload == "batch":
         return run_batch(a, torch, L, synth)
+    if a.workload == "serve":
+        return run_serve(a, torch, L, synth)
     t_gen = time.time()
     xyz, h, val = synth.clustered_particles(n=a.particles)
     gen_s = time.time() - t_gen

@@ -193,6 +193,43 @@ sph_hoa_status sph_hoa_render(sph_hoa_index idx, const sph_hoa_camera* cam, cons
 sph_hoa_status sph_hoa_render_batch(sph_hoa_index idx, const sph_hoa_camera* cams, int32_t n_cams,
                                     const sph_hoa_tf* tf, float* rgba_out, void* stream);
 
+/* ---------------------------------------------------------------- render server
+ *
+ * A resident request loop: indices stay in device memory, render requests (one camera each) are
+ * queued from any host thread, and one worker thread batches them - the oldest request plus the
+ * queued requests with the same index and transfer function, in arrival order, while the batch's
+ * estimated device memory stays within the budget and its rays within max_batch_rays - into one
+ * sph_hoa_render_batch launch chain on the server's own stream.  Each image is bit-identical to
+ * sph_hoa_render of its camera alone.  An index added to a server belongs to it until the server
+ * is destroyed (no other call may use it meanwhile); the transfer function's device array and the
+ * output buffers must stay valid until the request has completed.
+ */
+typedef struct sph_hoa_server_s* sph_hoa_server;
+
+typedef struct {
+  int64_t completed, failed, queued, batches;
+  int64_t n_rays, n_pairs;    /* over the completed batches */
+  double busy_s;              /* worker time spent rendering */
+  double p50_ms, p99_ms, max_ms; /* request latency, submit to completion, over completed requests */
+} sph_hoa_server_stats;
+
+/* hbm_budget_bytes: admission bound on a batch's estimated transient device memory (a single
+ * request larger than it still runs alone); max_batch_rays: bound on a batch's rays. */
+sph_hoa_status sph_hoa_server_create(int64_t hbm_budget_bytes, int64_t max_batch_rays, sph_hoa_server* out);
+/* Registers an index; *slot names it in submissions. */
+sph_hoa_status sph_hoa_server_add_index(sph_hoa_server server, sph_hoa_index idx, int32_t* slot);
+/* Queues one render (arguments as sph_hoa_render, checked now); *request_id names it. */
+sph_hoa_status sph_hoa_server_submit(sph_hoa_server server, int32_t slot, const sph_hoa_camera* cam,
+                                     const sph_hoa_tf* tf, float* rgba_out, int64_t* request_id);
+/* Waits up to timeout_s seconds (< 0: without limit).  *done = 1 once the request has completed
+ * (then its image is in rgba_out, *latency_ms holds its latency if non-NULL, the id is released,
+ * and the status is the request's own); *done = 0 on time-out (status OK, id still valid). */
+sph_hoa_status sph_hoa_server_wait(sph_hoa_server server, int64_t request_id, double timeout_s, int32_t* done,
+                                   double* latency_ms);
+sph_hoa_status sph_hoa_server_get_stats(sph_hoa_server server, sph_hoa_server_stats* stats);
+/* Renders what is still queued, stops the worker and frees the server (not its indices). */
+sph_hoa_status sph_hoa_server_destroy(sph_hoa_server server);
+
 sph_hoa_status sph_hoa_index_free(sph_hoa_index idx);
 
 /* Host copy of the index parameters. */

@@ -70,6 +70,13 @@ class TF(ctypes.Structure):
                 ("step", ctypes.c_float)]
 
 
+class ServerStats(ctypes.Structure):
+    _fields_ = [("completed", ctypes.c_int64), ("failed", ctypes.c_int64), ("queued", ctypes.c_int64),
+                ("batches", ctypes.c_int64), ("n_rays", ctypes.c_int64), ("n_pairs", ctypes.c_int64),
+                ("busy_s", ctypes.c_double), ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double),
+                ("max_ms", ctypes.c_double)]
+
+
 class Stats(ctypes.Structure):
     _fields_ = [("n_rays", ctypes.c_int64), ("n_pairs", ctypes.c_int64), ("n_knots", ctypes.c_int64),
                 ("n_pieces", ctypes.c_int64), ("max_hits", ctypes.c_int64), ("rays_global", ctypes.c_int64),
@@ -78,6 +85,8 @@ class Stats(ctypes.Structure):
 
 
 EXPORTS = ["sph_hoa_build_index", "sph_hoa_approx_rays", "sph_hoa_render", "sph_hoa_render_batch",
+           "sph_hoa_server_create", "sph_hoa_server_add_index", "sph_hoa_server_submit", "sph_hoa_server_wait",
+           "sph_hoa_server_get_stats", "sph_hoa_server_destroy",
            "sph_hoa_index_free",
            "sph_hoa_index_get_info", "sph_hoa_index_get_lut", "sph_hoa_index_get_grid", "sph_hoa_index_get_stats",
            "sph_hoa_index_set_timing",
@@ -100,6 +109,13 @@ def lib():
     L.sph_hoa_approx_rays.argtypes = [vp, ctypes.POINTER(Rays), ctypes.POINTER(Field), u32, vp]
     L.sph_hoa_render.argtypes = [vp, ctypes.POINTER(Camera), ctypes.POINTER(TF), vp, vp]
     L.sph_hoa_render_batch.argtypes = [vp, ctypes.POINTER(Camera), i32, ctypes.POINTER(TF), vp, vp]
+    L.sph_hoa_server_create.argtypes = [i64, i64, ctypes.POINTER(vp)]
+    L.sph_hoa_server_add_index.argtypes = [vp, vp, ctypes.POINTER(i32)]
+    L.sph_hoa_server_submit.argtypes = [vp, i32, ctypes.POINTER(Camera), ctypes.POINTER(TF), vp,
+                                        ctypes.POINTER(i64)]
+    L.sph_hoa_server_wait.argtypes = [vp, i64, dbl, ctypes.POINTER(i32), ctypes.POINTER(dbl)]
+    L.sph_hoa_server_get_stats.argtypes = [vp, ctypes.POINTER(ServerStats)]
+    L.sph_hoa_server_destroy.argtypes = [vp]
     L.sph_hoa_index_free.argtypes = [vp]
     L.sph_hoa_index_get_info.argtypes = [vp, ctypes.POINTER(IndexInfo)]
     L.sph_hoa_index_get_lut.argtypes = [vp, vp, vp, vp]
@@ -333,6 +349,63 @@ def sph_hoa_render_batch(index, cameras, tf_rgba, v_min, v_max, step, out=None):
         views.append(out[o:o + h * w].view(h, w, 4))
         o += h * w
     return out, views
+
+
+class Server:
+    """Render server (sph_hoa_server_*): resident indices, a request queue and continuous batching
+    by a native worker thread.  submit() returns a request id; wait() blocks until the image is in
+    the output tensor."""
+
+    def __init__(self, hbm_budget_bytes=8 << 30, max_batch_rays=1 << 24):
+        h = ctypes.c_void_p()
+        _check(lib().sph_hoa_server_create(int(hbm_budget_bytes), int(max_batch_rays), ctypes.byref(h)))
+        self.handle = h
+        self._keep = {}
+
+    def add_index(self, index):
+        slot = ctypes.c_int32()
+        _check(lib().sph_hoa_server_add_index(self.handle, index.handle, ctypes.byref(slot)))
+        self._keep[("index", slot.value)] = index
+        return slot.value
+
+    def submit(self, slot, camera: dict, tf_rgba, v_min, v_max, step, out=None):
+        import torch
+
+        c = make_camera(camera)
+        tf = _dev_f32(tf_rgba).reshape(-1, 4)
+        if out is None:
+            out = torch.empty((c.height, c.width, 4), dtype=torch.float32, device="cuda")
+        # inputs written on torch's stream must be complete before the server's stream reads them
+        torch.cuda.current_stream().synchronize()
+        t = TF(_ptr(tf).value, tf.shape[0], v_min, v_max, step)
+        rid = ctypes.c_int64()
+        _check(lib().sph_hoa_server_submit(self.handle, slot, ctypes.byref(c), ctypes.byref(t), _ptr(out),
+                                           ctypes.byref(rid)))
+        self._keep[rid.value] = (tf, out)
+        return rid.value, out
+
+    def wait(self, request_id, timeout_s=-1.0):
+        """(done, latency_ms); raises SphHoaError if the request failed."""
+        done = ctypes.c_int32()
+        lat = ctypes.c_double()
+        try:
+            _check(lib().sph_hoa_server_wait(self.handle, int(request_id), float(timeout_s), ctypes.byref(done),
+                                             ctypes.byref(lat)))
+        finally:
+            if done.value:
+                self._keep.pop(request_id, None)
+        return bool(done.value), lat.value
+
+    def stats(self):
+        s = ServerStats()
+        _check(lib().sph_hoa_server_get_stats(self.handle, ctypes.byref(s)))
+        return {f: getattr(s, f) for f, _ in ServerStats._fields_}
+
+    def close(self):
+        if self.handle:
+            _check(lib().sph_hoa_server_destroy(self.handle))
+            self.handle = None
+            self._keep.clear()
 
 
 def sph_hoa_optimal_knots(kernel, pieces, degree, lam):

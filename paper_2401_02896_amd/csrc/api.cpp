@@ -13,8 +13,8 @@
 
 #include "impl.h"
 
-struct sph_hoa_index_s {
-  sph::Index ix;
+struct sph_hoa_server_s {
+  sph::Server* s;
 };
 
 namespace {
@@ -414,3 +414,59 @@ sph_hoa_status sph_hoa_optimal_tau(sph_hoa_kernel kernel, int32_t degree, double
 }
 
 }  // extern "C"
+
+sph_hoa_status sph_hoa_server_create(int64_t hbm_budget_bytes, int64_t max_batch_rays, sph_hoa_server* out) {
+  return guarded([&]() {
+    require(out != nullptr, "NULL argument");
+    require(hbm_budget_bytes > 0 && max_batch_rays > 0, "budget and max_batch_rays must be > 0");
+    *out = nullptr;
+    std::unique_ptr<sph_hoa_server_s> h(new sph_hoa_server_s{nullptr});
+    h->s = sph::server_create(hbm_budget_bytes, max_batch_rays);
+    *out = h.release();
+  });
+}
+
+sph_hoa_status sph_hoa_server_add_index(sph_hoa_server server, sph_hoa_index idx, int32_t* slot) {
+  return guarded([&]() {
+    require(server && idx && slot, "NULL argument");
+    *slot = sph::server_add_index(server->s, idx);
+  });
+}
+
+sph_hoa_status sph_hoa_server_submit(sph_hoa_server server, int32_t slot, const sph_hoa_camera* cam,
+                                     const sph_hoa_tf* tf, float* rgba_out, int64_t* request_id) {
+  return guarded([&]() {
+    require(server && cam && tf && rgba_out && request_id, "NULL argument");
+    check_tf(tf);
+    check_camera(sph::server_index(server->s, slot)->ix, cam, tf);
+    *request_id = sph::server_submit(server->s, slot, cam, tf, rgba_out);
+  });
+}
+
+sph_hoa_status sph_hoa_server_wait(sph_hoa_server server, int64_t request_id, double timeout_s, int32_t* done,
+                                   double* latency_ms) {
+  return guarded([&]() {
+    require(server && done, "NULL argument");
+    *done = 0;
+    sph_hoa_status rs = SPH_HOA_OK;
+    std::string re;
+    if (!sph::server_wait(server->s, request_id, timeout_s, latency_ms, &rs, &re)) return;
+    *done = 1;
+    if (rs != SPH_HOA_OK) throw sph::Error(rs, "request failed: " + re);
+  });
+}
+
+sph_hoa_status sph_hoa_server_get_stats(sph_hoa_server server, sph_hoa_server_stats* stats) {
+  return guarded([&]() {
+    require(server && stats, "NULL argument");
+    sph::server_stats(server->s, stats);
+  });
+}
+
+sph_hoa_status sph_hoa_server_destroy(sph_hoa_server server) {
+  return guarded([&]() {
+    if (!server) return;
+    sph::server_destroy(server->s);
+    delete server;
+  });
+}

@@ -168,6 +168,25 @@ struct Index {
   }
 };
 
+}  // namespace sph
+
+struct sph_hoa_index_s {
+  sph::Index ix;
+};
+
+namespace sph {
+
+// render server (serve.cpp)
+struct Server;
+Server* server_create(int64_t hbm_budget, int64_t max_rays);
+void server_destroy(Server* s);
+int server_add_index(Server* s, sph_hoa_index idx);
+sph_hoa_index server_index(Server* s, int slot);
+int64_t server_submit(Server* s, int slot, const sph_hoa_camera* cam, const sph_hoa_tf* tf, float* out);
+bool server_wait(Server* s, int64_t id, double timeout_s, double* latency_ms, sph_hoa_status* req_status,
+                 std::string* req_error);
+void server_stats(Server* s, sph_hoa_server_stats* st);
+
 // build (index.hip)
 void build_index_device(Index& ix, const float* xyz, const float* h, const float* value, hipStream_t st);
 void get_grid_device(Index& ix, uint64_t* morton, int32_t* level, int32_t* order, hipStream_t st);

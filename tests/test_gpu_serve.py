@@ -1,0 +1,130 @@
+"""Render server (sph_hoa_server_*): resident index, request queue, continuous batching.
+
+Every image served in a mix of concurrent requests must equal, bit for bit, the image
+sph_hoa_render gives for the same camera alone; admission by the memory budget decides how
+requests share batches; errors surface at submission or at the wait.
+"""
+import threading
+
+import pytest
+
+import synth
+from tests import gpu_helpers as H
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - only on the GPU machine
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_2401_02896_amd as L  # noqa: E402
+
+VMAX, STEP = 4.0e4, 1.4 / 256
+
+
+def _cams():
+    base = synth.tiny_camera()
+    persp = {"eye": [0.5, 0.5, -1.0], "look_at": [0.5, 0.5, 0.5], "up": [0.0, 1.0, 0.0], "fov_y_deg": 40.0,
+             "ortho": 0, "ortho_half_extent": 0.0, "width": 40, "height": 32, "t_min": 0.5, "t_max": 2.5}
+    cams = []
+    for i in range(12):
+        if i % 3 == 0:
+            cams.append(dict(base, width=8 + 4 * i, height=16))
+        elif i % 3 == 1:
+            cams.append(dict(persp, width=24 + i, height=20, fov_y_deg=20.0 + 2 * i))
+        else:
+            cams.append(dict(base, eye=[-0.2, 0.5, 0.5], look_at=[1.0, 0.5, 0.5], width=12, height=12 + i))
+    return cams
+
+
+def _refs(idx, cams, tfs):
+    out = []
+    for i, cam in enumerate(cams):
+        out.append(L.sph_hoa_render(idx, cam, tfs[i % len(tfs)], 0.0, VMAX, STEP).clone())
+    torch.cuda.synchronize()
+    return out
+
+
+def test_served_images_equal_single_renders():
+    sc = H.tiny_scene()
+    idx = sc.index()
+    tfs = [torch.as_tensor(synth.transfer_function(seed=3), device="cuda"),
+           torch.as_tensor(synth.transfer_function(seed=8), device="cuda")]
+    cams = _cams()
+    refs = _refs(idx, cams, tfs)
+    big = synth.tiny_camera(256, 256)
+    big_ref = L.sph_hoa_render(idx, big, tfs[0], 0.0, VMAX, STEP).clone()
+    torch.cuda.synchronize()
+    srv = L.Server(hbm_budget_bytes=1 << 30)
+    try:
+        slot = srv.add_index(idx)
+        # a large request first keeps the worker busy while the small ones queue up behind it
+        big_id, big_out = srv.submit(slot, big, tfs[0], 0.0, VMAX, STEP)
+        ids = [None] * len(cams)
+        outs = [None] * len(cams)
+
+        def submitter(k):
+            for i in range(k, len(cams), 3):
+                ids[i], outs[i] = srv.submit(slot, cams[i], tfs[i % 2], 0.0, VMAX, STEP)
+
+        th = [threading.Thread(target=submitter, args=(k,)) for k in range(3)]
+        for t in th:
+            t.start()
+        for t in th:
+            t.join()
+        done, lat = srv.wait(big_id, 120.0)
+        assert done and lat > 0
+        assert torch.equal(big_out, big_ref)
+        for i, cam in enumerate(cams):
+            done, lat = srv.wait(ids[i], 120.0)
+            assert done
+            assert torch.equal(outs[i], refs[i]), cam
+        st = srv.stats()
+        assert st["completed"] == len(cams) + 1 and st["failed"] == 0 and st["queued"] == 0
+        assert st["batches"] < st["completed"]  # requests shared launches
+        assert 0 < st["p50_ms"] <= st["p99_ms"] <= st["max_ms"]
+    finally:
+        srv.close()
+
+
+def test_budget_admits_one_request_per_batch():
+    sc = H.tiny_scene()
+    idx = sc.index()
+    tf = torch.as_tensor(synth.transfer_function(), device="cuda")
+    cams = _cams()[:6]
+    refs = _refs(idx, cams, [tf])
+    srv = L.Server(hbm_budget_bytes=1)  # nothing fits beside the head request
+    try:
+        slot = srv.add_index(idx)
+        sub = [srv.submit(slot, c, tf, 0.0, VMAX, STEP) for c in cams]
+        for (rid, out), ref in zip(sub, refs):
+            assert srv.wait(rid, 120.0)[0]
+            assert torch.equal(out, ref)
+        st = srv.stats()
+        assert st["batches"] == st["completed"] == len(cams)
+    finally:
+        srv.close()
+
+
+def test_server_errors_and_timeouts():
+    sc = H.tiny_scene()
+    idx = sc.index()
+    tf = torch.as_tensor(synth.transfer_function(), device="cuda")
+    srv = L.Server()
+    try:
+        slot = srv.add_index(idx)
+        with pytest.raises(L.SphHoaError):
+            srv.submit(slot + 5, synth.tiny_camera(8, 8), tf, 0.0, VMAX, STEP)
+        with pytest.raises(L.SphHoaError):
+            srv.submit(slot, dict(synth.tiny_camera(8, 8), t_min=2.0, t_max=1.0), tf, 0.0, VMAX, STEP)
+        with pytest.raises(L.SphHoaError):
+            srv.wait(12345, 0.0)
+        rid, out = srv.submit(slot, synth.tiny_camera(64, 64), tf, 0.0, VMAX, STEP)
+        done, _ = srv.wait(rid, 0.0)  # may or may not be finished yet
+        if not done:
+            done, _ = srv.wait(rid, 120.0)
+        assert done
+        with pytest.raises(L.SphHoaError):  # the id was released by the completed wait
+            srv.wait(rid, 0.0)
+    finally:
+        srv.close()
