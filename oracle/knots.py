@@ -33,7 +33,10 @@ middle knot of even K; odd K has no middle knot).
 Pinned by tests/test_oracle_knots.py: exact zero tail of every particle's own
 accumulation, shifted evenness of the piecewise polynomial it encodes, the
 symmetry of the positions, and closeness of the encoded function to the
-scaled, shifted table approximation.
+scaled, shifted table approximation.  The wrap-around accumulation of the
+bit-length study (accumulate_wrapped) is pinned by the closed form of the
+rule's result (each jump polynomial re-expanded about the last knot, summed)
+and by direct evaluation of the encoded polynomial at sample points.
 """
 from __future__ import annotations
 
@@ -124,3 +127,27 @@ def accumulate(knots):
         prev = t
         out.append((t, list(state)))
     return out
+
+
+def accumulate_wrapped(dist, jumps, g, steps, bits):
+    """Final state of accumulator g of the integer bit-length study (Sec. 5.1): the accumulation
+    rule (Eq. accumulation-rule) over `steps` knots in wrap-around `bits`-bit integers.
+
+    dist: table of knot distances (distance from the previous knot); jumps: table of jump
+    coefficient lists (integers, any sign).  Knot s of accumulator g is table entry
+    (g + s mod 4) mod len(dist); knot 0 sits at position 0 and knot s > 0 at the previous position
+    plus that entry's distance.  The accumulation is done exactly (accumulate above) and reduced
+    modulo 2^bits at the end, which equals reducing after every multiply and add because reduction
+    modulo 2^bits is a ring homomorphism of the integers.  Returns the D + 1 residues in
+    [0, 2^bits)."""
+    n = len(dist)
+    seq = []
+    t = 0
+    for s in range(steps):
+        k = (g + s % 4) % n
+        if s > 0:
+            t += int(dist[k])
+        seq.append((t, k, [int(x) for x in jumps[k]]))
+    final = accumulate(seq)[-1][1]
+    m = 1 << bits
+    return [x % m for x in final]

@@ -140,3 +140,24 @@ def random_rays(seed: int, n: int, box=(0.0, 1.0)):
     v = tgt - o
     v /= np.linalg.norm(v, axis=1, keepdims=True)
     return o.astype(np.float32), v.astype(np.float32)
+
+
+def bit_tables(seed: int = 6, n_table: int = 37, degree: int = 3, bits: int = 64):
+    """Knot table of the integer bit-length study: distances uint32 [n_table] and jump limbs
+    uint32 [n_table, degree + 1, bits // 32] (low limb first), uniform over the full 32-bit range
+    except entry 0, which is all ones (every carry propagates) with distance 2^32 - 1."""
+    rng = np.random.default_rng(seed)
+    L = bits // 32
+    dist = rng.integers(0, 1 << 32, n_table, dtype=np.uint64).astype(np.uint32)
+    jumps = rng.integers(0, 1 << 32, (n_table, degree + 1, L), dtype=np.uint64).astype(np.uint32)
+    dist[0] = 0xFFFFFFFF
+    jumps[0] = 0xFFFFFFFF
+    return dist, jumps
+
+
+def limbs_to_int(limbs) -> int:
+    """Unsigned integer of little-endian uint32 limbs."""
+    v = 0
+    for i, x in enumerate(limbs):
+        v |= int(x) << (32 * i)
+    return v

@@ -88,3 +88,39 @@ def test_quantized_close_to_table_function():
 
 def test_rint_ties_to_even():
     assert knots.rint(2.5) == 2 and knots.rint(3.5) == 4 and knots.rint(-2.5) == -2
+
+
+def test_wrapped_accumulation_hand_case():
+    """Sec. 5.1 study, worked by hand: D = 1, one table entry (distance 3, jump 1 + 2 x), four
+    knots at 0, 3, 6, 9.  At the last knot the encoded function is sum_s (1 + 2 (x - t_s)): value
+    4 + 2 (9 + 6 + 3 + 0) = 40, slope 8; in 4-bit arithmetic 8 and 8."""
+    assert knots.accumulate_wrapped([3], [[1, 2]], 0, 4, 32) == [40, 8]
+    assert knots.accumulate_wrapped([3], [[1, 2]], 0, 4, 4) == [8, 8]
+    # two entries: knot s of accumulator 1 takes entry (1 + s mod 4) mod 2 = 1, 0, 1, 0
+    # with distances 7 (entry 0) and 5 (entry 1): positions 0, 7, 12, 19; jumps x, 1, x, 1
+    got = knots.accumulate_wrapped([7, 5], [[1, 0], [0, 1]], 1, 4, 64)
+    assert got == [(19 - 0) + 1 + (19 - 12) + 1, 2]
+
+
+@pytest.mark.parametrize("bits", [32, 64, 96, 128])
+@pytest.mark.parametrize("D", [1, 3, 6])
+def test_wrapped_accumulation_equals_encoded_function(bits, D):
+    """The rule's state at the last knot is the encoded function re-expanded about that knot: its
+    polynomial at x = t_last + u equals the sum of every knot's jump polynomial at x (the encoding
+    of Sec. 2, evaluated directly), modulo 2^bits."""
+    import synth
+
+    dist, jumps = synth.bit_tables(seed=10 + D, n_table=5, degree=D, bits=bits)
+    table = [[synth.limbs_to_int(jumps[k, d]) for d in range(D + 1)] for k in range(5)]
+    m = 1 << bits
+    for g in (0, 3, 7):
+        steps = 12
+        got = knots.accumulate_wrapped(dist, table, g, steps, bits)
+        kn, t = [], 0
+        for s in range(steps):
+            k = (g + s % 4) % 5
+            t += int(dist[k]) if s > 0 else 0
+            kn.append((t, k, table[k]))
+        for u in (0, 1, 2, 1000, 1 << 33):
+            x = t + u
+            assert sum(c * u ** d for d, c in enumerate(got)) % m == _eval_exact(kn, x) % m
