@@ -29,11 +29,13 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X published peaks and the integer arithmetic rates used for the ALU roofline
-# (256 CUs x 4 SIMD x 16 lanes x 2.4 GHz; 32-bit integer multiplies issue at a quarter rate).
+# MI355X unit counts and clock, and the integer arithmetic rate used for the ALU roofline
+# (256 CUs x 4 SIMD x 16 lanes x 2.4 GHz).  On gfx950 the 32-bit integer multiplies
+# (v_mul_lo_u32, v_mad_u64_u32) issue at the full VALU rate: the 32-bit loop of the bit-length
+# workload below sustains more than twice a quarter-rate bound.
 N_CU, CLOCK_HZ = 256, 2.4e9
-LANES_PER_CLK = N_CU * 64                       # full-rate 32-bit VALU lanes per clock
-INT32_MUL_PER_S = LANES_PER_CLK / 4 * CLOCK_HZ  # 9.83e12 32-bit multiplies / s
+LANES_PER_CLK = N_CU * 64                   # 32-bit VALU lanes per clock
+INT32_MUL_PER_S = LANES_PER_CLK * CLOCK_HZ  # 3.93e13 32-bit multiplies / s
 
 
 def parse():
@@ -48,10 +50,11 @@ def parse():
     ap.add_argument("--rate", type=float, default=20.0, help="serve workload: Poisson arrival rate (requests/s)")
     ap.add_argument("--duration", type=float, default=8.0, help="serve workload: seconds of arrivals")
     ap.add_argument("--sides", default="64,128,256", help="serve workload: image sides (uniform choice)")
-    ap.add_argument("--workload", choices=("plain", "batch", "serve"), default="plain",
+    ap.add_argument("--workload", choices=("plain", "batch", "serve", "bitlength"), default="plain",
                     help="plain: the 1M-particle 512x512 frame (the reported metric); batch: camera bundles "
                          "of 32^2..512^2 rendered with one sph_hoa_render_batch call; serve: Poisson render "
-                         "requests to the native render server")
+                         "requests to the native render server; bitlength: the accumulation rule in 32/64/96/"
+                         "128-bit integers (the cost study of Sec. 5.1)")
     ap.add_argument("--batch-cams", type=int, default=64, help="cameras per batch (batch workload)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="instead of the benchmark, run 5 plain device copies of MIB MiB each (the "
@@ -208,6 +211,48 @@ def run_serve(a, torch, L, synth):
     print(json.dumps(result), flush=True)
 
 
+def run_bitlength(a, torch, L, synth):
+    """Integer bit-length study (Sec. 5.1): the accumulation rule (Taylor shift by a 32-bit knot
+    distance, then the jump added) in wrap-around 32, 64, 96 and 128-bit integers, 2^20
+    independent accumulators x 1024 knots per launch, degrees 2, 3 and 4.  Reports knots/s per
+    width and the cost of each width relative to 32 bits (the paper puts emulated 64/96/128-bit
+    operations at about 9x/24x/45x a 32-bit one on the GPUs it used).  value = knots/s at 64 bits,
+    D = 3 (the width and degree of the field kernel)."""
+    n, steps = 1 << 20, 1024
+    widths, degrees = (32, 64, 96, 128), (2, 3, 4)
+    ms = {}
+    for D in degrees:
+        for bits in widths:
+            dist, jumps = synth.bit_tables(seed=6, n_table=37, degree=D, bits=bits)
+            for _ in range(max(1, a.warmup)):
+                L.sph_hoa_accumulate_bits(bits, D, dist, jumps, n, steps, want_out=False)
+            t = [L.sph_hoa_accumulate_bits(bits, D, dist, jumps, n, steps, want_out=False)[1]
+                 for _ in range(a.steps)]
+            ms[(D, bits)] = float(np.median(t))
+    knots = float(n) * steps
+    rate = {f"D{D}_w{b}": knots / (ms[(D, b)] * 1e-3) for D in degrees for b in widths}
+    cost = {f"D{D}_w{b}": ms[(D, b)] / ms[(D, 32)] for D in degrees for b in widths}
+    mul32 = 3 * 4 / 2 * knots / (ms[(3, 32)] * 1e-3)   # D (D + 1) / 2 32-bit multiplies per knot
+    result = {
+        "metric": "accumulation-rule knots/s by integer width (64-bit, D=3); cost relative to 32-bit",
+        "value": rate["D3_w64"], "unit": "knots/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": ms[(3, 64)], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u64", "data": "synthetic",
+        "config": {"workload": f"bitlength: {n} accumulators x {steps} knots per launch (4-knot cycle in "
+                               "registers), full-range 32-bit distances and W-bit jumps, widths 32/64/96/128, "
+                               "D = 2, 3, 4",
+                   "ms_per_launch": {f"D{D}_w{b}": ms[(D, b)] for D in degrees for b in widths},
+                   "knots_per_s": rate, "cost_vs_32bit": cost,
+                   "paper_cost_vs_32bit": {"w64": 9, "w96": 24, "w128": 45}},
+        "roofline": {"bound": "alu", "achieved": mul32, "peak": INT32_MUL_PER_S, "unit": "int32 mul/s",
+                     "frac": mul32 / INT32_MUL_PER_S, "traffic": None,
+                     "note": "32-bit, D=3 launch: the rule's 6 multiplies per knot against the full-rate "
+                             "32-bit multiply peak"},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(result), flush=True)
+
+
 def kernel_source_digest():
     import hashlib
 
@@ -263,6 +308,8 @@ def main():
         return run_batch(a, torch, L, synth)
     if a.workload == "serve":
         return run_serve(a, torch, L, synth)
+    if a.workload == "bitlength":
+        return run_bitlength(a, torch, L, synth)
     t_gen = time.time()
     xyz, h, val = synth.clustered_particles(n=a.particles)
     gen_s = time.time() - t_gen

@@ -36,7 +36,9 @@ typedef enum {
   SPH_HOA_E_OVERFLOW = 3,      /* a quantized position or coefficient leaves its integer range */
   SPH_HOA_E_DEVICE = 4,        /* HIP runtime error */
   SPH_HOA_E_UNSUPPORTED = 5,   /* configuration outside the implemented range */
-  SPH_HOA_E_INTERNAL = 6       /* an internal invariant failed (e.g. a ray's knots did not cancel) */
+  SPH_HOA_E_INTERNAL = 6,      /* an internal invariant failed (e.g. a ray's knots did not cancel) */
+  SPH_HOA_E_BUSY = 7,          /* render server: request rejected, the queue is at its limit */
+  SPH_HOA_E_CANCELLED = 8      /* render server: the request was cancelled before it ran */
 } sph_hoa_status;
 
 typedef enum {
@@ -211,11 +213,21 @@ typedef struct {
   int64_t n_rays, n_pairs;    /* over the completed batches */
   double busy_s;              /* worker time spent rendering */
   double p50_ms, p99_ms, max_ms; /* request latency, submit to completion, over completed requests */
+  int64_t rejected;           /* submissions refused by the admission limits */
+  int64_t cancelled;          /* requests cancelled while queued */
 } sph_hoa_server_stats;
 
 /* hbm_budget_bytes: admission bound on a batch's estimated transient device memory (a single
  * request larger than it still runs alone); max_batch_rays: bound on a batch's rays. */
 sph_hoa_status sph_hoa_server_create(int64_t hbm_budget_bytes, int64_t max_batch_rays, sph_hoa_server* out);
+/* Admission limits checked at submission (0: no limit): max_queued - a submission that finds
+ * this many requests waiting is refused with E_BUSY; max_request_bytes - a request whose own
+ * estimated transient device memory exceeds it is refused with E_OUT_OF_MEMORY (it could never
+ * run within that bound).  Refused submissions get no id and count in stats.rejected. */
+sph_hoa_status sph_hoa_server_set_admission(sph_hoa_server server, int64_t max_queued, int64_t max_request_bytes);
+/* paused != 0: the worker starts no new batch (a batch already running completes; submissions
+ * still queue); 0: resume.  Destroying a paused server still renders what is queued. */
+sph_hoa_status sph_hoa_server_pause(sph_hoa_server server, int32_t paused);
 /* Registers an index; *slot names it in submissions. */
 sph_hoa_status sph_hoa_server_add_index(sph_hoa_server server, sph_hoa_index idx, int32_t* slot);
 /* Queues one render (arguments as sph_hoa_render, checked now); *request_id names it. */
@@ -226,9 +238,31 @@ sph_hoa_status sph_hoa_server_submit(sph_hoa_server server, int32_t slot, const 
  * and the status is the request's own); *done = 0 on time-out (status OK, id still valid). */
 sph_hoa_status sph_hoa_server_wait(sph_hoa_server server, int64_t request_id, double timeout_s, int32_t* done,
                                    double* latency_ms);
+/* Cancels a request that is still queued: *cancelled = 1, and its wait then reports done with
+ * status E_CANCELLED (its output buffer is left untouched).  A request already taken by the worker
+ * or completed is not affected (*cancelled = 0).  Unknown id: E_INVALID_ARG. */
+sph_hoa_status sph_hoa_server_cancel(sph_hoa_server server, int64_t request_id, int32_t* cancelled);
 sph_hoa_status sph_hoa_server_get_stats(sph_hoa_server server, sph_hoa_server_stats* stats);
 /* Renders what is still queued, stops the worker and frees the server (not its indices). */
 sph_hoa_status sph_hoa_server_destroy(sph_hoa_server server);
+
+/* ---------------------------------------------------------------- integer bit length
+ *
+ * Microbenchmark of the accumulation rule (Eq. accumulation-rule) in wrap-around W-bit integers,
+ * the cost the paper weighs in Sec. 5.1 (32-bit against emulated 64, 96 and 128 bits).  W = bits
+ * in {32, 64, 96, 128}; a W-bit value is W/32 uint32 limbs, low limb first.  n_threads independent
+ * accumulators each take `steps` knots: knot s of accumulator g is table entry
+ * k = (g + s mod 4) mod n_table.  At knot 0 the state is jumps[k]; at every later knot the state is
+ * first shifted forward by dist[k] (the distance from the previous knot: D (D + 1) / 2
+ * multiply-adds of a W-bit coefficient by the 32-bit distance) and then jumps[k] is added, all
+ * modulo 2^W.  Host buffers (read or written before the call returns): dist [n_table],
+ * jumps [n_table][D + 1][W/32], out_host [n_threads][D + 1][W/32] (the final states; NULL: timing
+ * only).  *ms_out (may be NULL): the kernel's duration from hipEvents on `stream`.  Limits:
+ * 1 <= degree <= 6, n_table >= 1, 1 <= n_threads <= 2^26, steps a positive multiple of 4;
+ * otherwise E_INVALID_ARG.  Synchronous; device buffers are allocated and freed per call. */
+sph_hoa_status sph_hoa_accumulate_bits(int32_t bits, int32_t degree, const uint32_t* dist, const uint32_t* jumps,
+                                       int32_t n_table, int64_t n_threads, int32_t steps, uint32_t* out_host,
+                                       float* ms_out, void* stream);
 
 sph_hoa_status sph_hoa_index_free(sph_hoa_index idx);
 

@@ -19,7 +19,7 @@ KERNEL_WENDLAND_C2 = 1
 FLAG_EXACT = 1
 
 STATUS = {0: "OK", 1: "E_INVALID_ARG", 2: "E_OUT_OF_MEMORY", 3: "E_OVERFLOW", 4: "E_DEVICE", 5: "E_UNSUPPORTED",
-          6: "E_INTERNAL"}
+          6: "E_INTERNAL", 7: "E_BUSY", 8: "E_CANCELLED"}
 
 
 class SphHoaError(RuntimeError):
@@ -74,7 +74,7 @@ class ServerStats(ctypes.Structure):
     _fields_ = [("completed", ctypes.c_int64), ("failed", ctypes.c_int64), ("queued", ctypes.c_int64),
                 ("batches", ctypes.c_int64), ("n_rays", ctypes.c_int64), ("n_pairs", ctypes.c_int64),
                 ("busy_s", ctypes.c_double), ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double),
-                ("max_ms", ctypes.c_double)]
+                ("max_ms", ctypes.c_double), ("rejected", ctypes.c_int64), ("cancelled", ctypes.c_int64)]
 
 
 class Stats(ctypes.Structure):
@@ -86,7 +86,8 @@ class Stats(ctypes.Structure):
 
 EXPORTS = ["sph_hoa_build_index", "sph_hoa_approx_rays", "sph_hoa_render", "sph_hoa_render_batch",
            "sph_hoa_server_create", "sph_hoa_server_add_index", "sph_hoa_server_submit", "sph_hoa_server_wait",
-           "sph_hoa_server_get_stats", "sph_hoa_server_destroy",
+           "sph_hoa_server_get_stats", "sph_hoa_server_destroy", "sph_hoa_server_set_admission",
+           "sph_hoa_server_cancel", "sph_hoa_server_pause", "sph_hoa_accumulate_bits",
            "sph_hoa_index_free",
            "sph_hoa_index_get_info", "sph_hoa_index_get_lut", "sph_hoa_index_get_grid", "sph_hoa_index_get_stats",
            "sph_hoa_index_set_timing",
@@ -116,6 +117,10 @@ def lib():
     L.sph_hoa_server_wait.argtypes = [vp, i64, dbl, ctypes.POINTER(i32), ctypes.POINTER(dbl)]
     L.sph_hoa_server_get_stats.argtypes = [vp, ctypes.POINTER(ServerStats)]
     L.sph_hoa_server_destroy.argtypes = [vp]
+    L.sph_hoa_server_set_admission.argtypes = [vp, i64, i64]
+    L.sph_hoa_server_cancel.argtypes = [vp, i64, ctypes.POINTER(i32)]
+    L.sph_hoa_server_pause.argtypes = [vp, i32]
+    L.sph_hoa_accumulate_bits.argtypes = [i32, i32, vp, vp, i32, i64, i32, vp, ctypes.POINTER(ctypes.c_float), vp]
     L.sph_hoa_index_free.argtypes = [vp]
     L.sph_hoa_index_get_info.argtypes = [vp, ctypes.POINTER(IndexInfo)]
     L.sph_hoa_index_get_lut.argtypes = [vp, vp, vp, vp]
@@ -396,6 +401,22 @@ class Server:
                 self._keep.pop(request_id, None)
         return bool(done.value), lat.value
 
+    def set_admission(self, max_queued=0, max_request_bytes=0):
+        """Refuse submissions when max_queued requests wait (E_BUSY) or when one request alone
+        would need more than max_request_bytes of device memory (E_OUT_OF_MEMORY); 0: no limit."""
+        _check(lib().sph_hoa_server_set_admission(self.handle, int(max_queued), int(max_request_bytes)))
+
+    def pause(self, paused=True):
+        """Stop (True) or resume (False) the worker taking new batches; submissions still queue."""
+        _check(lib().sph_hoa_server_pause(self.handle, 1 if paused else 0))
+
+    def cancel(self, request_id):
+        """True if the request was still queued and is now cancelled (its wait raises
+        E_CANCELLED); False if it already ran or is running."""
+        c = ctypes.c_int32()
+        _check(lib().sph_hoa_server_cancel(self.handle, int(request_id), ctypes.byref(c)))
+        return bool(c.value)
+
     def stats(self):
         s = ServerStats()
         _check(lib().sph_hoa_server_get_stats(self.handle, ctypes.byref(s)))
@@ -450,3 +471,24 @@ def sph_hoa_optimal_tau(kernel, degree, sigma, h_repr, phi_repr):
     t = ctypes.c_double()
     _check(lib().sph_hoa_optimal_tau(kernel, degree, sigma, h_repr, phi_repr, ctypes.byref(t)))
     return t.value
+
+
+def sph_hoa_accumulate_bits(bits, degree, dist, jumps, n_threads, steps, want_out=True):
+    """Accumulation rule in wrap-around `bits`-bit integers (Sec. 5.1 cost study).
+
+    dist: uint32 [n_table]; jumps: uint32 [n_table, degree + 1, bits // 32] (low limb first).
+    Returns (states uint32 [n_threads, degree + 1, bits // 32] or None, kernel milliseconds)."""
+    import numpy as np
+
+    L = bits // 32
+    d = np.ascontiguousarray(dist, dtype=np.uint32)
+    j = np.ascontiguousarray(jumps, dtype=np.uint32)
+    if j.shape != (d.shape[0], degree + 1, L):
+        raise ValueError(f"jumps must have shape {(d.shape[0], degree + 1, L)}, got {j.shape}")
+    out = np.zeros((n_threads, degree + 1, L), dtype=np.uint32) if want_out else None
+    ms = ctypes.c_float()
+    _check(lib().sph_hoa_accumulate_bits(bits, degree, d.ctypes.data_as(ctypes.c_void_p),
+                                         j.ctypes.data_as(ctypes.c_void_p), d.shape[0], n_threads, steps,
+                                         out.ctypes.data_as(ctypes.c_void_p) if want_out else None,
+                                         ctypes.byref(ms), _stream()))
+    return out, ms.value

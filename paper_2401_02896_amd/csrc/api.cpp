@@ -92,6 +92,8 @@ const char* sph_hoa_status_string(sph_hoa_status s) {
     case SPH_HOA_E_DEVICE: return "device error";
     case SPH_HOA_E_UNSUPPORTED: return "unsupported configuration";
     case SPH_HOA_E_INTERNAL: return "internal invariant failed";
+    case SPH_HOA_E_BUSY: return "request queue full";
+    case SPH_HOA_E_CANCELLED: return "request cancelled";
   }
   return "unknown status";
 }
@@ -413,6 +415,16 @@ sph_hoa_status sph_hoa_optimal_tau(sph_hoa_kernel kernel, int32_t degree, double
   });
 }
 
+sph_hoa_status sph_hoa_accumulate_bits(int32_t bits, int32_t degree, const uint32_t* dist, const uint32_t* jumps,
+                                       int32_t n_table, int64_t n_threads, int32_t steps, uint32_t* out_host,
+                                       float* ms_out, void* stream) {
+  return guarded([&]() {
+    require(dist && jumps, "NULL argument");
+    sph::accumulate_bits(bits, degree, dist, jumps, n_table, n_threads, steps, out_host, ms_out,
+                         static_cast<hipStream_t>(stream));
+  });
+}
+
 }  // extern "C"
 
 sph_hoa_status sph_hoa_server_create(int64_t hbm_budget_bytes, int64_t max_batch_rays, sph_hoa_server* out) {
@@ -453,6 +465,29 @@ sph_hoa_status sph_hoa_server_wait(sph_hoa_server server, int64_t request_id, do
     if (!sph::server_wait(server->s, request_id, timeout_s, latency_ms, &rs, &re)) return;
     *done = 1;
     if (rs != SPH_HOA_OK) throw sph::Error(rs, "request failed: " + re);
+  });
+}
+
+sph_hoa_status sph_hoa_server_set_admission(sph_hoa_server server, int64_t max_queued, int64_t max_request_bytes) {
+  return guarded([&]() {
+    require(server != nullptr, "NULL argument");
+    require(max_queued >= 0 && max_request_bytes >= 0, "limits must be >= 0");
+    sph::server_set_admission(server->s, max_queued, max_request_bytes);
+  });
+}
+
+sph_hoa_status sph_hoa_server_pause(sph_hoa_server server, int32_t paused) {
+  return guarded([&]() {
+    require(server != nullptr, "NULL argument");
+    sph::server_pause(server->s, paused != 0);
+  });
+}
+
+sph_hoa_status sph_hoa_server_cancel(sph_hoa_server server, int64_t request_id, int32_t* cancelled) {
+  return guarded([&]() {
+    require(server && cancelled, "NULL argument");
+    *cancelled = 0;
+    *cancelled = sph::server_cancel(server->s, request_id) ? 1 : 0;
   });
 }
 

@@ -186,6 +186,9 @@ int64_t server_submit(Server* s, int slot, const sph_hoa_camera* cam, const sph_
 bool server_wait(Server* s, int64_t id, double timeout_s, double* latency_ms, sph_hoa_status* req_status,
                  std::string* req_error);
 void server_stats(Server* s, sph_hoa_server_stats* st);
+void server_set_admission(Server* s, int64_t max_queued, int64_t max_request_bytes);
+bool server_cancel(Server* s, int64_t id);
+void server_pause(Server* s, bool paused);
 
 // build (index.hip)
 void build_index_device(Index& ix, const float* xyz, const float* h, const float* value, hipStream_t st);
@@ -201,6 +204,10 @@ struct FieldOut {
 // n_batch > 0: render the cameras batch[0..n_batch) together (rays concatenated in camera order)
 void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam, const sph_hoa_rays* rays,
               FieldOut& out, hipStream_t st, const sph_hoa_camera* batch = nullptr, int n_batch = 0);
+
+// integer bit-length microbenchmark of the accumulation rule (bitlength.hip); host buffers
+void accumulate_bits(int bits, int D, const uint32_t* dist, const uint32_t* jumps, int n_table, int64_t n_threads,
+                     int steps, uint32_t* out_host, float* ms, hipStream_t st);
 
 // small device utilities (util.hip)
 void device_exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, DevBuf& tmp, hipStream_t st);

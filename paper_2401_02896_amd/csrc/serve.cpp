@@ -1,6 +1,7 @@
 // Render server: resident indices, a request queue and continuous batching.
 //
-// Requests (one camera each) are queued by any host thread.  One worker thread repeatedly takes
+// Requests (one camera each) are queued by any host thread, subject to admission limits (queue
+// length, one request's estimated memory); a queued request can be cancelled.  One worker thread repeatedly takes
 // the oldest request and admits, in arrival order, the queued requests that use the same index
 // and transfer function while the batch's estimated device memory stays within the budget; the
 // batch is rendered by one batched launch chain (run_rays over all its cameras), and each image
@@ -56,13 +57,15 @@ struct Server {
   std::deque<std::shared_ptr<Request>> queue;
   std::unordered_map<int64_t, std::shared_ptr<Request>> live;
   int64_t next_id = 1;
-  bool stop = false;
+  bool stop = false, paused = false;
   std::thread worker;
   hipStream_t stream = nullptr;
   DevBuf staging;
   // statistics
   std::vector<double> latencies_ms;
-  int64_t completed = 0, failed = 0, batches = 0, pairs = 0, rays = 0;
+  int64_t completed = 0, failed = 0, batches = 0, pairs = 0, rays = 0, rejected = 0, cancelled = 0;
+  // admission limits (0: none)
+  int64_t max_queued = 0, max_request_bytes = 0;
   double busy_s = 0.0;
 
   // device bytes of one request's transient buffers, from the index's hits-per-ray estimate
@@ -79,8 +82,8 @@ struct Server {
       std::vector<std::shared_ptr<Request>> batch;
       {
         std::unique_lock<std::mutex> lk(mu);
-        cv_work.wait(lk, [&] { return stop || !queue.empty(); });
-        if (queue.empty()) return;  // stop requested and drained
+        cv_work.wait(lk, [&] { return stop || (!paused && !queue.empty()); });
+        if (queue.empty()) return;  // stop requested and drained (a stop overrides a pause)
         // oldest request first; then admit compatible requests in arrival order within the budget
         const std::shared_ptr<Request> head = queue.front();
         queue.pop_front();
@@ -209,6 +212,18 @@ int64_t server_submit(Server* s, int slot, const sph_hoa_camera* cam, const sph_
     std::lock_guard<std::mutex> lk(s->mu);
     if (slot < 0 || slot >= (int)s->indices.size()) throw Error(SPH_HOA_E_INVALID_ARG, "unknown index slot");
     if (s->stop) throw Error(SPH_HOA_E_INVALID_ARG, "server is shutting down");
+    if (s->max_request_bytes > 0) {
+      const int64_t b = s->estimate_bytes(slot, *cam);
+      if (b > s->max_request_bytes) {
+        ++s->rejected;
+        throw Error(SPH_HOA_E_OUT_OF_MEMORY, "request needs about " + std::to_string(b) +
+                                                 " bytes of device memory, above the per-request limit");
+      }
+    }
+    if (s->max_queued > 0 && (int64_t)s->queue.size() >= s->max_queued) {
+      ++s->rejected;
+      throw Error(SPH_HOA_E_BUSY, "request queue is full");
+    }
     r->id = s->next_id++;
     s->live[r->id] = r;
     s->queue.push_back(r);
@@ -233,9 +248,44 @@ bool server_wait(Server* s, int64_t id, double timeout_s, double* latency_ms, sp
   return true;
 }
 
+void server_set_admission(Server* s, int64_t max_queued, int64_t max_request_bytes) {
+  std::lock_guard<std::mutex> lk(s->mu);
+  s->max_queued = max_queued;
+  s->max_request_bytes = max_request_bytes;
+}
+
+void server_pause(Server* s, bool paused) {
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->paused = paused;
+  }
+  s->cv_work.notify_all();
+}
+
+bool server_cancel(Server* s, int64_t id) {
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->live.find(id);
+    if (it == s->live.end()) throw Error(SPH_HOA_E_INVALID_ARG, "unknown or already collected request id");
+    const std::shared_ptr<Request> r = it->second;
+    auto q = std::find(s->queue.begin(), s->queue.end(), r);
+    if (q == s->queue.end()) return false;  // taken by the worker or already done
+    s->queue.erase(q);
+    r->done = true;
+    r->status = SPH_HOA_E_CANCELLED;
+    r->error = "cancelled";
+    r->t_done = now_s();
+    ++s->cancelled;
+  }
+  s->cv_done.notify_all();
+  return true;
+}
+
 void server_stats(Server* s, sph_hoa_server_stats* st) {
   std::lock_guard<std::mutex> lk(s->mu);
   std::memset(st, 0, sizeof(*st));
+  st->rejected = s->rejected;
+  st->cancelled = s->cancelled;
   st->completed = s->completed;
   st->failed = s->failed;
   st->queued = (int64_t)s->queue.size();

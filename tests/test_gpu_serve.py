@@ -128,3 +128,66 @@ def test_server_errors_and_timeouts():
             srv.wait(rid, 0.0)
     finally:
         srv.close()
+
+
+def test_admission_limits_cancel_and_pause():
+    import time
+
+    sc = H.tiny_scene()
+    idx = sc.index()
+    tf = torch.as_tensor(synth.transfer_function(), device="cuda")
+    cams = _cams()[:4]
+    refs = _refs(idx, cams, [tf])
+    srv = L.Server()
+    try:
+        slot = srv.add_index(idx)
+        srv.set_admission(max_queued=2)
+        srv.pause(True)
+        r0, _ = srv.submit(slot, cams[0], tf, 0.0, VMAX, STEP)
+        r1, o1 = srv.submit(slot, cams[1], tf, 0.0, VMAX, STEP)
+        with pytest.raises(L.SphHoaError) as e:  # two already wait
+            srv.submit(slot, cams[2], tf, 0.0, VMAX, STEP)
+        assert L.STATUS[e.value.status] == "E_BUSY"
+        assert srv.cancel(r0)
+        with pytest.raises(L.SphHoaError) as e:
+            srv.wait(r0, 0.0)
+        assert L.STATUS[e.value.status] == "E_CANCELLED"
+        with pytest.raises(L.SphHoaError):  # the cancelled id was collected by its wait
+            srv.cancel(r0)
+        r2, o2 = srv.submit(slot, cams[2], tf, 0.0, VMAX, STEP)  # room again
+        assert srv.stats()["queued"] == 2
+        assert srv.wait(r1, 0.2)[0] is False and srv.stats()["completed"] == 0  # paused: nothing runs
+        srv.pause(False)
+        assert srv.wait(r1, 120.0)[0] and srv.wait(r2, 120.0)[0]
+        assert torch.equal(o1, refs[1]) and torch.equal(o2, refs[2])
+        # a request that already ran cannot be cancelled; its wait still reports it
+        r3, o3 = srv.submit(slot, cams[3], tf, 0.0, VMAX, STEP)
+        t0 = time.time()
+        while srv.stats()["completed"] < 3 and time.time() - t0 < 60:
+            time.sleep(0.01)
+        assert not srv.cancel(r3)
+        assert srv.wait(r3, 120.0)[0] and torch.equal(o3, refs[3])
+        # one request larger than the per-request memory bound is refused outright
+        srv.set_admission(max_queued=0, max_request_bytes=1000)
+        with pytest.raises(L.SphHoaError) as e:
+            srv.submit(slot, synth.tiny_camera(64, 64), tf, 0.0, VMAX, STEP)
+        assert L.STATUS[e.value.status] == "E_OUT_OF_MEMORY"
+        st = srv.stats()
+        assert st["rejected"] == 2 and st["cancelled"] == 1 and st["completed"] == 3 and st["failed"] == 0
+    finally:
+        srv.close()
+
+
+def test_destroy_drains_a_paused_queue():
+    sc = H.tiny_scene()
+    idx = sc.index()
+    tf = torch.as_tensor(synth.transfer_function(), device="cuda")
+    cam = _cams()[1]
+    ref = _refs(idx, [cam], [tf])[0]
+    srv = L.Server()
+    slot = srv.add_index(idx)
+    srv.pause(True)
+    _, out = srv.submit(slot, cam, tf, 0.0, VMAX, STEP)
+    srv.close()  # renders what is queued, then stops
+    torch.cuda.synchronize()
+    assert torch.equal(out, ref)
