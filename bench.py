@@ -349,10 +349,11 @@ def main():
     gather_ms = st["ms_gather"] / max(1, st["timed_calls"])
     # Roofline of the field kernel (ALU bound).  Algorithmic work per contribution: the integer
     # multiplies of the accumulation rule applied once to each of the particle's K + 1 knots,
-    # D(D+1)/2 products of a 64-bit coefficient by a 32-bit distance, 3 32-bit multiplies each.
+    # D(D+1)/2 products of a 64-bit coefficient by a 32-bit distance, 2 32-bit multiplies each
+    # (v_mad_u64_u32 for the low word, v_mul_lo_u32 for the high word).
     # (The kernel applies the rule three times per knot - aggregate, peak, pieces - and adds the
     # float64 merge, so the fraction also measures that overhead.)
-    mul32_per_pair = (K + 1) * (D * (D + 1) // 2) * 3
+    mul32_per_pair = (K + 1) * (D * (D + 1) // 2) * 2
     achieved = mul32_per_pair * pairs_per_frame / (field_ms * 1e-3) / 1e12
     peak = INT32_MUL_PER_S / 1e12
     roofline = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tmul32/s",
