@@ -29,6 +29,8 @@ Pinned by tests/test_oracle_lut.py: the dimension floor(K D / 2) of the space
 evenness/continuity/compact support of the result, local optimality of the
 knots, the overall approximation errors E_{K,D} printed in Fig. 4, and the line
 integral of the approximation against the closed-form kernel column integral.
+The storage rounding of the table precision study (round_storage) is pinned by
+hand-worked ties and by torch's float32 -> bfloat16 conversion.
 """
 from __future__ import annotations
 
@@ -425,3 +427,22 @@ def overall_error(kind: str, K: int, D: int, n: int, thetas=None):
         e2 = np.array([project(kind, float(l), th, K, D)["E2"] for l, th in zip(lams, thetas)])
     integral = np.sum(lams * e2) * (q / n)
     return math.sqrt(2.0 * math.pi * integral) / kernels.kappa(kind), thetas, e2
+
+
+def round_storage(values, fmt: str):
+    """Table values as a float table stored in `fmt` holds them, returned as float64 (the table
+    precision study; the table is that of Sec. 3.1).
+
+    fp64: unchanged.  fp32: the nearest float32.  bf16: the nearest float32, then the nearest
+    number with 8 significant bits, ties to even: with f = m 2^e, 1/2 <= |m| < 1 (frexp), the
+    result is rint(256 m) / 256 * 2^e (rint rounds half to even; every step is exact in float64)."""
+    a = np.asarray(values, dtype=np.float64)
+    if fmt == "fp64":
+        return a.copy()
+    f = a.astype(np.float32).astype(np.float64)
+    if fmt == "fp32":
+        return f
+    if fmt != "bf16":
+        raise ValueError(fmt)
+    m, e = np.frexp(f)
+    return np.ldexp(np.rint(m * 256.0) / 256.0, e)

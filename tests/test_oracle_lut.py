@@ -151,3 +151,28 @@ def test_fig4_approximation_errors():
         res = p.map(_overall, cases)
     for K, D, E in res:
         assert abs(E / F["E"][(K, D)] - 1) < 4e-4, (K, D, E)
+
+
+def test_storage_rounding_hand_cases():
+    """bf16 keeps 8 significant bits: the spacing just above 1 is 2^-7.  1 + 2^-8 lies halfway
+    between 1 and 1 + 2^-7 and goes to the even one (1); 1 + 3 2^-8 lies halfway between
+    1 + 2^-7 (odd last bit) and 1 + 2^-6, and goes to 1 + 2^-6; just above a tie rounds up."""
+    x = np.array([1.0, 1 + 2.0 ** -8, 1 + 3 * 2.0 ** -8, 1 + 2.0 ** -8 + 2.0 ** -20, -(1 + 3 * 2.0 ** -8),
+                  0.0, 3.0, 255.5, 256.5, 2.0 ** -130])
+    want = np.array([1.0, 1.0, 1 + 2.0 ** -6, 1 + 2.0 ** -7, -(1 + 2.0 ** -6), 0.0, 3.0, 256.0, 256.0,
+                     2.0 ** -130])
+    assert np.array_equal(lut.round_storage(x, "bf16"), want)
+    # fp32: 1 + 2^-30 is not a float32 and rounds to 1; 1/3 rounds to the float32 nearest it
+    assert lut.round_storage(np.array([1 + 2.0 ** -30]), "fp32")[0] == 1.0
+    assert lut.round_storage(np.array([1.0 / 3.0]), "fp32")[0] == float(np.float32(1.0 / 3.0))
+    assert np.array_equal(lut.round_storage(x, "fp64"), x)
+
+
+def test_storage_rounding_matches_torch_bfloat16():
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(7)
+    x = np.concatenate([rng.normal(0, 1, 20000) * 10.0 ** rng.uniform(-12, 12, 20000),
+                        rng.uniform(-1, 1, 20000)])
+    f32 = torch.from_numpy(x.astype(np.float32))
+    ref = f32.to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(lut.round_storage(x, "bf16"), ref)
