@@ -50,11 +50,13 @@ def parse():
     ap.add_argument("--rate", type=float, default=20.0, help="serve workload: Poisson arrival rate (requests/s)")
     ap.add_argument("--duration", type=float, default=8.0, help="serve workload: seconds of arrivals")
     ap.add_argument("--sides", default="64,128,256", help="serve workload: image sides (uniform choice)")
-    ap.add_argument("--workload", choices=("plain", "batch", "serve", "bitlength"), default="plain",
+    ap.add_argument("--workload", choices=("plain", "batch", "serve", "bitlength", "precision"), default="plain",
                     help="plain: the 1M-particle 512x512 frame (the reported metric); batch: camera bundles "
                          "of 32^2..512^2 rendered with one sph_hoa_render_batch call; serve: Poisson render "
                          "requests to the native render server; bitlength: the accumulation rule in 32/64/96/"
-                         "128-bit integers (the cost study of Sec. 5.1)")
+                         "128-bit integers (the cost study of Sec. 5.1); precision: the plain frame with the "
+                         "float table stored in fp64 / fp32 / bf16, timed, with pixel errors against the "
+                         "float64 oracle")
     ap.add_argument("--batch-cams", type=int, default=64, help="cameras per batch (batch workload)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="instead of the benchmark, run 5 plain device copies of MIB MiB each (the "
@@ -253,6 +255,65 @@ def run_bitlength(a, torch, L, synth):
     print(json.dumps(result), flush=True)
 
 
+def run_precision(a, torch, L, synth):
+    """Table storage precision: the plain frame (1M clustered particles, Wendland C2, K = 4, D = 3,
+    tol 1e-3, 512^2) rendered with the float table of Sec. 3.1 stored in fp64, fp32 and bf16.
+    Reports the frame time of each and its pixel differences, against the fp64-table frame and
+    against the float64 oracle on a bounded sample of rays.  value = contributions/s with the
+    bf16 table."""
+    xyz, h, val = synth.clustered_particles(n=a.particles)
+    kind, K, D, tol = "wendland", 4, 3, 1e-3
+    cam = synth.plain_camera(a.size, a.size)
+    tf = synth.transfer_function()
+    vmin, vmax, step = 0.0, 300.0, 2.0 / 512
+    res, imgs = {}, {}
+    for fmt in ("fp64", "fp32", "bf16"):
+        idx = L.sph_hoa_build_index(xyz, h, val, kernel=L.KERNEL_WENDLAND_C2, degree=D, pieces=K, lut_entries=4096,
+                                    merge_tol=tol, lut_precision=fmt)
+        out = torch.empty((cam["height"], cam["width"], 4), dtype=torch.float32, device="cuda")
+        for _ in range(max(1, a.warmup)):
+            L.sph_hoa_render(idx, cam, tf, vmin, vmax, step, out=out)
+        torch.cuda.synchronize()
+        lat, pairs = [], 0
+        for _ in range(a.steps):
+            ts = time.perf_counter()
+            L.sph_hoa_render(idx, cam, tf, vmin, vmax, step, out=out)
+            torch.cuda.synchronize()
+            lat.append(time.perf_counter() - ts)
+            pairs += idx.stats()["n_pairs"]
+        imgs[fmt] = out.reshape(-1, 4).cpu().numpy().astype(np.float64)
+        res[fmt] = {"p50_ms": float(np.percentile(np.array(lat) * 1e3, 50)),
+                    "contributions_per_s": pairs / sum(lat)}
+        if fmt == "fp64":
+            info = idx.info()
+        idx.free()
+    for fmt in ("fp32", "bf16"):
+        d = np.abs(imgs[fmt] - imgs["fp64"])
+        res[fmt]["max_abs_rgba_vs_fp64_table"] = float(d.max())
+        res[fmt]["mean_abs_rgba_vs_fp64_table"] = float(d.mean())
+    oracle = None
+    if not a.no_cpu:
+        _, _, results = cpu_baseline(a, xyz, h, val, info, cam, tf, vmin, vmax, step, kind, K, D, tol,
+                                     imgs["fp64"].astype(np.float32))
+        kept = [(r, px) for (r, _, px, m, _) in results if m > 1e-6]
+        for fmt in ("fp64", "fp32", "bf16"):
+            e = [float(np.max(np.abs(imgs[fmt][r] - px))) for r, px in kept]
+            res[fmt]["max_abs_rgba_vs_oracle"] = max(e) if e else None
+            res[fmt]["mean_abs_rgba_vs_oracle"] = float(np.mean(e)) if e else None
+        oracle = f"{len(kept)} random rays of the frame, float64 oracle with the float64 table"
+    result = {
+        "metric": "particle-ray contributions/s with the bf16 table; pixel error vs fp64 table and oracle",
+        "value": res["bf16"]["contributions_per_s"], "unit": "contributions/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": res["bf16"]["p50_ms"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+        "config": {"workload": f"precision: plain frame ({a.particles} clustered particles, Wendland C2, K=4, D=3, "
+                               f"tol 1e-3, {a.size}x{a.size}) with the table stored in fp64 / fp32 / bf16",
+                   "by_table_precision": res, "oracle_sample": oracle},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(result), flush=True)
+
+
 def kernel_source_digest():
     import hashlib
 
@@ -310,6 +371,8 @@ def main():
         return run_serve(a, torch, L, synth)
     if a.workload == "bitlength":
         return run_bitlength(a, torch, L, synth)
+    if a.workload == "precision":
+        return run_precision(a, torch, L, synth)
     t_gen = time.time()
     xyz, h, val = synth.clustered_particles(n=a.particles)
     gen_s = time.time() - t_gen
@@ -379,7 +442,7 @@ def main():
     }
     img = out.cpu().numpy().reshape(-1, 4)
     if not a.no_cpu:
-        result["cpu_baseline"], result["parity"] = cpu_baseline(a, xyz, h, val, info, cam, tf, vmin, vmax, step,
+        result["cpu_baseline"], result["parity"], _ = cpu_baseline(a, xyz, h, val, info, cam, tf, vmin, vmax, step,
                                                                 kind, K, D, tol, img)
     print(json.dumps(result), flush=True)
 
@@ -441,7 +504,7 @@ def cpu_baseline(a, xyz, h, val, info, cam, tf, vmin, vmax, step, kind, K, D, to
     parity = {"rays": len(results), "rays_compared": len(diffs),
               "max_abs_rgba": max(diffs) if diffs else None, "tol": 1e-4,
               "quanta_rel_diff": {"tau": abs(info["tau"] / tau - 1), "sigma": abs(info["sigma"] / sigma - 1)}}
-    return base, parity
+    return base, parity, results
 
 
 if __name__ == "__main__":

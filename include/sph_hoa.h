@@ -48,6 +48,14 @@ typedef enum {
 
 /* approx_rays: also return the sorted knots and the pre-merge exact integer pieces */
 #define SPH_HOA_FLAG_EXACT 1u
+/* sph_hoa_params.flags: storage precision of the float table (the knots theta_k and projection
+ * jumps s-hat of Sec. 3.1), for the precision study.  Every table value is rounded once, when the
+ * index is built, to the nearest float32 (LUT_FP32) or to the nearest bfloat16 of that float32
+ * (LUT_BF16: 8 significant bits, ties to even); the per-hit quantization (Sec. 4.3) then uses the
+ * rounded values, and the integer accumulation stays exact (the closure is computed from the
+ * rounded jumps).  At most one of the two; neither: float64. */
+#define SPH_HOA_FLAG_LUT_FP32 2u
+#define SPH_HOA_FLAG_LUT_BF16 4u
 
 /* Method parameters (Sec. 3.2 K and D, Sec. 4.4 quanta, Sec. 5 bit length). */
 typedef struct {
@@ -62,7 +70,7 @@ typedef struct {
   double tau;           /* > 0: length quantum to use instead of the minimiser of Q_D */
   const double* knot_table; /* optional HOST array [lut_entries][ceil(K/2)] of optimal knots theta_k
                                (units of h) replacing the library's own optimisation (Sec. 3.4); copied */
-  uint32_t flags;       /* reserved, 0 */
+  uint32_t flags;       /* 0, SPH_HOA_FLAG_LUT_FP32 or SPH_HOA_FLAG_LUT_BF16 */
 } sph_hoa_params;
 
 typedef struct sph_hoa_index_s* sph_hoa_index; /* opaque; owns its device memory */
@@ -76,6 +84,7 @@ typedef struct {
   double cell0;         /* finest cell size c_0 (a power of two) */
   int32_t n_levels;
   int32_t level_dims[32][3];
+  uint32_t lut_flags;   /* table storage precision the index was built with (params.flags) */
 } sph_hoa_index_info;
 
 /* Rays x(t) = origin + t * dir, t in [t_min, t_max] (Fig. 1). */

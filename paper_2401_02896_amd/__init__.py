@@ -17,6 +17,8 @@ LIB_PATH = os.path.join(HERE, "libsph_hoa.so")
 KERNEL_CUBIC = 0
 KERNEL_WENDLAND_C2 = 1
 FLAG_EXACT = 1
+FLAG_LUT_FP32 = 2
+FLAG_LUT_BF16 = 4
 
 STATUS = {0: "OK", 1: "E_INVALID_ARG", 2: "E_OUT_OF_MEMORY", 3: "E_OVERFLOW", 4: "E_DEVICE", 5: "E_UNSUPPORTED",
           6: "E_INTERNAL", 7: "E_BUSY", 8: "E_CANCELLED"}
@@ -40,7 +42,8 @@ class IndexInfo(ctypes.Structure):
                 ("pieces", ctypes.c_int32), ("lut_entries", ctypes.c_int32), ("tau", ctypes.c_double),
                 ("sigma", ctypes.c_double), ("a_max", ctypes.c_double), ("h_repr", ctypes.c_double),
                 ("phi_repr", ctypes.c_double), ("grid_lo", ctypes.c_double * 3), ("cell0", ctypes.c_double),
-                ("n_levels", ctypes.c_int32), ("level_dims", (ctypes.c_int32 * 3) * 32)]
+                ("n_levels", ctypes.c_int32), ("level_dims", (ctypes.c_int32 * 3) * 32),
+                ("lut_flags", ctypes.c_uint32)]
 
 
 class Rays(ctypes.Structure):
@@ -188,7 +191,7 @@ class Index:
                 "lut_entries": inf.lut_entries, "tau": inf.tau, "sigma": inf.sigma, "a_max": inf.a_max,
                 "h_repr": inf.h_repr, "phi_repr": inf.phi_repr, "grid_lo": list(inf.grid_lo), "cell0": inf.cell0,
                 "n_levels": inf.n_levels,
-                "level_dims": [list(inf.level_dims[l]) for l in range(inf.n_levels)]}
+                "level_dims": [list(inf.level_dims[l]) for l in range(inf.n_levels)], "lut_flags": inf.lut_flags}
 
     def lut(self):
         import numpy as np
@@ -221,8 +224,9 @@ class Index:
 
 
 def sph_hoa_build_index(xyz, h, value, kernel=KERNEL_CUBIC, degree=2, pieces=4, lut_entries=4096, merge_tol=1e-3,
-                        a_max=0.0, h_repr=0.0, phi_repr=0.0, tau=0.0, knot_table=None):
-    """Build an index (sph_hoa_build_index).  xyz [n,3], h [n], value [n]: tensors or arrays."""
+                        a_max=0.0, h_repr=0.0, phi_repr=0.0, tau=0.0, knot_table=None, lut_precision="fp64"):
+    """Build an index (sph_hoa_build_index).  xyz [n,3], h [n], value [n]: tensors or arrays.
+    lut_precision: storage precision of the float table, "fp64", "fp32" or "bf16"."""
     import numpy as np
 
     x = _dev_f32(xyz)
@@ -231,7 +235,10 @@ def sph_hoa_build_index(xyz, h, value, kernel=KERNEL_CUBIC, degree=2, pieces=4, 
     n = int(hh.numel())
     if x.numel() != 3 * n or v.numel() != n:
         raise ValueError("xyz must be [n, 3], h and value [n]")
-    p = Params(degree, pieces, lut_entries, 64, merge_tol, a_max, h_repr, phi_repr, tau, None, 0)
+    flags = {"fp64": 0, "fp32": FLAG_LUT_FP32, "bf16": FLAG_LUT_BF16}.get(lut_precision)
+    if flags is None:
+        raise ValueError(f"lut_precision must be fp64, fp32 or bf16, got {lut_precision!r}")
+    p = Params(degree, pieces, lut_entries, 64, merge_tol, a_max, h_repr, phi_repr, tau, None, flags)
     kt = None
     if knot_table is not None:
         kt = np.ascontiguousarray(knot_table, dtype=np.float64)

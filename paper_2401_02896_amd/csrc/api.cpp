@@ -81,6 +81,22 @@ void check_method(int K, int D) {
 
 }  // namespace
 
+namespace {
+// Float64 -> nearest float32, and for bf16 further to the nearest value with 8 significant bits
+// (ties to even), the storage formats of the table precision study.
+double round_storage(double x, bool bf16) {
+  const float f = (float)x;
+  if (!bf16 || !std::isfinite(f)) return (double)f;
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  const uint32_t lsb = (u >> 16) & 1u;
+  u = (u + 0x7fffu + lsb) & 0xffff0000u;
+  float r;
+  std::memcpy(&r, &u, 4);
+  return (double)r;
+}
+}  // namespace
+
 extern "C" {
 
 const char* sph_hoa_status_string(sph_hoa_status s) {
@@ -117,7 +133,9 @@ sph_hoa_status sph_hoa_build_index(const float* xyz, const float* h, const float
     require(std::isfinite(p->merge_tol) && p->merge_tol >= 0.0, "merge_tol must be finite and >= 0");
     require(std::isfinite(p->a_max) && std::isfinite(p->h_repr) && std::isfinite(p->phi_repr) &&
                 std::isfinite(p->tau), "quanta parameters must be finite");
-    require(p->flags == 0, "params.flags is reserved");
+    require((p->flags & ~(SPH_HOA_FLAG_LUT_FP32 | SPH_HOA_FLAG_LUT_BF16)) == 0,
+            "params.flags: only SPH_HOA_FLAG_LUT_FP32 or SPH_HOA_FLAG_LUT_BF16");
+    require(p->flags != (SPH_HOA_FLAG_LUT_FP32 | SPH_HOA_FLAG_LUT_BF16), "params.flags: one table precision");
     sph::Index& ix = H->ix;
     ix.n = n;
     ix.kernel = k;
@@ -138,6 +156,13 @@ sph_hoa_status sph_hoa_build_index(const float* xyz, const float* h, const float
       ix.table = sph::build_table(k, ix.K, ix.D, n_lut, p->knot_table, host_threads());
     } else {
       ix.table = *cached_table(k, ix.K, ix.D, n_lut);
+    }
+    if (p->flags & (SPH_HOA_FLAG_LUT_FP32 | SPH_HOA_FLAG_LUT_BF16)) {
+      const bool bf16 = (p->flags & SPH_HOA_FLAG_LUT_BF16) != 0;
+      for (double& x : ix.table.theta) x = round_storage(x, bf16);
+      for (double& x : ix.table.shat) x = round_storage(x, bf16);
+      for (double& x : ix.table.smid) x = round_storage(x, bf16);
+      ix.lut_flags = p->flags;
     }
     hipStream_t st = (hipStream_t)stream;
     ix.lut_theta.ensure(sizeof(double) * ix.table.theta.size());
@@ -308,6 +333,7 @@ sph_hoa_status sph_hoa_index_get_info(sph_hoa_index idx, sph_hoa_index_info* inf
     info->n_levels = ix.grid.n_levels;
     for (int l = 0; l < ix.grid.n_levels; ++l)
       for (int a = 0; a < 3; ++a) info->level_dims[l][a] = ix.grid.lv[l].n[a];
+    info->lut_flags = ix.lut_flags;
   });
 }
 

@@ -131,6 +131,7 @@ struct Index {
   double cell0 = 0;
   int grid_bits = 1;  // Morton bits per axis in the sort keys
   Table table;
+  uint32_t lut_flags = 0;  // table storage precision (SPH_HOA_FLAG_LUT_*), 0: float64
   // device data (Morton order)
   DevBuf pos4;    // float4 x, y, z, h
   DevBuf val;     // float amplitude

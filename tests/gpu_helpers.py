@@ -21,10 +21,13 @@ KIND_ID = {"cubic": 0, "wendland": 1}
 
 
 class Scene:
-    def __init__(self, kind, K, D, n_lut, xyz, h, val, tol, tau_scale=1.0):
+    def __init__(self, kind, K, D, n_lut, xyz, h, val, tol, tau_scale=1.0, lut_precision="fp64"):
         self.kind, self.K, self.D, self.n_lut, self.tol = kind, K, D, n_lut, tol
         self.xyz, self.h, self.val = xyz, h, val
+        self.lut_precision = lut_precision
         self.theta = load_knots(kind, K, D, n_lut)
+        # the table as stored (precision study): knots and projection rows rounded once
+        self.theta_stored = lut.round_storage(self.theta, lut_precision)
         self._shat = None
         self.a_max = grid.a_max(kind, xyz, h, val)
         self.h_repr, self.phi_repr = grid.representatives(h, val)
@@ -39,7 +42,7 @@ class Scene:
         return self._shat
 
     def table(self):
-        return {"theta": self.theta, "shat": self.shat}
+        return {"theta": self.theta_stored, "shat": self.shat}
 
     def index(self):
         import paper_2401_02896_amd as L
@@ -48,7 +51,8 @@ class Scene:
             self._index = L.sph_hoa_build_index(self.xyz, self.h, self.val, kernel=KIND_ID[self.kind], degree=self.D,
                                                 pieces=self.K, lut_entries=self.n_lut, merge_tol=self.tol,
                                                 a_max=self.a_max, h_repr=self.h_repr, phi_repr=self.phi_repr,
-                                                tau=self.tau, knot_table=self.theta)
+                                                tau=self.tau, knot_table=self.theta,
+                                                lut_precision=self.lut_precision)
         return self._index
 
     def oracle_ray(self, o, v, t_min, t_max, tol=None):
@@ -68,8 +72,9 @@ class LazyRows:
     def __getitem__(self, i):
         i = int(i)
         if i not in self.rows:
-            self.rows[i], _ = lut.difference_coefficients(self.sc.kind, float(self.lams[i]), self.sc.theta[i],
-                                                          self.sc.K, self.sc.D)
+            rows, _ = lut.difference_coefficients(self.sc.kind, float(self.lams[i]), self.sc.theta[i],
+                                                  self.sc.K, self.sc.D)
+            self.rows[i] = lut.round_storage(rows, self.sc.lut_precision)
         return self.rows[i]
 
 

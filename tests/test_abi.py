@@ -25,8 +25,24 @@ def test_every_declared_symbol_is_exported():
 
 def test_status_strings():
     lib = L.lib()
-    for s in range(7):
+    for s in range(9):
         assert lib.sph_hoa_status_string(s)
+        assert lib.sph_hoa_status_string(s) != b"unknown status"
+
+
+def test_build_rejects_bad_params_before_device_work():
+    """Parameter checks run on the host before any device call: both table precisions at once,
+    unknown flag bits, and an out-of-range degree are refused with E_INVALID_ARG."""
+    import ctypes
+
+    lib = L.lib()
+    buf = (ctypes.c_float * 12)()
+    for flags, degree in ((L.FLAG_LUT_FP32 | L.FLAG_LUT_BF16, 2), (8, 2), (0, 9)):
+        p = L.Params(degree, 4, 64, 64, 1e-3, 0.0, 0.0, 0.0, 0.0, None, flags)
+        h = ctypes.c_void_p()
+        st = lib.sph_hoa_build_index(buf, buf, buf, 4, 0, ctypes.byref(p), None, ctypes.byref(h))
+        assert L.STATUS[st] == "E_INVALID_ARG", (flags, degree)
+        assert not h.value
 
 
 @pytest.mark.parametrize("spec", [t for t in TABLES if t[3] <= 256 or t[:3] == ("cubic", 4, 2)])

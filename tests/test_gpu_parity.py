@@ -1,6 +1,6 @@
 """GPU parity of the HIP library against the oracle (calls go through the C ABI).
 
-Bars (derived in the design doc): grid keys, hit sets, knot order, quantized
+Bars (each derived where it is asserted): grid keys, hit sets, knot order, quantized
 positions and exact-piece boundaries bit-exact; exact-piece values and the
 ray peak within 1e-9 of the peak (1e-6 for D >= 4: the projection coefficients
 are computed independently on both sides); merged FP32 field within 1e-5 of
@@ -32,8 +32,9 @@ TINY_SAMPLE = np.unique(np.concatenate([np.arange(0, 130), np.arange(2000, 2070)
                                         RNG.integers(0, 4096, 40)]))
 
 
-def _check_ray(sc, out, r, f, coef_tol=1e-8, field_tol=1e-5):
-    """Compare ray r of an exact-mode approx_rays result with the oracle's ray field f."""
+def _check_ray(sc, out, r, f, coef_tol=1e-8, field_tol=1e-5, vtol=None):
+    """Compare ray r of an exact-mode approx_rays result with the oracle's ray field f
+    (vtol: bar of the exact-piece values relative to the ray peak; default by degree)."""
     D = sc.D
     ko = out["knot_offsets"].cpu().numpy()
     kt = out["knot_t"][ko[r]:ko[r + 1]].cpu().numpy()
@@ -48,7 +49,8 @@ def _check_ray(sc, out, r, f, coef_tol=1e-8, field_tol=1e-5):
     ec = out["exact_coef"][eo[r]:eo[r + 1]].cpu().numpy()
     pcs = f["pieces"]
     assert et.tolist() == [p[0] for p in pcs] and ee.tolist() == [p[1] for p in pcs]
-    vtol = 1e-9 if D <= 3 else 1e-6
+    if vtol is None:
+        vtol = 1e-9 if D <= 3 else 1e-6
     if pcs:
         # integer coefficients: the jumps come from independently computed projections, whose
         # conditioning grows with D, so each order is compared relative to its largest value on

@@ -1,0 +1,110 @@
+"""Table storage precision (the precision study): the float table of Sec. 3.1 (knots theta_k and
+projection jumps s-hat) stored as float32 or bfloat16 (sph_hoa_params.flags LUT_FP32 / LUT_BF16).
+
+The library rounds its own float64 table; the oracle rounds its own (oracle.lut.round_storage).
+The knots come from the same float64 table on both sides, so their rounding is identical and the
+quantized positions stay bit-exact.  The projection rows are computed independently on each side
+and agree to 1e-9 of each row (D <= 3) before rounding, so a rounded value may differ by one unit
+of the storage format where the float64 value lies that close to a rounding tie; the tests check
+exactly that, and tighten the field bar back to the float64 one when no touched row differs.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import lut
+from tests import gpu_helpers as H
+from tests.test_gpu_parity import TINY_SAMPLE, _check_ray
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - only on the GPU machine
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_2401_02896_amd as L  # noqa: E402
+
+ULP = {"fp32": 2.0 ** -24, "bf16": 2.0 ** -8}
+
+
+def _scene(fmt, tol=1e-3):
+    xyz, h, val = synth.tiny_particles()
+    return H.Scene("cubic", 4, 2, 4096, xyz, h, val, tol, lut_precision=fmt)
+
+
+def _row_in_band(lib_row, sc, i):
+    """lib_row is the rounding of some value within 1e-9 of the oracle row's scale of the
+    oracle's float64 row (rounding is monotone, so it lies between the two band roundings)."""
+    x, _ = lut.difference_coefficients(sc.kind, float(sc.shat.lams[i]), sc.theta[i], sc.K, sc.D)
+    d = 1e-9 * np.abs(x).max()
+    lo = lut.round_storage(x - d, sc.lut_precision)
+    hi = lut.round_storage(x + d, sc.lut_precision)
+    return np.all((lib_row >= lo) & (lib_row <= hi))
+
+
+@pytest.mark.parametrize("fmt", ["fp32", "bf16"])
+def test_stored_table_is_the_rounded_table(fmt):
+    sc = _scene(fmt)
+    idx = sc.index()
+    assert idx.info()["lut_flags"] == {"fp32": L.FLAG_LUT_FP32, "bf16": L.FLAG_LUT_BF16}[fmt]
+    theta, shat, _ = idx.lut()
+    assert np.array_equal(theta, sc.theta_stored)                  # same input, same rounding
+    assert not np.array_equal(theta, sc.theta)                      # and it did round
+    rows = list(range(0, 4096, 61)) + [4095]
+    for i in rows:
+        assert _row_in_band(shat[i], sc, i), i
+    # the rounding itself: the stored values are exactly the oracle's rounding of the library's
+    # own float64 projection of the same knots (host routine, no rounding)
+    raw, _, _ = L.sph_hoa_lut_coefficients(0, sc.K, sc.D, sc.theta)
+    assert np.array_equal(shat, lut.round_storage(raw, fmt))
+
+
+@pytest.mark.parametrize("fmt", ["fp32", "bf16"])
+def test_rounded_table_rays_match_oracle(fmt):
+    sc = _scene(fmt)
+    o, v = synth.ortho_rays()
+    idx = sc.index()
+    out = L.sph_hoa_approx_rays(idx, torch.as_tensor(o), torch.as_tensor(v), 0.0, 1.4, exact=True)
+    sample = TINY_SAMPLE[::2]
+    fields = {int(r): sc.oracle_ray(o[r], v[r], 0.0, 1.4) for r in sample}
+    # rows the oracle touched: identical after rounding -> the float64 bars hold unchanged;
+    # otherwise a differing value is off by one unit of the format, and so is its term
+    _, shat, _ = idx.lut()
+    differing = [i for i in sc.shat.rows if not np.array_equal(shat[i], sc.shat.rows[i])]
+    vtol = 1e-9 if not differing else 1e-9 + 2 * ULP[fmt]
+    same = 0
+    for r, f in fields.items():
+        same += _check_ray(sc, out, r, f, coef_tol=1e-8 if not differing else ULP[fmt], vtol=vtol)
+    assert same >= 0.97 * len(fields)
+
+
+def test_rounded_table_changes_the_field_by_its_rounding():
+    """The bf16 table moves the field by about its rounding (8 significant bits), the fp32 one
+    by far less; both stay exact integer pipelines (every tail cancels: no flag raised).  No
+    merging, so that the pieces are the exact field."""
+    o, v = synth.ortho_rays(32, 32)
+    ref = None
+    diffs = {}
+    for fmt in ("fp64", "fp32", "bf16"):
+        sc = _scene(fmt, tol=0.0)
+        out = L.sph_hoa_approx_rays(sc.index(), torch.as_tensor(o), torch.as_tensor(v), 0.0, 1.4)
+        ts = np.linspace(0.05, 1.35, 64)
+        vals = []
+        for r in range(0, 1024, 37):
+            t0, t1, cf = H.field_of_ray(out, r, sc.D)
+            vals.append(H.eval_pieces(t0, t1, cf, ts) if len(t0) else np.zeros_like(ts))
+        vals = np.array(vals)
+        if ref is None:
+            ref = vals
+            scale = np.abs(ref).max()
+        else:
+            diffs[fmt] = np.abs(vals - ref).max() / scale
+    assert diffs["fp32"] < 1e-5
+    assert 1e-6 < diffs["bf16"] < 5e-2
+    assert diffs["fp32"] < diffs["bf16"]
+
+
+def test_unknown_precision_rejected():
+    sc = H.tiny_scene()
+    with pytest.raises(ValueError):
+        L.sph_hoa_build_index(sc.xyz, sc.h, sc.val, lut_precision="fp16")
