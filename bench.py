@@ -50,13 +50,15 @@ def parse():
     ap.add_argument("--rate", type=float, default=20.0, help="serve workload: Poisson arrival rate (requests/s)")
     ap.add_argument("--duration", type=float, default=8.0, help="serve workload: seconds of arrivals")
     ap.add_argument("--sides", default="64,128,256", help="serve workload: image sides (uniform choice)")
-    ap.add_argument("--workload", choices=("plain", "batch", "serve", "bitlength", "precision"), default="plain",
+    ap.add_argument("--workload", choices=("plain", "batch", "serve", "bitlength", "precision", "sprinkle"),
+                    default="plain",
                     help="plain: the 1M-particle 512x512 frame (the reported metric); batch: camera bundles "
                          "of 32^2..512^2 rendered with one sph_hoa_render_batch call; serve: Poisson render "
                          "requests to the native render server; bitlength: the accumulation rule in 32/64/96/"
                          "128-bit integers (the cost study of Sec. 5.1); precision: the plain frame with the "
                          "float table stored in fp64 / fp32 / bf16, timed, with pixel errors against the "
-                         "float64 oracle")
+                         "float64 oracle; sprinkle: the float32 accumulation variant with and without "
+                         "reinitialization knots (Sec. 4.1), its residue behind the particles and its time")
     ap.add_argument("--batch-cams", type=int, default=64, help="cameras per batch (batch workload)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="instead of the benchmark, run 5 plain device copies of MIB MiB each (the "
@@ -314,6 +316,86 @@ def run_precision(a, torch, L, synth):
     print(json.dumps(result), flush=True)
 
 
+def run_sprinkle(a, torch, L, synth):
+    """Float accumulation variant (Sec. 4.1): the plain set (1M clustered particles, Wendland C2,
+    K = 4, D = 3) seen by 128 x 128 rays from the plain camera's eye through a grid over the middle
+    plane of the cube (x, y in [0.15, 0.85], z = 0.5); every ray swept in
+    float32 without and with 10 reinitialization knots (sph_hoa_float_rays), against the exact
+    integer path on the same rays (sph_hoa_approx_rays, whose fields return exactly to zero).
+    Residue = the largest |float field| behind the ray's last knot (piece ends from there to t_max)
+    over the ray's peak |value|.
+    value = contributions/s of the float sweep without reinitialization knots."""
+    xyz, h, val = synth.clustered_particles(n=a.particles)
+    idx = L.sph_hoa_build_index(xyz, h, val, kernel=L.KERNEL_WENDLAND_C2, degree=3, pieces=4, lut_entries=4096,
+                                merge_tol=1e-3)
+    cam = synth.plain_camera(128, 128)
+    g = np.linspace(0.15, 0.85, 128)
+    gx, gy = np.meshgrid(g, g, indexing="xy")
+    tgt = np.stack([gx.ravel(), gy.ravel(), np.full(gx.size, 0.5)], axis=1)
+    eye = np.array(cam["eye"], np.float64)
+    dirs = tgt - eye
+    dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+    o = torch.as_tensor(np.tile(eye, (len(dirs), 1)).astype(np.float32), device="cuda")
+    v = torch.as_tensor(dirs.astype(np.float32), device="cuda")
+    t_min, t_max = float(cam["t_min"]), float(cam["t_max"])
+    n = o.shape[0]
+    # the exact path on the same rays: its fields end exactly at each ray's last knot
+    L.sph_hoa_approx_rays(idx, o, v, t_min, t_max)
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    ex = L.sph_hoa_approx_rays(idx, o, v, t_min, t_max)
+    torch.cuda.synchronize()
+    exact_s = time.perf_counter() - ts
+    eo = ex["ray_offsets"]
+    ecnt = eo[1:] - eo[:-1]
+    ecnt_h = ecnt.cpu().numpy()
+    te = ex["t_end"].cpu().numpy()
+    last_knot_h = np.where(ecnt_h > 0, te[np.maximum(eo[1:].cpu().numpy() - 1, 0)], -1e30)
+    res = {}
+    for n_re in (0, 10):
+        L.sph_hoa_float_rays(idx, o, v, t_min, t_max, n_reinit=n_re)  # warm-up
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        out = L.sph_hoa_float_rays(idx, o, v, t_min, t_max, n_reinit=n_re)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - ts
+        # per-ray maxima on the host over each ray's slot range (unused slots are zero)
+        offs = out["ray_offsets"].cpu().numpy()
+        cf = out["coef"].cpu().numpy().astype(np.float64)
+        ts0 = out["t_start"].cpu().numpy()
+        Lg = out["t_end"].cpu().numpy().astype(np.float64) - ts0
+        v0 = np.abs(cf[:, 0])
+        v1 = np.abs(sum(cf[:, d] * Lg ** d for d in range(cf.shape[1])))
+        ray_of_slot = np.repeat(np.arange(n), np.diff(offs))
+        # behind the particles: pieces from the ray's last knot on (the exact field is zero there)
+        behind = ts0 >= last_knot_h[ray_of_slot] - 1e-5
+        vb = np.where(behind, np.maximum(v0, v1), 0.0)
+        peak = np.maximum.reduceat(v0, offs[:-1])
+        resid = np.maximum.reduceat(vb, offs[:-1])
+        del cf, v0, v1, vb, Lg, ts0, ray_of_slot, behind
+        keep = (peak > 0) & (ecnt_h > 0)
+        rel = resid[keep] / peak[keep]
+        res[f"reinit_{n_re}"] = {"s": dt, "contributions_per_s": out["n_pairs"] / dt,
+                                 "residue_rel_median": float(np.median(rel)),
+                                 "residue_rel_p99": float(np.percentile(rel, 99)), "residue_rel_max": float(rel.max()),
+                                 "rays_residue_above_1e-3": int((rel > 1e-3).sum()),
+                                 "rays_with_particles": int(rel.size)}
+        pairs = out["n_pairs"]
+        del out
+    result = {
+        "metric": "float32 sweep contributions/s; residue behind the particles relative to the ray peak",
+        "value": res["reinit_0"]["contributions_per_s"], "unit": "contributions/s", "n_gpus": 1, "steps": 1,
+        "warmup": 1, "ms_per_step": res["reinit_0"]["s"] * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"sprinkle: {a.particles} clustered particles, Wendland C2, K=4, D=3, 128x128 rays "
+                               "from the plain camera's eye, float32 sweep with 0 and 10 reinitialization knots",
+                   "pairs": pairs, "float": res, "exact_path_s": exact_s,
+                   "exact_path_contributions_per_s": pairs / exact_s, "exact_path_residue": 0.0},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(result), flush=True)
+
+
 def kernel_source_digest():
     import hashlib
 
@@ -373,6 +455,8 @@ def main():
         return run_bitlength(a, torch, L, synth)
     if a.workload == "precision":
         return run_precision(a, torch, L, synth)
+    if a.workload == "sprinkle":
+        return run_sprinkle(a, torch, L, synth)
     t_gen = time.time()
     xyz, h, val = synth.clustered_particles(n=a.particles)
     gen_s = time.time() - t_gen

@@ -71,6 +71,10 @@ typedef struct {
   const double* knot_table; /* optional HOST array [lut_entries][ceil(K/2)] of optimal knots theta_k
                                (units of h) replacing the library's own optimisation (Sec. 3.4); copied */
   uint32_t flags;       /* 0, SPH_HOA_FLAG_LUT_FP32 or SPH_HOA_FLAG_LUT_BF16 */
+  const double* jump_table;     /* optional HOST [lut_entries][ceil(K/2)][D+1]: projection jumps s-hat at
+                                   +theta_k (Sec. 3.1) replacing the library's projection; requires
+                                   knot_table (the knots they belong to); copied */
+  const double* jump_table_mid; /* with jump_table and even K: HOST [lut_entries][D+1] jumps at 0 */
 } sph_hoa_params;
 
 typedef struct sph_hoa_index_s* sph_hoa_index; /* opaque; owns its device memory */
@@ -203,6 +207,39 @@ sph_hoa_status sph_hoa_render(sph_hoa_index idx, const sph_hoa_camera* cam, cons
  */
 sph_hoa_status sph_hoa_render_batch(sph_hoa_index idx, const sph_hoa_camera* cams, int32_t n_cams,
                                     const sph_hoa_tf* tf, float* rgba_out, void* stream);
+
+/* ---------------------------------------------------------------- float accumulation variant
+ *
+ * The update rule swept along each ray in float32 (Sec. 4.1), with optional reinitialization
+ * knots, for measuring what the quantization of Sec. 4.2 avoids.  Same hits, closest points and
+ * table entries as the exact path; per hit the knots sit at tc -+ zf theta_k (and tc for even K)
+ * with tc, zf, vf the float32 roundings of t_chi, zeta, amplitude, and carry the jumps
+ * s-hat_kd vf / zf^(3+d) (at -theta_k times (-1)^(d+1); at 0 the table's middle jump).  Knots are
+ * ordered by (position, particle input index, kidx) and swept by one thread per ray: shift the
+ * state to the knot (in-place Taylor shift), add the jump.  n_reinit >= 1 places reinitialization
+ * knots at T_s = t_min + s (t_max - t_min) / (n_reinit + 1), s = 1..n_reinit (float32): each holds
+ * the sum, in increasing particle input index, of the localized coefficients at T_s of every
+ * particle whose first knot is <= T_s < its last knot (each from that particle's own float sweep
+ * of its knots <= T_s); the sweep takes them after all knots at positions <= T_s.  Output: one
+ * piece per gap between consecutive event positions, coefficients of (t - t_start)^d at its start,
+ * and a last piece from the final event to t_max (exactly zero in exact arithmetic).  Ray r's
+ * pieces occupy slots [ray_offsets[r], ray_offsets[r] + ray_counts[r]) with
+ * ray_offsets[r] = (K + 1) * (hits before r) + r * (n_reinit + 2); the call needs
+ * capacity >= ray_offsets[n], reported in n_slots (E_OUT_OF_MEMORY, with nothing written, when
+ * capacity is smaller: call again with enough).  0 <= n_reinit <= 1024.  Synchronises `stream`. */
+typedef struct {
+  int64_t capacity;      /* piece slots allocated by the caller */
+  int64_t* ray_offsets;  /* device [n + 1] */
+  int64_t* ray_counts;   /* device [n] */
+  float* t_start;        /* device [capacity] */
+  float* t_end;          /* device [capacity] */
+  float* coef;           /* device [capacity][D + 1], powers of (t - t_start) */
+  int64_t n_slots;       /* out (host): slots the call needs */
+  int64_t n_pairs;       /* out (host) */
+} sph_hoa_float_field;
+
+sph_hoa_status sph_hoa_float_rays(sph_hoa_index idx, const sph_hoa_rays* rays, int32_t n_reinit,
+                                  sph_hoa_float_field* out, void* stream);
 
 /* ---------------------------------------------------------------- render server
  *

@@ -34,7 +34,8 @@ class Params(ctypes.Structure):
     _fields_ = [("degree", ctypes.c_int32), ("pieces", ctypes.c_int32), ("lut_entries", ctypes.c_int32),
                 ("int_bits", ctypes.c_int32), ("merge_tol", ctypes.c_double), ("a_max", ctypes.c_double),
                 ("h_repr", ctypes.c_double), ("phi_repr", ctypes.c_double), ("tau", ctypes.c_double),
-                ("knot_table", ctypes.POINTER(ctypes.c_double)), ("flags", ctypes.c_uint32)]
+                ("knot_table", ctypes.POINTER(ctypes.c_double)), ("flags", ctypes.c_uint32),
+                ("jump_table", ctypes.POINTER(ctypes.c_double)), ("jump_table_mid", ctypes.POINTER(ctypes.c_double))]
 
 
 class IndexInfo(ctypes.Structure):
@@ -44,6 +45,12 @@ class IndexInfo(ctypes.Structure):
                 ("phi_repr", ctypes.c_double), ("grid_lo", ctypes.c_double * 3), ("cell0", ctypes.c_double),
                 ("n_levels", ctypes.c_int32), ("level_dims", (ctypes.c_int32 * 3) * 32),
                 ("lut_flags", ctypes.c_uint32)]
+
+
+class FloatField(ctypes.Structure):
+    _fields_ = [("capacity", ctypes.c_int64), ("ray_offsets", ctypes.c_void_p), ("ray_counts", ctypes.c_void_p),
+                ("t_start", ctypes.c_void_p), ("t_end", ctypes.c_void_p), ("coef", ctypes.c_void_p),
+                ("n_slots", ctypes.c_int64), ("n_pairs", ctypes.c_int64)]
 
 
 class Rays(ctypes.Structure):
@@ -90,7 +97,7 @@ class Stats(ctypes.Structure):
 EXPORTS = ["sph_hoa_build_index", "sph_hoa_approx_rays", "sph_hoa_render", "sph_hoa_render_batch",
            "sph_hoa_server_create", "sph_hoa_server_add_index", "sph_hoa_server_submit", "sph_hoa_server_wait",
            "sph_hoa_server_get_stats", "sph_hoa_server_destroy", "sph_hoa_server_set_admission",
-           "sph_hoa_server_cancel", "sph_hoa_server_pause", "sph_hoa_accumulate_bits",
+           "sph_hoa_server_cancel", "sph_hoa_server_pause", "sph_hoa_accumulate_bits", "sph_hoa_float_rays",
            "sph_hoa_index_free",
            "sph_hoa_index_get_info", "sph_hoa_index_get_lut", "sph_hoa_index_get_grid", "sph_hoa_index_get_stats",
            "sph_hoa_index_set_timing",
@@ -123,6 +130,7 @@ def lib():
     L.sph_hoa_server_set_admission.argtypes = [vp, i64, i64]
     L.sph_hoa_server_cancel.argtypes = [vp, i64, ctypes.POINTER(i32)]
     L.sph_hoa_server_pause.argtypes = [vp, i32]
+    L.sph_hoa_float_rays.argtypes = [vp, ctypes.POINTER(Rays), i32, ctypes.POINTER(FloatField), vp]
     L.sph_hoa_accumulate_bits.argtypes = [i32, i32, vp, vp, i32, i64, i32, vp, ctypes.POINTER(ctypes.c_float), vp]
     L.sph_hoa_index_free.argtypes = [vp]
     L.sph_hoa_index_get_info.argtypes = [vp, ctypes.POINTER(IndexInfo)]
@@ -224,9 +232,12 @@ class Index:
 
 
 def sph_hoa_build_index(xyz, h, value, kernel=KERNEL_CUBIC, degree=2, pieces=4, lut_entries=4096, merge_tol=1e-3,
-                        a_max=0.0, h_repr=0.0, phi_repr=0.0, tau=0.0, knot_table=None, lut_precision="fp64"):
+                        a_max=0.0, h_repr=0.0, phi_repr=0.0, tau=0.0, knot_table=None, lut_precision="fp64",
+                        jump_table=None, jump_table_mid=None):
     """Build an index (sph_hoa_build_index).  xyz [n,3], h [n], value [n]: tensors or arrays.
-    lut_precision: storage precision of the float table, "fp64", "fp32" or "bf16"."""
+    lut_precision: storage precision of the float table, "fp64", "fp32" or "bf16".
+    jump_table [lut_entries, ceil(K/2), D+1] / jump_table_mid [lut_entries, D+1] (even K): projection
+    jumps replacing the library's own (with knot_table)."""
     import numpy as np
 
     x = _dev_f32(xyz)
@@ -243,10 +254,51 @@ def sph_hoa_build_index(xyz, h, value, kernel=KERNEL_CUBIC, degree=2, pieces=4, 
     if knot_table is not None:
         kt = np.ascontiguousarray(knot_table, dtype=np.float64)
         p.knot_table = kt.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    jt = jm = None
+    if jump_table is not None:
+        jt = np.ascontiguousarray(jump_table, dtype=np.float64)
+        p.jump_table = jt.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    if jump_table_mid is not None:
+        jm = np.ascontiguousarray(jump_table_mid, dtype=np.float64)
+        p.jump_table_mid = jm.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     handle = ctypes.c_void_p()
     _check(lib().sph_hoa_build_index(_ptr(x), _ptr(hh), _ptr(v), n, kernel, ctypes.byref(p), _stream(),
                                      ctypes.byref(handle)))
     return Index(handle, pieces, degree, n)
+
+
+def sph_hoa_float_rays(index, origin, direction, t_min, t_max, n_reinit=0):
+    """Float accumulation variant (sph_hoa_float_rays): per-ray pieces of the float32 sweep.
+
+    Returns a dict: ray_offsets [n+1], ray_counts [n], t_start, t_end, coef [slots, D+1] (powers of
+    t - t_start), all device tensors over the slot layout, and n_pairs."""
+    import torch
+
+    o = _dev_f32(origin).reshape(-1, 3)
+    d = _dev_f32(direction).reshape(-1, 3)
+    n = o.shape[0]
+    D = index.D
+    r = Rays(n, _ptr(o).value, _ptr(d).value, t_min, t_max)
+    offs = torch.zeros(n + 1, dtype=torch.int64, device="cuda")
+    cnt = torch.zeros(max(n, 1), dtype=torch.int64, device="cuda")
+    f = FloatField()
+    f.capacity = 0
+    f.ray_offsets, f.ray_counts = _ptr(offs).value, _ptr(cnt).value
+    st = lib().sph_hoa_float_rays(index.handle, ctypes.byref(r), int(n_reinit), ctypes.byref(f), _stream())
+    if st == 0 and n == 0:
+        return {"ray_offsets": offs, "ray_counts": cnt[:0], "t_start": None, "t_end": None, "coef": None,
+                "n_pairs": 0}
+    if st != 2:
+        _check(st)
+    slots = int(f.n_slots)
+    t0 = torch.zeros(max(slots, 1), dtype=torch.float32, device="cuda")
+    t1 = torch.zeros(max(slots, 1), dtype=torch.float32, device="cuda")
+    coef = torch.zeros(max(slots, 1) * (D + 1), dtype=torch.float32, device="cuda")
+    f.capacity = slots
+    f.t_start, f.t_end, f.coef = _ptr(t0).value, _ptr(t1).value, _ptr(coef).value
+    _check(lib().sph_hoa_float_rays(index.handle, ctypes.byref(r), int(n_reinit), ctypes.byref(f), _stream()))
+    return {"ray_offsets": offs, "ray_counts": cnt[:n], "t_start": t0[:slots], "t_end": t1[:slots],
+            "coef": coef[: slots * (D + 1)].reshape(-1, D + 1), "n_pairs": int(f.n_pairs)}
 
 
 def sph_hoa_approx_rays(index, origin, direction, t_min, t_max, capacity=None, exact=False, exact_capacity=None):

@@ -157,6 +157,21 @@ sph_hoa_status sph_hoa_build_index(const float* xyz, const float* h, const float
     } else {
       ix.table = *cached_table(k, ix.K, ix.D, n_lut);
     }
+    if (p->jump_table) {
+      require(p->knot_table != nullptr, "jump_table needs the knot_table it belongs to");
+      const int64_t ns = (int64_t)n_lut * ix.P * (ix.D + 1);
+      for (int64_t i = 0; i < ns; ++i) require(std::isfinite(p->jump_table[i]), "jump_table entries must be finite");
+      ix.table.shat.assign(p->jump_table, p->jump_table + ns);
+      const int64_t nm = (int64_t)n_lut * (ix.D + 1);
+      if (ix.K % 2 == 0) {
+        require(p->jump_table_mid != nullptr, "even K needs jump_table_mid");
+        for (int64_t i = 0; i < nm; ++i)
+          require(std::isfinite(p->jump_table_mid[i]), "jump_table_mid entries must be finite");
+        ix.table.smid.assign(p->jump_table_mid, p->jump_table_mid + nm);
+      } else {
+        ix.table.smid.assign(nm, 0.0);
+      }
+    }
     if (p->flags & (SPH_HOA_FLAG_LUT_FP32 | SPH_HOA_FLAG_LUT_BF16)) {
       const bool bf16 = (p->flags & SPH_HOA_FLAG_LUT_BF16) != 0;
       for (double& x : ix.table.theta) x = round_storage(x, bf16);
@@ -171,6 +186,10 @@ sph_hoa_status sph_hoa_build_index(const float* xyz, const float* h, const float
                                   hipMemcpyHostToDevice, st), "copy");
     sph::hip_check(hipMemcpyAsync(ix.lut_shat.p, ix.table.shat.data(), sizeof(double) * ix.table.shat.size(),
                                   hipMemcpyHostToDevice, st), "copy");
+    ix.lut_smid.ensure(sizeof(double) * std::max<size_t>(1, ix.table.smid.size()));
+    if (!ix.table.smid.empty())
+      sph::hip_check(hipMemcpyAsync(ix.lut_smid.p, ix.table.smid.data(), sizeof(double) * ix.table.smid.size(),
+                                    hipMemcpyHostToDevice, st), "copy");
     sph::build_index_device(ix, xyz, h, value, st);
     const double int_max = 9223372036854775807.0;  // 2^63 - 1 (rounds to 2^63 in double)
     if (ix.a_max > 0.0) {
@@ -239,6 +258,40 @@ sph_hoa_status sph_hoa_approx_rays(sph_hoa_index idx, const sph_hoa_rays* rays, 
       }
       return;
     }
+    sph::run_rays(ix, rays->n, false, nullptr, rays, fo, st);
+  });
+}
+
+sph_hoa_status sph_hoa_float_rays(sph_hoa_index idx, const sph_hoa_rays* rays, int32_t n_reinit,
+                                  sph_hoa_float_field* out, void* stream) {
+  return guarded([&]() {
+    require(idx && rays && out, "NULL argument");
+    require(rays->n >= 0 && rays->n < (int64_t(1) << 31), "ray count must be in 0..2^31-1");
+    require(std::isfinite(rays->t_min) && std::isfinite(rays->t_max) && rays->t_min < rays->t_max,
+            "need finite t_min < t_max");
+    require(n_reinit >= 0 && n_reinit <= 1024, "n_reinit must be in 0..1024");
+    require(out->capacity >= 0, "capacity must be >= 0");
+    if (rays->n > 0) {
+      require(rays->origin && rays->dir, "NULL ray arrays");
+      require(out->ray_offsets && out->ray_counts, "NULL output arrays");
+      require(out->capacity == 0 || (out->t_start && out->t_end && out->coef), "NULL piece arrays");
+    }
+    sph::Index& ix = idx->ix;
+    require(ix.n < (int64_t(1) << 29), "the float variant needs fewer than 2^29 particles");
+    hipStream_t st = (hipStream_t)stream;
+    ix.last_stream = st;
+    out->n_slots = out->n_pairs = 0;
+    if (rays->n == 0) {
+      if (out->ray_offsets) {
+        const int64_t z = 0;
+        sph::hip_check(hipMemcpyAsync(out->ray_offsets, &z, 8, hipMemcpyHostToDevice, st), "copy");
+        sph::hip_check(hipStreamSynchronize(st), "sync");
+      }
+      return;
+    }
+    sph::FieldOut fo{nullptr, nullptr, nullptr, false};
+    fo.flt = out;
+    fo.n_reinit = n_reinit;
     sph::run_rays(ix, rays->n, false, nullptr, rays, fo, st);
   });
 }

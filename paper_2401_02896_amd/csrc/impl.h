@@ -139,6 +139,8 @@ struct Index {
   DevBuf morton;  // uint64 key (level << 57 | morton)
   DevBuf cell_begin, cell_end;  // uint32 per cell, all levels
   DevBuf lut_theta, lut_shat;   // double
+  DevBuf lut_smid;              // double [n][D+1] jumps at 0 (even K; float variant only)
+  DevBuf float_scratch;         // float variant, per work-group
   // per-call scratch
   DevBuf rays_o, rays_v;        // double [n][3]
   DevBuf hit_count, hit_off;    // int64 [n + 1]
@@ -201,7 +203,31 @@ struct FieldOut {
   float* rgba;           // render mode
   const sph_hoa_tf* tf;
   bool exact;
+  sph_hoa_float_field* flt = nullptr;  // float accumulation variant (floatpath.hip)
+  int n_reinit = 0;
 };
+
+// float accumulation variant (floatpath.hip)
+struct FloatArgs {
+  const double *o, *v;
+  int64_t n_rays;
+  double t_min, t_max;
+  const int64_t* hit_off;
+  const uint32_t* hits;
+  const float4* pos4;
+  const float* val;
+  const int32_t* orig;
+  const double *theta, *shat, *smid;
+  int n_lut, K, P, even_k, D, n_reinit;
+  char* scratch;
+  int64_t scratch_stride, cap_h;
+  const int64_t* out_off;
+  int64_t* out_cnt;
+  float *t0, *t1, *coef;
+  uint32_t* flags;
+};
+int64_t float_field_capacity(int64_t total_pairs, int64_t n_rays, int K, int n_reinit);
+void launch_float_field(FloatArgs& F, int64_t max_hits, DevBuf& scratch, int64_t* out_off, hipStream_t st);
 // n_batch > 0: render the cameras batch[0..n_batch) together (rays concatenated in camera order)
 void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam, const sph_hoa_rays* rays,
               FieldOut& out, hipStream_t st, const sph_hoa_camera* batch = nullptr, int n_batch = 0);

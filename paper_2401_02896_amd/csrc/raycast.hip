@@ -1808,6 +1808,45 @@ void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam,
   }
   if (ix.timing) hip_check(hipEventRecord(ix.ev[3], st), "event");
   hip_check(hipGetLastError(), "gather launch");
+  if (out.flt) {
+    // float accumulation variant: same hits, its own sweep
+    sph_hoa_float_field* ff = out.flt;
+    const int64_t need = float_field_capacity(total_pairs, n_rays, K, out.n_reinit);
+    ff->n_slots = need;
+    ff->n_pairs = total_pairs;
+    if (need > ff->capacity) throw Error(SPH_HOA_E_OUT_OF_MEMORY, "float field capacity too small");
+    FloatArgs F{};
+    F.o = G.o;
+    F.v = G.v;
+    F.n_rays = n_rays;
+    F.t_min = t_min;
+    F.t_max = t_max;
+    F.hit_off = ix.hit_off.as<int64_t>();
+    F.hits = ix.hits.as<uint32_t>();
+    F.pos4 = ix.pos4.as<float4>();
+    F.val = ix.val.as<float>();
+    F.orig = ix.orig.as<int32_t>();
+    F.theta = ix.lut_theta.as<double>();
+    F.shat = ix.lut_shat.as<double>();
+    F.smid = ix.lut_smid.as<double>();
+    F.n_lut = ix.n_lut;
+    F.K = K;
+    F.P = P;
+    F.even_k = (K % 2 == 0) ? 1 : 0;
+    F.D = D;
+    F.n_reinit = out.n_reinit;
+    F.out_cnt = ff->ray_counts;
+    F.t0 = ff->t_start;
+    F.t1 = ff->t_end;
+    F.coef = ff->coef;
+    F.flags = flags;
+    launch_float_field(F, (int64_t)mh, ix.float_scratch, ff->ray_offsets, st);
+    uint32_t fl2 = 0;
+    hip_check(hipMemcpyAsync(&fl2, flags, 4, hipMemcpyDeviceToHost, st), "copy");
+    hip_check(hipStreamSynchronize(st), "sync");
+    if (fl2 & kFlagCapacity) throw Error(SPH_HOA_E_INTERNAL, "float field wrote past its slots");
+    return;
+  }
   // ---- field kernel
   FieldArgs A{};
   A.o = G.o;
