@@ -359,7 +359,8 @@ def run_sprinkle(a, torch, L, synth):
         out = L.sph_hoa_float_rays(idx, o, v, t_min, t_max, n_reinit=n_re)
         torch.cuda.synchronize()
         dt = time.perf_counter() - ts
-        # per-ray maxima on the host over each ray's slot range (unused slots are zero)
+        # per-ray maxima on the host over each ray's slot range (unused slots are zero); a device
+        # gather of ~1e8 rows by index returned wrong rows with this torch build
         offs = out["ray_offsets"].cpu().numpy()
         cf = out["coef"].cpu().numpy().astype(np.float64)
         ts0 = out["t_start"].cpu().numpy()

@@ -309,14 +309,18 @@ __device__ bool particle_pixels(const CamDev& c, float4 p, int* c0, int* c1, int
       a0 = b0 = -1e30;
       a1 = b1 = 1e30;
     } else {
-      const double hp = 1.5707963267948966;
-      const double rx = sqrt(x * x + z * z), ry = sqrt(y * y + z * z);
-      const double ax = asin(fmin(1.0, R / rx)), ay = asin(fmin(1.0, R / ry));
-      const double tx = atan2(x, z), ty = atan2(y, z);
-      a0 = (tx - ax <= -hp) ? -1e30 : tan(tx - ax) / (c.g * c.aspect);
-      a1 = (tx + ax >= hp) ? 1e30 : tan(tx + ax) / (c.g * c.aspect);
-      b0 = (ty - ay <= -hp) ? -1e30 : tan(ty - ay) / c.g;
-      b1 = (ty + ay >= hp) ? 1e30 : tan(ty + ay) / c.g;
+      // In the (x, z) plane the sphere is seen at angle theta (tan theta = x / z) with half-width
+      // alpha (sin alpha = R / sqrt(x^2 + z^2)); the screen bounds are tan(theta -+ alpha), by the
+      // tangent addition formula with tan alpha = R / sqrt(x^2 + z^2 - R^2).  A bound is unbounded
+      // when theta -+ alpha leaves (-pi/2, pi/2), i.e. when cos(theta -+ alpha), whose sign is that
+      // of 1 +- tan theta tan alpha, is not positive.  Same for (y, z).
+      const double tx = x / z, ty = y / z;
+      const double sx = R / sqrt(x * x + z * z - R * R), sy = R / sqrt(y * y + z * z - R * R);
+      const double dx0 = 1.0 + tx * sx, dx1 = 1.0 - tx * sx, dy0 = 1.0 + ty * sy, dy1 = 1.0 - ty * sy;
+      a0 = (dx0 <= 0.0) ? -1e30 : (tx - sx) / dx0 / (c.g * c.aspect);
+      a1 = (dx1 <= 0.0) ? 1e30 : (tx + sx) / dx1 / (c.g * c.aspect);
+      b0 = (dy0 <= 0.0) ? -1e30 : (ty - sy) / dy0 / c.g;
+      b1 = (dy1 <= 0.0) ? 1e30 : (ty + sy) / dy1 / c.g;
     }
   }
   // a = (2 col + 1) / W - 1  and  b = 1 - (2 row + 1) / H
@@ -372,17 +376,22 @@ struct TileHitArgs {
   const float4* pos4;
   const int64_t* tile_off;
   const uint32_t* items;
+  unsigned long long* masks;  // [items]: pixels of the tile each candidate hits (bit = lane)
   int64_t* count;
   const int64_t* off;
   uint32_t* hits;
   unsigned long long* max_hits;
 };
 
-// one wave per tile, one lane per pixel ray; candidates staged through LDS 64 at a time
+// One wave per tile, one lane per pixel ray; candidates staged through LDS 64 at a time.  The
+// counting pass tests every (candidate, pixel) pair and keeps, per candidate, the wave's 64-bit
+// mask of the pixels it hits; the filling pass only reads the masks back, so the float64 tests
+// run once.  Hits are written in candidate order in both layouts.
 template <bool FILL>
 __global__ void __launch_bounds__(64) k_tile_hits(TileHitArgs T) {
   __shared__ float4 cp[64];
   __shared__ uint32_t cj[64];
+  __shared__ unsigned long long cm[64];
   const int64_t tile = blockIdx.x;
   const int lane = threadIdx.x;
   int lo = 0, hi = T.n_cams - 1;
@@ -400,7 +409,7 @@ __global__ void __launch_bounds__(64) k_tile_hits(TileHitArgs T) {
   const bool valid = col < c.W && row < c.H;
   const int64_t r = valid ? T.ray_base[lo] + (int64_t)row * c.W + col : 0;
   double o[3] = {0, 0, 0}, v[3] = {0, 0, 1};
-  if (valid)
+  if (!FILL && valid)
     for (int k = 0; k < 3; ++k) {
       o[k] = T.o[3 * r + k];
       v[k] = T.v[3 * r + k];
@@ -413,17 +422,24 @@ __global__ void __launch_bounds__(64) k_tile_hits(TileHitArgs T) {
     if (k < e) {
       const uint32_t j = T.items[k];
       cj[lane] = j;
-      cp[lane] = T.pos4[j];
+      if (FILL) cm[lane] = T.masks[k];
+      else cp[lane] = T.pos4[j];
     }
     __syncthreads();
     const int m = (int)min((int64_t)64, e - base);
-    if (valid) {
+    if (FILL) {
+      if (valid)
+        for (int q = 0; q < m; ++q)
+          if ((cm[q] >> lane) & 1ull) T.hits[out0 + cnt++] = cj[q];
+    } else {
+      unsigned long long mine = 0;
       for (int q = 0; q < m; ++q) {
-        if (pair_hit(o, v, cp[q], t_min, t_max)) {
-          if (FILL) T.hits[out0 + cnt] = cj[q];
-          ++cnt;
-        }
+        const bool hit = valid && pair_hit(o, v, cp[q], t_min, t_max);
+        const unsigned long long bm = __ballot(hit);
+        mine = (lane == q) ? bm : mine;
+        cnt += hit ? 1 : 0;
       }
+      if (k < e) T.masks[k] = mine;
     }
     __syncthreads();
   }
@@ -1757,6 +1773,7 @@ void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam,
     hip_check(hipMemcpyAsync(&n_items, ix.tile_off.as<int64_t>() + n_tiles, 8, hipMemcpyDeviceToHost, st), "copy");
     hip_check(hipStreamSynchronize(st), "sync");
     ix.tile_items.ensure(sizeof(uint32_t) * std::max<int64_t>(1, n_items));
+    ix.tile_masks.ensure(sizeof(unsigned long long) * std::max<int64_t>(1, n_items));
     B.items = ix.tile_items.as<uint32_t>();
     k_bin<true><<<blocks_for(n_pairs_bin, 256), 256, 0, st>>>(B);
     TH.o = G.o;
@@ -1768,6 +1785,7 @@ void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam,
     TH.pos4 = B.pos4;
     TH.tile_off = B.tile_off;
     TH.items = B.items;
+    TH.masks = ix.tile_masks.as<unsigned long long>();
     TH.count = G.count;
     TH.max_hits = max_hits;
     k_tile_hits<false><<<(unsigned)n_tiles, 64, 0, st>>>(TH);
