@@ -765,9 +765,9 @@ __device__ __forceinline__ int key_kidx(uint64_t key) { return (int)((uint32_t)k
 // Scan state carried between threads.
 template <int D>
 struct Agg {
-  int64_t t;  // position of the last knot
   uint64_t a[D + 1];
-  int valid;
+  int32_t t;  // position of the last knot
+  int32_t valid;
 };
 
 template <int D>
@@ -785,16 +785,18 @@ __device__ __forceinline__ void agg_combine(const Agg<D>& x, const Agg<D>& y, Ag
   uint64_t s[D + 1];
 #pragma unroll
   for (int d = 0; d <= D; ++d) s[d] = x.a[d];
-  taylor_shift<D>(s, (uint32_t)(y.t - x.t));
+  taylor_shift<D>(s, (uint32_t)y.t - (uint32_t)x.t);
 #pragma unroll
   for (int d = 0; d <= D; ++d) out.a[d] = s[d] + y.a[d];
 }
 
 template <int D>
 struct Shared {
-  Agg<D> hs[kFieldThreads];                  // scan of the thread aggregates
+  union {                          // never live together: LDS is the ray layout's capacity
+    Agg<D> hs[kFieldThreads];      // scan of the thread aggregates (passes A and B)
+    float part[kFieldThreads][4];  // compositing partials (render, at the end)
+  };
   uint32_t rtab[32 * (kFieldThreads / 64)];  // radix sort tables
-  float part[kFieldThreads][4];
   int64_t wtot[kFieldThreads / 64];
   unsigned long long peak;
   int64_t ray;
