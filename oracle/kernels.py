@@ -3,8 +3,11 @@
 Follows the paper's introduction (Eq. cubic-kernel: the cubic B-spline with
 support bound q = 2), Sec. 3.1 (the normalized ray-restricted kernel
 B_Lambda(t) = w(sqrt(Lambda^2 + t^2))) and Sec. 4.4 / App. A.4 (the constants
-kappa and kappa').  The Wendland C2 kernel is not in the paper; it is the
-standard 3-D normalisation (21/16pi)(1 - r/2)^4 (1 + 2r) on [0, 2).
+kappa and kappa').  The Wendland kernels are not in the paper (it allows any
+piecewise polynomial kernel); they are the standard 3-D forms with support 2h:
+  C2: (21/16pi)   (1 - r/2)^4 (1 + 2r),
+  C4: (495/256pi) (1 - r/2)^6 (1 + 3r + 35/12 r^2),
+  C6: (1365/512pi)(1 - r/2)^8 (1 + 4r + 25/4 r^2 + 4 r^3)  on [0, 2).
 
 Every kernel here is a piecewise polynomial in r, stored as
 (r_lo, r_hi, ascending coefficients) times a constant factor, so that the
@@ -17,14 +20,49 @@ normalisation 2*pi*int Lambda*Sigma(Lambda) dLambda = 1.
 """
 from __future__ import annotations
 
+import functools
 import math
 
 import numpy as np
 from numpy.polynomial import polynomial as P
+from fractions import Fraction
 
 CUBIC = "cubic"
-WENDLAND = "wendland"
-KINDS = (CUBIC, WENDLAND)
+WENDLAND = "wendland"        # Wendland C2
+WENDLAND_C4 = "wendland_c4"
+WENDLAND_C6 = "wendland_c6"
+KINDS = (CUBIC, WENDLAND, WENDLAND_C4, WENDLAND_C6)
+
+# Wendland kernels as (factor, power n of (1 - r/2), polynomial p ascending in r, exact)
+_WENDLAND = {
+    WENDLAND: (21.0 / (16.0 * math.pi), 4, [Fraction(1), Fraction(2)]),
+    WENDLAND_C4: (495.0 / (256.0 * math.pi), 6, [Fraction(1), Fraction(3), Fraction(35, 12)]),
+    WENDLAND_C6: (1365.0 / (512.0 * math.pi), 8, [Fraction(1), Fraction(4), Fraction(25, 4), Fraction(4)]),
+}
+
+
+def _pmul(a, b):
+    out = [Fraction(0)] * (len(a) + len(b) - 1)
+    for i, x in enumerate(a):
+        for j, y in enumerate(b):
+            out[i + j] += x * y
+    return out
+
+
+def pieces_exact(kind: str):
+    """Kernel pieces [(r_lo, r_hi, exact rational coefficients ascending in r)] and the
+    constant factor (the only irrational part)."""
+    if kind == CUBIC:
+        # (2-r)^3 - 4(1-r)^3 = 4 - 6r^2 + 3r^3 on [0,1); (2-r)^3 on [1,2)
+        return ([(0.0, 1.0, [Fraction(4), Fraction(0), Fraction(-6), Fraction(3)]),
+                 (1.0, 2.0, [Fraction(8), Fraction(-12), Fraction(6), Fraction(-1)])], 1.0 / (4.0 * math.pi))
+    if kind in _WENDLAND:
+        fac, n, p = _WENDLAND[kind]
+        poly = [Fraction(1)]
+        for _ in range(n):
+            poly = _pmul(poly, [Fraction(1), Fraction(-1, 2)])
+        return [(0.0, 2.0, _pmul(poly, p))], fac
+    raise ValueError(kind)
 
 Q_SUPPORT = 2.0  # both kernels vanish for r >= 2
 
@@ -41,21 +79,24 @@ def pieces(kind: str):
 
     cubic (Eq. cubic-kernel):  (1/4pi)[(2-r)^3 - 4(1-r)^3] on [0,1) which expands
     to (1/4pi)(4 - 6r^2 + 3r^3), and (1/4pi)(2-r)^3 on [1,2).
-    wendland C2: (21/16pi)(1-r/2)^4 (1+2r) on [0,2).
+    Wendland: factor (1-r/2)^n p(r) on [0,2) (module docstring).
     """
     if kind == CUBIC:
         inner = P.polysub(P.polypow([2.0, -1.0], 3), 4.0 * P.polypow([1.0, -1.0], 3))
         outer = P.polypow([2.0, -1.0], 3)
         return [(0.0, 1.0, inner), (1.0, 2.0, outer)], 1.0 / (4.0 * math.pi)
-    if kind == WENDLAND:
-        poly = P.polymul(P.polypow([1.0, -0.5], 4), [1.0, 2.0])
-        return [(0.0, 2.0, poly)], 21.0 / (16.0 * math.pi)
+    if kind in _WENDLAND:
+        pcs, fac = pieces_exact(kind)
+        return [(lo, hi, np.array([float(c) for c in co])) for lo, hi, co in pcs], fac
     raise ValueError(kind)
 
 
 def w(kind: str, r):
-    """Kernel value w(r) for r >= 0 (zero outside the support)."""
+    """Kernel value w(r) for r >= 0 (zero outside the support); Wendland kernels are evaluated
+    in their factored form, which has no cancellation near r = 2."""
     r = np.asarray(r, dtype=np.float64)
+    if kind in _WENDLAND:
+        return w_near_edge(kind, r, np.maximum(2.0 - r, 0.0) * (r >= 0))
     out = np.zeros_like(r)
     pcs, fac = pieces(kind)
     for lo, hi, c in pcs:
@@ -67,8 +108,8 @@ def w(kind: str, r):
 def w_near_edge(kind: str, r, two_minus_r):
     """w(r) evaluated with 2 - r supplied separately (accurate near r -> 2).
 
-    Only the outermost piece uses the supplied 2 - r; both kernels are written as
-    a polynomial in (2 - r) there: cubic (2-r)^3, Wendland ((2-r)/2)^4 (1+2r).
+    Only the outermost piece uses the supplied 2 - r; every kernel is written as
+    a polynomial in (2 - r) there: cubic (2-r)^3, Wendland ((2-r)/2)^n p(r).
     """
     r = np.asarray(r, dtype=np.float64)
     e = np.asarray(two_minus_r, dtype=np.float64)
@@ -79,9 +120,10 @@ def w_near_edge(kind: str, r, two_minus_r):
         out[m_in] = (4.0 - 6.0 * r[m_in] ** 2 + 3.0 * r[m_in] ** 3) / (4.0 * math.pi)
         out[m_out] = e[m_out] ** 3 / (4.0 * math.pi)
         return out
-    if kind == WENDLAND:
+    if kind in _WENDLAND:
+        fac, n, p = _WENDLAND[kind]
         m = e > 0.0
-        out[m] = 21.0 / (16.0 * math.pi) * (0.5 * e[m]) ** 4 * (1.0 + 2.0 * r[m])
+        out[m] = fac * (0.5 * e[m]) ** n * P.polyval(r[m], [float(c) for c in p])
         return out
     raise ValueError(kind)
 
@@ -96,14 +138,18 @@ def w0(kind: str) -> float:
     return float(w(kind, np.array([0.0]))[0])
 
 
+def _int_exact(coefs, lo, hi, shift):
+    """int_lo^hi sum_i c_i r^(i + shift) dr in exact rational arithmetic."""
+    a, b = Fraction(lo), Fraction(hi)
+    return sum(c * (b ** (i + shift + 1) - a ** (i + shift + 1)) / (i + shift + 1) for i, c in enumerate(coefs))
+
+
 def volume_integral(kind: str) -> float:
-    """4 pi int_0^q r^2 w(r) dr (must be 1 for a normalised SPH kernel)."""
-    pcs, fac = pieces(kind)
-    tot = 0.0
-    for lo, hi, c in pcs:
-        ci = P.polyint(P.polymul(c, [0.0, 0.0, 1.0]))
-        tot += P.polyval(hi, ci) - P.polyval(lo, ci)
-    return 4.0 * math.pi * fac * tot
+    """4 pi int_0^q r^2 w(r) dr (must be 1 for a normalised SPH kernel); the polynomial part is
+    integrated exactly."""
+    pcs, fac = pieces_exact(kind)
+    tot = sum(_int_exact(c, lo, hi, 2) for lo, hi, c in pcs)
+    return 4.0 * math.pi * fac * float(tot)
 
 
 def kappa(kind: str) -> float:
@@ -112,13 +158,9 @@ def kappa(kind: str) -> float:
     The L2 norm of a normalized particle's contribution; the paper prints
     roughly 0.352 for the cubic kernel.
     """
-    pcs, fac = pieces(kind)
-    tot = 0.0
-    for lo, hi, c in pcs:
-        integrand = P.polymul(P.polymul(c, c), [0.0, 0.0, 1.0])
-        ci = P.polyint(integrand)
-        tot += P.polyval(hi, ci) - P.polyval(lo, ci)
-    return math.sqrt(4.0 * math.pi * fac * fac * tot)
+    pcs, fac = pieces_exact(kind)
+    tot = sum(_int_exact(_pmul(c, c), lo, hi, 2) for lo, hi, c in pcs)
+    return math.sqrt(4.0 * math.pi * fac * fac * float(tot))
 
 
 def dB_dt(kind: str, lam: float, t):
@@ -133,6 +175,7 @@ def dB_dt(kind: str, lam: float, t):
     return fac * out
 
 
+@functools.lru_cache(maxsize=None)
 def kappa_prime(kind: str) -> float:
     """kappa' = (int_0^q Lambda int_R [d/dt B_Lambda(t)]^2 dt dLambda)^(1/2).
 

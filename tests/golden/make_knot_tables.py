@@ -28,6 +28,8 @@ TABLES = [
     ("wendland", 6, 4, 128),
     ("cubic", 4, 4, 256),
     ("wendland", 4, 1, 256),
+    ("wendland_c4", 4, 3, 64),
+    ("wendland_c6", 2, 2, 64),
 ]
 
 
