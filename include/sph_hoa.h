@@ -43,7 +43,9 @@ typedef enum {
 
 typedef enum {
   SPH_HOA_KERNEL_CUBIC = 0,       /* cubic B-spline, Eq. cubic-kernel, support q = 2 */
-  SPH_HOA_KERNEL_WENDLAND_C2 = 1  /* (21/16pi)(1-r/2)^4(1+2r), support q = 2 */
+  SPH_HOA_KERNEL_WENDLAND_C2 = 1, /* (21/16pi)(1-r/2)^4(1+2r), support q = 2 */
+  SPH_HOA_KERNEL_WENDLAND_C4 = 2, /* (495/256pi)(1-r/2)^6(1+3r+35/12 r^2), support q = 2 */
+  SPH_HOA_KERNEL_WENDLAND_C6 = 3  /* (1365/512pi)(1-r/2)^8(1+4r+25/4 r^2+4r^3), support q = 2 */
 } sph_hoa_kernel;
 
 /* approx_rays: also return the sorted knots and the pre-merge exact integer pieces */

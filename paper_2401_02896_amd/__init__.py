@@ -16,6 +16,8 @@ LIB_PATH = os.path.join(HERE, "libsph_hoa.so")
 
 KERNEL_CUBIC = 0
 KERNEL_WENDLAND_C2 = 1
+KERNEL_WENDLAND_C4 = 2
+KERNEL_WENDLAND_C6 = 3
 FLAG_EXACT = 1
 FLAG_LUT_FP32 = 2
 FLAG_LUT_BF16 = 4

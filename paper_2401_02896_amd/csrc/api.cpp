@@ -70,6 +70,8 @@ std::shared_ptr<const sph::Table> cached_table(sph::Kernel k, int K, int D, int 
 sph::Kernel kernel_of(sph_hoa_kernel k) {
   if (k == SPH_HOA_KERNEL_CUBIC) return sph::Kernel::Cubic;
   if (k == SPH_HOA_KERNEL_WENDLAND_C2) return sph::Kernel::Wendland;
+  if (k == SPH_HOA_KERNEL_WENDLAND_C4) return sph::Kernel::WendlandC4;
+  if (k == SPH_HOA_KERNEL_WENDLAND_C6) return sph::Kernel::WendlandC6;
   throw sph::Error(SPH_HOA_E_INVALID_ARG, "unknown kernel");
 }
 

@@ -75,8 +75,12 @@ double kernel_w_edge(Kernel k, double r, double e) {
     if (r < 1.0) return (4.0 - 6.0 * r * r + 3.0 * r * r * r) / (4.0 * kPi);
     return e * e * e / (4.0 * kPi);
   }
-  double h = 0.5 * e;
-  return 21.0 / (16.0 * kPi) * h * h * h * h * (1.0 + 2.0 * r);
+  const double h = 0.5 * e;  // 1 - r / 2
+  const double h2 = h * h, h4 = h2 * h2;
+  if (k == Kernel::WendlandC4) return 495.0 / (256.0 * kPi) * h4 * h2 * (1.0 + r * (3.0 + r * (35.0 / 12.0)));
+  if (k == Kernel::WendlandC6)
+    return 1365.0 / (512.0 * kPi) * h4 * h4 * (1.0 + r * (4.0 + r * (25.0 / 4.0 + r * 4.0)));
+  return 21.0 / (16.0 * kPi) * h4 * (1.0 + 2.0 * r);
 }
 
 double kernel_dw(Kernel k, double r) {
@@ -85,8 +89,12 @@ double kernel_dw(Kernel k, double r) {
     if (r < 1.0) return (-12.0 * r + 9.0 * r * r) / (4.0 * kPi);
     return -3.0 * (2.0 - r) * (2.0 - r) / (4.0 * kPi);
   }
-  double a = 1.0 - 0.5 * r;
-  return 21.0 / (16.0 * kPi) * (-5.0 * r) * a * a * a;
+  const double a = 1.0 - 0.5 * r, a2 = a * a, a4 = a2 * a2;
+  // derivatives of the factored forms (1 - r/2)^n p(r)
+  if (k == Kernel::WendlandC4) return 495.0 / (256.0 * kPi) * (-14.0 / 3.0) * r * (1.0 + 2.5 * r) * a4 * a;
+  if (k == Kernel::WendlandC6)
+    return 1365.0 / (512.0 * kPi) * (-5.5) * r * (1.0 + r * (3.5 + 4.0 * r)) * a4 * a2 * a;
+  return 21.0 / (16.0 * kPi) * (-5.0 * r) * a2 * a;
 }
 
 struct Quad {

@@ -13,7 +13,7 @@
 
 namespace sph {
 
-enum class Kernel : int { Cubic = 0, Wendland = 1 };
+enum class Kernel : int { Cubic = 0, Wendland = 1, WendlandC4 = 2, WendlandC6 = 3 };
 
 constexpr double kSupport = 2.0;  // q for both kernels
 

@@ -17,7 +17,7 @@ import synth
 from oracle import field, geometry, grid, lut, quanta, render
 from tests.golden.make_knot_tables import load as load_knots
 
-KIND_ID = {"cubic": 0, "wendland": 1}
+KIND_ID = {"cubic": 0, "wendland": 1, "wendland_c4": 2, "wendland_c6": 3}
 
 
 class Scene:

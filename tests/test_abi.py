@@ -11,6 +11,7 @@ from oracle import quanta
 from tests.golden.make_knot_tables import TABLES, load
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+KIND_ID = {"cubic": 0, "wendland": 1, "wendland_c4": 2, "wendland_c6": 3}
 
 
 def test_every_declared_symbol_is_exported():
@@ -53,7 +54,7 @@ def test_library_knot_tables_match_oracle(spec):
     to more than a few digits) are compared on their error instead of their position.
     """
     kind, K, D, n = spec
-    th, e2 = L.sph_hoa_knot_table(0 if kind == "cubic" else 1, K, D, n)
+    th, e2 = L.sph_hoa_knot_table(KIND_ID[kind], K, D, n)
     ref = load(*spec)
     d = np.abs(th / ref - 1).max(axis=1)
     flat = e2 < 1e-12 * 0.1
@@ -68,7 +69,7 @@ def test_library_projection_matches_oracle(spec):
 
     kind, K, D, n = spec
     theta = load(*spec)
-    shat, smid, e2 = L.sph_hoa_lut_coefficients(0 if kind == "cubic" else 1, K, D, theta)
+    shat, smid, e2 = L.sph_hoa_lut_coefficients(KIND_ID[kind], K, D, theta)
     lams = lut.lambda_midpoints(kind, n)
     rows = sorted(set(list(range(0, n, max(1, n // 24))) + [n - 1]))
     tol = 1e-9 if D <= 3 else 1e-7
@@ -80,7 +81,10 @@ def test_library_projection_matches_oracle(spec):
         assert abs(e2[i] - lut.project(kind, float(lams[i]), theta[i], K, D)["E2"]) <= 1e-6 * e2[i] + 1e-25
 
 
+@pytest.mark.parametrize("kind", list(KIND_ID))
 @pytest.mark.parametrize("D", [1, 2, 3, 4, 6])
-def test_library_tau_matches_oracle(D):
-    r = quanta.fig4_sigma_ratio("cubic")
-    assert abs(L.sph_hoa_optimal_tau(0, D, r, 0.7, 3.0) / (0.7 * quanta.optimal_tau("cubic", D, r / 3.0)) - 1) < 1e-13
+def test_library_tau_matches_oracle(kind, D):
+    """The length quantum depends on the kernel through kappa and kappa' (App. A.4, A.5)."""
+    r = quanta.fig4_sigma_ratio(kind)
+    got = L.sph_hoa_optimal_tau(KIND_ID[kind], D, r, 0.7, 3.0)
+    assert abs(got / (0.7 * quanta.optimal_tau(kind, D, r / 3.0)) - 1) < 1e-12

@@ -171,9 +171,11 @@ def test_tiny_render_pixels():
 
 @pytest.mark.parametrize("kind,K,D,n_lut", [("cubic", 3, 3, 256), ("wendland", 2, 2, 256), ("cubic", 1, 2, 128),
                                             ("cubic", 5, 2, 128), ("wendland", 6, 4, 128), ("cubic", 4, 4, 256),
-                                            ("wendland", 4, 1, 256)])
+                                            ("wendland", 4, 1, 256), ("wendland_c4", 4, 3, 64),
+                                            ("wendland_c6", 2, 2, 64)])
 def test_configurations(kind, K, D, n_lut):
-    """K odd and even (middle knot / closure at +-theta_1), D = 1..4, signed amplitudes."""
+    """K odd and even (middle knot / closure at +-theta_1), D = 1..4, signed amplitudes; the cubic
+    spline and the Wendland C2, C4 and C6 kernels."""
     xyz, h, val = synth.random_scene(21 + K + 10 * D, 500, h_lo=0.03, h_hi=0.1, signed=True)
     # D = 1: the optimal length quantum is ~1e-9, too fine for int32 positions on these rays
     # (the library reports E_OVERFLOW then); a 100x coarser quantum is given explicitly instead
