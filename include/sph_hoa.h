@@ -291,7 +291,8 @@ sph_hoa_status sph_hoa_server_wait(sph_hoa_server server, int64_t request_id, do
  * or completed is not affected (*cancelled = 0).  Unknown id: E_INVALID_ARG. */
 sph_hoa_status sph_hoa_server_cancel(sph_hoa_server server, int64_t request_id, int32_t* cancelled);
 sph_hoa_status sph_hoa_server_get_stats(sph_hoa_server server, sph_hoa_server_stats* stats);
-/* Renders what is still queued, stops the worker and frees the server (not its indices). */
+/* Renders what is still queued, stops the worker and frees the server (not its indices).  No other
+ * call on this server may be running or follow (waits included). */
 sph_hoa_status sph_hoa_server_destroy(sph_hoa_server server);
 
 /* ---------------------------------------------------------------- integer bit length
