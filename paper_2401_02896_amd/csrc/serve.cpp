@@ -5,8 +5,9 @@
 // repeatedly takes the oldest request and admits, in arrival order, the queued requests that use
 // the same index and transfer function while the batch's estimated device memory stays within the
 // budget; the batch is rendered by one batched launch chain (run_rays over all its cameras), and
-// each image is copied into its request's output buffer.  Every image is bit-identical to sph_hoa_render of
-// the same camera alone (the batched path computes each ray exactly as the single path does).
+// each image is copied into its request's output buffer.  Every image is bit-identical to
+// sph_hoa_render of the same camera alone (the batched path computes each ray exactly as the
+// single path does).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
