@@ -30,7 +30,8 @@ evenness/continuity/compact support of the result, local optimality of the
 knots, the overall approximation errors E_{K,D} printed in Fig. 4, and the line
 integral of the approximation against the closed-form kernel column integral.
 The storage rounding of the table precision study (round_storage) is pinned by
-hand-worked ties and by torch's float32 -> bfloat16 conversion.
+hand-worked ties, torch's float32 -> bfloat16 and numpy's float32 -> float16
+conversions.
 """
 from __future__ import annotations
 
@@ -435,14 +436,22 @@ def round_storage(values, fmt: str):
 
     fp64: unchanged.  fp32: the nearest float32.  bf16: the nearest float32, then the nearest
     number with 8 significant bits, ties to even: with f = m 2^e, 1/2 <= |m| < 1 (frexp), the
-    result is rint(256 m) / 256 * 2^e (rint rounds half to even; every step is exact in float64)."""
+    result is rint(256 m) / 256 * 2^e (rint rounds half to even; every step is exact in float64).
+    fp16: the nearest float32, then the nearest IEEE binary16: 11 significant bits for
+    |f| >= 2^-14 (rint(2048 m) / 2048 * 2^e), multiples of 2^-24 below (subnormals), infinity
+    beyond the largest finite value 65504."""
     a = np.asarray(values, dtype=np.float64)
     if fmt == "fp64":
         return a.copy()
     f = a.astype(np.float32).astype(np.float64)
     if fmt == "fp32":
         return f
-    if fmt != "bf16":
-        raise ValueError(fmt)
     m, e = np.frexp(f)
-    return np.ldexp(np.rint(m * 256.0) / 256.0, e)
+    if fmt == "bf16":
+        return np.ldexp(np.rint(m * 256.0) / 256.0, e)
+    if fmt != "fp16":
+        raise ValueError(fmt)
+    normal = np.ldexp(np.rint(m * 2048.0) / 2048.0, e)
+    sub = np.rint(f * 2.0 ** 24) * 2.0 ** -24
+    r = np.where(np.abs(f) >= 2.0 ** -14, normal, sub)
+    return np.where(np.abs(r) > 65504.0, np.copysign(np.inf, f), r)

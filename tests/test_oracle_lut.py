@@ -176,3 +176,17 @@ def test_storage_rounding_matches_torch_bfloat16():
     f32 = torch.from_numpy(x.astype(np.float32))
     ref = f32.to(torch.bfloat16).to(torch.float64).numpy()
     assert np.array_equal(lut.round_storage(x, "bf16"), ref)
+
+
+def test_storage_rounding_fp16_hand_cases_and_numpy():
+    """binary16 keeps 11 significant bits: 1 + 2^-11 is a tie between 1 and 1 + 2^-10 (even: 1);
+    below 2^-14 the spacing is 2^-24 (2^-25 is a tie between 0 and 2^-24: 0); 65504 is the
+    largest finite value, 65520 (a tie with the next binade's 65536) overflows."""
+    x = np.array([1 + 2.0 ** -11, 1 + 3 * 2.0 ** -11, 2.0 ** -25, 3e-8, 65504.0, 65520.0, -65520.0])
+    want = np.array([1.0, 1 + 2.0 ** -9, 0.0, 2.0 ** -24, 65504.0, np.inf, -np.inf])
+    assert np.array_equal(lut.round_storage(x, "fp16"), want)
+    rng = np.random.default_rng(9)
+    y = np.concatenate([rng.normal(0, 1, 20000) * 10.0 ** rng.uniform(-10, 4.5, 20000), rng.uniform(-1, 1, 2000)])
+    with np.errstate(over="ignore"):
+        ref = y.astype(np.float32).astype(np.float16).astype(np.float64)
+    assert np.array_equal(lut.round_storage(y, "fp16"), ref)
