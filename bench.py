@@ -259,7 +259,7 @@ def run_bitlength(a, torch, L, synth):
 
 def run_precision(a, torch, L, synth):
     """Table storage precision: the plain frame (1M clustered particles, Wendland C2, K = 4, D = 3,
-    tol 1e-3, 512^2) rendered with the float table of Sec. 3.1 stored in fp64, fp32 and bf16.
+    tol 1e-3, 512^2) rendered with the float table of Sec. 3.1 stored in fp64, fp32, bf16 and fp16.
     Reports the frame time of each and its pixel differences, against the fp64-table frame and
     against the float64 oracle on a bounded sample of rays.  value = contributions/s with the
     bf16 table."""
@@ -269,7 +269,7 @@ def run_precision(a, torch, L, synth):
     tf = synth.transfer_function()
     vmin, vmax, step = 0.0, 300.0, 2.0 / 512
     res, imgs = {}, {}
-    for fmt in ("fp64", "fp32", "bf16"):
+    for fmt in ("fp64", "fp32", "bf16", "fp16"):
         idx = L.sph_hoa_build_index(xyz, h, val, kernel=L.KERNEL_WENDLAND_C2, degree=D, pieces=K, lut_entries=4096,
                                     merge_tol=tol, lut_precision=fmt)
         out = torch.empty((cam["height"], cam["width"], 4), dtype=torch.float32, device="cuda")
@@ -289,7 +289,7 @@ def run_precision(a, torch, L, synth):
         if fmt == "fp64":
             info = idx.info()
         idx.free()
-    for fmt in ("fp32", "bf16"):
+    for fmt in ("fp32", "bf16", "fp16"):
         d = np.abs(imgs[fmt] - imgs["fp64"])
         res[fmt]["max_abs_rgba_vs_fp64_table"] = float(d.max())
         res[fmt]["mean_abs_rgba_vs_fp64_table"] = float(d.mean())
@@ -298,7 +298,7 @@ def run_precision(a, torch, L, synth):
         _, _, results = cpu_baseline(a, xyz, h, val, info, cam, tf, vmin, vmax, step, kind, K, D, tol,
                                      imgs["fp64"].astype(np.float32))
         kept = [(r, px) for (r, _, px, m, _) in results if m > 1e-6]
-        for fmt in ("fp64", "fp32", "bf16"):
+        for fmt in ("fp64", "fp32", "bf16", "fp16"):
             e = [float(np.max(np.abs(imgs[fmt][r] - px))) for r, px in kept]
             res[fmt]["max_abs_rgba_vs_oracle"] = max(e) if e else None
             res[fmt]["mean_abs_rgba_vs_oracle"] = float(np.mean(e)) if e else None
@@ -309,7 +309,7 @@ def run_precision(a, torch, L, synth):
         "warmup": a.warmup, "ms_per_step": res["bf16"]["p50_ms"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "int64", "data": "synthetic",
         "config": {"workload": f"precision: plain frame ({a.particles} clustered particles, Wendland C2, K=4, D=3, "
-                               f"tol 1e-3, {a.size}x{a.size}) with the table stored in fp64 / fp32 / bf16",
+                               f"tol 1e-3, {a.size}x{a.size}) with the table stored in fp64 / fp32 / bf16 / fp16",
                    "by_table_precision": res, "oracle_sample": oracle},
         "cpu_baseline": None,
     }

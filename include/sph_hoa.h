@@ -52,12 +52,15 @@ typedef enum {
 #define SPH_HOA_FLAG_EXACT 1u
 /* sph_hoa_params.flags: storage precision of the float table (the knots theta_k and projection
  * jumps s-hat of Sec. 3.1), for the precision study.  Every table value is rounded once, when the
- * index is built, to the nearest float32 (LUT_FP32) or to the nearest bfloat16 of that float32
- * (LUT_BF16: 8 significant bits, ties to even); the per-hit quantization (Sec. 4.3) then uses the
- * rounded values, and the integer accumulation stays exact (the closure is computed from the
- * rounded jumps).  At most one of the two; neither: float64. */
+ * index is built, to the nearest float32 (LUT_FP32), to the nearest bfloat16 of that float32
+ * (LUT_BF16: 8 significant bits, ties to even) or to the nearest IEEE binary16 of that float32
+ * (LUT_FP16: 11 significant bits, subnormals below 2^-14, ties to even; a value beyond 65504
+ * becomes infinite and is reported by the render as E_OVERFLOW); the per-hit quantization
+ * (Sec. 4.3) then uses the rounded values, and the integer accumulation stays exact (the closure is
+ * computed from the rounded jumps).  At most one of them; none: float64. */
 #define SPH_HOA_FLAG_LUT_FP32 2u
 #define SPH_HOA_FLAG_LUT_BF16 4u
+#define SPH_HOA_FLAG_LUT_FP16 8u
 
 /* Method parameters (Sec. 3.2 K and D, Sec. 4.4 quanta, Sec. 5 bit length). */
 typedef struct {
@@ -72,7 +75,7 @@ typedef struct {
   double tau;           /* > 0: length quantum to use instead of the minimiser of Q_D */
   const double* knot_table; /* optional HOST array [lut_entries][ceil(K/2)] of optimal knots theta_k
                                (units of h) replacing the library's own optimisation (Sec. 3.4); copied */
-  uint32_t flags;       /* 0, SPH_HOA_FLAG_LUT_FP32 or SPH_HOA_FLAG_LUT_BF16 */
+  uint32_t flags;       /* 0 or one of SPH_HOA_FLAG_LUT_FP32 / _BF16 / _FP16 */
   const double* jump_table;     /* optional HOST [lut_entries][ceil(K/2)][D+1]: projection jumps s-hat at
                                    +theta_k (Sec. 3.1) replacing the library's projection; requires
                                    knot_table (the knots they belong to); copied */

@@ -21,6 +21,7 @@ KERNEL_WENDLAND_C6 = 3
 FLAG_EXACT = 1
 FLAG_LUT_FP32 = 2
 FLAG_LUT_BF16 = 4
+FLAG_LUT_FP16 = 8
 
 STATUS = {0: "OK", 1: "E_INVALID_ARG", 2: "E_OUT_OF_MEMORY", 3: "E_OVERFLOW", 4: "E_DEVICE", 5: "E_UNSUPPORTED",
           6: "E_INTERNAL", 7: "E_BUSY", 8: "E_CANCELLED"}
@@ -237,7 +238,7 @@ def sph_hoa_build_index(xyz, h, value, kernel=KERNEL_CUBIC, degree=2, pieces=4, 
                         a_max=0.0, h_repr=0.0, phi_repr=0.0, tau=0.0, knot_table=None, lut_precision="fp64",
                         jump_table=None, jump_table_mid=None):
     """Build an index (sph_hoa_build_index).  xyz [n,3], h [n], value [n]: tensors or arrays.
-    lut_precision: storage precision of the float table, "fp64", "fp32" or "bf16".
+    lut_precision: storage precision of the float table, "fp64", "fp32", "bf16" or "fp16".
     jump_table [lut_entries, ceil(K/2), D+1] / jump_table_mid [lut_entries, D+1] (even K): projection
     jumps replacing the library's own (with knot_table)."""
     import numpy as np
@@ -248,9 +249,9 @@ def sph_hoa_build_index(xyz, h, value, kernel=KERNEL_CUBIC, degree=2, pieces=4, 
     n = int(hh.numel())
     if x.numel() != 3 * n or v.numel() != n:
         raise ValueError("xyz must be [n, 3], h and value [n]")
-    flags = {"fp64": 0, "fp32": FLAG_LUT_FP32, "bf16": FLAG_LUT_BF16}.get(lut_precision)
+    flags = {"fp64": 0, "fp32": FLAG_LUT_FP32, "bf16": FLAG_LUT_BF16, "fp16": FLAG_LUT_FP16}.get(lut_precision)
     if flags is None:
-        raise ValueError(f"lut_precision must be fp64, fp32 or bf16, got {lut_precision!r}")
+        raise ValueError(f"lut_precision must be fp64, fp32, bf16 or fp16, got {lut_precision!r}")
     p = Params(degree, pieces, lut_entries, 64, merge_tol, a_max, h_repr, phi_repr, tau, None, flags)
     kt = None
     if knot_table is not None:

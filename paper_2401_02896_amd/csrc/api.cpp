@@ -84,11 +84,13 @@ void check_method(int K, int D) {
 }  // namespace
 
 namespace {
-// Float64 -> nearest float32, and for bf16 further to the nearest value with 8 significant bits
-// (ties to even), the storage formats of the table precision study.
-double round_storage(double x, bool bf16) {
+// Float64 -> nearest float32, then for bf16 the nearest value with 8 significant bits (ties to
+// even) and for fp16 the nearest IEEE binary16 (the storage formats of the table precision study).
+enum class Storage { F32, BF16, F16 };
+double round_storage(double x, Storage fmt) {
   const float f = (float)x;
-  if (!bf16 || !std::isfinite(f)) return (double)f;
+  if (fmt == Storage::F32 || !std::isfinite(f)) return (double)f;
+  if (fmt == Storage::F16) return (double)(_Float16)f;
   uint32_t u;
   std::memcpy(&u, &f, 4);
   const uint32_t lsb = (u >> 16) & 1u;
@@ -135,9 +137,11 @@ sph_hoa_status sph_hoa_build_index(const float* xyz, const float* h, const float
     require(std::isfinite(p->merge_tol) && p->merge_tol >= 0.0, "merge_tol must be finite and >= 0");
     require(std::isfinite(p->a_max) && std::isfinite(p->h_repr) && std::isfinite(p->phi_repr) &&
                 std::isfinite(p->tau), "quanta parameters must be finite");
-    require((p->flags & ~(SPH_HOA_FLAG_LUT_FP32 | SPH_HOA_FLAG_LUT_BF16)) == 0,
-            "params.flags: only SPH_HOA_FLAG_LUT_FP32 or SPH_HOA_FLAG_LUT_BF16");
-    require(p->flags != (SPH_HOA_FLAG_LUT_FP32 | SPH_HOA_FLAG_LUT_BF16), "params.flags: one table precision");
+    const uint32_t lut_bits = SPH_HOA_FLAG_LUT_FP32 | SPH_HOA_FLAG_LUT_BF16 | SPH_HOA_FLAG_LUT_FP16;
+    require((p->flags & ~lut_bits) == 0, "params.flags: only the SPH_HOA_FLAG_LUT_* table precisions");
+    require(p->flags == 0 || p->flags == SPH_HOA_FLAG_LUT_FP32 || p->flags == SPH_HOA_FLAG_LUT_BF16 ||
+                p->flags == SPH_HOA_FLAG_LUT_FP16,
+            "params.flags: one table precision");
     sph::Index& ix = H->ix;
     ix.n = n;
     ix.kernel = k;
@@ -174,11 +178,13 @@ sph_hoa_status sph_hoa_build_index(const float* xyz, const float* h, const float
         ix.table.smid.assign(nm, 0.0);
       }
     }
-    if (p->flags & (SPH_HOA_FLAG_LUT_FP32 | SPH_HOA_FLAG_LUT_BF16)) {
-      const bool bf16 = (p->flags & SPH_HOA_FLAG_LUT_BF16) != 0;
-      for (double& x : ix.table.theta) x = round_storage(x, bf16);
-      for (double& x : ix.table.shat) x = round_storage(x, bf16);
-      for (double& x : ix.table.smid) x = round_storage(x, bf16);
+    if (p->flags != 0) {
+      const Storage fmt = (p->flags == SPH_HOA_FLAG_LUT_BF16)   ? Storage::BF16
+                          : (p->flags == SPH_HOA_FLAG_LUT_FP16) ? Storage::F16
+                                                                : Storage::F32;
+      for (double& x : ix.table.theta) x = round_storage(x, fmt);
+      for (double& x : ix.table.shat) x = round_storage(x, fmt);
+      for (double& x : ix.table.smid) x = round_storage(x, fmt);
       ix.lut_flags = p->flags;
     }
     hipStream_t st = (hipStream_t)stream;

@@ -1,5 +1,6 @@
 """Table storage precision (the precision study): the float table of Sec. 3.1 (knots theta_k and
-projection jumps s-hat) stored as float32 or bfloat16 (sph_hoa_params.flags LUT_FP32 / LUT_BF16).
+projection jumps s-hat) stored as float32, bfloat16 or binary16 (sph_hoa_params.flags LUT_FP32 /
+LUT_BF16 / LUT_FP16).
 
 The library rounds its own float64 table; the oracle rounds its own (oracle.lut.round_storage).
 The knots come from the same float64 table on both sides, so their rounding is identical and the
@@ -24,7 +25,8 @@ if not torch.cuda.is_available():  # pragma: no cover - only on the GPU machine
 
 import paper_2401_02896_amd as L  # noqa: E402
 
-ULP = {"fp32": 2.0 ** -24, "bf16": 2.0 ** -8}
+ULP = {"fp32": 2.0 ** -24, "bf16": 2.0 ** -8, "fp16": 2.0 ** -11}
+FLAG = {"fp32": L.FLAG_LUT_FP32, "bf16": L.FLAG_LUT_BF16, "fp16": L.FLAG_LUT_FP16}
 
 
 def _scene(fmt, tol=1e-3):
@@ -42,11 +44,11 @@ def _row_in_band(lib_row, sc, i):
     return np.all((lib_row >= lo) & (lib_row <= hi))
 
 
-@pytest.mark.parametrize("fmt", ["fp32", "bf16"])
+@pytest.mark.parametrize("fmt", ["fp32", "bf16", "fp16"])
 def test_stored_table_is_the_rounded_table(fmt):
     sc = _scene(fmt)
     idx = sc.index()
-    assert idx.info()["lut_flags"] == {"fp32": L.FLAG_LUT_FP32, "bf16": L.FLAG_LUT_BF16}[fmt]
+    assert idx.info()["lut_flags"] == FLAG[fmt]
     theta, shat, _ = idx.lut()
     assert np.array_equal(theta, sc.theta_stored)                  # same input, same rounding
     assert not np.array_equal(theta, sc.theta)                      # and it did round
@@ -59,7 +61,7 @@ def test_stored_table_is_the_rounded_table(fmt):
     assert np.array_equal(shat, lut.round_storage(raw, fmt))
 
 
-@pytest.mark.parametrize("fmt", ["fp32", "bf16"])
+@pytest.mark.parametrize("fmt", ["fp32", "bf16", "fp16"])
 def test_rounded_table_rays_match_oracle(fmt):
     sc = _scene(fmt)
     o, v = synth.ortho_rays()
@@ -85,7 +87,7 @@ def test_rounded_table_changes_the_field_by_its_rounding():
     o, v = synth.ortho_rays(32, 32)
     ref = None
     diffs = {}
-    for fmt in ("fp64", "fp32", "bf16"):
+    for fmt in ("fp64", "fp32", "bf16", "fp16"):
         sc = _scene(fmt, tol=0.0)
         out = L.sph_hoa_approx_rays(sc.index(), torch.as_tensor(o), torch.as_tensor(v), 0.0, 1.4)
         ts = np.linspace(0.05, 1.35, 64)
@@ -101,10 +103,10 @@ def test_rounded_table_changes_the_field_by_its_rounding():
             diffs[fmt] = np.abs(vals - ref).max() / scale
     assert diffs["fp32"] < 1e-5
     assert 1e-6 < diffs["bf16"] < 5e-2
-    assert diffs["fp32"] < diffs["bf16"]
+    assert diffs["fp32"] < diffs["fp16"] < diffs["bf16"]
 
 
 def test_unknown_precision_rejected():
     sc = H.tiny_scene()
     with pytest.raises(ValueError):
-        L.sph_hoa_build_index(sc.xyz, sc.h, sc.val, lut_precision="fp16")
+        L.sph_hoa_build_index(sc.xyz, sc.h, sc.val, lut_precision="fp8")
