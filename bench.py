@@ -525,6 +525,37 @@ def main():
                    "tau": info["tau"], "sigma": info["sigma"], "index_build_s": index_s, "generate_s": gen_s},
         "roofline": roofline,
     }
+    # the same frame's rays through sph_hoa_approx_rays (merged fields, no classification), after
+    # the timed region: pixel-centre rays of the camera, arbitrary-ray gathering
+    eye = np.array(cam["eye"], np.float64)
+    fwd = np.array(cam["look_at"], np.float64) - eye
+    fwd /= np.linalg.norm(fwd)
+    rgt = np.cross(fwd, np.array(cam["up"], np.float64))
+    rgt /= np.linalg.norm(rgt)
+    upv = np.cross(rgt, fwd)
+    gy = math.tan(math.radians(cam["fov_y_deg"]) / 2)
+    Wd, Hd = cam["width"], cam["height"]
+    jj, ii = np.meshgrid(np.arange(Hd), np.arange(Wd), indexing="ij")
+    ax = (((2 * ii + 1) / Wd - 1) * gy * Wd / Hd).reshape(-1, 1)
+    by = ((1 - (2 * jj + 1) / Hd) * gy).reshape(-1, 1)
+    dirs = fwd[None, :] + ax * rgt[None, :] + by * upv[None, :]
+    dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+    ro = torch.as_tensor(np.tile(eye, (len(dirs), 1)).astype(np.float32), device="cuda")
+    rv = torch.as_tensor(dirs.astype(np.float32), device="cuda")
+    warm = L.sph_hoa_approx_rays(idx, ro, rv, cam["t_min"], cam["t_max"])
+    cap = int(warm["n_pieces"]) + 1024  # output sized once, as a caller reusing buffers would
+    del warm
+    torch.cuda.synchronize()
+    alat = []
+    for _ in range(3):
+        ts = time.perf_counter()
+        ap = L.sph_hoa_approx_rays(idx, ro, rv, cam["t_min"], cam["t_max"], capacity=cap)
+        torch.cuda.synchronize()
+        alat.append(time.perf_counter() - ts)
+    result["config"]["approx_rays_p50_ms"] = float(np.median(alat) * 1e3)
+    result["config"]["approx_rays_contributions_per_s"] = ap["n_pairs"] / float(np.median(alat))
+    result["config"]["approx_rays_pieces"] = int(ap["n_pieces"])
+    del ap, ro, rv
     img = out.cpu().numpy().reshape(-1, 4)
     if not a.no_cpu:
         result["cpu_baseline"], result["parity"], _ = cpu_baseline(a, xyz, h, val, info, cam, tf, vmin, vmax, step,
@@ -583,9 +614,18 @@ def cpu_baseline(a, xyz, h, val, info, cam, tf, vmin, vmax, step, kind, K, D, to
         elapsed = time.perf_counter() - t0
     hits = sum(r[1] for r in results)
     diffs = [float(np.max(np.abs(img[r] - px))) for (r, _, px, m, _) in results if m > 1e-6]
+    cpu = "unknown CPU"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    cpu = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     base = {"value": hits / elapsed, "unit": "contributions/s", "cores": cores, "kind": "oracle",
             "sample": f"{len(results)} random pixel rays of the same 512x512 frame (FP64 oracle with Python-integer "
-                      f"accumulation, {cores} worker processes, {elapsed:.1f} s wall)"}
+                      f"accumulation, {cores} worker processes on {cpu}, {elapsed:.1f} s wall)"}
     parity = {"rays": len(results), "rays_compared": len(diffs),
               "max_abs_rgba": max(diffs) if diffs else None, "tol": 1e-4,
               "quanta_rel_diff": {"tau": abs(info["tau"] / tau - 1), "sigma": abs(info["sigma"] / sigma - 1)}}
