@@ -103,8 +103,8 @@ __global__ void __launch_bounds__(kFloatThreads) k_float_field(FloatArgs F) {
   const float tmin_f = (float)F.t_min, tmax_f = (float)F.t_max;
   const float step_f = (tmax_f - tmin_f) / (float)(F.n_reinit + 1);
   for (int64_t r = blockIdx.x; r < F.n_rays; r += gridDim.x) {
-    const int64_t hoff = F.hit_off[r];
-    const int nh = (int)(F.hit_off[r + 1] - hoff);
+    const int64_t hoff = F.hit_slots ? r * F.hit_slots : F.hit_off[r];
+    const int nh = (int)(F.hit_off[r + 1] - F.hit_off[r]);
     const int nk = nh * K1;
     double o[3], v[3];
     for (int k = 0; k < 3; ++k) {

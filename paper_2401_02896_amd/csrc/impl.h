@@ -144,6 +144,8 @@ struct Index {
   // per-call scratch
   DevBuf rays_o, rays_v;        // double [n][3]
   DevBuf hit_count, hit_off;    // int64 [n + 1]
+  DevBuf hit_slots;             // uint32 [n][slots]: single-pass gathering of arbitrary rays
+  int64_t last_max_hits = 0;    // largest hit count of the previous arbitrary-ray call
   DevBuf hits;                  // uint32 [pairs]
   DevBuf tile_count, tile_off, tile_items;  // screen-tile binning of the particles (camera rays)
   DevBuf tile_masks;                         // per tile item: the tile pixels it hits
@@ -215,6 +217,7 @@ struct FloatArgs {
   double t_min, t_max;
   const int64_t* hit_off;
   const uint32_t* hits;
+  int64_t hit_slots;  // > 0: ray r's hits at hits[r * hit_slots ...]
   const float4* pos4;
   const float* val;
   const int32_t* orig;

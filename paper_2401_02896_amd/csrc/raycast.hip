@@ -118,6 +118,8 @@ struct GatherArgs {
   int64_t* count;       // count pass: hits per ray
   const int64_t* off;   // fill pass: offsets
   uint32_t* hits;       // fill pass: permuted particle indices
+  uint32_t* slots;      // count pass, optional: ray r's first n_slots hits at [r * n_slots, ...)
+  int64_t n_slots;
   unsigned long long* max_hits;
   uint32_t* flags;
 };
@@ -250,9 +252,11 @@ __global__ void __launch_bounds__(kGatherThreads) k_gather(GatherArgs A) {
           hit = pair_hit(o, v, A.pos4[j], t_min, t_max);
         }
         const uint64_t m = __ballot(hit);
-        if (FILL && hit) {
+        if (hit) {
           const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-          A.hits[out0 + found + __popcll(m & lt)] = j;
+          const int64_t pos = found + __popcll(m & lt);
+          if (FILL) A.hits[out0 + pos] = j;
+          else if (A.slots && pos < A.n_slots) A.slots[r * A.n_slots + pos] = j;
         }
         found += __popcll(m);
       }
@@ -470,6 +474,7 @@ struct FieldArgs {
   const int64_t* hit_count;
   const int64_t* hit_off;
   const uint32_t* hits;
+  int64_t hit_slots;  // > 0: ray r's hits at hits[r * hit_slots ...] (single-pass gathering)
   // particles (Morton order)
   const float4* pos4;
   const float* val;
@@ -889,7 +894,7 @@ __device__ void process_ray(const FieldArgs& A, Shared<D>& sh, const RayStore& S
   const int tid = threadIdx.x;
   const int K = A.mc.K, P = A.mc.P;
   const int64_t nk = nh * (K + 1);
-  const int64_t hoff = A.hit_off[r];
+  const int64_t hoff = A.hit_slots ? r * A.hit_slots : A.hit_off[r];
   double o[3], v[3];
   for (int k = 0; k < 3; ++k) {
     o[k] = A.o[3 * r + k];
@@ -1750,6 +1755,7 @@ void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam,
   BinArgs B{};
   TileHitArgs TH{};
   const int64_t n_pairs_bin = ix.n * (int64_t)n_cams;
+  int64_t n_slots = 0;  // arbitrary rays: per-ray hit slots of the single-pass gathering
   if (n_cams > 0) {
     // bin particles into screen tiles, then count hits per pixel ray from the tile lists
     B.pos4 = ix.pos4.as<float4>();
@@ -1793,6 +1799,19 @@ void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam,
     k_tile_hits<false><<<(unsigned)n_tiles, 64, 0, st>>>(TH);
     if (ix.timing) hip_check(hipEventRecord(ix.ev[1], st), "event");
   } else {
+    // Single pass when it fits: the counting walk also stores each ray's first n_slots hits in
+    // per-ray slots, sized from the previous call's longest ray; the filling walk then runs only
+    // if some ray has more hits than slots.
+    int64_t want = ix.last_max_hits > 0 ? ix.last_max_hits : 256;
+    n_slots = 16;
+    while (n_slots < want) n_slots <<= 1;
+    if (const char* f = std::getenv("SPH_HOA_GATHER_SLOTS")) n_slots = std::max<int64_t>(0, std::atoll(f));  // test hook
+    if (n_slots > 0 && n_rays * n_slots > ((int64_t)1 << 30)) n_slots = 0;  // over 4 GiB: two walks
+    if (n_slots > 0) {
+      ix.hit_slots.ensure(sizeof(uint32_t) * n_rays * n_slots);
+      G.slots = ix.hit_slots.as<uint32_t>();
+      G.n_slots = n_slots;
+    }
     if (ix.timing) hip_check(hipEventRecord(ix.ev[0], st), "event");
     k_gather<false><<<gblocks, kGatherThreads, 0, st>>>(G);
     if (ix.timing) hip_check(hipEventRecord(ix.ev[1], st), "event");
@@ -1815,17 +1834,25 @@ void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam,
   // the per-ray sort ranks a wave's keys in 16-bit fields: at most 1023 keys per thread
   if ((int64_t)mh * (K + 1) > (int64_t)1023 * kFieldThreads)
     throw Error(SPH_HOA_E_UNSUPPORTED, "more than 1023 * 256 knots on one ray");
-  ix.hits.ensure(sizeof(uint32_t) * std::max<int64_t>(1, total_pairs));
+  if (n_cams == 0) ix.last_max_hits = (int64_t)mh;
+  const bool single_pass = n_slots > 0 && (int64_t)mh <= n_slots;
+  const uint32_t* hit_lists = single_pass ? ix.hit_slots.as<uint32_t>() : nullptr;
+  if (!single_pass) {
+    ix.hits.ensure(sizeof(uint32_t) * std::max<int64_t>(1, total_pairs));
+    hit_lists = ix.hits.as<uint32_t>();
+  }
   G.off = ix.hit_off.as<int64_t>();
   G.hits = ix.hits.as<uint32_t>();
+  G.slots = nullptr;
   if (ix.timing) hip_check(hipEventRecord(ix.ev[2], st), "event");
   if (n_cams > 0) {
     TH.off = G.off;
     TH.hits = G.hits;
     k_tile_hits<true><<<(unsigned)n_tiles, 64, 0, st>>>(TH);
-  } else {
+  } else if (!single_pass) {
     k_gather<true><<<gblocks, kGatherThreads, 0, st>>>(G);
   }
+  const int64_t hit_slots = single_pass ? n_slots : 0;
   if (ix.timing) hip_check(hipEventRecord(ix.ev[3], st), "event");
   hip_check(hipGetLastError(), "gather launch");
   if (out.flt) {
@@ -1842,7 +1869,8 @@ void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam,
     F.t_min = t_min;
     F.t_max = t_max;
     F.hit_off = ix.hit_off.as<int64_t>();
-    F.hits = ix.hits.as<uint32_t>();
+    F.hits = hit_lists;
+    F.hit_slots = hit_slots;
     F.pos4 = ix.pos4.as<float4>();
     F.val = ix.val.as<float>();
     F.orig = ix.orig.as<int32_t>();
@@ -1890,7 +1918,8 @@ void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam,
   }
   A.hit_count = ix.hit_count.as<int64_t>();
   A.hit_off = ix.hit_off.as<int64_t>();
-  A.hits = ix.hits.as<uint32_t>();
+  A.hits = hit_lists;
+  A.hit_slots = hit_slots;
   A.pos4 = ix.pos4.as<float4>();
   A.val = ix.val.as<float>();
   A.orig = ix.orig.as<int32_t>();

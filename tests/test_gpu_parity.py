@@ -244,6 +244,33 @@ def test_field_kernel_configurations_identical():
     assert torch.equal(i1, i2)
 
 
+def test_gather_single_pass_identical():
+    """Arbitrary rays: the single-pass gathering (hits kept in per-ray slots during the counting
+    walk), its fallback when a ray has more hits than slots, and the two-walk gathering give the
+    same bits, exact pieces and knot lists included; the float variant reads the same hit lists."""
+    sc = H.tiny_scene()
+    o, v = synth.ortho_rays()
+    o, v = o[::3], v[::3]
+    res, flt = [], []
+    for slots in (None, "0", "4"):
+        if slots is not None:
+            os.environ["SPH_HOA_GATHER_SLOTS"] = slots
+        try:
+            res.append(_approx(sc, o, v, 0.0, 1.4))
+            flt.append(L.sph_hoa_float_rays(sc.index(), o, v, 0.0, 1.4, n_reinit=3))
+            torch.cuda.synchronize()
+        finally:
+            os.environ.pop("SPH_HOA_GATHER_SLOTS", None)
+    assert res[0]["n_pairs"] > 50000
+    for a in res[1:]:
+        for k in ("ray_offsets", "t_start", "t_end", "coef", "ray_peak", "exact_t", "exact_coef", "knot_t",
+                  "knot_pid", "knot_kidx"):
+            assert torch.equal(res[0][k], a[k]), k
+    for f in flt[1:]:
+        for k in ("ray_offsets", "ray_counts", "t_start", "t_end", "coef"):
+            assert torch.equal(flt[0][k], f[k]), k
+
+
 def test_deterministic():
     sc = H.tiny_scene()
     o, v = synth.ortho_rays()
