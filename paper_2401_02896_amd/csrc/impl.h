@@ -149,6 +149,7 @@ struct Index {
   DevBuf hits;                  // uint32 [pairs]
   DevBuf tile_count, tile_off, tile_items;  // screen-tile binning of the particles (camera rays)
   DevBuf tile_masks;                         // per tile item: the tile pixels it hits
+  DevBuf tile_order;                         // tiles by decreasing candidate count
   DevBuf scan_tmp;
   DevBuf counters;              // uint64 small counters / flags
   DevBuf slab;                  // per-work-group node / heavy-ray storage

@@ -78,7 +78,8 @@ __global__ void k_low32(const uint64_t* keys, int64_t n, uint32_t* out) {
     out[p] = (uint32_t)keys[p];
 }
 
-// Longest rays first: key = (2^32 - 1 - hits) << 32 | ray, sorted ascending.
+// Longest first (rays by hits, tiles by candidates): key = (2^32 - 1 - count) << 32 | index,
+// sorted ascending.
 __global__ void k_order_keys(const int64_t* count, int64_t n, uint64_t* keys) {
   for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
     const uint64_t c = (uint64_t)min(count[p], (int64_t)0xffffffff);
@@ -381,6 +382,7 @@ struct TileHitArgs {
   const int64_t* tile_off;
   const uint32_t* items;
   unsigned long long* masks;  // [items]: pixels of the tile each candidate hits (bit = lane)
+  const uint32_t* order;      // tiles in order of decreasing candidate count (the heavy ones start first)
   int64_t* count;
   const int64_t* off;
   uint32_t* hits;
@@ -396,7 +398,7 @@ __global__ void __launch_bounds__(64) k_tile_hits(TileHitArgs T) {
   __shared__ float4 cp[64];
   __shared__ uint32_t cj[64];
   __shared__ unsigned long long cm[64];
-  const int64_t tile = blockIdx.x;
+  const int64_t tile = T.order[blockIdx.x];
   const int lane = threadIdx.x;
   int lo = 0, hi = T.n_cams - 1;
   while (lo < hi) {
@@ -1794,6 +1796,17 @@ void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam,
     TH.tile_off = B.tile_off;
     TH.items = B.items;
     TH.masks = ix.tile_masks.as<unsigned long long>();
+    {
+      // tiles with the longest candidate lists first, so that they do not finish last
+      ix.order_keys.ensure(sizeof(uint64_t) * 2 * n_tiles);
+      uint64_t* k0 = ix.order_keys.as<uint64_t>();
+      uint64_t* k1 = k0 + n_tiles;
+      k_order_keys<<<blocks_for(n_tiles, 256), 256, 0, st>>>(tcnt64, n_tiles, k0);
+      const bool alt = device_sort_u64(k0, k1, n_tiles, 64, ix.sort_hist, ix.sort_offs, ix.scan_tmp, st);
+      ix.tile_order.ensure(sizeof(uint32_t) * n_tiles);
+      k_low32<<<blocks_for(n_tiles, 256), 256, 0, st>>>(alt ? k1 : k0, n_tiles, ix.tile_order.as<uint32_t>());
+      TH.order = ix.tile_order.as<uint32_t>();
+    }
     TH.count = G.count;
     TH.max_hits = max_hits;
     k_tile_hits<false><<<(unsigned)n_tiles, 64, 0, st>>>(TH);
