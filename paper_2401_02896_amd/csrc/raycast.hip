@@ -341,28 +341,67 @@ __device__ bool particle_pixels(const CamDev& c, float4 p, int* c0, int* c1, int
   return *c0 <= *c1 && *r0 <= *r1;
 }
 
-// (camera, particle) pairs, camera-major so that consecutive threads read consecutive particles
+// (camera, particle) pairs, camera-major so that consecutive threads read consecutive particles.
+// A particle can cover anything from one tile to hundreds (zoomed views), so each wave first
+// projects its 64 pairs and then walks the union of their (pair, tile) items 64 at a time: every
+// lane takes one item (its owner pair found by binary search in the wave's prefix sums).
 template <bool FILL>
 __global__ void __launch_bounds__(256) k_bin(BinArgs B) {
+  __shared__ int64_t s_ex[256];
+  __shared__ int64_t s_tb[256];
+  __shared__ int32_t s_tx0[256], s_w[256], s_ty0[256], s_tilesx[256];
+  __shared__ uint32_t s_j[256];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int64_t* ex = s_ex + wv * 64;
+  int64_t* tb = s_tb + wv * 64;
+  int32_t *tx0 = s_tx0 + wv * 64, *wd = s_w + wv * 64, *ty0 = s_ty0 + wv * 64, *tsx = s_tilesx + wv * 64;
+  uint32_t* jj = s_j + wv * 64;
   const int64_t total = B.n * (int64_t)B.n_cams;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
-    const int cam = (int)(i / B.n);
-    const int64_t j = i - (int64_t)cam * B.n;
-    const CamDev& c = B.cams[cam];
-    int c0, c1, r0, r1;
-    if (!particle_pixels(c, B.pos4[j], &c0, &c1, &r0, &r1)) continue;
-    const int tiles_x = (c.W + kTile - 1) / kTile;
-    const int64_t tb = B.tile_base[cam];
-    for (int ty = r0 / kTile; ty <= r1 / kTile; ++ty)
-      for (int tx = c0 / kTile; tx <= c1 / kTile; ++tx) {
-        const int64_t t = tb + (int64_t)ty * tiles_x + tx;
+  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < total; base += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = base + threadIdx.x;
+    int64_t ntiles = 0;
+    if (i < total) {
+      const int cam = (int)(i / B.n);
+      const int64_t j = i - (int64_t)cam * B.n;
+      const CamDev& c = B.cams[cam];
+      int c0, c1, r0, r1;
+      if (particle_pixels(c, B.pos4[j], &c0, &c1, &r0, &r1)) {
+        const int x0 = c0 / kTile, x1 = c1 / kTile, y0 = r0 / kTile, y1 = r1 / kTile;
+        ntiles = (int64_t)(x1 - x0 + 1) * (y1 - y0 + 1);
+        tx0[lane] = x0;
+        wd[lane] = x1 - x0 + 1;
+        ty0[lane] = y0;
+        tsx[lane] = (c.W + kTile - 1) / kTile;
+        tb[lane] = B.tile_base[cam];
+        jj[lane] = (uint32_t)j;
+      }
+    }
+    const int64_t incl = wave_incl_scan(ntiles);
+    const int64_t tot = __shfl(incl, 63, 64);
+    ex[lane] = incl - ntiles;
+    __builtin_amdgcn_wave_barrier();
+    for (int64_t k = 0; k < tot; k += 64) {
+      const int64_t q = k + lane;
+      if (q < tot) {
+        // owner: the last lane whose first item is <= q (lanes without items share the next
+        // lane's start, so the search never stops on one of them)
+        int lo = 0, hi = 63;
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (ex[mid] <= q) lo = mid;
+          else hi = mid - 1;
+        }
+        const int local = (int)(q - ex[lo]);  // < tiles of one image < 2^25
+        const int64_t t = tb[lo] + (int64_t)(ty0[lo] + local / wd[lo]) * tsx[lo] + tx0[lo] + local % wd[lo];
         if (FILL) {
-          const unsigned int k = atomicAdd(&B.tile_cursor[t], 1u);
-          B.items[B.tile_off[t] + k] = (uint32_t)j;
+          const unsigned int kk = atomicAdd(&B.tile_cursor[t], 1u);
+          B.items[B.tile_off[t] + kk] = jj[lo];
         } else {
           atomicAdd(&B.tile_count[t], 1u);
         }
       }
+    }
+    __builtin_amdgcn_wave_barrier();
   }
 }
 
