@@ -9,6 +9,16 @@ piecewise polynomial kernel); they are the standard 3-D forms with support 2h:
   C4: (495/256pi) (1 - r/2)^6 (1 + 3r + 35/12 r^2),
   C6: (1365/512pi)(1 - r/2)^8 (1 + 4r + 25/4 r^2 + 4 r^3)  on [0, 2).
 
+Gradient fields (Sec. 6 says the procedure carries over to other features that the particles
+generate additively, gradients among them): with y = (x - chi)/h a particle's gradient is
+h^-4 w'(r) y / r.  On a ray its part across the ray is a field of the radial function
+g(r) = -w'(r)/r, which for the Wendland kernels is again (1 - r/2)^m times a polynomial:
+  C2: (21/16pi) 5 (1 - r/2)^3,
+  C4: (495/256pi) (14/3) (1 - r/2)^5 (1 + 5r/2),
+  C6: (1365/512pi) (11/2) (1 - r/2)^7 (1 + 7r/2 + 4r^2)
+(kinds "<kernel>_grad"; pinned against difference quotients of w and by
+4 pi int r^2 g dr = 4 pi int_0^2 w dr, which integration by parts gives).
+
 Every kernel here is a piecewise polynomial in r, stored as
 (r_lo, r_hi, ascending coefficients) times a constant factor, so that the
 integrals below can be written out in closed form.
@@ -31,13 +41,21 @@ CUBIC = "cubic"
 WENDLAND = "wendland"        # Wendland C2
 WENDLAND_C4 = "wendland_c4"
 WENDLAND_C6 = "wendland_c6"
-KINDS = (CUBIC, WENDLAND, WENDLAND_C4, WENDLAND_C6)
+WENDLAND_GRAD = "wendland_grad"
+WENDLAND_C4_GRAD = "wendland_c4_grad"
+WENDLAND_C6_GRAD = "wendland_c6_grad"
+GRAD_OF = {WENDLAND: WENDLAND_GRAD, WENDLAND_C4: WENDLAND_C4_GRAD, WENDLAND_C6: WENDLAND_C6_GRAD}
+KINDS = (CUBIC, WENDLAND, WENDLAND_C4, WENDLAND_C6, WENDLAND_GRAD, WENDLAND_C4_GRAD, WENDLAND_C6_GRAD)
 
 # Wendland kernels as (factor, power n of (1 - r/2), polynomial p ascending in r, exact)
 _WENDLAND = {
     WENDLAND: (21.0 / (16.0 * math.pi), 4, [Fraction(1), Fraction(2)]),
     WENDLAND_C4: (495.0 / (256.0 * math.pi), 6, [Fraction(1), Fraction(3), Fraction(35, 12)]),
     WENDLAND_C6: (1365.0 / (512.0 * math.pi), 8, [Fraction(1), Fraction(4), Fraction(25, 4), Fraction(4)]),
+    # g = -w'/r (module docstring)
+    WENDLAND_GRAD: (21.0 / (16.0 * math.pi) * 5.0, 3, [Fraction(1)]),
+    WENDLAND_C4_GRAD: (495.0 / (256.0 * math.pi) * (14.0 / 3.0), 5, [Fraction(1), Fraction(5, 2)]),
+    WENDLAND_C6_GRAD: (1365.0 / (512.0 * math.pi) * 5.5, 7, [Fraction(1), Fraction(7, 2), Fraction(4)]),
 }
 
 

@@ -17,7 +17,8 @@ import synth
 from oracle import field, geometry, grid, lut, quanta, render
 from tests.golden.make_knot_tables import load as load_knots
 
-KIND_ID = {"cubic": 0, "wendland": 1, "wendland_c4": 2, "wendland_c6": 3}
+KIND_ID = {"cubic": 0, "wendland": 1, "wendland_c4": 2, "wendland_c6": 3, "wendland_grad": 4,
+           "wendland_c4_grad": 5, "wendland_c6_grad": 6}
 
 
 class Scene:
@@ -101,6 +102,21 @@ def eval_pieces(t0, t1, coef, ts):
         m = (ts >= a) & (ts < b)
         u = (ts[m] - a) / (b - a)
         out[m] = np.polyval(c[::-1], u)
+    return out
+
+
+def eval_exact_pieces(pieces, tau, sigma, ts, deriv=False):
+    """Value (or t-derivative) at world positions ts of exact integer pieces
+    [(t_start, t_end, coefficients, _)] in length quanta (0 outside the pieces), float64."""
+    out = np.zeros_like(ts)
+    for a, b, c, *_ in pieces:
+        m = (ts >= a * tau) & (ts < b * tau)
+        x = ts[m] / tau - a
+        cf = [float(q) for q in c]
+        if deriv:
+            out[m] = sigma / tau * sum(d * cf[d] * x ** (d - 1) for d in range(1, len(cf)))
+        else:
+            out[m] = sigma * sum(cf[d] * x ** d for d in range(len(cf)))
     return out
 
 
