@@ -50,7 +50,8 @@ def parse():
     ap.add_argument("--rate", type=float, default=20.0, help="serve workload: Poisson arrival rate (requests/s)")
     ap.add_argument("--duration", type=float, default=8.0, help="serve workload: seconds of arrivals")
     ap.add_argument("--sides", default="64,128,256", help="serve workload: image sides (uniform choice)")
-    ap.add_argument("--workload", choices=("plain", "batch", "serve", "bitlength", "precision", "sprinkle"),
+    ap.add_argument("--workload", choices=("plain", "batch", "serve", "bitlength", "precision", "sprinkle",
+                                           "gradient"),
                     default="plain",
                     help="plain: the 1M-particle 512x512 frame (the reported metric); batch: camera bundles "
                          "of 32^2..512^2 rendered with one sph_hoa_render_batch call; serve: Poisson render "
@@ -58,7 +59,9 @@ def parse():
                          "128-bit integers (the cost study of Sec. 5.1); precision: the plain frame with the "
                          "float table stored in fp64 / fp32 / bf16, timed, with pixel errors against the "
                          "float64 oracle; sprinkle: the float32 accumulation variant with and without "
-                         "reinitialization knots (Sec. 4.1), its residue behind the particles and its time")
+                         "reinitialization knots (Sec. 4.1), its residue behind the particles and its time; "
+                         "gradient: the value field and the four transverse gradient fields (Sec. 6) on the "
+                         "plain frame's rays")
     ap.add_argument("--batch-cams", type=int, default=64, help="cameras per batch (batch workload)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="instead of the benchmark, run 5 plain device copies of MIB MiB each (the "
@@ -397,6 +400,86 @@ def run_sprinkle(a, torch, L, synth):
     print(json.dumps(result), flush=True)
 
 
+def camera_rays(cam, torch):
+    """Pixel-centre rays of a pinhole camera as device float32 tensors (origins, unit directions)."""
+    eye = np.array(cam["eye"], np.float64)
+    fwd = np.array(cam["look_at"], np.float64) - eye
+    fwd /= np.linalg.norm(fwd)
+    rgt = np.cross(fwd, np.array(cam["up"], np.float64))
+    rgt /= np.linalg.norm(rgt)
+    upv = np.cross(rgt, fwd)
+    gy = math.tan(math.radians(cam["fov_y_deg"]) / 2)
+    Wd, Hd = cam["width"], cam["height"]
+    jj, ii = np.meshgrid(np.arange(Hd), np.arange(Wd), indexing="ij")
+    ax = (((2 * ii + 1) / Wd - 1) * gy * Wd / Hd).reshape(-1, 1)
+    by = ((1 - (2 * jj + 1) / Hd) * gy).reshape(-1, 1)
+    dirs = fwd[None, :] + ax * rgt[None, :] + by * upv[None, :]
+    dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+    ro = torch.as_tensor(np.tile(eye, (len(dirs), 1)).astype(np.float32), device="cuda")
+    rv = torch.as_tensor(dirs.astype(np.float32), device="cuda")
+    return ro, rv
+
+
+def run_gradient(a, torch, L, synth):
+    """Gradient fields (Sec. 6): on the plain frame's pixel-centre rays (1M clustered particles,
+    Wendland C2, K = 4, D = 3, tol 1e-3, 512^2 rays), the value field and the four fields of the
+    transverse kernel -w'/r with particle values c/h^2 and c chi_a/h^2, from which every gradient
+    component along a ray is assembled ((v.e) F' - alpha G_0 - beta.(G_x, G_y, G_z)), each through
+    sph_hoa_approx_rays with merged output.  A step is all five fields of all rays.
+    value = contributions/s over the five fields."""
+    xyz, h, val = synth.clustered_particles(n=a.particles)
+    K, D, tol = 4, 3, 1e-3
+    cam = synth.plain_camera(a.size, a.size)
+    ro, rv = camera_rays(cam, torch)
+    c = val.astype(np.float64) / (h.astype(np.float64) ** 2)
+    gvals = [c.astype(np.float32)] + [(c * xyz[:, k].astype(np.float64)).astype(np.float32) for k in range(3)]
+    t_idx = time.time()
+    idxs = [L.sph_hoa_build_index(xyz, h, val, kernel=L.KERNEL_WENDLAND_C2, degree=D, pieces=K, lut_entries=4096,
+                                  merge_tol=tol)]
+    idxs += [L.sph_hoa_build_index(xyz, h, g, kernel=L.KERNEL_WENDLAND_C2_GRAD, degree=D, pieces=K,
+                                   lut_entries=4096, merge_tol=tol) for g in gvals]
+    build_s = time.time() - t_idx
+    caps = []
+    for idx in idxs:
+        warm = L.sph_hoa_approx_rays(idx, ro, rv, cam["t_min"], cam["t_max"])
+        caps.append(int(warm["n_pieces"]) + 1024)
+        del warm
+    for _ in range(max(0, a.warmup - 1)):
+        for idx, cap in zip(idxs, caps):
+            L.sph_hoa_approx_rays(idx, ro, rv, cam["t_min"], cam["t_max"], capacity=cap)
+    torch.cuda.synchronize()
+    lat, pairs, pieces = [], 0, [0] * len(idxs)
+    per_field = [0.0] * len(idxs)
+    for _ in range(a.steps):
+        ts = time.perf_counter()
+        for f, (idx, cap) in enumerate(zip(idxs, caps)):
+            tf0 = time.perf_counter()
+            out = L.sph_hoa_approx_rays(idx, ro, rv, cam["t_min"], cam["t_max"], capacity=cap)
+            torch.cuda.synchronize()
+            per_field[f] += time.perf_counter() - tf0
+            pairs += out["n_pairs"]
+            pieces[f] = int(out["n_pieces"])
+            del out
+        lat.append(time.perf_counter() - ts)
+    names = ["value F", "G_0 (c/h^2)", "G_x (c chi_x/h^2)", "G_y (c chi_y/h^2)", "G_z (c chi_z/h^2)"]
+    result = {
+        "metric": "particle-ray contributions/s over the value field and the four transverse gradient fields",
+        "value": pairs / sum(lat), "unit": "contributions/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": float(np.median(lat) * 1e3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+        "config": {"workload": f"gradient: {a.size}x{a.size} pixel-centre rays of the plain camera, {a.particles} "
+                               "clustered particles, Wendland C2 and its transverse kernel -w'/r, K=4, D=3, "
+                               "tol 1e-3, five fields per step",
+                   "fields": {n: {"ms_per_call": per_field[i] / a.steps * 1e3, "pieces": pieces[i]}
+                              for i, n in enumerate(names)},
+                   "index_build_s": build_s},
+        "cpu_baseline": None,
+    }
+    for idx in idxs:
+        idx.free()
+    print(json.dumps(result), flush=True)
+
+
 def kernel_source_digest():
     import hashlib
 
@@ -458,6 +541,8 @@ def main():
         return run_precision(a, torch, L, synth)
     if a.workload == "sprinkle":
         return run_sprinkle(a, torch, L, synth)
+    if a.workload == "gradient":
+        return run_gradient(a, torch, L, synth)
     t_gen = time.time()
     xyz, h, val = synth.clustered_particles(n=a.particles)
     gen_s = time.time() - t_gen
@@ -527,21 +612,7 @@ def main():
     }
     # the same frame's rays through sph_hoa_approx_rays (merged fields, no classification), after
     # the timed region: pixel-centre rays of the camera, arbitrary-ray gathering
-    eye = np.array(cam["eye"], np.float64)
-    fwd = np.array(cam["look_at"], np.float64) - eye
-    fwd /= np.linalg.norm(fwd)
-    rgt = np.cross(fwd, np.array(cam["up"], np.float64))
-    rgt /= np.linalg.norm(rgt)
-    upv = np.cross(rgt, fwd)
-    gy = math.tan(math.radians(cam["fov_y_deg"]) / 2)
-    Wd, Hd = cam["width"], cam["height"]
-    jj, ii = np.meshgrid(np.arange(Hd), np.arange(Wd), indexing="ij")
-    ax = (((2 * ii + 1) / Wd - 1) * gy * Wd / Hd).reshape(-1, 1)
-    by = ((1 - (2 * jj + 1) / Hd) * gy).reshape(-1, 1)
-    dirs = fwd[None, :] + ax * rgt[None, :] + by * upv[None, :]
-    dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
-    ro = torch.as_tensor(np.tile(eye, (len(dirs), 1)).astype(np.float32), device="cuda")
-    rv = torch.as_tensor(dirs.astype(np.float32), device="cuda")
+    ro, rv = camera_rays(cam, torch)
     warm = L.sph_hoa_approx_rays(idx, ro, rv, cam["t_min"], cam["t_max"])
     cap = int(warm["n_pieces"]) + 1024  # output sized once, as a caller reusing buffers would
     del warm

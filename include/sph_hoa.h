@@ -45,7 +45,18 @@ typedef enum {
   SPH_HOA_KERNEL_CUBIC = 0,       /* cubic B-spline, Eq. cubic-kernel, support q = 2 */
   SPH_HOA_KERNEL_WENDLAND_C2 = 1, /* (21/16pi)(1-r/2)^4(1+2r), support q = 2 */
   SPH_HOA_KERNEL_WENDLAND_C4 = 2, /* (495/256pi)(1-r/2)^6(1+3r+35/12 r^2), support q = 2 */
-  SPH_HOA_KERNEL_WENDLAND_C6 = 3  /* (1365/512pi)(1-r/2)^8(1+4r+25/4 r^2+4r^3), support q = 2 */
+  SPH_HOA_KERNEL_WENDLAND_C6 = 3, /* (1365/512pi)(1-r/2)^8(1+4r+25/4 r^2+4r^3), support q = 2 */
+  /* Transverse gradient kernels g(r) = -w'(r)/r of the Wendland kernels (Sec. 6: the procedure
+   * carries over to other features that particles generate additively, such as gradients).  With
+   * y = (x - chi)/h a particle's gradient is h^-4 w'(r) y / r; on a ray x = o + t v its component
+   * along a unit axis e is (v.e) d/dt[h^-3 w] - h^-5 g(r) (alpha + beta.chi), where
+   * alpha = o.e - (o.v)(v.e) and beta = (v.e) v - e are constants of the ray.  The gradient along e
+   * is therefore (v.e) F'(t) - alpha G0(t) - beta.(Gx, Gy, Gz)(t): F the field of w with values c,
+   * G0 and Gx, Gy, Gz the fields of g with values c/h^2 and c chi_x/h^2, c chi_y/h^2, c chi_z/h^2
+   * (indices built from those values; values may be negative). */
+  SPH_HOA_KERNEL_WENDLAND_C2_GRAD = 4, /* (21/16pi) 5 (1-r/2)^3 */
+  SPH_HOA_KERNEL_WENDLAND_C4_GRAD = 5, /* (495/256pi)(14/3)(1-r/2)^5(1+5r/2) */
+  SPH_HOA_KERNEL_WENDLAND_C6_GRAD = 6  /* (1365/512pi)(11/2)(1-r/2)^7(1+7r/2+4r^2) */
 } sph_hoa_kernel;
 
 /* approx_rays: also return the sorted knots and the pre-merge exact integer pieces */

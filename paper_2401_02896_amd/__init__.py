@@ -18,6 +18,10 @@ KERNEL_CUBIC = 0
 KERNEL_WENDLAND_C2 = 1
 KERNEL_WENDLAND_C4 = 2
 KERNEL_WENDLAND_C6 = 3
+# transverse gradient kernels g = -w'/r of the Wendland kernels (gradient fields, Sec. 6)
+KERNEL_WENDLAND_C2_GRAD = 4
+KERNEL_WENDLAND_C4_GRAD = 5
+KERNEL_WENDLAND_C6_GRAD = 6
 FLAG_EXACT = 1
 FLAG_LUT_FP32 = 2
 FLAG_LUT_BF16 = 4

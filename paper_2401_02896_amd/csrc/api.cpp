@@ -72,6 +72,9 @@ sph::Kernel kernel_of(sph_hoa_kernel k) {
   if (k == SPH_HOA_KERNEL_WENDLAND_C2) return sph::Kernel::Wendland;
   if (k == SPH_HOA_KERNEL_WENDLAND_C4) return sph::Kernel::WendlandC4;
   if (k == SPH_HOA_KERNEL_WENDLAND_C6) return sph::Kernel::WendlandC6;
+  if (k == SPH_HOA_KERNEL_WENDLAND_C2_GRAD) return sph::Kernel::WendlandGrad;
+  if (k == SPH_HOA_KERNEL_WENDLAND_C4_GRAD) return sph::Kernel::WendlandC4Grad;
+  if (k == SPH_HOA_KERNEL_WENDLAND_C6_GRAD) return sph::Kernel::WendlandC6Grad;
   throw sph::Error(SPH_HOA_E_INVALID_ARG, "unknown kernel");
 }
 

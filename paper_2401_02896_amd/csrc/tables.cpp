@@ -77,6 +77,11 @@ double kernel_w_edge(Kernel k, double r, double e) {
   }
   const double h = 0.5 * e;  // 1 - r / 2
   const double h2 = h * h, h4 = h2 * h2;
+  // g = -w'/r of the Wendland kernels, (1 - r/2)^(n-1) times a polynomial
+  if (k == Kernel::WendlandGrad) return 21.0 / (16.0 * kPi) * 5.0 * h2 * h;
+  if (k == Kernel::WendlandC4Grad) return 495.0 / (256.0 * kPi) * (14.0 / 3.0) * h4 * h * (1.0 + 2.5 * r);
+  if (k == Kernel::WendlandC6Grad)
+    return 1365.0 / (512.0 * kPi) * 5.5 * h4 * h2 * h * (1.0 + r * (3.5 + 4.0 * r));
   if (k == Kernel::WendlandC4) return 495.0 / (256.0 * kPi) * h4 * h2 * (1.0 + r * (3.0 + r * (35.0 / 12.0)));
   if (k == Kernel::WendlandC6)
     return 1365.0 / (512.0 * kPi) * h4 * h4 * (1.0 + r * (4.0 + r * (25.0 / 4.0 + r * 4.0)));
@@ -90,6 +95,9 @@ double kernel_dw(Kernel k, double r) {
     return -3.0 * (2.0 - r) * (2.0 - r) / (4.0 * kPi);
   }
   const double a = 1.0 - 0.5 * r, a2 = a * a, a4 = a2 * a2;
+  if (k == Kernel::WendlandGrad) return 21.0 / (16.0 * kPi) * (-7.5) * a2;
+  if (k == Kernel::WendlandC4Grad) return 495.0 / (256.0 * kPi) * (-35.0) * r * a4;
+  if (k == Kernel::WendlandC6Grad) return 1365.0 / (512.0 * kPi) * (-33.0) * r * (1.0 + 3.0 * r) * a4 * a2;
   // derivatives of the factored forms (1 - r/2)^n p(r)
   if (k == Kernel::WendlandC4) return 495.0 / (256.0 * kPi) * (-14.0 / 3.0) * r * (1.0 + 2.5 * r) * a4 * a;
   if (k == Kernel::WendlandC6)

@@ -13,7 +13,18 @@
 
 namespace sph {
 
-enum class Kernel : int { Cubic = 0, Wendland = 1, WendlandC4 = 2, WendlandC6 = 3 };
+// The *Grad kernels are g(r) = -w'(r) / r of the Wendland kernel named: the radial factor of a
+// particle's gradient, h^-4 w'(r) y / r with y = (x - chi) / h.  Along a ray the gradient's part
+// across the ray is a field of g (Sec. 6: features generated additively by the particles).
+enum class Kernel : int {
+  Cubic = 0,
+  Wendland = 1,
+  WendlandC4 = 2,
+  WendlandC6 = 3,
+  WendlandGrad = 4,
+  WendlandC4Grad = 5,
+  WendlandC6Grad = 6
+};
 
 constexpr double kSupport = 2.0;  // q for both kernels
 

@@ -30,6 +30,10 @@ TABLES = [
     ("wendland", 4, 1, 256),
     ("wendland_c4", 4, 3, 64),
     ("wendland_c6", 2, 2, 64),
+    ("wendland_grad", 4, 3, 64),
+    ("wendland_grad", 4, 3, 1024),
+    ("wendland_c4_grad", 3, 2, 64),
+    ("wendland_c6_grad", 2, 2, 64),
 ]
 
 

@@ -11,7 +11,8 @@ from oracle import quanta
 from tests.golden.make_knot_tables import TABLES, load
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-KIND_ID = {"cubic": 0, "wendland": 1, "wendland_c4": 2, "wendland_c6": 3}
+KIND_ID = {"cubic": 0, "wendland": 1, "wendland_c4": 2, "wendland_c6": 3, "wendland_grad": 4,
+           "wendland_c4_grad": 5, "wendland_c6_grad": 6}
 
 
 def test_every_declared_symbol_is_exported():

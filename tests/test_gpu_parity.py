@@ -172,20 +172,28 @@ def test_tiny_render_pixels():
 @pytest.mark.parametrize("kind,K,D,n_lut", [("cubic", 3, 3, 256), ("wendland", 2, 2, 256), ("cubic", 1, 2, 128),
                                             ("cubic", 5, 2, 128), ("wendland", 6, 4, 128), ("cubic", 4, 4, 256),
                                             ("wendland", 4, 1, 256), ("wendland_c4", 4, 3, 64),
-                                            ("wendland_c6", 2, 2, 64)])
+                                            ("wendland_c6", 2, 2, 64), ("wendland_grad", 4, 3, 64),
+                                            ("wendland_c4_grad", 3, 2, 64), ("wendland_c6_grad", 2, 2, 64)])
 def test_configurations(kind, K, D, n_lut):
     """K odd and even (middle knot / closure at +-theta_1), D = 1..4, signed amplitudes; the cubic
-    spline and the Wendland C2, C4 and C6 kernels."""
+    spline, the Wendland C2, C4 and C6 kernels and the transverse gradient kernels -w'/r of the
+    Wendland kernels (gradient fields)."""
     xyz, h, val = synth.random_scene(21 + K + 10 * D, 500, h_lo=0.03, h_hi=0.1, signed=True)
     # D = 1: the optimal length quantum is ~1e-9, too fine for int32 positions on these rays
     # (the library reports E_OVERFLOW then); a 100x coarser quantum is given explicitly instead
     sc = H.Scene(kind, K, D, n_lut, xyz, h, val, 1e-3, tau_scale=100.0 if D == 1 else 1.0)
     o, v = synth.random_rays(7 + K, 37)
     out = _approx(sc, o, v, -0.5, 3.5)
+    # transverse gradient kernels: for small Lambda the outer optimal knot sits at or beyond the
+    # support (the kernel is nearly one polynomial there), the Gram system of Sec. 3.3 is close to
+    # singular and the two float64 projections agree to about 1.3e-10 of a table row (1e-13 for
+    # the kernels themselves); signed amplitudes add per-particle errors while the values cancel
+    # (up to ~100x), hence a value bar of 1e-7 of the ray peak for these kernels
+    vtol = 1e-7 if kind.endswith("_grad") else None
     same = 0
     for r in range(37):
         f = sc.oracle_ray(o[r], v[r], -0.5, 3.5)
-        same += _check_ray(sc, out, r, f)
+        same += _check_ray(sc, out, r, f, vtol=vtol)
     assert same >= 35
 
 
