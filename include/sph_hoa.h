@@ -204,6 +204,20 @@ sph_hoa_status sph_hoa_approx_rays(sph_hoa_index idx, const sph_hoa_rays* rays, 
                                    uint32_t flags, void* stream);
 
 /*
+ * Fields of several indices along the same rays with one hit gathering (Sec. 2 pass 1 done once):
+ * out[i] receives exactly what sph_hoa_approx_rays(idx[i], rays, &out[i], flags, stream) gives.
+ * For fields that the same particles generate with other values or kernels, e.g. the value field
+ * and the four transverse gradient fields (Sec. 6; SPH_HOA_KERNEL_WENDLAND_C2_GRAD).
+ * idx: HOST array of n_idx >= 1 indices built from the same positions and smoothing lengths (same
+ * order; values, kernel, K, D and quanta may differ) — compared on the device first,
+ * SPH_HOA_E_INVALID_ARG if they differ.  out: HOST array of n_idx fields, each as for
+ * sph_hoa_approx_rays.  Processes idx[0] first (it gathers), then the others in order; on an
+ * error the outputs from the failing index on are undefined.  Synchronises `stream`.
+ */
+sph_hoa_status sph_hoa_approx_rays_shared(const sph_hoa_index* idx, int32_t n_idx, const sph_hoa_rays* rays,
+                                          sph_hoa_field* out, uint32_t flags, void* stream);
+
+/*
  * Render: camera rays, per-ray field, merge with the index's merge_tol,
  * classification with `tf` and front-to-back emission-absorption compositing.
  * rgba_out: device float32 [height][width][4] (premultiplied colour, alpha = 1 - T).

@@ -101,7 +101,7 @@ class Stats(ctypes.Structure):
                 ("timed_calls", ctypes.c_int64), ("ms_gather", ctypes.c_double), ("ms_field", ctypes.c_double)]
 
 
-EXPORTS = ["sph_hoa_build_index", "sph_hoa_approx_rays", "sph_hoa_render", "sph_hoa_render_batch",
+EXPORTS = ["sph_hoa_build_index", "sph_hoa_approx_rays", "sph_hoa_approx_rays_shared", "sph_hoa_render", "sph_hoa_render_batch",
            "sph_hoa_server_create", "sph_hoa_server_add_index", "sph_hoa_server_submit", "sph_hoa_server_wait",
            "sph_hoa_server_get_stats", "sph_hoa_server_destroy", "sph_hoa_server_set_admission",
            "sph_hoa_server_cancel", "sph_hoa_server_pause", "sph_hoa_accumulate_bits", "sph_hoa_float_rays",
@@ -125,6 +125,8 @@ def lib():
     vp, i64, i32, u32, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32, ctypes.c_double
     L.sph_hoa_build_index.argtypes = [vp, vp, vp, i64, ctypes.c_int, ctypes.POINTER(Params), vp, ctypes.POINTER(vp)]
     L.sph_hoa_approx_rays.argtypes = [vp, ctypes.POINTER(Rays), ctypes.POINTER(Field), u32, vp]
+    L.sph_hoa_approx_rays_shared.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(Rays), ctypes.POINTER(Field),
+                                             u32, vp]
     L.sph_hoa_render.argtypes = [vp, ctypes.POINTER(Camera), ctypes.POINTER(TF), vp, vp]
     L.sph_hoa_render_batch.argtypes = [vp, ctypes.POINTER(Camera), i32, ctypes.POINTER(TF), vp, vp]
     L.sph_hoa_server_create.argtypes = [i64, i64, ctypes.POINTER(vp)]
@@ -308,13 +310,59 @@ def sph_hoa_float_rays(index, origin, direction, t_min, t_max, n_reinit=0):
             "coef": coef[: slots * (D + 1)].reshape(-1, D + 1), "n_pairs": int(f.n_pairs)}
 
 
+def _alloc_field(n, D, cap, ecap, exact):
+    """Device output tensors of one sph_hoa_field and the struct pointing at them."""
+    import torch
+
+    t = {"offs": torch.empty(n + 1, dtype=torch.int64, device="cuda"),
+         "t0": torch.empty(max(cap, 1), dtype=torch.float32, device="cuda"),
+         "t1": torch.empty(max(cap, 1), dtype=torch.float32, device="cuda"),
+         "coef": torch.empty(max(cap, 1) * (D + 1), dtype=torch.float32, device="cuda"),
+         "peak": torch.empty(max(n, 1), dtype=torch.float32, device="cuda")}
+    f = Field()
+    f.capacity = cap
+    f.ray_offsets, f.t_start, f.t_end, f.coef, f.ray_peak = (_ptr(t["offs"]).value, _ptr(t["t0"]).value,
+                                                             _ptr(t["t1"]).value, _ptr(t["coef"]).value,
+                                                             _ptr(t["peak"]).value)
+    if exact:
+        t["offsets"] = torch.empty(n + 1, dtype=torch.int64, device="cuda")
+        t["t"] = torch.empty(max(ecap, 1), dtype=torch.int64, device="cuda")
+        t["end"] = torch.empty(max(ecap, 1), dtype=torch.int64, device="cuda")
+        t["ecoef"] = torch.empty(max(ecap, 1) * (D + 1), dtype=torch.int64, device="cuda")
+        t["knot_offsets"] = torch.empty(n + 1, dtype=torch.int64, device="cuda")
+        t["knot_t"] = torch.empty(max(ecap, 1), dtype=torch.int64, device="cuda")
+        t["knot_pid"] = torch.empty(max(ecap, 1), dtype=torch.int32, device="cuda")
+        t["knot_kidx"] = torch.empty(max(ecap, 1), dtype=torch.int32, device="cuda")
+        f.exact_capacity = ecap
+        f.exact_offsets, f.exact_t, f.exact_end, f.exact_coef = (_ptr(t["offsets"]).value, _ptr(t["t"]).value,
+                                                                 _ptr(t["end"]).value, _ptr(t["ecoef"]).value)
+        f.knot_capacity = ecap
+        f.knot_offsets, f.knot_t, f.knot_pid, f.knot_kidx = (_ptr(t["knot_offsets"]).value, _ptr(t["knot_t"]).value,
+                                                             _ptr(t["knot_pid"]).value, _ptr(t["knot_kidx"]).value)
+    return f, t
+
+
+def _field_result(f, t, n, D, exact):
+    out = {"ray_offsets": t["offs"], "t_start": t["t0"][: f.n_pieces], "t_end": t["t1"][: f.n_pieces],
+           "coef": t["coef"][: f.n_pieces * (D + 1)].reshape(-1, D + 1), "ray_peak": t["peak"][:n],
+           "n_pieces": f.n_pieces, "n_pairs": f.n_pairs, "n_knots": f.n_knots, "n_exact_pieces": f.n_exact_pieces}
+    if exact:
+        out["exact_offsets"] = t["offsets"]
+        out["exact_t"] = t["t"][: f.n_exact_pieces]
+        out["exact_end"] = t["end"][: f.n_exact_pieces]
+        out["exact_coef"] = t["ecoef"][: f.n_exact_pieces * (D + 1)].reshape(-1, D + 1)
+        out["knot_offsets"] = t["knot_offsets"]
+        out["knot_t"] = t["knot_t"][: f.n_knots]
+        out["knot_pid"] = t["knot_pid"][: f.n_knots]
+        out["knot_kidx"] = t["knot_kidx"][: f.n_knots]
+    return out
+
+
 def sph_hoa_approx_rays(index, origin, direction, t_min, t_max, capacity=None, exact=False, exact_capacity=None):
     """Per-ray merged fields (sph_hoa_approx_rays).  Returns a dict of device tensors and counts.
 
     capacity: pieces to allocate (default: grows and retries once on E_OUT_OF_MEMORY).
     """
-    import torch
-
     o = _dev_f32(origin).reshape(-1, 3)
     d = _dev_f32(direction).reshape(-1, 3)
     n = o.shape[0]
@@ -322,33 +370,7 @@ def sph_hoa_approx_rays(index, origin, direction, t_min, t_max, capacity=None, e
     cap = capacity if capacity is not None else max(1024, 64 * n)
     ecap = exact_capacity if exact_capacity is not None else max(1024, 64 * n)
     for attempt in range(2):
-        offs = torch.empty(n + 1, dtype=torch.int64, device="cuda")
-        t0 = torch.empty(max(cap, 1), dtype=torch.float32, device="cuda")
-        t1 = torch.empty(max(cap, 1), dtype=torch.float32, device="cuda")
-        coef = torch.empty(max(cap, 1) * (D + 1), dtype=torch.float32, device="cuda")
-        peak = torch.empty(max(n, 1), dtype=torch.float32, device="cuda")
-        f = Field()
-        f.capacity = cap
-        f.ray_offsets, f.t_start, f.t_end, f.coef, f.ray_peak = (_ptr(offs).value, _ptr(t0).value, _ptr(t1).value,
-                                                                 _ptr(coef).value, _ptr(peak).value)
-        ex = {}
-        if exact:
-            ex["offsets"] = torch.empty(n + 1, dtype=torch.int64, device="cuda")
-            ex["t"] = torch.empty(max(ecap, 1), dtype=torch.int64, device="cuda")
-            ex["end"] = torch.empty(max(ecap, 1), dtype=torch.int64, device="cuda")
-            ex["coef"] = torch.empty(max(ecap, 1) * (D + 1), dtype=torch.int64, device="cuda")
-            kcap = ex.get("kcap", ecap)
-            ex["knot_offsets"] = torch.empty(n + 1, dtype=torch.int64, device="cuda")
-            ex["knot_t"] = torch.empty(max(kcap, 1), dtype=torch.int64, device="cuda")
-            ex["knot_pid"] = torch.empty(max(kcap, 1), dtype=torch.int32, device="cuda")
-            ex["knot_kidx"] = torch.empty(max(kcap, 1), dtype=torch.int32, device="cuda")
-            f.exact_capacity = ecap
-            f.exact_offsets, f.exact_t, f.exact_end, f.exact_coef = (_ptr(ex["offsets"]).value, _ptr(ex["t"]).value,
-                                                                     _ptr(ex["end"]).value, _ptr(ex["coef"]).value)
-            f.knot_capacity = kcap
-            f.knot_offsets, f.knot_t, f.knot_pid, f.knot_kidx = (_ptr(ex["knot_offsets"]).value,
-                                                                 _ptr(ex["knot_t"]).value, _ptr(ex["knot_pid"]).value,
-                                                                 _ptr(ex["knot_kidx"]).value)
+        f, t = _alloc_field(n, D, cap, ecap, exact)
         r = Rays(n, _ptr(o).value, _ptr(d).value, t_min, t_max)
         st = lib().sph_hoa_approx_rays(index.handle, ctypes.byref(r), ctypes.byref(f), FLAG_EXACT if exact else 0,
                                        _stream())
@@ -358,19 +380,42 @@ def sph_hoa_approx_rays(index, origin, direction, t_min, t_max, capacity=None, e
             continue
         _check(st)
         break
-    out = {"ray_offsets": offs, "t_start": t0[: f.n_pieces], "t_end": t1[: f.n_pieces],
-           "coef": coef[: f.n_pieces * (D + 1)].reshape(-1, D + 1), "ray_peak": peak[:n], "n_pieces": f.n_pieces,
-           "n_pairs": f.n_pairs, "n_knots": f.n_knots, "n_exact_pieces": f.n_exact_pieces}
-    if exact:
-        out["exact_offsets"] = ex["offsets"]
-        out["exact_t"] = ex["t"][: f.n_exact_pieces]
-        out["exact_end"] = ex["end"][: f.n_exact_pieces]
-        out["exact_coef"] = ex["coef"][: f.n_exact_pieces * (D + 1)].reshape(-1, D + 1)
-        out["knot_offsets"] = ex["knot_offsets"]
-        out["knot_t"] = ex["knot_t"][: f.n_knots]
-        out["knot_pid"] = ex["knot_pid"][: f.n_knots]
-        out["knot_kidx"] = ex["knot_kidx"][: f.n_knots]
-    return out
+    return _field_result(f, t, n, D, exact)
+
+
+def sph_hoa_approx_rays_shared(indices, origin, direction, t_min, t_max, capacity=None, exact=False,
+                               exact_capacity=None):
+    """Fields of several indices of the same particles along the same rays, the hits gathered once
+    (sph_hoa_approx_rays_shared).  Returns one dict per index, as sph_hoa_approx_rays.
+
+    capacity: pieces to allocate per field (default: grows on E_OUT_OF_MEMORY and retries)."""
+    o = _dev_f32(origin).reshape(-1, 3)
+    d = _dev_f32(direction).reshape(-1, 3)
+    n = o.shape[0]
+    k = len(indices)
+    caps = [capacity if capacity is not None else max(1024, 64 * n)] * k
+    ecaps = [exact_capacity if exact_capacity is not None else max(1024, 64 * n)] * k
+    for attempt in range(k + 1):
+        allocs = [_alloc_field(n, ix.D, caps[i], ecaps[i], exact) for i, ix in enumerate(indices)]
+        fields = (Field * k)(*[f for f, _ in allocs])
+        handles = (ctypes.c_void_p * k)(*[ix.handle.value if isinstance(ix.handle, ctypes.c_void_p) else ix.handle
+                                          for ix in indices])
+        r = Rays(n, _ptr(o).value, _ptr(d).value, t_min, t_max)
+        st = lib().sph_hoa_approx_rays_shared(handles, k, ctypes.byref(r), fields, FLAG_EXACT if exact else 0,
+                                              _stream())
+        if st == 2 and capacity is None and attempt < k:
+            grown = False
+            for i in range(k):
+                if fields[i].n_pieces > caps[i] or (exact and (fields[i].n_exact_pieces > ecaps[i]
+                                                               or fields[i].n_knots > ecaps[i])):
+                    caps[i] = max(caps[i], int(fields[i].n_pieces) + 1)
+                    ecaps[i] = max(ecaps[i], int(fields[i].n_exact_pieces) + 1, int(fields[i].n_knots) + 1)
+                    grown = True
+            if grown:
+                continue
+        _check(st)
+        break
+    return [_field_result(fields[i], allocs[i][1], n, ix.D, exact) for i, ix in enumerate(indices)]
 
 
 def make_camera(cam: dict) -> Camera:

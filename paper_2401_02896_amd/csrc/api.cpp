@@ -230,46 +230,71 @@ sph_hoa_status sph_hoa_index_free(sph_hoa_index idx) {
   });
 }
 
+namespace {
+
+// One field of sph_hoa_approx_rays; gathered: the index whose call on the same rays just gathered
+// the hits (shared gathering) or nullptr.
+void approx_rays_one(sph_hoa_index idx, const sph_hoa_rays* rays, sph_hoa_field* out, uint32_t flags, void* stream,
+                     const sph::Index* gathered) {
+  require(idx && rays && out, "NULL argument");
+  require(flags == 0 || flags == SPH_HOA_FLAG_EXACT, "unknown flags");
+  require(rays->n >= 0 && rays->n < (int64_t(1) << 31), "ray count must be in 0..2^31-1");
+  require(std::isfinite(rays->t_min) && std::isfinite(rays->t_max) && rays->t_min < rays->t_max,
+          "need finite t_min < t_max");
+  require(out->capacity >= 0, "capacity must be >= 0");
+  if (rays->n > 0) {
+    require(rays->origin && rays->dir, "NULL ray arrays");
+    require(out->ray_offsets && out->ray_peak, "NULL output arrays");
+    require(out->capacity == 0 || (out->t_start && out->t_end && out->coef), "NULL piece arrays");
+  }
+  const bool exact = (flags & SPH_HOA_FLAG_EXACT) != 0;
+  if (exact && idx->ix.n >= (int64_t(1) << 29))
+    throw sph::Error(SPH_HOA_E_UNSUPPORTED, "exact mode needs fewer than 2^29 particles");
+  if (exact && rays->n > 0) {
+    require(out->exact_offsets && out->knot_offsets, "exact mode needs offset arrays");
+    require(out->exact_capacity == 0 || (out->exact_t && out->exact_end && out->exact_coef), "exact arrays");
+    require(out->knot_capacity == 0 || (out->knot_t && out->knot_pid && out->knot_kidx), "knot arrays");
+  }
+  sph::Index& ix = idx->ix;
+  const double span = std::max(std::fabs((double)rays->t_min), std::fabs((double)rays->t_max)) +
+                      ix.grid.lv[ix.grid.n_levels - 1].c;
+  if (!(span / ix.tau < 2.1e9))
+    throw sph::Error(SPH_HOA_E_OVERFLOW, "ray segment too long for int32 positions (|t| + q h_max >= 2^31 tau)");
+  sph::FieldOut fo{out, nullptr, nullptr, exact};
+  hipStream_t st = (hipStream_t)stream;
+  ix.last_stream = st;
+  if (rays->n == 0) {
+    out->n_pieces = out->n_pairs = out->n_knots = out->n_exact_pieces = 0;
+    if (out->ray_offsets) {
+      const int64_t z = 0;
+      sph::hip_check(hipMemcpyAsync(out->ray_offsets, &z, 8, hipMemcpyHostToDevice, st), "copy");
+      sph::hip_check(hipStreamSynchronize(st), "sync");
+    }
+    return;
+  }
+  sph::run_rays(ix, rays->n, false, nullptr, rays, fo, st, nullptr, 0, gathered);
+}
+
+}  // namespace
+
 sph_hoa_status sph_hoa_approx_rays(sph_hoa_index idx, const sph_hoa_rays* rays, sph_hoa_field* out, uint32_t flags,
                                    void* stream) {
+  return guarded([&]() { approx_rays_one(idx, rays, out, flags, stream, nullptr); });
+}
+
+sph_hoa_status sph_hoa_approx_rays_shared(const sph_hoa_index* idx, int32_t n_idx, const sph_hoa_rays* rays,
+                                          sph_hoa_field* out, uint32_t flags, void* stream) {
   return guarded([&]() {
-    require(idx && rays && out, "NULL argument");
-    require(flags == 0 || flags == SPH_HOA_FLAG_EXACT, "unknown flags");
-    require(rays->n >= 0 && rays->n < (int64_t(1) << 31), "ray count must be in 0..2^31-1");
-    require(std::isfinite(rays->t_min) && std::isfinite(rays->t_max) && rays->t_min < rays->t_max,
-            "need finite t_min < t_max");
-    require(out->capacity >= 0, "capacity must be >= 0");
-    if (rays->n > 0) {
-      require(rays->origin && rays->dir, "NULL ray arrays");
-      require(out->ray_offsets && out->ray_peak, "NULL output arrays");
-      require(out->capacity == 0 || (out->t_start && out->t_end && out->coef), "NULL piece arrays");
-    }
-    const bool exact = (flags & SPH_HOA_FLAG_EXACT) != 0;
-    if (exact && idx->ix.n >= (int64_t(1) << 29))
-      throw sph::Error(SPH_HOA_E_UNSUPPORTED, "exact mode needs fewer than 2^29 particles");
-    if (exact && rays->n > 0) {
-      require(out->exact_offsets && out->knot_offsets, "exact mode needs offset arrays");
-      require(out->exact_capacity == 0 || (out->exact_t && out->exact_end && out->exact_coef), "exact arrays");
-      require(out->knot_capacity == 0 || (out->knot_t && out->knot_pid && out->knot_kidx), "knot arrays");
-    }
-    sph::Index& ix = idx->ix;
-    const double span = std::max(std::fabs((double)rays->t_min), std::fabs((double)rays->t_max)) +
-                        ix.grid.lv[ix.grid.n_levels - 1].c;
-    if (!(span / ix.tau < 2.1e9))
-      throw sph::Error(SPH_HOA_E_OVERFLOW, "ray segment too long for int32 positions (|t| + q h_max >= 2^31 tau)");
-    sph::FieldOut fo{out, nullptr, nullptr, exact};
+    require(idx && out && rays, "NULL argument");
+    require(n_idx >= 1, "need at least one index");
+    for (int32_t i = 0; i < n_idx; ++i) require(idx[i] != nullptr, "NULL index");
     hipStream_t st = (hipStream_t)stream;
-    ix.last_stream = st;
-    if (rays->n == 0) {
-      out->n_pieces = out->n_pairs = out->n_knots = out->n_exact_pieces = 0;
-      if (out->ray_offsets) {
-        const int64_t z = 0;
-        sph::hip_check(hipMemcpyAsync(out->ray_offsets, &z, 8, hipMemcpyHostToDevice, st), "copy");
-        sph::hip_check(hipStreamSynchronize(st), "sync");
-      }
-      return;
-    }
-    sph::run_rays(ix, rays->n, false, nullptr, rays, fo, st);
+    for (int32_t i = 1; i < n_idx; ++i)
+      require(sph::same_particles(idx[0]->ix, idx[i]->ix, st),
+              "shared gathering needs indices of the same particles (positions, smoothing lengths, order)");
+    approx_rays_one(idx[0], rays, &out[0], flags, stream, nullptr);
+    for (int32_t i = 1; i < n_idx; ++i)
+      approx_rays_one(idx[i], rays, &out[i], flags, stream, rays->n > 0 ? &idx[0]->ix : nullptr);
   });
 }
 

@@ -147,6 +147,11 @@ struct Index {
   DevBuf hit_slots;             // uint32 [n][slots]: single-pass gathering of arbitrary rays
   int64_t last_max_hits = 0;    // largest hit count of the previous arbitrary-ray call
   DevBuf hits;                  // uint32 [pairs]
+  // where the previous arbitrary-ray call left its hit lists (for fields sharing that gathering):
+  // per-ray slots of last_hit_slots entries, or compact lists in `hits` (last_hit_slots = 0)
+  int64_t last_hit_slots = 0;
+  int64_t last_hit_rays = -1;   // ray count of that call (-1: none)
+  int64_t last_hit_max = 0;     // its largest hit count
   DevBuf tile_count, tile_off, tile_items;  // screen-tile binning of the particles (camera rays)
   DevBuf tile_masks;                         // per tile item: the tile pixels it hits
   DevBuf tile_order;                         // tiles by decreasing candidate count
@@ -234,8 +239,14 @@ struct FloatArgs {
 int64_t float_field_capacity(int64_t total_pairs, int64_t n_rays, int K, int n_reinit);
 void launch_float_field(FloatArgs& F, int64_t max_hits, DevBuf& scratch, int64_t* out_off, hipStream_t st);
 // n_batch > 0: render the cameras batch[0..n_batch) together (rays concatenated in camera order)
+// gathered != nullptr (arbitrary rays only): take the hit lists of gathered's previous call on the
+// same rays instead of gathering (the two indices hold the same particles: same_particles)
 void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam, const sph_hoa_rays* rays,
-              FieldOut& out, hipStream_t st, const sph_hoa_camera* batch = nullptr, int n_batch = 0);
+              FieldOut& out, hipStream_t st, const sph_hoa_camera* batch = nullptr, int n_batch = 0,
+              const Index* gathered = nullptr);
+// true if a and b hold the same particles in the same order (positions, smoothing lengths and
+// input indices bit for bit), so that every ray has the same hit list in both (index.hip)
+bool same_particles(const Index& a, const Index& b, hipStream_t st);
 
 // integer bit-length microbenchmark of the accumulation rule (bitlength.hip); host buffers
 void accumulate_bits(int bits, int D, const uint32_t* dist, const uint32_t* jumps, int n_table, int64_t n_threads,

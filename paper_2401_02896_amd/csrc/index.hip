@@ -492,6 +492,35 @@ void build_index_device(Index& ix, const float* xyz, const float* h, const float
   ix.grid_bits = bits;
 }
 
+// Clears *diff if every particle record (position and smoothing length, input index) is equal in
+// both indices; grid-stride, any grid.
+__global__ void __launch_bounds__(256) k_same_particles(const float4* a, const float4* b, const int32_t* oa,
+                                                        const int32_t* ob, int64_t n, unsigned int* diff) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const float4 p = a[i], q = b[i];
+    const bool same = __float_as_uint(p.x) == __float_as_uint(q.x) && __float_as_uint(p.y) == __float_as_uint(q.y) &&
+                      __float_as_uint(p.z) == __float_as_uint(q.z) && __float_as_uint(p.w) == __float_as_uint(q.w) &&
+                      oa[i] == ob[i];
+    if (!same) atomicOr(diff, 1u);
+  }
+}
+
+bool same_particles(const Index& a, const Index& b, hipStream_t st) {
+  if (a.n != b.n) return false;
+  if (a.n == 0) return true;
+  DevBuf d;
+  d.ensure(sizeof(unsigned int));
+  unsigned int* diff = d.as<unsigned int>();
+  hip_check(hipMemsetAsync(diff, 0, sizeof(unsigned int), st), "memset");
+  k_same_particles<<<grid_for(a.n), kThreads, 0, st>>>(a.pos4.as<float4>(), b.pos4.as<float4>(), a.orig.as<int32_t>(),
+                                                       b.orig.as<int32_t>(), a.n, diff);
+  hip_check(hipGetLastError(), "compare launch");
+  unsigned int h = 1;
+  hip_check(hipMemcpyAsync(&h, diff, sizeof(h), hipMemcpyDeviceToHost, st), "copy");
+  hip_check(hipStreamSynchronize(st), "sync");
+  return h == 0;
+}
+
 void get_grid_device(Index& ix, uint64_t* morton, int32_t* level, int32_t* order, hipStream_t st) {
   const int64_t n = ix.n;
   k_level_of<<<grid_for(n), kThreads, 0, st>>>(ix.morton.as<uint64_t>(), n, ix.grid_bits, level, morton);

@@ -1719,8 +1719,10 @@ void Index::collect_timing() {
 }
 
 void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam, const sph_hoa_rays* rays,
-              FieldOut& out, hipStream_t st, const sph_hoa_camera* batch, int n_batch) {
+              FieldOut& out, hipStream_t st, const sph_hoa_camera* batch, int n_batch, const Index* gathered) {
   const int D = ix.D, K = ix.K, P = ix.P;
+  if (gathered && (camera || n_batch > 0 || gathered->last_hit_rays != n_rays))
+    throw Error(SPH_HOA_E_INTERNAL, "shared gathering needs the same arbitrary rays");
   ix.collect_timing();
   ix.tuner.collect();
   ix.render_stats_pending = false;
@@ -1775,9 +1777,11 @@ void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam,
     t_max = (double)rays->t_max;
   }
   hip_check(hipGetLastError(), "ray launch");
-  // hit counts
+  // hit counts (another index's, when the gathering is shared)
   ix.hit_count.ensure(sizeof(int64_t) * (n_rays + 1));
   ix.hit_off.ensure(sizeof(int64_t) * (n_rays + 1));
+  int64_t* hit_count = gathered ? gathered->hit_count.as<int64_t>() : ix.hit_count.as<int64_t>();
+  int64_t* hit_off = gathered ? gathered->hit_off.as<int64_t>() : ix.hit_off.as<int64_t>();
   GatherArgs G{};
   G.o = ix.rays_o.as<double>();
   G.v = ix.rays_v.as<double>();
@@ -1850,6 +1854,12 @@ void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam,
     TH.max_hits = max_hits;
     k_tile_hits<false><<<(unsigned)n_tiles, 64, 0, st>>>(TH);
     if (ix.timing) hip_check(hipEventRecord(ix.ev[1], st), "event");
+  } else if (gathered) {
+    // the hit lists of the other index's call on these rays: no gathering (zero gathering time)
+    if (ix.timing) {
+      hip_check(hipEventRecord(ix.ev[0], st), "event");
+      hip_check(hipEventRecord(ix.ev[1], st), "event");
+    }
   } else {
     // Single pass when it fits: the counting walk also stores each ray's first n_slots hits in
     // per-ray slots, sized from the previous call's longest ray; the filling walk then runs only
@@ -1869,15 +1879,18 @@ void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam,
     if (ix.timing) hip_check(hipEventRecord(ix.ev[1], st), "event");
   }
   hip_check(hipGetLastError(), "gather launch");
-  device_exclusive_scan_i64(ix.hit_count.as<int64_t>(), ix.hit_off.as<int64_t>(), n_rays, ix.scan_tmp, st);
-  k_set_last<<<1, 1, 0, st>>>(ix.hit_off.as<int64_t>(), ix.hit_count.as<int64_t>(), n_rays);
+  if (!gathered) {
+    device_exclusive_scan_i64(hit_count, hit_off, n_rays, ix.scan_tmp, st);
+    k_set_last<<<1, 1, 0, st>>>(hit_off, hit_count, n_rays);
+  }
   int64_t total_pairs = 0;
   unsigned long long mh = 0;
   uint32_t fl = 0;
-  hip_check(hipMemcpyAsync(&total_pairs, ix.hit_off.as<int64_t>() + n_rays, 8, hipMemcpyDeviceToHost, st), "copy");
-  hip_check(hipMemcpyAsync(&mh, max_hits, 8, hipMemcpyDeviceToHost, st), "copy");
+  hip_check(hipMemcpyAsync(&total_pairs, hit_off + n_rays, 8, hipMemcpyDeviceToHost, st), "copy");
+  if (!gathered) hip_check(hipMemcpyAsync(&mh, max_hits, 8, hipMemcpyDeviceToHost, st), "copy");
   hip_check(hipMemcpyAsync(&fl, flags, 4, hipMemcpyDeviceToHost, st), "copy");
   hip_check(hipStreamSynchronize(st), "sync");
+  if (gathered) mh = (unsigned long long)gathered->last_hit_max;
   if (fl & kFlagBadInput) throw Error(SPH_HOA_E_INVALID_ARG, "ray origin/direction not finite or direction not unit");
   if (fl & kFlagWindow) throw Error(SPH_HOA_E_INTERNAL, "grid enumeration window exceeded");
   ix.stats.n_pairs = total_pairs;
@@ -1887,13 +1900,18 @@ void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam,
   if ((int64_t)mh * (K + 1) > (int64_t)1023 * kFieldThreads)
     throw Error(SPH_HOA_E_UNSUPPORTED, "more than 1023 * 256 knots on one ray");
   if (n_cams == 0) ix.last_max_hits = (int64_t)mh;
-  const bool single_pass = n_slots > 0 && (int64_t)mh <= n_slots;
-  const uint32_t* hit_lists = single_pass ? ix.hit_slots.as<uint32_t>() : nullptr;
-  if (!single_pass) {
+  const bool single_pass = gathered ? gathered->last_hit_slots > 0 : (n_slots > 0 && (int64_t)mh <= n_slots);
+  const uint32_t* hit_lists = nullptr;
+  if (gathered) {
+    hit_lists = single_pass ? gathered->hit_slots.as<uint32_t>() : gathered->hits.as<uint32_t>();
+    n_slots = gathered->last_hit_slots;
+  } else if (single_pass) {
+    hit_lists = ix.hit_slots.as<uint32_t>();
+  } else {
     ix.hits.ensure(sizeof(uint32_t) * std::max<int64_t>(1, total_pairs));
     hit_lists = ix.hits.as<uint32_t>();
   }
-  G.off = ix.hit_off.as<int64_t>();
+  G.off = hit_off;
   G.hits = ix.hits.as<uint32_t>();
   G.slots = nullptr;
   if (ix.timing) hip_check(hipEventRecord(ix.ev[2], st), "event");
@@ -1901,10 +1919,19 @@ void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam,
     TH.off = G.off;
     TH.hits = G.hits;
     k_tile_hits<true><<<(unsigned)n_tiles, 64, 0, st>>>(TH);
-  } else if (!single_pass) {
+  } else if (!single_pass && !gathered) {
     k_gather<true><<<gblocks, kGatherThreads, 0, st>>>(G);
   }
   const int64_t hit_slots = single_pass ? n_slots : 0;
+  // the hit lists this index can share with the next call: its own, or none (its buffers may have
+  // been resized) when it used another index's
+  if (n_cams > 0 || (gathered && gathered != &ix)) {
+    ix.last_hit_rays = -1;
+  } else if (!gathered) {
+    ix.last_hit_slots = hit_slots;
+    ix.last_hit_rays = n_rays;
+    ix.last_hit_max = (int64_t)mh;
+  }
   if (ix.timing) hip_check(hipEventRecord(ix.ev[3], st), "event");
   hip_check(hipGetLastError(), "gather launch");
   if (out.flt) {
@@ -1920,7 +1947,7 @@ void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam,
     F.n_rays = n_rays;
     F.t_min = t_min;
     F.t_max = t_max;
-    F.hit_off = ix.hit_off.as<int64_t>();
+    F.hit_off = hit_off;
     F.hits = hit_lists;
     F.hit_slots = hit_slots;
     F.pos4 = ix.pos4.as<float4>();
@@ -1962,14 +1989,14 @@ void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam,
     ix.order_keys.ensure(sizeof(uint64_t) * 2 * n_rays);
     uint64_t* k0 = ix.order_keys.as<uint64_t>();
     uint64_t* k1 = k0 + n_rays;
-    k_order_keys<<<blocks_for(n_rays, 256), 256, 0, st>>>(ix.hit_count.as<int64_t>(), n_rays, k0);
+    k_order_keys<<<blocks_for(n_rays, 256), 256, 0, st>>>(hit_count, n_rays, k0);
     const bool alt = device_sort_u64(k0, k1, n_rays, 64, ix.sort_hist, ix.sort_offs, ix.scan_tmp, st);
     ix.order.ensure(sizeof(uint32_t) * n_rays);
     k_low32<<<blocks_for(n_rays, 256), 256, 0, st>>>(alt ? k1 : k0, n_rays, ix.order.as<uint32_t>());
     A.order = ix.order.as<uint32_t>();
   }
-  A.hit_count = ix.hit_count.as<int64_t>();
-  A.hit_off = ix.hit_off.as<int64_t>();
+  A.hit_count = hit_count;
+  A.hit_off = hit_off;
   A.hits = hit_lists;
   A.hit_slots = hit_slots;
   A.pos4 = ix.pos4.as<float4>();
@@ -2054,7 +2081,7 @@ void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam,
       A.ex_end = A.ex_t + f->exact_capacity;
       A.ex_coef = A.ex_end + f->exact_capacity;
       knot_off.ensure(sizeof(int64_t) * (n_rays + 1));
-      k_scale_i64<<<blocks_for(n_rays + 1, 256), 256, 0, st>>>(ix.hit_off.as<int64_t>(), knot_off.as<int64_t>(),
+      k_scale_i64<<<blocks_for(n_rays + 1, 256), 256, 0, st>>>(hit_off, knot_off.as<int64_t>(),
                                                                n_rays + 1, K + 1);
       A.knot_off = knot_off.as<int64_t>();
       A.knot_cap = f->knot_capacity;

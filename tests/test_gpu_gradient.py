@@ -69,3 +69,62 @@ def test_gradient_fields_match_oracle():
             assert np.max(np.abs(got - ref)) <= 0.08 * scale, (r, e)
         checked += 1
     assert checked >= 8
+
+
+def _same(a, b):
+    assert a.keys() == b.keys()
+    for k in a:
+        if isinstance(a[k], torch.Tensor):
+            assert torch.equal(a[k], b[k]), k
+        else:
+            assert a[k] == b[k], k
+
+
+@pytest.mark.parametrize("slots", [None, "0"])
+def test_shared_gathering_equals_separate_calls(slots):
+    """sph_hoa_approx_rays_shared gives each index exactly what its own sph_hoa_approx_rays call
+    gives, with single-pass (per-ray slots) and two-walk gathering, for indices of the same
+    particles with other values, kernels, K and D."""
+    import os
+
+    xyz, h, val = synth.random_scene(43, 300, h_lo=0.04, h_hi=0.1)
+    o, v = synth.random_rays(8, 40)
+    gv = G.transverse_values(xyz, h, val)
+    scs = [H.Scene("wendland", 4, 3, 4096, xyz, h, val, 1e-3)]
+    scs += [H.Scene("wendland_grad", 4, 3, 1024, xyz, h, g, 1e-3) for g in gv]
+    scs += [H.Scene("wendland_c4_grad", 3, 2, 64, xyz, h, gv[1], 0.0)]
+    idx = [s.index() for s in scs]
+    if slots is not None:
+        os.environ["SPH_HOA_GATHER_SLOTS"] = slots
+    try:
+        for exact in (True, False):
+            shared = L.sph_hoa_approx_rays_shared(idx, torch.as_tensor(o), torch.as_tensor(v), T0, T1, exact=exact)
+            for i, ix in enumerate(idx):
+                sep = L.sph_hoa_approx_rays(ix, torch.as_tensor(o), torch.as_tensor(v), T0, T1, exact=exact)
+                _same(shared[i], sep)
+    finally:
+        os.environ.pop("SPH_HOA_GATHER_SLOTS", None)
+    assert shared[0]["n_pairs"] > 100
+
+
+def test_shared_gathering_rejects_other_particles():
+    xyz, h, val = synth.random_scene(43, 300, h_lo=0.04, h_hi=0.1)
+    a = H.Scene("wendland", 4, 3, 4096, xyz, h, val, 1e-3).index()
+    h2 = h.copy()
+    h2[17] *= np.float32(1.01)
+    b = H.Scene("wendland", 4, 3, 4096, xyz, h2, val, 1e-3).index()
+    o, v = synth.random_rays(8, 4)
+    with pytest.raises(RuntimeError, match="E_INVALID_ARG"):
+        L.sph_hoa_approx_rays_shared([a, b], torch.as_tensor(o), torch.as_tensor(v), T0, T1)
+    # empty ray set: nothing to gather, every field empty
+    out = L.sph_hoa_approx_rays_shared([a, a], torch.zeros((0, 3)), torch.zeros((0, 3)), T0, T1)
+    assert [x["n_pieces"] for x in out] == [0, 0]
+    # one index several times (with timing on: a sharing call records no gathering time): every
+    # field equals the single call
+    a.set_timing(True)
+    outs = L.sph_hoa_approx_rays_shared([a, a, a], torch.as_tensor(o), torch.as_tensor(v), T0, T1)
+    st = a.stats()
+    assert st["n_rays"] == len(o)
+    ref = L.sph_hoa_approx_rays(a, torch.as_tensor(o), torch.as_tensor(v), T0, T1)
+    for x in outs:
+        _same(x, ref)
