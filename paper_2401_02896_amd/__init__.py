@@ -404,13 +404,19 @@ def sph_hoa_approx_rays_shared(indices, origin, direction, t_min, t_max, capacit
         st = lib().sph_hoa_approx_rays_shared(handles, k, ctypes.byref(r), fields, FLAG_EXACT if exact else 0,
                                               _stream())
         if st == 2 and capacity is None and attempt < k:
+            # the call stops at the first field that does not fit; the fields after it have not run,
+            # so they get at least the same capacity (fields of the same rays are of similar size)
             grown = False
             for i in range(k):
                 if fields[i].n_pieces > caps[i] or (exact and (fields[i].n_exact_pieces > ecaps[i]
                                                                or fields[i].n_knots > ecaps[i])):
                     caps[i] = max(caps[i], int(fields[i].n_pieces) + 1)
                     ecaps[i] = max(ecaps[i], int(fields[i].n_exact_pieces) + 1, int(fields[i].n_knots) + 1)
+                    for j in range(i + 1, k):
+                        caps[j] = max(caps[j], caps[i] + caps[i] // 8)
+                        ecaps[j] = max(ecaps[j], ecaps[i] + ecaps[i] // 8)
                     grown = True
+                    break
             if grown:
                 continue
         _check(st)
