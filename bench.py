@@ -513,7 +513,7 @@ def main():
     a = parse()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {a.gpus}): every ray is independent, so N GPUs would "
-              "split the image; this build measures the one-GPU share.", file=sys.stderr)
+              "split the image; this benchmark measures the one-GPU share.", file=sys.stderr)
         sys.exit(2)
     import torch
 

@@ -20,7 +20,7 @@ from tests.test_gpu_parity import TINY_SAMPLE, _check_ray
 pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
-if not torch.cuda.is_available():  # pragma: no cover - only on the GPU machine
+if not torch.cuda.is_available():  # pragma: no cover - needs a GPU
     pytest.skip("needs a GPU", allow_module_level=True)
 
 import paper_2401_02896_amd as L  # noqa: E402

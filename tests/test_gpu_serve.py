@@ -14,7 +14,7 @@ from tests import gpu_helpers as H
 pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
-if not torch.cuda.is_available():  # pragma: no cover - only on the GPU machine
+if not torch.cuda.is_available():  # pragma: no cover - needs a GPU
     pytest.skip("needs a GPU", allow_module_level=True)
 
 import paper_2401_02896_amd as L  # noqa: E402
