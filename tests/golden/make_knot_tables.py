@@ -32,6 +32,7 @@ TABLES = [
     ("wendland_c6", 2, 2, 64),
     ("wendland_grad", 4, 3, 64),
     ("wendland_grad", 4, 3, 1024),
+    ("wendland_grad", 4, 3, 4096),
     ("wendland_c4_grad", 3, 2, 64),
     ("wendland_c6_grad", 2, 2, 64),
 ]

@@ -128,3 +128,32 @@ def test_shared_gathering_rejects_other_particles():
     ref = L.sph_hoa_approx_rays(a, torch.as_tensor(o), torch.as_tensor(v), T0, T1)
     for x in outs:
         _same(x, ref)
+
+
+def test_full_size_gradient_fields_sampled():
+    """The gradient workload at full size (the plain frame's 1M clustered particles and 512 x 512
+    pixel-centre rays, K = 4, D = 3, tol 1e-3): the five fields of one shared call over all rays,
+    the benchmark's launch configuration, equal five separate calls bit for bit, and the exact
+    pieces of sampled rays meet the parity bars against the oracle."""
+    from oracle import geometry
+
+    xyz, h, val = synth.clustered_particles()
+    scs = [H.Scene("wendland", 4, 3, 4096, xyz, h, val, 1e-3)]
+    scs += [H.Scene("wendland_grad", 4, 3, 4096, xyz, h, g, 1e-3) for g in G.transverse_values(xyz, h, val)]
+    idx = [s.index() for s in scs]
+    oo, vv = geometry.camera_rays(synth.plain_camera())
+    o32 = torch.as_tensor(oo.astype(np.float32))
+    v32 = torch.as_tensor(vv.astype(np.float32))
+    shared = L.sph_hoa_approx_rays_shared(idx, o32, v32, 1.0, 3.0)
+    assert shared[0]["n_pairs"] > 1.5e8
+    for i, ix in enumerate(idx):
+        sep = L.sph_hoa_approx_rays(ix, o32, v32, 1.0, 3.0)
+        _same(shared[i], sep)
+        del sep
+    del shared
+    pix = np.array([512 * 256 + 256, int(np.random.default_rng(78).integers(0, 512 * 512))])
+    out = L.sph_hoa_approx_rays_shared(idx, o32[pix], v32[pix], 1.0, 3.0, exact=True)
+    for k, r in enumerate(pix):
+        for sc, o in zip(scs, out):
+            f = sc.oracle_ray(o32[r].numpy(), v32[r].numpy(), 1.0, 3.0)
+            _check_ray(sc, o, k, f)
