@@ -18,27 +18,35 @@ the pieces.
 Peak (this implementation's reading of the ray's peak value): sigma times the
 largest |a_0| over the starts of the exact pieces.
 
-Merge (the paper has no merge step; this is this implementation's definition):
-the sorted knots are cut into chunks of MERGE_CHUNK consecutive knots, and the
-exact piece that starts at knot i belongs to chunk floor(i / MERGE_CHUNK)
-(a piece starts at the last knot of each group of equal positions).  Within a
-chunk, pieces are merged greedily from left to right; then, for levels
-l = 0, 1, ..., the node lists of chunk groups [g, g + 2^l) and
-[g + 2^l, g + 2^(l+1)) are joined and their two boundary nodes merged when
-the result passes.  A merged node over [a, b] carries the L2 projection P of
-the exact field F onto polynomials of degree <= D on [a, b] and its residual
-r = int_a^b (F - P)^2 dt; it passes when r <= (tol * peak)^2 * (b - a).
-Projections use the shifted Legendre basis on [0, 1]; the projection of a
-union and its residual follow exactly from the parts because F - P_part is
-orthogonal to polynomials of degree <= D on the part:
-  P_U = projection of (P_A on A, P_B on B);
-  r_U = r_A + r_B + int_A (P_A - P_U)^2 + int_B (P_B - P_U)^2.
-With tol = 0 nothing is merged.
+Merge (the paper has no merge step; this is this implementation's definition,
+a plain greedy pass over the whole ray): starting at the first exact piece, the
+current merged interval [a, b] is extended by the next exact piece as long as
+the extension passes, and a new merged interval starts at the first piece whose
+addition fails.  An interval passes when the squared L2 distance r of the
+exact field F from P, the L2 projection of F onto polynomials of degree <= D
+on the interval, satisfies r <= (tol * peak)^2 * (b - a) (lengths in world
+units), i.e. the RMS error is at most tol * peak.  A single exact piece always
+passes (F is itself a polynomial of degree <= D there).  P and r are computed
+directly from the exact pieces of the interval, with no incremental update:
+Gauss-Legendre quadrature with D + 1 nodes on every exact piece (exact for the
+degree-2D integrands), P in the shifted Legendre basis of the interval,
+r = sum over the pieces of the quadrature of (F - P)^2.  With tol = 0 nothing
+is merged.  The smallest relative distance of any decision from its threshold
+is kept as the ray's margin (decisions closer than rounding to the threshold
+may differ between two float64 evaluations).
+
+check_merged validates any merged field given as (start, end, coefficients)
+against the exact pieces, independently of how it was produced: breakpoints on
+exact piece boundaries, contiguous cover of the exact pieces, every merged
+piece within the tolerance (residual of the projection, recomputed here) and
+its coefficients equal to that projection within a stated bar.
 
 Pinned by tests/test_oracle_field.py: the accumulation against brute-force
 evaluation of every particle's own polynomial, the zero tail, the merge
-partition invariants, residuals against exact rational arithmetic and the
-greedy maximality of each chunk.
+partition invariants, the merge's decisions against the same greedy pass run
+in exact rational arithmetic (monomial moments and a Gram solve with Python
+fractions, a different formulation), moments 0..D of every merged piece, and
+the checker against planted mistakes.
 """
 from __future__ import annotations
 
@@ -48,7 +56,6 @@ import numpy as np
 
 from . import geometry, knots as knots_mod, lut as lut_mod
 
-MERGE_CHUNK = 16
 
 
 def ray_knots(o, v, t_min, t_max, xyz, zeta, value, table, quanta, K, D, kind, hits=None):
@@ -104,7 +111,7 @@ def peak(pieces, sigma):
 # ---------------------------------------------------------------- merge machinery
 
 def _shifted_legendre(D):
-    """Shifted Legendre polynomials P~_j(u) = P_j(2u - 1), j = 0..D, as power-basis rows."""
+    """Shifted Legendre polynomials P~_j(u) = P_j(2u - 1), j = 0..D, as power-basis rows [j, power]."""
     from numpy.polynomial import legendre as L
     from numpy.polynomial import polynomial as Pw
 
@@ -113,125 +120,150 @@ def _shifted_legendre(D):
         c = np.zeros(j + 1)
         c[j] = 1.0
         pw = L.leg2poly(c)  # in x
-        # substitute x = 2u - 1
         acc = np.zeros(1)
         for m, cm in enumerate(pw):
             acc = Pw.polyadd(acc, cm * Pw.polypow([-1.0, 2.0], m))
         row = np.zeros(D + 1)
         row[: len(acc)] = acc
         rows.append(row)
-    return np.array(rows)  # [j, power]
+    return np.array(rows)
 
 
-class Merger:
-    """Legendre-basis L2 projections on intervals of the quantized line."""
+class Projector:
+    """L2 projections of a ray's exact field onto polynomials of degree <= D on unions of
+    consecutive exact pieces, computed directly from the pieces (float64)."""
 
-    def __init__(self, D, tau, sigma):
+    def __init__(self, pieces, D, tau, sigma):
         self.D = D
         self.tau = float(tau)
         self.sigma = float(sigma)
-        self.L = _shifted_legendre(D)               # P~_j in powers of u
+        self.L = _shifted_legendre(D)
         xg, wg = np.polynomial.legendre.leggauss(D + 1)
-        self.u = 0.5 * (xg + 1.0)                    # nodes on [0, 1]
-        self.wu = 0.5 * wg
-        self.Pu = self._leg_at(self.u)               # [j, node]
+        self.xg = 0.5 * (xg + 1.0)   # nodes on [0, 1]
+        self.wg = 0.5 * wg
+        n = len(pieces)
+        self.start = np.array([p[0] for p in pieces], dtype=np.int64)
+        self.end = np.array([p[1] for p in pieces], dtype=np.int64)
+        lens = (self.end - self.start).astype(np.float64)
+        # F at the Gauss nodes of every piece: sigma * sum_d a_d x^d, x in quanta from the piece start
+        F = np.zeros((n, D + 1))
+        for i, p in enumerate(pieces):
+            x = lens[i] * self.xg
+            F[i] = self.sigma * sum(float(p[2][d]) * x ** d for d in range(D + 1))
+        self.F = F
+        self.lens = lens
 
-    def _leg_at(self, u):
+    def legendre_at(self, u):
         return np.array([np.polyval(self.L[j][::-1], u) for j in range(self.D + 1)])
 
-    def leaf(self, t_a, t_b, coefs):
-        """Node of an exact piece: F(u) = sigma * sum_d a_d (L u)^d, L = t_b - t_a quanta."""
-        Lq = t_b - t_a
-        beta = np.array([self.sigma * float(coefs[d]) * float(Lq) ** d for d in range(self.D + 1)])
-        # Legendre coefficients: gamma_j = (2j+1) int_0^1 F P~_j du (exact by Gauss-Legendre)
-        F = np.polyval(beta[::-1], self.u)
-        gamma = np.array([(2 * j + 1) * np.sum(self.wu * F * self.Pu[j]) for j in range(self.D + 1)])
-        return {"a": t_a, "b": t_b, "g": gamma, "r": 0.0}
+    def node(self, lo, hi):
+        """Projection and residual of the union of pieces lo..hi (inclusive)."""
+        a, b = int(self.start[lo]), int(self.end[hi])
+        Lq = float(b - a)
+        off = (self.start[lo:hi + 1] - a).astype(np.float64)
+        x = off[:, None] + self.lens[lo:hi + 1, None] * self.xg[None, :]       # quanta from a
+        w = self.lens[lo:hi + 1, None] * self.wg[None, :]                      # quanta
+        F = self.F[lo:hi + 1]
+        Pj = self.legendre_at(x / Lq)                                          # [j, piece, node]
+        g = np.array([(2 * j + 1) / Lq * np.sum(w * F * Pj[j]) for j in range(self.D + 1)])
+        P = np.tensordot(g, Pj, axes=1)
+        r = self.tau * float(np.sum(w * (F - P) ** 2))
+        return {"a": a, "b": b, "g": g, "r": r, "lo": lo, "hi": hi}
 
-    def eval(self, node, u):
-        return np.sum(node["g"][:, None] * self._leg_at(np.atleast_1d(u)), axis=0)
-
-    def combine(self, A, B):
-        """Projection and residual of the union of adjacent nodes A = [a, b], B = [b, c]."""
-        a, b, c = A["a"], A["b"], B["b"]
-        lam = float(b - a) / float(c - a)
-        uA = lam * self.u                 # A's nodes in union coordinates
-        uB = lam + (1.0 - lam) * self.u   # B's nodes in union coordinates
-        FA = self.eval(A, self.u)
-        FB = self.eval(B, self.u)
-        PA = self._leg_at(uA)
-        PB = self._leg_at(uB)
-        g = np.array([(2 * j + 1) * (lam * np.sum(self.wu * FA * PA[j]) + (1.0 - lam) * np.sum(self.wu * FB * PB[j]))
-                      for j in range(self.D + 1)])
-        U = {"a": a, "b": c, "g": g}
-        dA = FA - np.sum(g[:, None] * PA, axis=0)
-        dB = FB - np.sum(g[:, None] * PB, axis=0)
-        lenA = float(b - a) * self.tau
-        lenB = float(c - b) * self.tau
-        U["r"] = A["r"] + B["r"] + lenA * np.sum(self.wu * dA * dA) + lenB * np.sum(self.wu * dB * dB)
-        return U
-
-    def passes(self, node, tol, pk):
-        thr = (tol * pk) ** 2 * (float(node["b"] - node["a"]) * self.tau)
-        if thr > 0.0:
-            self.margin = min(self.margin, abs(node["r"] - thr) / thr)
-        return node["r"] <= thr
-
-    margin = float("inf")  # smallest relative distance of a merge decision from its threshold
+    def threshold(self, node, tol, pk):
+        return (tol * pk) ** 2 * (float(node["b"] - node["a"]) * self.tau)
 
     def to_power(self, node):
         """Coefficients c_d of the node's polynomial in powers of u = (t - t_a) / (t_b - t_a)."""
         return node["g"] @ self.L
 
 
-def merge(sorted_knots, pieces, tol, tau, sigma, D, chunk=MERGE_CHUNK):
-    """Merged nodes of one ray (definition in the module docstring)."""
-    M = Merger(D, tau, sigma)
-    pk = peak(pieces, sigma)
-    if not pieces:
-        return [], M
-    leaves = [(M.leaf(a, b, c), ki) for (a, b, c, ki) in pieces]
+def merge(pieces, tol, tau, sigma, D):
+    """Greedy merge over the whole ray (definition in the module docstring).
+
+    Returns (nodes, projector, margin)."""
+    M = Projector(pieces, D, tau, sigma)
+    margin = float("inf")
+    n = len(pieces)
+    if n == 0:
+        return [], M, margin
     if tol <= 0.0:
-        return [n for n, _ in leaves], M
-    n_chunks = (len(sorted_knots) + chunk - 1) // chunk
-    per_chunk = [[] for _ in range(n_chunks)]
-    for node, ki in leaves:
-        per_chunk[ki // chunk].append(node)
-    groups = []
-    for lst in per_chunk:
-        out = []
-        cur = None
-        for node in lst:
-            if cur is None:
-                cur = node
-                continue
-            cand = M.combine(cur, node)
-            if M.passes(cand, tol, pk):
+        return [M.node(i, i) for i in range(n)], M, margin
+    pk = peak(pieces, sigma)
+    nodes = []
+    s = 0
+    while s < n:
+        cur = M.node(s, s)
+        e = s
+        while e + 1 < n:
+            cand = M.node(s, e + 1)
+            thr = M.threshold(cand, tol, pk)
+            if thr > 0.0:
+                margin = min(margin, abs(cand["r"] - thr) / thr)
+            if cand["r"] <= thr:
                 cur = cand
+                e += 1
             else:
-                out.append(cur)
-                cur = node
-        if cur is not None:
-            out.append(cur)
-        groups.append(out)
-    width = 1
-    while width < n_chunks:
-        new_groups = []
-        for g in range(0, len(groups), 2):
-            left = groups[g]
-            right = groups[g + 1] if g + 1 < len(groups) else None
-            if right is None:
-                new_groups.append(left)
-                continue
-            if left and right:
-                cand = M.combine(left[-1], right[0])
-                if M.passes(cand, tol, pk):
-                    new_groups.append(left[:-1] + [cand] + right[1:])
-                    continue
-            new_groups.append(left + right)
-        groups = new_groups
-        width *= 2
-    return groups[0], M
+                break
+        nodes.append(cur)
+        s = e + 1
+    return nodes, M, margin
+
+
+def check_merged(pieces, merged, tol, tau, sigma, D, coef_tol=1e-5, resid_slack=1e-9):
+    """Validity of a merged field against the ray's exact pieces.
+
+    merged: [(qa, qb, coef)] with qa, qb the piece ends in length quanta (integers) and coef the
+    power coefficients in u = (t - qa tau) / ((qb - qa) tau).  Checks that the breakpoints are exact
+    piece boundaries, that the merged pieces cover the exact pieces contiguously, that each merged
+    piece's projection residual is within (tol * peak)^2 * length (up to a relative slack for the
+    rounding of the two float64 evaluations), and that its coefficients equal that projection within
+    coef_tol * peak at 17 points of the piece.  Returns a dict with 'errors' (empty when valid),
+    'n' (merged pieces), 'max_coef_err' and 'max_resid_ratio' (relative to the peak / threshold)."""
+    errors = []
+    out = {"errors": errors, "n": len(merged), "max_coef_err": 0.0, "max_resid_ratio": 0.0}
+    if not pieces:
+        if merged:
+            errors.append("pieces on an empty ray")
+        return out
+    if not merged:
+        errors.append("no pieces on a non-empty ray")
+        return out
+    M = Projector(pieces, D, tau, sigma)
+    pk = peak(pieces, sigma)
+    index_of_start = {int(s): i for i, s in enumerate(M.start)}
+    index_of_end = {int(e): i for i, e in enumerate(M.end)}
+    if int(merged[0][0]) != int(M.start[0]):
+        errors.append("first merged piece does not start at the first exact piece")
+    if int(merged[-1][1]) != int(M.end[-1]):
+        errors.append("last merged piece does not end at the last exact piece")
+    for (qa, _, _), (_, qb_prev, _) in zip(merged[1:], merged[:-1]):
+        if int(qa) != int(qb_prev):
+            errors.append(f"gap or overlap at {qa} / {qb_prev}")
+    us = np.linspace(0.0, 1.0, 17)
+    for qa, qb, coef in merged:
+        qa, qb = int(qa), int(qb)
+        if qa not in index_of_start or qb not in index_of_end or qb <= qa:
+            errors.append(f"merged piece [{qa}, {qb}) not on exact piece boundaries")
+            continue
+        lo, hi = index_of_start[qa], index_of_end[qb]
+        node = M.node(lo, hi)
+        if tol <= 0.0:
+            if lo != hi:
+                errors.append(f"merged piece [{qa}, {qb}) joins exact pieces with merging off")
+        else:
+            thr = M.threshold(node, tol, pk)
+            ratio = node["r"] / thr if thr > 0 else (0.0 if node["r"] == 0 else float("inf"))
+            out["max_resid_ratio"] = max(out["max_resid_ratio"], ratio)
+            if lo != hi and node["r"] > thr * (1.0 + resid_slack):
+                errors.append(f"merged piece [{qa}, {qb}) exceeds the tolerance (ratio {ratio})")
+        ref = np.polyval(M.to_power(node)[::-1], us)
+        got = np.polyval(np.asarray(coef, dtype=np.float64)[::-1], us)
+        err = float(np.max(np.abs(got - ref))) / pk if pk > 0 else float(np.max(np.abs(got - ref)))
+        out["max_coef_err"] = max(out["max_coef_err"], err)
+        if err > coef_tol:
+            errors.append(f"merged piece [{qa}, {qb}) coefficients off the projection by {err} of the peak")
+    return out
 
 
 def ray_field(o, v, t_min, t_max, xyz, zeta, value, table, quanta, K, D, kind, tol, hits=None):
@@ -239,11 +271,16 @@ def ray_field(o, v, t_min, t_max, xyz, zeta, value, table, quanta, K, D, kind, t
     hits, sk = ray_knots(o, v, t_min, t_max, xyz, zeta, value, table, quanta, K, D, kind, hits=hits)
     pieces, tail = exact_pieces(sk)
     tau, sigma = quanta
-    nodes, M = merge(sk, pieces, tol, tau, sigma, D)
+    nodes, M, margin = merge(pieces, tol, tau, sigma, D)
     return {"hits": hits, "knots": sk, "pieces": pieces, "tail": tail, "peak": peak(pieces, sigma),
-            "nodes": nodes, "merger": M, "margin": M.margin}
+            "nodes": nodes, "merger": M, "margin": margin}
 
 
 def node_output(node, M):
     """(t_start, t_end, power coefficients in u) in world units (float64)."""
     return node["a"] * M.tau, node["b"] * M.tau, M.to_power(node)
+
+
+def node_output_q(node, M):
+    """(start, end in length quanta, power coefficients in u), the form check_merged takes."""
+    return node["a"], node["b"], M.to_power(node)

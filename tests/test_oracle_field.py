@@ -166,30 +166,146 @@ def test_merge_invariants_exact(setup, tol):
         assert abs(float(resid_world) - node["r"]) <= 1e-6 * float((Fraction(tol) * pk) ** 2 * Lw * Fraction(tau))
 
 
-def test_merge_greedy_maximal_within_chunks(setup):
-    """Within a chunk, a node was closed only because adding the next piece failed the test."""
+def _solve_exact(G, m):
+    """Gaussian elimination in Python fractions (G symmetric positive definite)."""
+    n = len(m)
+    A = [list(G[i]) + [m[i]] for i in range(n)]
+    for c in range(n):
+        for r in range(c + 1, n):
+            f = A[r][c] / A[c][c]
+            for k in range(c, n + 1):
+                A[r][k] -= f * A[c][k]
+    y = [Fraction(0)] * n
+    for r in range(n - 1, -1, -1):
+        y[r] = (A[r][n] - sum(A[r][k] * y[k] for k in range(r + 1, n))) / A[r][r]
+    return y
+
+
+def _exact_greedy(pieces, tol, D):
+    """The whole-ray greedy merge decided in exact rational arithmetic, by a formulation other
+    than the oracle's: the field of each exact piece expanded in powers of x = t - a (a the merged
+    interval's start, in quanta), running monomial moments m_k = int F x^k and the energy
+    int F^2 added piece by piece, the projection from the Gram system G_jk = L^(j+k+1)/(j+k+1)
+    and the residual int F^2 - m.y.  sigma^2 tau is common to the residual and the threshold
+    (tol max|a_0|)^2 L, so both are compared without it.  Returns the merged intervals."""
+    if not pieces:
+        return []
+    A0 = max(abs(int(p[2][0])) for p in pieces)
+    tol_q = Fraction(tol)
+
+    def piece_terms(p, a):
+        ta, tb, c = p[0], p[1], [int(x) for x in p[2]]
+        xi, xe = ta - a, tb - a
+        # F(x) = sum_d c_d (x - xi)^d = sum_e ce_e x^e
+        ce = [sum(c[d] * math.comb(d, e) * (-xi) ** (d - e) for d in range(e, D + 1)) for e in range(D + 1)]
+        mom = [sum(Fraction(ce[e] * (xe ** (e + k + 1) - xi ** (e + k + 1)), e + k + 1) for e in range(D + 1))
+               for k in range(D + 1)]
+        en = sum(Fraction(ce[e] * ce[f] * (xe ** (e + f + 1) - xi ** (e + f + 1)), e + f + 1)
+                 for e in range(D + 1) for f in range(D + 1))
+        return mom, en
+
+    out = []
+    s, n = 0, len(pieces)
+    while s < n:
+        a = pieces[s][0]
+        mom, en = piece_terms(pieces[s], a)
+        e = s
+        while e + 1 < n:
+            m2, e2 = piece_terms(pieces[e + 1], a)
+            mom_c = [x + y for x, y in zip(mom, m2)]
+            en_c = en + e2
+            Lq = pieces[e + 1][1] - a
+            G = [[Fraction(Lq ** (j + k + 1), j + k + 1) for k in range(D + 1)] for j in range(D + 1)]
+            y = _solve_exact(G, mom_c)
+            resid = en_c - sum(mi * yi for mi, yi in zip(mom_c, y))
+            if resid <= (tol_q * A0) ** 2 * Lq:
+                mom, en, e = mom_c, en_c, e + 1
+            else:
+                break
+        out.append((a, pieces[e][1]))
+        s = e + 1
+    return out
+
+
+@pytest.mark.parametrize("seed,tol", [(13, 1e-2), (14, 1e-3), (17, 3e-3)])
+def test_merge_equals_exact_rational_greedy(setup, seed, tol):
+    """Every decision of the float64 greedy merge (extend while the projection's residual is
+    within the tolerance, over the whole ray) is the decision exact rational arithmetic takes, so
+    each merged interval is greedy-maximal: all its prefixes pass and adding the next exact piece
+    fails."""
     s = setup
-    o, v = _ray(14)
-    tol = 1e-3
-    hits, sk = field.ray_knots(o, v, -10.0, 10.0, s["xyz"], s["h"], s["val"], s["table"], s["q"], s["K"], s["D"], s["kind"])
-    pieces, _ = field.exact_pieces(sk)
+    o, v = _ray(seed)
+    f = field.ray_field(o, v, -10.0, 10.0, s["xyz"], s["h"], s["val"], s["table"], s["q"], s["K"], s["D"],
+                        s["kind"], tol)
+    assert f["margin"] > 1e-9, f["margin"]
+    got = [(n["a"], n["b"]) for n in f["nodes"]]
+    assert len(got) > 3 and len(got) < len(f["pieces"])
+    assert got == _exact_greedy(f["pieces"], tol, s["D"])
+
+
+def test_merge_of_one_polynomial_is_one_piece():
+    """Exact pieces that all carry one cubic (split at arbitrary integer points, coefficients by
+    the exact Taylor shift) merge into a single piece whose residual is zero and whose coefficients
+    are the cubic's, at any tolerance > 0; with tol = 0 nothing merges."""
+    D = 3
+    tau, sigma = 1e-4, 1e-12
+    base = [7 * 10 ** 9, -3 * 10 ** 7, 5 * 10 ** 4, -11]          # polynomial in x = t - 1000 (quanta)
+    cuts = [1000, 1013, 1040, 1041, 1100, 1177, 1300]
+
+    def shifted(x0):
+        return [sum(base[d] * math.comb(d, e) * (x0 - 1000) ** (d - e) for d in range(e, D + 1)) for e in range(D + 1)]
+
+    pieces = [(a, b, shifted(a), i) for i, (a, b) in enumerate(zip(cuts[:-1], cuts[1:]))]
+    nodes, M, _ = field.merge(pieces, 1e-6, tau, sigma, D)
+    assert len(nodes) == 1 and nodes[0]["a"] == 1000 and nodes[0]["b"] == 1300
+    assert nodes[0]["r"] <= 1e-20 * (sigma * base[0]) ** 2
+    L = 300
+    want = [sigma * base[d] * L ** d for d in range(D + 1)]
+    assert np.allclose(M.to_power(nodes[0]), want, rtol=1e-12, atol=1e-12 * abs(want[0]))
+    nodes0, _, _ = field.merge(pieces, 0.0, tau, sigma, D)
+    assert [(n["a"], n["b"]) for n in nodes0] == [(a, b) for a, b, _, _ in pieces]
+
+
+def test_check_merged_catches_planted_mistakes(setup):
+    """The validity checker accepts the oracle's own merge and flags each planted mistake: a
+    breakpoint off the exact knots, a gap, a piece that exceeds the tolerance, coefficients off
+    the projection by 3e-5 of the peak, a missing tail, merging with tol = 0."""
+    s = setup
+    D = s["D"]
     tau, sigma = s["q"]
-    M = field.Merger(s["D"], tau, sigma)
-    pk = field.peak(pieces, sigma)
-    chunk_of = {p[0]: p[3] // field.MERGE_CHUNK for p in pieces}
-    nodes, _ = field.merge(sk, pieces, tol, tau, sigma, s["D"])
-    by_start = {p[0]: p for p in pieces}
-    for A, B in zip(nodes[:-1], nodes[1:]):
-        if chunk_of[A["a"]] == chunk_of[B["a"]]:
-            nxt = by_start[B["a"]]
-            # greedy state of A: rebuild by merging A's pieces from the left
-            cur = None
-            for p in pieces:
-                if A["a"] <= p[0] < A["b"]:
-                    leaf = M.leaf(p[0], p[1], p[2])
-                    cur = leaf if cur is None else M.combine(cur, leaf)
-            cand = M.combine(cur, M.leaf(nxt[0], nxt[1], nxt[2]))
-            assert not M.passes(cand, tol, pk)
+    tol = 1e-3
+    o, v = _ray(13)
+    f = field.ray_field(o, v, -10.0, 10.0, s["xyz"], s["h"], s["val"], s["table"], s["q"], s["K"], D, s["kind"], tol)
+    pieces, M = f["pieces"], f["merger"]
+    good = [field.node_output_q(n, M) for n in f["nodes"]]
+    chk = field.check_merged(pieces, good, tol, tau, sigma, D)
+    assert chk["errors"] == [] and chk["n"] == len(good) and chk["max_resid_ratio"] <= 1.0
+    i = max(range(len(good) - 1), key=lambda k: good[k][1] - good[k][0])
+    a, b, c = good[i]
+    off = [list(x) for x in good]
+    off[i][1] = b - 1
+    off[i + 1][0] = b - 1
+    assert field.check_merged(pieces, [tuple(x) for x in off], tol, tau, sigma, D)["errors"]
+    gap = good[:i] + good[i + 1:]
+    assert field.check_merged(pieces, gap, tol, tau, sigma, D)["errors"]
+    # join every pair of neighbours: at least one union exceeds the tolerance
+    joined = []
+    for k in range(0, len(good) - 1, 2):
+        lo = [p for p in range(len(pieces)) if pieces[p][0] == good[k][0]][0]
+        hi = [p for p in range(len(pieces)) if pieces[p][1] == good[k + 1][1]][0]
+        nd = M.node(lo, hi)
+        joined.append(field.node_output_q(nd, M))
+    if len(good) % 2:
+        joined.append(good[-1])
+    assert any("exceeds" in e for e in field.check_merged(pieces, joined, tol, tau, sigma, D)["errors"])
+    pert = [list(x) for x in good]
+    pert[i][2] = np.array(pert[i][2], dtype=np.float64)
+    pert[i][2][0] += 3e-5 * f["peak"]
+    assert any("coefficients" in e for e in field.check_merged(pieces, [tuple(x) for x in pert], tol, tau, sigma, D)["errors"])
+    assert field.check_merged(pieces, good[:-1], tol, tau, sigma, D)["errors"]
+    assert field.check_merged(pieces, good, 0.0, tau, sigma, D)["errors"]
+    exact = [field.node_output_q(M.node(k, k), M) for k in range(len(pieces))]
+    assert field.check_merged(pieces, exact, 0.0, tau, sigma, D)["errors"] == []
 
 
 def test_field_close_to_sph_truth(setup):
