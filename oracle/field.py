@@ -210,11 +210,13 @@ def merge(pieces, tol, tau, sigma, D):
     return nodes, M, margin
 
 
-def check_merged(pieces, merged, tol, tau, sigma, D, coef_tol=1e-5, resid_slack=1e-9):
+def check_merged(pieces, merged, tol, tau, sigma, D, coef_tol=1e-5, resid_slack=1e-9, ends=None):
     """Validity of a merged field against the ray's exact pieces.
 
     merged: [(qa, qb, coef)] with qa, qb the piece ends in length quanta (integers) and coef the
-    power coefficients in u = (t - qa tau) / ((qb - qa) tau).  Checks that the breakpoints are exact
+    power coefficients in u = (t - qa tau) / ((qb - qa) tau), or, when ends = [(ta, tb)] is given
+    (world positions, one pair per merged piece, e.g. roundings of the exact ends), in
+    u = (t - ta) / (tb - ta) (a piece with ta = tb is the constant coef[0]).  Checks that the breakpoints are exact
     piece boundaries, that the merged pieces cover the exact pieces contiguously, that each merged
     piece's projection residual is within (tol * peak)^2 * length (up to a relative slack for the
     rounding of the two float64 evaluations), and that its coefficients equal that projection within
@@ -241,7 +243,7 @@ def check_merged(pieces, merged, tol, tau, sigma, D, coef_tol=1e-5, resid_slack=
         if int(qa) != int(qb_prev):
             errors.append(f"gap or overlap at {qa} / {qb_prev}")
     us = np.linspace(0.0, 1.0, 17)
-    for qa, qb, coef in merged:
+    for i, (qa, qb, coef) in enumerate(merged):
         qa, qb = int(qa), int(qb)
         if qa not in index_of_start or qb not in index_of_end or qb <= qa:
             errors.append(f"merged piece [{qa}, {qb}) not on exact piece boundaries")
@@ -258,7 +260,13 @@ def check_merged(pieces, merged, tol, tau, sigma, D, coef_tol=1e-5, resid_slack=
             if lo != hi and node["r"] > thr * (1.0 + resid_slack):
                 errors.append(f"merged piece [{qa}, {qb}) exceeds the tolerance (ratio {ratio})")
         ref = np.polyval(M.to_power(node)[::-1], us)
-        got = np.polyval(np.asarray(coef, dtype=np.float64)[::-1], us)
+        cf = np.asarray(coef, dtype=np.float64)
+        if ends is None:
+            got = np.polyval(cf[::-1], us)
+        else:
+            ta, tb = float(ends[i][0]), float(ends[i][1])
+            ts = (qa + us * (qb - qa)) * float(tau)
+            got = np.polyval(cf[::-1], (ts - ta) / (tb - ta)) if tb != ta else np.full_like(us, cf[0])
         err = float(np.max(np.abs(got - ref))) / pk if pk > 0 else float(np.max(np.abs(got - ref)))
         out["max_coef_err"] = max(out["max_coef_err"], err)
         if err > coef_tol:

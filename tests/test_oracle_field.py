@@ -308,6 +308,36 @@ def test_check_merged_catches_planted_mistakes(setup):
     assert field.check_merged(pieces, exact, 0.0, tau, sigma, D)["errors"] == []
 
 
+def test_check_merged_on_given_ends(setup):
+    """Coefficients given on other ends (float32 roundings of the exact ones): the same polynomial
+    re-expressed on those ends passes, the unchanged coefficients evaluated on shifted ends fail."""
+    s = setup
+    D = s["D"]
+    tau, sigma = s["q"]
+    tol = 1e-3
+    o, v = _ray(13)
+    f = field.ray_field(o, v, -10.0, 10.0, s["xyz"], s["h"], s["val"], s["table"], s["q"], s["K"], D, s["kind"], tol)
+    pieces, M = f["pieces"], f["merger"]
+    good = [field.node_output_q(n, M) for n in f["nodes"]]
+    # ends moved by 1 % of each piece: u = al + be u' with al = (ta' - ta) / L, be = (tb' - ta') / L
+    moved, recoef, ends = [], [], []
+    for qa, qb, c in good:
+        ta, tb = qa * tau, qb * tau
+        L = tb - ta
+        ta2, tb2 = ta + 0.01 * L, tb - 0.01 * L
+        al, be = (ta2 - ta) / L, (tb2 - ta2) / L
+        comp = np.polynomial.polynomial.polyval(np.polynomial.polynomial.Polynomial([al, be]),
+                                                np.asarray(c, dtype=np.float64))
+        recoef.append((qa, qb, comp.coef))
+        moved.append((qa, qb, c))
+        ends.append((ta2, tb2))
+    assert field.check_merged(pieces, recoef, tol, tau, sigma, D, ends=ends)["errors"] == []
+    assert any("coefficients" in e for e in field.check_merged(pieces, moved, tol, tau, sigma, D, ends=ends)["errors"])
+    exact_ends = [(qa * tau, qb * tau) for qa, qb, _ in good]
+    chk = field.check_merged(pieces, good, tol, tau, sigma, D, ends=exact_ends)
+    assert chk["errors"] == [] and chk["max_coef_err"] < 1e-9
+
+
 def test_field_close_to_sph_truth(setup):
     """The exact quantized field approximates the true SPH sum along the ray
     (relative L2 error of the order of E_{4,2} ~ 0.8 %, plus the nearest-entry error of a
