@@ -117,9 +117,11 @@ typedef struct {
 
 /* Output of approx_rays.  Merged piece i of ray r is index ray_offsets[r] + j:
  * F(t) = sum_d coef[i][d] * u^d with u = (t - t_start[i]) / (t_end[i] - t_start[i]),
- * valid on [t_start[i], t_end[i]]; the field is zero outside a ray's pieces.  u is defined by
- * the exact piece ends (integer knot positions times tau); t_start / t_end are their float32
- * roundings, so evaluating u from them adds at most |dF/dt| * ulp(t). */
+ * valid on [t_start[i], t_end[i]]; the field is zero outside a ray's pieces.  The pieces' exact
+ * ends are integer knot positions times tau; t_start / t_end hold their float32 roundings, and the
+ * coefficients are re-expressed about those stored ends (in float64, then rounded to float32), so
+ * u computed from t_start / t_end evaluates the merged piece itself.  A piece whose two float32
+ * ends coincide (shorter than their resolution) holds its start value in coef[i][0] and zeros. */
 typedef struct {
   int64_t capacity;      /* pieces allocated by the caller */
   int64_t* ray_offsets;  /* device [n + 1] */
@@ -225,6 +227,30 @@ sph_hoa_status sph_hoa_approx_rays_shared(const sph_hoa_index* idx, int32_t n_id
  */
 sph_hoa_status sph_hoa_render(sph_hoa_index idx, const sph_hoa_camera* cam, const sph_hoa_tf* tf,
                               float* rgba_out, void* stream);
+
+/*
+ * Fields along a camera's pixel rays, with the rays and the hit gathering of sph_hoa_render (the
+ * screen-tile binning of Sec. 2's first pass): out receives what sph_hoa_approx_rays gives for
+ * arbitrary rays (ray index = row * width + col; same flags, capacities and errors), and the merged
+ * pieces are those sph_hoa_render classifies and composites for that camera.  Synchronises `stream`.
+ */
+sph_hoa_status sph_hoa_approx_camera(sph_hoa_index idx, const sph_hoa_camera* cam, sph_hoa_field* out,
+                                     uint32_t flags, void* stream);
+
+/*
+ * First pass only (Sec. 2: every particle is assigned to all relevant viewing rays; Fig. 1: a
+ * particle is relevant to a ray when Lambda < q and its support interval overlaps [t_min, t_max]).
+ * sph_hoa_camera_hits gathers as sph_hoa_render does (screen tiles), sph_hoa_ray_hits as
+ * sph_hoa_approx_rays does (grid walk).  hit_offsets: device int64 [n + 1]; hit_ids: device int32
+ * [capacity], the particles' input indices; ray r's hits are hit_ids[hit_offsets[r] ..
+ * hit_offsets[r + 1]) in an unspecified order.  *n_pairs (host) receives the number of hits; when
+ * it exceeds capacity the call returns E_OUT_OF_MEMORY with *n_pairs set and hit_ids untouched.
+ * Synchronises `stream`.
+ */
+sph_hoa_status sph_hoa_camera_hits(sph_hoa_index idx, const sph_hoa_camera* cam, int64_t* hit_offsets,
+                                   int32_t* hit_ids, int64_t capacity, int64_t* n_pairs, void* stream);
+sph_hoa_status sph_hoa_ray_hits(sph_hoa_index idx, const sph_hoa_rays* rays, int64_t* hit_offsets,
+                                int32_t* hit_ids, int64_t capacity, int64_t* n_pairs, void* stream);
 
 /*
  * Render a batch of cameras (each with its own size, frame and t range) with one launch chain:

@@ -101,7 +101,8 @@ class Stats(ctypes.Structure):
                 ("timed_calls", ctypes.c_int64), ("ms_gather", ctypes.c_double), ("ms_field", ctypes.c_double)]
 
 
-EXPORTS = ["sph_hoa_build_index", "sph_hoa_approx_rays", "sph_hoa_approx_rays_shared", "sph_hoa_render", "sph_hoa_render_batch",
+EXPORTS = ["sph_hoa_build_index", "sph_hoa_approx_rays", "sph_hoa_approx_rays_shared", "sph_hoa_approx_camera",
+           "sph_hoa_camera_hits", "sph_hoa_ray_hits", "sph_hoa_render", "sph_hoa_render_batch",
            "sph_hoa_server_create", "sph_hoa_server_add_index", "sph_hoa_server_submit", "sph_hoa_server_wait",
            "sph_hoa_server_get_stats", "sph_hoa_server_destroy", "sph_hoa_server_set_admission",
            "sph_hoa_server_cancel", "sph_hoa_server_pause", "sph_hoa_accumulate_bits", "sph_hoa_float_rays",
@@ -127,6 +128,9 @@ def lib():
     L.sph_hoa_approx_rays.argtypes = [vp, ctypes.POINTER(Rays), ctypes.POINTER(Field), u32, vp]
     L.sph_hoa_approx_rays_shared.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(Rays), ctypes.POINTER(Field),
                                              u32, vp]
+    L.sph_hoa_approx_camera.argtypes = [vp, ctypes.POINTER(Camera), ctypes.POINTER(Field), u32, vp]
+    L.sph_hoa_camera_hits.argtypes = [vp, ctypes.POINTER(Camera), vp, vp, i64, ctypes.POINTER(i64), vp]
+    L.sph_hoa_ray_hits.argtypes = [vp, ctypes.POINTER(Rays), vp, vp, i64, ctypes.POINTER(i64), vp]
     L.sph_hoa_render.argtypes = [vp, ctypes.POINTER(Camera), ctypes.POINTER(TF), vp, vp]
     L.sph_hoa_render_batch.argtypes = [vp, ctypes.POINTER(Camera), i32, ctypes.POINTER(TF), vp, vp]
     L.sph_hoa_server_create.argtypes = [i64, i64, ctypes.POINTER(vp)]
@@ -435,6 +439,63 @@ def make_camera(cam: dict) -> Camera:
     c.width, c.height = int(cam["width"]), int(cam["height"])
     c.t_min, c.t_max = float(cam["t_min"]), float(cam["t_max"])
     return c
+
+
+def sph_hoa_approx_camera(index, camera: dict, capacity=None, exact=False, exact_capacity=None):
+    """Fields along a camera's pixel rays with the render's gathering (sph_hoa_approx_camera);
+    returns the dict of sph_hoa_approx_rays (capacity: as there)."""
+    c = make_camera(camera)
+    n = c.width * c.height
+    D = index.D
+    cap = capacity if capacity is not None else max(1024, 64 * n)
+    ecap = exact_capacity if exact_capacity is not None else max(1024, 64 * n)
+    for attempt in range(2):
+        f, t = _alloc_field(n, D, cap, ecap, exact)
+        st = lib().sph_hoa_approx_camera(index.handle, ctypes.byref(c), ctypes.byref(f), FLAG_EXACT if exact else 0,
+                                         _stream())
+        if st == 2 and attempt == 0 and capacity is None:
+            cap = max(cap, int(f.n_pieces) + 1)
+            ecap = max(ecap, int(f.n_exact_pieces) + 1, int(f.n_knots) + 1)
+            continue
+        _check(st)
+        break
+    return _field_result(f, t, n, D, exact)
+
+
+def _hits(call, n, capacity):
+    import torch
+
+    offs = torch.empty(n + 1, dtype=torch.int64, device="cuda")
+    cap = capacity if capacity is not None else max(1024, 256 * n)
+    for attempt in range(2):
+        ids = torch.empty(max(cap, 1), dtype=torch.int32, device="cuda")
+        npairs = ctypes.c_int64(0)
+        st = call(_ptr(offs), _ptr(ids), cap, ctypes.byref(npairs))
+        if st == 2 and attempt == 0 and capacity is None and npairs.value > cap:
+            cap = int(npairs.value)
+            continue
+        _check(st)
+        break
+    return offs, ids[: npairs.value]
+
+
+def sph_hoa_camera_hits(index, camera: dict, capacity=None):
+    """Hit lists of a camera's pixel rays as the render gathers them (sph_hoa_camera_hits): returns
+    (offsets [n + 1] int64, ids [pairs] int32 input indices), device tensors; each ray's ids are in
+    an unspecified order."""
+    c = make_camera(camera)
+    return _hits(lambda o, i, cap, npr: lib().sph_hoa_camera_hits(index.handle, ctypes.byref(c), o, i, cap, npr,
+                                                                  _stream()), c.width * c.height, capacity)
+
+
+def sph_hoa_ray_hits(index, origin, direction, t_min, t_max, capacity=None):
+    """Hit lists of arbitrary rays as sph_hoa_approx_rays gathers them (sph_hoa_ray_hits)."""
+    o = _dev_f32(origin).reshape(-1, 3)
+    d = _dev_f32(direction).reshape(-1, 3)
+    n = o.shape[0]
+    r = Rays(n, _ptr(o).value, _ptr(d).value, t_min, t_max)
+    return _hits(lambda op, i, cap, npr: lib().sph_hoa_ray_hits(index.handle, ctypes.byref(r), op, i, cap, npr,
+                                                                _stream()), n, capacity)
 
 
 def sph_hoa_render(index, camera: dict, tf_rgba, v_min, v_max, step, out=None):

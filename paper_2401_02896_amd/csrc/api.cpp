@@ -232,6 +232,24 @@ sph_hoa_status sph_hoa_index_free(sph_hoa_index idx) {
 
 namespace {
 
+// Output arrays of a field call for n rays; returns whether exact mode is on.
+bool check_field_out(const sph::Index& ix, const sph_hoa_field* out, int64_t n, uint32_t flags) {
+  require(out->capacity >= 0, "capacity must be >= 0");
+  if (n > 0) {
+    require(out->ray_offsets && out->ray_peak, "NULL output arrays");
+    require(out->capacity == 0 || (out->t_start && out->t_end && out->coef), "NULL piece arrays");
+  }
+  const bool exact = (flags & SPH_HOA_FLAG_EXACT) != 0;
+  if (exact && ix.n >= (int64_t(1) << 29))
+    throw sph::Error(SPH_HOA_E_UNSUPPORTED, "exact mode needs fewer than 2^29 particles");
+  if (exact && n > 0) {
+    require(out->exact_offsets && out->knot_offsets, "exact mode needs offset arrays");
+    require(out->exact_capacity == 0 || (out->exact_t && out->exact_end && out->exact_coef), "exact arrays");
+    require(out->knot_capacity == 0 || (out->knot_t && out->knot_pid && out->knot_kidx), "knot arrays");
+  }
+  return exact;
+}
+
 // One field of sph_hoa_approx_rays; gathered: the index whose call on the same rays just gathered
 // the hits (shared gathering) or nullptr.
 void approx_rays_one(sph_hoa_index idx, const sph_hoa_rays* rays, sph_hoa_field* out, uint32_t flags, void* stream,
@@ -241,20 +259,8 @@ void approx_rays_one(sph_hoa_index idx, const sph_hoa_rays* rays, sph_hoa_field*
   require(rays->n >= 0 && rays->n < (int64_t(1) << 31), "ray count must be in 0..2^31-1");
   require(std::isfinite(rays->t_min) && std::isfinite(rays->t_max) && rays->t_min < rays->t_max,
           "need finite t_min < t_max");
-  require(out->capacity >= 0, "capacity must be >= 0");
-  if (rays->n > 0) {
-    require(rays->origin && rays->dir, "NULL ray arrays");
-    require(out->ray_offsets && out->ray_peak, "NULL output arrays");
-    require(out->capacity == 0 || (out->t_start && out->t_end && out->coef), "NULL piece arrays");
-  }
-  const bool exact = (flags & SPH_HOA_FLAG_EXACT) != 0;
-  if (exact && idx->ix.n >= (int64_t(1) << 29))
-    throw sph::Error(SPH_HOA_E_UNSUPPORTED, "exact mode needs fewer than 2^29 particles");
-  if (exact && rays->n > 0) {
-    require(out->exact_offsets && out->knot_offsets, "exact mode needs offset arrays");
-    require(out->exact_capacity == 0 || (out->exact_t && out->exact_end && out->exact_coef), "exact arrays");
-    require(out->knot_capacity == 0 || (out->knot_t && out->knot_pid && out->knot_kidx), "knot arrays");
-  }
+  if (rays->n > 0) require(rays->origin && rays->dir, "NULL ray arrays");
+  const bool exact = check_field_out(idx->ix, out, rays->n, flags);
   sph::Index& ix = idx->ix;
   const double span = std::max(std::fabs((double)rays->t_min), std::fabs((double)rays->t_max)) +
                       ix.grid.lv[ix.grid.n_levels - 1].c;
@@ -351,8 +357,9 @@ void check_camera(const sph::Index& ix, const sph_hoa_camera* cam, const sph_hoa
   const double cx = fy * cam->up[2] - fz * cam->up[1], cy = fz * cam->up[0] - fx * cam->up[2],
                cz = fx * cam->up[1] - fy * cam->up[0];
   require(fx * fx + fy * fy + fz * fz > 0 && cx * cx + cy * cy + cz * cz > 0, "degenerate camera frame");
-  require(((double)cam->t_max - (double)cam->t_min) / (double)tf->step < 1073741824.0,
-          "step too small: more than 2^30 samples per ray");
+  if (tf)
+    require(((double)cam->t_max - (double)cam->t_min) / (double)tf->step < 1073741824.0,
+            "step too small: more than 2^30 samples per ray");
   const double span = std::max(std::fabs((double)cam->t_min), std::fabs((double)cam->t_max)) +
                       ix.grid.lv[ix.grid.n_levels - 1].c;
   if (!(span / ix.tau < 2.1e9))
@@ -379,6 +386,81 @@ sph_hoa_status sph_hoa_render(sph_hoa_index idx, const sph_hoa_camera* cam, cons
     sph::FieldOut fo{nullptr, rgba_out, tf, false};
     sph::run_rays(ix, (int64_t)cam->width * cam->height, true, cam, nullptr, fo, st);
   });
+}
+
+sph_hoa_status sph_hoa_approx_camera(sph_hoa_index idx, const sph_hoa_camera* cam, sph_hoa_field* out, uint32_t flags,
+                                     void* stream) {
+  return guarded([&]() {
+    require(idx && cam && out, "NULL argument");
+    require(flags == 0 || flags == SPH_HOA_FLAG_EXACT, "unknown flags");
+    sph::Index& ix = idx->ix;
+    check_camera(ix, cam, nullptr);
+    const int64_t n = (int64_t)cam->width * cam->height;
+    const bool exact = check_field_out(ix, out, n, flags);
+    hipStream_t st = (hipStream_t)stream;
+    ix.last_stream = st;
+    sph::FieldOut fo{out, nullptr, nullptr, exact};
+    sph::run_rays(ix, n, true, cam, nullptr, fo, st);
+  });
+}
+
+namespace {
+void check_hits_out(int64_t n, const int64_t* offsets, const int32_t* ids, int64_t capacity, const int64_t* n_pairs) {
+  require(n_pairs != nullptr, "NULL n_pairs");
+  require(capacity >= 0, "capacity must be >= 0");
+  require(n == 0 || offsets != nullptr, "NULL hit_offsets");
+  require(capacity == 0 || ids != nullptr, "NULL hit_ids");
+}
+}  // namespace
+
+sph_hoa_status sph_hoa_camera_hits(sph_hoa_index idx, const sph_hoa_camera* cam, int64_t* hit_offsets,
+                                   int32_t* hit_ids, int64_t capacity, int64_t* n_pairs, void* stream) {
+  if (n_pairs) *n_pairs = 0;
+  sph::HitsOut ho{hit_offsets, hit_ids, capacity, 0};
+  const sph_hoa_status s = guarded([&]() {
+    require(idx && cam, "NULL argument");
+    sph::Index& ix = idx->ix;
+    check_camera(ix, cam, nullptr);
+    const int64_t n = (int64_t)cam->width * cam->height;
+    check_hits_out(n, hit_offsets, hit_ids, capacity, n_pairs);
+    hipStream_t st = (hipStream_t)stream;
+    ix.last_stream = st;
+    sph::FieldOut fo{nullptr, nullptr, nullptr, false};
+    fo.hits = &ho;
+    sph::run_rays(ix, n, true, cam, nullptr, fo, st);
+  });
+  if (n_pairs) *n_pairs = ho.n_pairs;
+  return s;
+}
+
+sph_hoa_status sph_hoa_ray_hits(sph_hoa_index idx, const sph_hoa_rays* rays, int64_t* hit_offsets, int32_t* hit_ids,
+                                int64_t capacity, int64_t* n_pairs, void* stream) {
+  if (n_pairs) *n_pairs = 0;
+  sph::HitsOut ho{hit_offsets, hit_ids, capacity, 0};
+  const sph_hoa_status s = guarded([&]() {
+    require(idx && rays, "NULL argument");
+    require(rays->n >= 0 && rays->n < (int64_t(1) << 31), "ray count must be in 0..2^31-1");
+    require(std::isfinite(rays->t_min) && std::isfinite(rays->t_max) && rays->t_min < rays->t_max,
+            "need finite t_min < t_max");
+    if (rays->n > 0) require(rays->origin && rays->dir, "NULL ray arrays");
+    check_hits_out(rays->n, hit_offsets, hit_ids, capacity, n_pairs);
+    sph::Index& ix = idx->ix;
+    hipStream_t st = (hipStream_t)stream;
+    ix.last_stream = st;
+    if (rays->n == 0) {
+      if (hit_offsets) {
+        const int64_t z = 0;
+        sph::hip_check(hipMemcpyAsync(hit_offsets, &z, 8, hipMemcpyHostToDevice, st), "copy");
+        sph::hip_check(hipStreamSynchronize(st), "sync");
+      }
+      return;
+    }
+    sph::FieldOut fo{nullptr, nullptr, nullptr, false};
+    fo.hits = &ho;
+    sph::run_rays(ix, rays->n, false, nullptr, rays, fo, st);
+  });
+  if (n_pairs) *n_pairs = ho.n_pairs;
+  return s;
 }
 
 sph_hoa_status sph_hoa_render_batch(sph_hoa_index idx, const sph_hoa_camera* cams, int32_t n_cams,

@@ -207,6 +207,14 @@ void build_index_device(Index& ix, const float* xyz, const float* h, const float
 void get_grid_device(Index& ix, uint64_t* morton, int32_t* level, int32_t* order, hipStream_t st);
 
 // per-frame (raycast.hip)
+// Hit lists of the first pass, exported as input indices (sph_hoa_camera_hits / sph_hoa_ray_hits).
+struct HitsOut {
+  int64_t* offsets;  // device [n + 1]
+  int32_t* ids;      // device [capacity]
+  int64_t capacity;
+  int64_t n_pairs;   // out
+};
+
 struct FieldOut {
   sph_hoa_field* field;  // approx mode (null for render)
   float* rgba;           // render mode
@@ -214,6 +222,7 @@ struct FieldOut {
   bool exact;
   sph_hoa_float_field* flt = nullptr;  // float accumulation variant (floatpath.hip)
   int n_reinit = 0;
+  HitsOut* hits = nullptr;  // stop after the gathering and export the hit lists
 };
 
 // float accumulation variant (floatpath.hip)

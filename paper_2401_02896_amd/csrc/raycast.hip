@@ -1252,13 +1252,46 @@ __device__ void process_ray(const FieldArgs& A, Shared<D>& sh, const RayStore& S
       for (int32_t q = S.chead[c]; q < S.ccnt[c]; ++q) {
         const Node<D>& nd = nodes[c * kChunk + q];
         if (pos < A.out_cap) {
-          A.st_t0[pos] = (float)((double)nd.a * tau);
-          A.st_t1[pos] = (float)((double)nd.b * tau);
+          // The piece is delivered on its float32 ends fa, fb: the projection, a polynomial in
+          // u = (t - ta) / (tb - ta) over the exact ends, is re-expressed in u' = (t - fa) / (fb - fa)
+          // by composing it with u = al + be u' (exact in real arithmetic, float64 here), so that a
+          // caller evaluating on the stored ends gets the projection itself.
+          const double ta = (double)nd.a * tau, tb = (double)nd.b * tau;
+          const float fa = (float)ta, fb = (float)tb;
+          const double len = (double)((int64_t)nd.b - (int64_t)nd.a) * tau;
+          double cu[D + 1];
+#pragma unroll
           for (int d = 0; d <= D; ++d) {
             double s = 0.0;
+#pragma unroll
             for (int j = 0; j <= D; ++j) s += nd.g[j] * A.mt.leg2pow[j][d];
-            A.st_coef[pos * (D + 1) + d] = (float)s;
+            cu[d] = s;
           }
+          const double al = ((double)fa - ta) / len;
+          const double be = ((double)fb - (double)fa) / len;
+          double rc[D + 1];
+#pragma unroll
+          for (int d = 0; d <= D; ++d) rc[d] = 0.0;
+          if (fb > fa) {
+            // Horner composition: rc = (...(c_D (al + be x) + c_{D-1}) (al + be x) + ...) + c_0
+            rc[0] = cu[D];
+#pragma unroll
+            for (int d = D - 1; d >= 0; --d) {
+#pragma unroll
+              for (int k = D - d; k >= 1; --k) rc[k] = rc[k] * al + rc[k - 1] * be;
+              rc[0] = rc[0] * al + cu[d];
+            }
+          } else {
+            // float32 ends coincide (a piece shorter than their resolution): its value at the start
+            double s = cu[D];
+#pragma unroll
+            for (int d = D - 1; d >= 0; --d) s = s * al + cu[d];
+            rc[0] = s;
+          }
+          A.st_t0[pos] = fa;
+          A.st_t1[pos] = fb;
+#pragma unroll
+          for (int d = 0; d <= D; ++d) A.st_coef[pos * (D + 1) + d] = (float)rc[d];
         }
         ++pos;
       }
@@ -1494,6 +1527,16 @@ __global__ void k_copy_exact(const int64_t* ray_ex, const int64_t* final_off, in
 __global__ void k_scale_i64(const int64_t* a, int64_t* b, int64_t n, int64_t f) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     b[i] = a[i] * f;
+}
+
+// Hit lists as input indices: ray r's hits from its compact list (hit_slots = 0) or its slots.
+__global__ void k_export_hits(const int64_t* hit_off, const uint32_t* hits, int64_t hit_slots, int64_t n,
+                              const int32_t* orig, int32_t* ids) {
+  for (int64_t r = blockIdx.x; r < n; r += gridDim.x) {
+    const int64_t b = hit_off[r], e = hit_off[r + 1];
+    const uint32_t* src = hit_slots ? hits + r * hit_slots : hits + b;
+    for (int64_t i = threadIdx.x; i < e - b; i += blockDim.x) ids[b + i] = orig[src[i]];
+  }
 }
 
 __global__ void k_set_last(int64_t* off, const int64_t* cnt, int64_t n) {
@@ -1934,6 +1977,18 @@ void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam,
   }
   if (ix.timing) hip_check(hipEventRecord(ix.ev[3], st), "event");
   hip_check(hipGetLastError(), "gather launch");
+  if (out.hits) {
+    HitsOut* ho = out.hits;
+    ho->n_pairs = total_pairs;
+    if (total_pairs > ho->capacity) throw Error(SPH_HOA_E_OUT_OF_MEMORY, "hit capacity too small");
+    hip_check(hipMemcpyAsync(ho->offsets, hit_off, sizeof(int64_t) * (n_rays + 1), hipMemcpyDeviceToDevice, st),
+              "copy");
+    k_export_hits<<<(unsigned)std::min<int64_t>(n_rays, 1 << 20), 64, 0, st>>>(
+        hit_off, hit_lists, hit_slots, n_rays, ix.orig.as<int32_t>(), ho->ids);
+    hip_check(hipGetLastError(), "export launch");
+    hip_check(hipStreamSynchronize(st), "sync");
+    return;
+  }
   if (out.flt) {
     // float accumulation variant: same hits, its own sweep
     sph_hoa_float_field* ff = out.flt;

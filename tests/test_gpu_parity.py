@@ -3,11 +3,12 @@
 Bars (each derived where it is asserted): grid keys, hit sets, knot order, quantized
 positions and exact-piece boundaries bit-exact; exact-piece values and the
 ray peak within 1e-9 of the peak (1e-6 for D >= 4: the projection coefficients
-are computed independently on both sides); merged FP32 field within 1e-5 of
-the ray peak;
-pixels within 1e-4.  Merge decisions closer than 1e-6 (relative) to their
-threshold may legitimately differ; such rays are checked by the invariants of
-the merge instead of equality.
+are computed independently on both sides); merged float32 field, evaluated on the
+library's own float32 piece ends, within 1e-5 of the ray peak of the L2
+projection on each merged piece, with every merged piece validated by the
+oracle's checker (breakpoints on exact knots, contiguous cover, residual within
+the tolerance); pixels within 1e-4 of the oracle's compositing of those
+projections.  No ray or pixel is exempt.
 """
 import math
 import os
@@ -32,69 +33,23 @@ TINY_SAMPLE = np.unique(np.concatenate([np.arange(0, 130), np.arange(2000, 2070)
                                         RNG.integers(0, 4096, 40)]))
 
 
-def _check_ray(sc, out, r, f, coef_tol=1e-8, field_tol=1e-5, vtol=None):
-    """Compare ray r of an exact-mode approx_rays result with the oracle's ray field f
-    (vtol: bar of the exact-piece values relative to the ray peak; default by degree)."""
-    D = sc.D
-    ko = out["knot_offsets"].cpu().numpy()
-    kt = out["knot_t"][ko[r]:ko[r + 1]].cpu().numpy()
-    kp = out["knot_pid"][ko[r]:ko[r + 1]].cpu().numpy()
-    kk = out["knot_kidx"][ko[r]:ko[r + 1]].cpu().numpy()
-    ref = f["knots"]
-    assert len(kt) == len(ref), (r, len(kt), len(ref))
-    assert list(zip(kt.tolist(), kp.tolist(), kk.tolist())) == [(t, p, k) for (t, p, k, _) in ref]
-    eo = out["exact_offsets"].cpu().numpy()
-    et = out["exact_t"][eo[r]:eo[r + 1]].cpu().numpy()
-    ee = out["exact_end"][eo[r]:eo[r + 1]].cpu().numpy()
-    ec = out["exact_coef"][eo[r]:eo[r + 1]].cpu().numpy()
-    pcs = f["pieces"]
-    assert et.tolist() == [p[0] for p in pcs] and ee.tolist() == [p[1] for p in pcs]
-    if vtol is None:
-        vtol = 1e-9 if D <= 3 else 1e-6
-    if pcs:
-        # integer coefficients: the jumps come from independently computed projections, whose
-        # conditioning grows with D, so each order is compared relative to its largest value on
-        # the ray; the piece values they encode must agree to 1e-9 of the ray's peak for D <= 3.
-        # For D >= 4 the Gram system of Sec. 3.1 is ill-conditioned enough that the two FP64
-        # solves differ by ~1e-9 per table row, and with signed amplitudes those per-particle
-        # errors do not cancel as the values do (~100x); the bar there is 1e-6 of the peak, ten
-        # times inside the 1e-5 bar of the merged field below
-        oc = np.array([[float(x) for x in p[2]] for p in pcs])
-        scale = np.maximum(np.abs(oc).max(axis=0), 1.0)
-        assert np.all(np.abs(ec.astype(np.float64) - oc) <= coef_tol * 100 * scale + 1.0), r
-        L = (ee - et).astype(np.float64)
-        for x in (0.0, 0.5, 1.0):
-            xs = x * L
-            vg = sum(ec[:, d].astype(np.float64) * xs ** d for d in range(D + 1))
-            vo = sum(oc[:, d] * xs ** d for d in range(D + 1))
-            assert np.max(np.abs(vg - vo)) * sc.sigma <= vtol * max(f["peak"], 1e-300) + 4 * sc.sigma, r
-    pk = float(out["ray_peak"][r].cpu())
-    # the peak is a float32 of the largest piece value: its rounding plus the value bar
-    assert abs(pk - f["peak"]) <= (vtol + 6e-8) * f["peak"], (r, pk, f["peak"])
-    # merged field
-    t0, t1, cf = H.field_of_ray(out, r, D)
-    onodes = [field.node_output(n, f["merger"]) for n in f["nodes"]]
-    if not onodes:
-        assert len(t0) == 0
-        return True
-    same = len(onodes) == len(t0) and all(np.float32(a) == x and np.float32(b) == y
-                                          for (a, b, _), x, y in zip(onodes, t0, t1))
-    if f["margin"] > 1e-6:
-        assert same, (r, len(onodes), len(t0), f["margin"])
-    if same:
-        ts = np.concatenate([np.linspace(a, b, 9, endpoint=False)[1:] for (a, b, _) in onodes])
-        ref_v = H.eval_pieces(np.array([a for a, _, _ in onodes]), np.array([b for _, b, _ in onodes]),
-                              np.array([c for _, _, c in onodes]), ts)
-        # the coefficients refer to the exact piece ends (quantized positions times tau), of which
-        # t_start / t_end are the float32 roundings checked above; evaluating on the rounded ends
-        # would add slope * ulp(t), which dominates for small particles
-        got_v = H.eval_pieces(np.array([a for a, _, _ in onodes]), np.array([b for _, b, _ in onodes]), cf, ts)
-        assert np.max(np.abs(got_v - ref_v)) <= field_tol * f["peak"], (r, np.max(np.abs(got_v - ref_v)) / f["peak"])
-    else:
-        # partition invariants only
-        assert t0[0] == np.float32(onodes[0][0]) and t1[-1] == np.float32(onodes[-1][1])
-        assert np.all(t1[:-1] == t0[1:])
-    return same
+def _check_ray(sc, out, r, f, coef_tol=1e-8, field_tol=1e-5, vtol=None, hits=None):
+    """Compare ray r of an exact-mode approx_rays result (device tensors, or host_out of it) with
+    the oracle's ray field f (bars: tests/gpu_helpers.compare_ray)."""
+    h = out if isinstance(out.get("t_start"), np.ndarray) else H.host_out(out)
+    g = H.ray_data(h, r)
+    if hits is not None:
+        g["hits"] = hits
+    errs, _ = H.compare_ray(sc, f, g, coef_tol=coef_tol, field_tol=field_tol, vtol=vtol)
+    assert not errs, (r, errs)
+    return True
+
+
+def _report(name, s):
+    print(f"{name}: pieces library {s['pieces_library']} vs plain greedy {s['pieces_plain_greedy']}, "
+          f"max coefficient error {s['max_coef_err']:.2e} of the peak, max pixel diff {s['max_pixel_diff']:.2e}",
+          flush=True)
+    assert not s["bad"], list(s["bad"].items())[:5]
 
 
 def _approx(sc, o, v, t_min, t_max, exact=True):
@@ -136,37 +91,49 @@ def test_lut_projection_matches_oracle():
         assert np.max(np.abs(shat[i] - ref)) <= 1e-9 * scale, i
 
 
-def test_tiny_exact_and_merged_fields():
-    """Plain method, tiny scene (4,096 particles, 64 x 64 orthographic rays, D = 2, cubic)."""
+def test_tiny_all_rays_fields_and_hits():
+    """Plain method, tiny scene (4,096 particles, 64 x 64 orthographic rays, D = 2, cubic): every
+    ray's hit set (grid walk), knot list, exact pieces, peak and merged field against the oracle."""
     sc = H.tiny_scene()
     o, v = synth.ortho_rays()
     out = _approx(sc, o, v, 0.0, 1.4)
     assert out["n_pairs"] > 200000
-    same = 0
-    for r in TINY_SAMPLE:
-        f = sc.oracle_ray(o[r], v[r], 0.0, 1.4)
-        same += _check_ray(sc, out, int(r), f)
-    assert same >= 0.97 * len(TINY_SAMPLE)
+    h = H.host_out(out)
+    offs, ids = L.sph_hoa_ray_hits(sc.index(), o, v, 0.0, 1.4)
+    hits = H.hit_lists(offs, ids, range(len(o)))
+    tasks = []
+    for r in range(len(o)):
+        g = H.ray_data(h, r)
+        g["hits"] = hits[r]
+        tasks.append((r, o[r], v[r], 0.0, 1.4, g, {}))
+    _report("tiny fields", H.summarize(H.compare_rays_parallel(sc, tasks)))
 
 
-def test_tiny_render_pixels():
+def test_tiny_render_all_pixels_and_hits():
+    """Every pixel of the tiny camera's render against the oracle's compositing of the projections
+    on the library's merged partition (read back with sph_hoa_approx_camera, which shares the
+    render's gathering and merge, and validated by the oracle's checker), and every pixel ray's
+    hit set as the render gathers it (screen tiles)."""
     sc = H.tiny_scene()
     cam = synth.tiny_camera()
     tf = synth.transfer_function()
     vmax = 4.0e4
     step = 1.4 / 256
     img = L.sph_hoa_render(sc.index(), cam, tf, 0.0, vmax, step).cpu().numpy().reshape(-1, 4)
-    oo, vv = geometry.camera_rays(cam)
-    checked = 0
-    for r in TINY_SAMPLE[::2]:
-        f = sc.oracle_ray(oo[r], vv[r], 0.0, 1.4)
-        if f["margin"] <= 1e-6:
-            continue
-        px = H.oracle_pixel(sc, f, 0.0, 1.4, tf.astype(np.float64), 0.0, vmax, step)
-        assert np.max(np.abs(img[r] - px)) <= 1e-4, (r, img[r], px)
-        checked += 1
-    assert checked > 0.9 * len(TINY_SAMPLE[::2])
     assert np.all(img[:, 3] >= 0) and np.all(img[:, 3] <= 1)
+    fo = L.sph_hoa_approx_camera(sc.index(), cam, exact=True)
+    h = H.host_out(fo)
+    offs, ids = L.sph_hoa_camera_hits(sc.index(), cam)
+    n = cam["width"] * cam["height"]
+    hits = H.hit_lists(offs, ids, range(n))
+    oo, vv = geometry.camera_rays(cam)
+    tf64 = tf.astype(np.float64)
+    tasks = []
+    for r in range(n):
+        g = H.ray_data(h, r)
+        g["hits"] = hits[r]
+        tasks.append((r, oo[r], vv[r], 0.0, 1.4, g, {"pixel": (img[r], 0.0, 1.4, tf64, 0.0, vmax, step)}))
+    _report("tiny render", H.summarize(H.compare_rays_parallel(sc, tasks)))
 
 
 @pytest.mark.parametrize("kind,K,D,n_lut", [("cubic", 3, 3, 256), ("wendland", 2, 2, 256), ("cubic", 1, 2, 128),
@@ -190,11 +157,12 @@ def test_configurations(kind, K, D, n_lut):
     # the kernels themselves); signed amplitudes add per-particle errors while the values cancel
     # (up to ~100x), hence a value bar of 1e-7 of the ray peak for these kernels
     vtol = 1e-7 if kind.endswith("_grad") else None
-    same = 0
+    h = H.host_out(out)
+    offs, ids = L.sph_hoa_ray_hits(sc.index(), o, v, -0.5, 3.5)
+    hits = H.hit_lists(offs, ids, range(37))
     for r in range(37):
         f = sc.oracle_ray(o[r], v[r], -0.5, 3.5)
-        same += _check_ray(sc, out, r, f, vtol=vtol)
-    assert same >= 35
+        _check_ray(sc, h, r, f, vtol=vtol, hits=hits[r])
 
 
 def test_no_merge_outputs_exact_pieces():
@@ -203,9 +171,10 @@ def test_no_merge_outputs_exact_pieces():
     o, v = synth.random_rays(3, 21)
     out = _approx(sc, o, v, -0.5, 3.5)
     assert out["n_pieces"] == out["n_exact_pieces"]
+    h = H.host_out(out)
     for r in range(21):
         f = sc.oracle_ray(o[r], v[r], -0.5, 3.5, tol=0.0)
-        assert _check_ray(sc, out, r, f)
+        assert _check_ray(sc, h, r, f)
 
 
 def test_device_memory_path_is_identical():
@@ -348,30 +317,60 @@ def test_argument_errors():
     assert e.value.status == 2
 
 
-def test_full_size_plain_config_sampled():
-    """Plain GPU path at full size (1M clustered particles, Wendland C2, D = 3, 512 x 512
-    perspective): the rendered frame in the benchmark's launch configuration, checked on
-    sampled pixels and on the exact/merged fields of sampled rays."""
+@pytest.fixture(scope="module")
+def plain():
+    """Plain GPU path at full size: 1M clustered particles, Wendland C2, K = 4, D = 3, tol 1e-3."""
     xyz, h, val = synth.clustered_particles()
-    sc = H.Scene("wendland", 4, 3, 4096, xyz, h, val, 1e-3)
+    return H.Scene("wendland", 4, 3, 4096, xyz, h, val, 1e-3)
+
+
+def _plain_sample(n_rays, k=2621, seed=2621):
+    """The seeded 1 % ray subsample of the plain frame."""
+    return np.sort(np.random.default_rng(seed).choice(n_rays, size=k, replace=False))
+
+
+def test_full_size_hit_sets(plain):
+    """The render's hit sets of the seeded 1 % subsample (2,621 rays) of the 512 x 512 plain frame
+    equal the oracle's brute-force sets (every particle tested) bit for bit."""
+    sc = plain
+    cam = synth.plain_camera()
+    offs, ids = L.sph_hoa_camera_hits(sc.index(), cam)
+    assert int(offs[-1]) > 1.5e8
+    oo, vv = geometry.camera_rays(cam)
+    sample = _plain_sample(len(oo))
+    hits = H.hit_lists(offs, ids, sample)
+    res = H.compare_hits_parallel(sc, [(int(r), oo[r], vv[r], 1.0, 3.0, hits[int(r)]) for r in sample])
+    bad = [r for r, (same, _) in res.items() if not same]
+    print(f"full-size hit sets: {len(res)} rays, {sum(n for _, n in res.values())} hits, {len(bad)} differ",
+          flush=True)
+    assert not bad, bad[:10]
+
+
+def test_full_size_plain_config_sampled(plain):
+    """The rendered frame in the benchmark's launch configuration (512 x 512 perspective): 256 rays
+    of the seeded subsample - merged fields (the render's partition, sph_hoa_approx_camera) valid
+    with coefficients on the library's float32 ends within 1e-5 of the peak, pixels within 1e-4
+    of the oracle's compositing on that partition, hit sets bit-exact."""
+    sc = plain
     cam = synth.plain_camera()
     tf = synth.transfer_function()
     vmax, step = 300.0, 2.0 / 512
     img = L.sph_hoa_render(sc.index(), cam, tf, 0.0, vmax, step).cpu().numpy().reshape(-1, 4)
     st = sc.index().stats()
     assert st["n_pairs"] > 1.5e8
+    fo = L.sph_hoa_approx_camera(sc.index(), cam)
+    h = H.host_out(fo)
+    del fo
     oo, vv = geometry.camera_rays(cam)
-    rng = np.random.default_rng(77)
-    pix = np.concatenate([[512 * 256 + 256, 512 * 200 + 300], rng.integers(0, 512 * 512, 8)])
-    for r in pix:
-        f = sc.oracle_ray(oo[r], vv[r], 1.0, 3.0)
-        if f["margin"] <= 1e-6:
-            continue
-        px = H.oracle_pixel(sc, f, 1.0, 3.0, tf.astype(np.float64), 0.0, vmax, step)
-        assert np.max(np.abs(img[r] - px)) <= 1e-4, (r, img[r], px)
-    # fields of a few sampled rays (float32 copies of the camera rays)
-    o32, v32 = oo[pix[:4]].astype(np.float32), vv[pix[:4]].astype(np.float32)
-    out = _approx(sc, o32, v32, 1.0, 3.0)
-    for i in range(4):
-        f = sc.oracle_ray(o32[i], v32[i], 1.0, 3.0)
-        _check_ray(sc, out, i, f)
+    sample = _plain_sample(len(oo))[::10][:256]
+    offs, ids = L.sph_hoa_camera_hits(sc.index(), cam)
+    hits = H.hit_lists(offs, ids, sample)
+    del offs, ids
+    tf64 = tf.astype(np.float64)
+    tasks = []
+    for r in sample:
+        r = int(r)
+        g = H.ray_data(h, r)
+        g["hits"] = hits[r]
+        tasks.append((r, oo[r], vv[r], 1.0, 3.0, g, {"pixel": (img[r], 1.0, 3.0, tf64, 0.0, vmax, step)}))
+    _report("full-size fields", H.summarize(H.compare_rays_parallel(sc, tasks)))
