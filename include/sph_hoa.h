@@ -229,6 +229,29 @@ sph_hoa_status sph_hoa_render(sph_hoa_index idx, const sph_hoa_camera* cam, cons
                               float* rgba_out, void* stream);
 
 /*
+ * sph_hoa_render without allocation, for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, hosts that forbid hipMalloc): same arguments, checks
+ * and result as sph_hoa_render (bit for bit), but every per-call device buffer (rays, hit counts
+ * and lists, screen-tile lists, sort and scan temporaries, the field kernel's slabs and counters)
+ * is placed in one fixed array of sph_hoa_static_scratch_bytes() bytes (128 MiB) that the library
+ * holds on each device it runs on until the process ends; the call makes no hipMalloc, hipFree
+ * or other allocating call.  A frame whose buffers do not fit (about 4 bytes per contribution
+ * for the hit lists plus 48 per ray, and at least one field work-group's slab; fewer persistent
+ * field work-groups run when not all slabs fit) returns SPH_HOA_E_OUT_OF_MEMORY; the device
+ * work is then drained and nothing is written to rgba_out.  All calls on one device share the
+ * array: calls that overlap on one device (from several host threads or streams) race and must
+ * be serialised by the caller.  Synchronises `stream` before returning.  The index's own
+ * per-call buffers are left as they were.
+ */
+sph_hoa_status sph_hoa_render_static(sph_hoa_index idx, const sph_hoa_camera* cam, const sph_hoa_tf* tf,
+                                     float* rgba_out, void* stream);
+/* Size in bytes of the fixed per-device scratch array of sph_hoa_render_static. */
+int64_t sph_hoa_static_scratch_bytes(void);
+/* Number of device allocations (hipMalloc) the library has made in this process so far, for
+ * callers that check that a region of their code allocates nothing.  Thread-safe. */
+int64_t sph_hoa_device_alloc_count(void);
+
+/*
  * Fields along a camera's pixel rays, with the rays and the hit gathering of sph_hoa_render (the
  * screen-tile binning of Sec. 2's first pass): out receives what sph_hoa_approx_rays gives for
  * arbitrary rays (ray index = row * width + col; same flags, capacities and errors), and the merged

@@ -102,7 +102,7 @@ class Stats(ctypes.Structure):
 
 
 EXPORTS = ["sph_hoa_build_index", "sph_hoa_approx_rays", "sph_hoa_approx_rays_shared", "sph_hoa_approx_camera",
-           "sph_hoa_camera_hits", "sph_hoa_ray_hits", "sph_hoa_render", "sph_hoa_render_batch",
+           "sph_hoa_camera_hits", "sph_hoa_ray_hits", "sph_hoa_render", "sph_hoa_render_static", "sph_hoa_render_batch",
            "sph_hoa_server_create", "sph_hoa_server_add_index", "sph_hoa_server_submit", "sph_hoa_server_wait",
            "sph_hoa_server_get_stats", "sph_hoa_server_destroy", "sph_hoa_server_set_admission",
            "sph_hoa_server_cancel", "sph_hoa_server_pause", "sph_hoa_accumulate_bits", "sph_hoa_float_rays",
@@ -132,6 +132,11 @@ def lib():
     L.sph_hoa_camera_hits.argtypes = [vp, ctypes.POINTER(Camera), vp, vp, i64, ctypes.POINTER(i64), vp]
     L.sph_hoa_ray_hits.argtypes = [vp, ctypes.POINTER(Rays), vp, vp, i64, ctypes.POINTER(i64), vp]
     L.sph_hoa_render.argtypes = [vp, ctypes.POINTER(Camera), ctypes.POINTER(TF), vp, vp]
+    L.sph_hoa_render_static.argtypes = [vp, ctypes.POINTER(Camera), ctypes.POINTER(TF), vp, vp]
+    L.sph_hoa_static_scratch_bytes.argtypes = []
+    L.sph_hoa_static_scratch_bytes.restype = i64
+    L.sph_hoa_device_alloc_count.argtypes = []
+    L.sph_hoa_device_alloc_count.restype = i64
     L.sph_hoa_render_batch.argtypes = [vp, ctypes.POINTER(Camera), i32, ctypes.POINTER(TF), vp, vp]
     L.sph_hoa_server_create.argtypes = [i64, i64, ctypes.POINTER(vp)]
     L.sph_hoa_server_add_index.argtypes = [vp, vp, ctypes.POINTER(i32)]
@@ -509,6 +514,30 @@ def sph_hoa_render(index, camera: dict, tf_rgba, v_min, v_max, step, out=None):
     t = TF(_ptr(tf).value, tf.shape[0], v_min, v_max, step)
     _check(lib().sph_hoa_render(index.handle, ctypes.byref(c), ctypes.byref(t), _ptr(out), _stream()))
     return out
+
+
+def sph_hoa_render_static(index, camera: dict, tf_rgba, v_min, v_max, step, out=None):
+    """sph_hoa_render with every per-call buffer in the library's fixed static device scratch (no
+    allocation inside the call; `out` may be preallocated)."""
+    import torch
+
+    c = make_camera(camera)
+    tf = _dev_f32(tf_rgba).reshape(-1, 4)
+    if out is None:
+        out = torch.empty((c.height, c.width, 4), dtype=torch.float32, device="cuda")
+    t = TF(_ptr(tf).value, tf.shape[0], v_min, v_max, step)
+    _check(lib().sph_hoa_render_static(index.handle, ctypes.byref(c), ctypes.byref(t), _ptr(out), _stream()))
+    return out
+
+
+def sph_hoa_static_scratch_bytes():
+    """Size of the fixed static scratch array of sph_hoa_render_static (bytes)."""
+    return int(lib().sph_hoa_static_scratch_bytes())
+
+
+def sph_hoa_device_alloc_count():
+    """Device allocations the library has made in this process so far."""
+    return int(lib().sph_hoa_device_alloc_count())
 
 
 def sph_hoa_render_batch(index, cameras, tf_rgba, v_min, v_max, step, out=None):

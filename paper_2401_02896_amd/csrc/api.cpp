@@ -388,6 +388,23 @@ sph_hoa_status sph_hoa_render(sph_hoa_index idx, const sph_hoa_camera* cam, cons
   });
 }
 
+sph_hoa_status sph_hoa_render_static(sph_hoa_index idx, const sph_hoa_camera* cam, const sph_hoa_tf* tf,
+                                     float* rgba_out, void* stream) {
+  return guarded([&]() {
+    require(idx && cam && tf && rgba_out, "NULL argument");
+    sph::Index& ix = idx->ix;
+    check_tf(tf);
+    check_camera(ix, cam, tf);
+    hipStream_t st = (hipStream_t)stream;
+    ix.last_stream = st;
+    sph::render_static(ix, cam, tf, rgba_out, st);
+  });
+}
+
+int64_t sph_hoa_static_scratch_bytes(void) { return sph::static_scratch_bytes(); }
+
+int64_t sph_hoa_device_alloc_count(void) { return sph::g_device_allocs.load(); }
+
 sph_hoa_status sph_hoa_approx_camera(sph_hoa_index idx, const sph_hoa_camera* cam, sph_hoa_field* out, uint32_t flags,
                                      void* stream) {
   return guarded([&]() {

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdint>
 #include <stdexcept>
 #include <string>
@@ -56,12 +57,34 @@ struct GridDev {
   LevelInfo lv[kMaxLevels];
 };
 
-// Device buffer that grows on demand and frees itself.
+// Device allocations the library has made in this process (every one goes through DevBuf).
+inline std::atomic<int64_t> g_device_allocs{0};
+
+// Bump region in caller-provided device memory: per-call buffers bound to it take their space
+// from it instead of allocating (see bind_static_scratch).
+struct Arena {
+  char* base = nullptr;
+  size_t cap = 0, used = 0;
+};
+
+// Device buffer that grows on demand and frees itself.  When bound to an arena it never
+// allocates: growing takes the next aligned range of the arena, or fails with E_OUT_OF_MEMORY.
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  Arena* arena = nullptr;
   void ensure(size_t b) {
     if (b <= bytes) return;
+    if (arena) {
+      const size_t off = (arena->used + 255) & ~size_t(255);
+      if (off > arena->cap || b > arena->cap - off)
+        throw Error(SPH_HOA_E_OUT_OF_MEMORY, "the call needs more than the " + std::to_string(arena->cap) +
+                                                 " bytes of static scratch memory");
+      p = arena->base + off;
+      bytes = b;
+      arena->used = off + b;
+      return;
+    }
     if (p) (void)hipFree(p);
     p = nullptr;
     bytes = 0;
@@ -71,12 +94,19 @@ struct DevBuf {
       (void)hipGetLastError();
       throw Error(SPH_HOA_E_OUT_OF_MEMORY, "device allocation of " + std::to_string(b) + " bytes failed");
     }
+    g_device_allocs.fetch_add(1, std::memory_order_relaxed);
     bytes = b;
+  }
+  // bytes that ensure() could still hand out (unbounded when not bound to an arena)
+  size_t room() const {
+    if (!arena) return SIZE_MAX;
+    const size_t off = (arena->used + 255) & ~size_t(255);
+    return off >= arena->cap ? 0 : arena->cap - off;
   }
   template <class T>
   T* as() const { return static_cast<T*>(p); }
   ~DevBuf() {
-    if (p) (void)hipFree(p);
+    if (p && !arena) (void)hipFree(p);
   }
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
@@ -113,6 +143,7 @@ struct FieldTuner {
   hipEvent_t ev[2] = {};
   static Key key_of(int D, bool render, int64_t pairs, int64_t rays, int64_t max_hits);
   int choose(const Key& k);
+  int chosen(const Key& k) const;  // the measured choice, 2 while not both measured; times nothing
   void begin(const Key& k, int wgs, int64_t pairs, hipStream_t st);
   void end(hipStream_t st);
   void collect();
@@ -166,6 +197,7 @@ struct Index {
   sph_hoa_stats stats{};
   FieldTuner tuner;
   bool render_stats_pending = false;  // placement counters of the last render not read back yet
+  bool no_alloc = false;              // inside sph_hoa_render_static: no allocation, no tuner timing
   hipStream_t last_stream = nullptr;
   // optional event timing of the kernels (sph_hoa_index_set_timing)
   bool timing = false;
@@ -201,6 +233,10 @@ void server_stats(Server* s, sph_hoa_server_stats* st);
 void server_set_admission(Server* s, int64_t max_queued, int64_t max_request_bytes);
 bool server_cancel(Server* s, int64_t id);
 void server_pause(Server* s, bool paused);
+
+// render with every per-call buffer in the library's static device scratch (static_scratch.hip)
+void render_static(Index& ix, const sph_hoa_camera* cam, const sph_hoa_tf* tf, float* rgba, hipStream_t st);
+int64_t static_scratch_bytes();
 
 // build (index.hip)
 void build_index_device(Index& ix, const float* xyz, const float* h, const float* value, hipStream_t st);

@@ -1710,6 +1710,12 @@ FieldTuner::Key FieldTuner::key_of(int D, bool render, int64_t pairs, int64_t ra
   return Key{D, render ? 1 : 0, lg(1 + pairs / std::max<int64_t>(1, rays)), lg(1 + max_hits)};
 }
 
+int FieldTuner::chosen(const Key& k) const {
+  const auto it = table.find(k);
+  if (it == table.end() || it->second.ms_per_pair[0] < 0 || it->second.ms_per_pair[1] < 0) return 2;
+  return it->second.ms_per_pair[1] < it->second.ms_per_pair[0] ? 1 : 2;
+}
+
 int FieldTuner::choose(const Key& k) {
   Entry& e = table[k];
   if (e.ms_per_pair[0] < 0) return 2;  // measure two work-groups per CU first, then one
@@ -2077,7 +2083,8 @@ void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam,
   const int64_t mh1 = std::max<int64_t>(1, (int64_t)mh);
   const bool render_mode = (out.rgba != nullptr);
   const FieldTuner::Key tkey = FieldTuner::key_of(D, render_mode, total_pairs, n_rays, (int64_t)mh);
-  int wgs = ix.tuner.choose(tkey);
+  // (the static-scratch entry point takes the tuner's choice without timing anything)
+  int wgs = ix.no_alloc ? ix.tuner.chosen(tkey) : ix.tuner.choose(tkey);
   if (const char* f = std::getenv("SPH_HOA_FIELD_WGS")) wgs = (std::atoi(f) == 1) ? 1 : 2;  // test hook
   const int64_t lds_budget = kLdsPerCu / wgs - (int64_t)lds_static - 512;
   int64_t lds = std::min<int64_t>(lds_budget, ray_store_bytes(mh1, max_knots, nj, true));
@@ -2092,12 +2099,18 @@ void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam,
   hip_check(hipGetDevice(&dev), "device");
   hip_check(hipGetDeviceProperties(&prop, dev), "props");
   const int per_cu = (int)std::max<int64_t>(1, std::min<int64_t>(wgs, kLdsPerCu / (lds + (int64_t)lds_static + 512)));
-  const int grid = (int)std::min<int64_t>((int64_t)prop.multiProcessorCount * per_cu, n_rays);
+  int grid = (int)std::min<int64_t>((int64_t)prop.multiProcessorCount * per_cu, n_rays);
   const int max_tier = ray_tier(mh1, max_knots, nj, lds);
   A.slab_jmp = align8((int64_t)node_bytes(D) * ((max_knots + kChunk - 1) / kChunk) * kChunk);
   A.slab_scratch = A.slab_jmp + (max_tier >= 1 ? align8(8 * (int64_t)nj * mh1) : 0);
   A.slab_store = A.slab_scratch + (max_tier >= 2 ? align8(8 * kpad_size(max_knots)) : 0);
   A.slab_stride = A.slab_store + (max_tier >= 3 ? align8(ray_store_bytes(mh1, max_knots, nj, true)) : 0) + 64;
+  if (ix.slab.arena) {
+    // fixed scratch: fewer persistent work-groups when their slabs do not all fit (same results)
+    const int64_t fit = (int64_t)(ix.slab.room() / (size_t)A.slab_stride);
+    if (fit < 1) throw Error(SPH_HOA_E_OUT_OF_MEMORY, "the longest ray needs more static scratch memory than is left");
+    grid = (int)std::min<int64_t>(grid, fit);
+  }
   ix.slab.ensure((size_t)A.slab_stride * grid);
   A.slab = ix.slab.as<char>();
   if (render_mode) {
@@ -2108,9 +2121,9 @@ void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam,
     A.tf_step = (double)out.tf->step;
     A.rgba = out.rgba;
     if (ix.timing) hip_check(hipEventRecord(ix.ev[4], st), "event");
-    ix.tuner.begin(tkey, wgs, total_pairs, st);
+    if (!ix.no_alloc) ix.tuner.begin(tkey, wgs, total_pairs, st);
     dispatch_field<true>(D, wgs, A, grid, (size_t)lds, st);
-    ix.tuner.end(st);
+    if (!ix.no_alloc) ix.tuner.end(st);
     ix.render_stats_pending = true;
     if (ix.timing) {
       hip_check(hipEventRecord(ix.ev[5], st), "event");
