@@ -498,9 +498,8 @@ __global__ void __launch_bounds__(64) k_tile_hits(TileHitArgs T) {
 
 struct MergeTables {
   double node[kMaxD + 1], wgt[kMaxD + 1];          // Gauss-Legendre on [0, 1], D + 1 points
-  double leg_at_node[kMaxD + 1][kMaxD + 1];        // P~_j(node_i) [j][i]
-  double pow2leg[kMaxD + 1][kMaxD + 1];            // gamma_j = sum_d pow2leg[j][d] beta_d
-  double leg2pow[kMaxD + 1][kMaxD + 1];            // c_d = sum_j gamma_j leg2pow[j][d]
+  double leg2pow[kMaxD + 1][kMaxD + 1];            // P~_j(u) = sum_d leg2pow[j][d] u^d (shifted Legendre)
+  double err_c;  // rounding bound of the merge test per exact piece, relative to the mean square
 };
 
 struct FieldArgs {
@@ -566,24 +565,18 @@ struct FieldArgs {
   float* rgba;
 };
 
+// A merged interval of exact pieces, held as what the merge test needs: the moments of the exact
+// field F about the interval's start and its energy (F in units of sigma, t in length quanta), from
+// which the L2 projection onto polynomials of degree <= D and its residual follow.  After the merge,
+// finalize_node() replaces the moments by the projection's power coefficients in u = (t - a) / (b - a).
 template <int D>
 struct Node {
-  int32_t a, b;
-  double g[D + 1];  // Legendre coefficients of the projection on [a, b] (in u = (t - a) / (b - a))
-  double r;         // accumulated squared L2 residual of the projection
-  double e;         // mean square of the projection over [a, b]: sum_j g_j^2 / (2j + 1)
+  int32_t a, b;     // [a, b] in length quanta
+  int32_t n;        // exact pieces in it
+  int32_t pad;
+  double m[D + 1];  // m_i = int_a^b F(t) (t - a)^i dt; after finalize_node: power coefficients (world units)
+  double e;         // int_a^b F(t)^2 dt
 };
-
-template <int D>
-__device__ __forceinline__ double mean_square(const double* g) {
-  double e = 0.0;
-#pragma unroll
-  for (int j = 0; j <= D; ++j) {
-    constexpr double one = 1.0;
-    e += g[j] * g[j] * (one / (2 * j + 1));
-  }
-  return e;
-}
 
 __device__ __forceinline__ int64_t rint_i64(double x, uint32_t* flags) {
   if (!(fabs(x) < 4.6e18)) {
@@ -692,117 +685,114 @@ __device__ bool hit_jumps(const MethodConsts& mc, const double (&sr)[kMaxP][D], 
   return ok;
 }
 
-// Shifted Legendre P~_j(x) for j = 0..D by the three-term recurrence on y = 2x - 1,
-// (j + 1) P_{j+1} = (2j + 1) y P_j - j P_{j-1}, with the constant ratios folded in.
+// Leaf of the merge: one exact piece [ta, tb) whose field is sum_d a_d (t - ta)^d (coef, wrap-around
+// integers read as signed).  Moments and energy by (D + 1)-point Gauss-Legendre quadrature, exact
+// for the degree <= 2D integrands.
 template <int D>
-__device__ __forceinline__ void legendre_at(double x, double* p) {
-  const double y = 2.0 * x - 1.0;
-  p[0] = 1.0;
-  if (D >= 1) p[1] = y;
-#pragma unroll
-  for (int j = 1; j < D; ++j) {
-    constexpr double one = 1.0;
-    const double a = (2.0 * j + 1.0) * (one / (j + 1)), b = (double)j * (one / (j + 1));
-    p[j + 1] = a * y * p[j] - b * p[j - 1];
-  }
-}
-
-template <int D>
-__device__ __forceinline__ Node<D> make_leaf(const MergeTables& mt, int32_t ta, int32_t tb, const uint64_t* coef,
-                                             double sigma) {
+__device__ __forceinline__ Node<D> make_leaf(const MergeTables& mt, int32_t ta, int32_t tb, const uint64_t* coef) {
   Node<D> n;
   n.a = ta;
   n.b = tb;
-  n.r = 0.0;
+  n.n = 1;
+  n.pad = 0;
   const double L = (double)((int64_t)tb - (int64_t)ta);
-  double beta[D + 1];
-  double p = 1.0;
+  double c[D + 1];
 #pragma unroll
-  for (int d = 0; d <= D; ++d) {
-    beta[d] = sigma * (double)(int64_t)coef[d] * p;
-    p *= L;
+  for (int d = 0; d <= D; ++d) c[d] = (double)(int64_t)coef[d];
+#pragma unroll
+  for (int i = 0; i <= D; ++i) n.m[i] = 0.0;
+  n.e = 0.0;
+#pragma unroll
+  for (int g = 0; g <= D; ++g) {
+    const double x = L * mt.node[g];
+    double f = c[D];
+#pragma unroll
+    for (int d = D - 1; d >= 0; --d) f = f * x + c[d];
+    const double wf = mt.wgt[g] * L * f;
+    n.e += wf * f;
+    double p = wf;
+#pragma unroll
+    for (int i = 0; i <= D; ++i) {
+      n.m[i] += p;
+      p *= x;
+    }
+  }
+  return n;
+}
+
+// Union of adjacent nodes A = [a, b] and B = [b, c]: B's moments moved from b to a
+// (m_i <- sum_j C(i, j) (b - a)^(i - j) m_j, as repeated synthetic steps) plus A's.
+template <int D>
+__device__ __forceinline__ Node<D> combine(const Node<D>& A, const Node<D>& B) {
+  Node<D> U;
+  U.a = A.a;
+  U.b = B.b;
+  U.n = A.n + B.n;
+  U.pad = 0;
+  const double dl = (double)((int64_t)B.a - (int64_t)A.a);
+  double m[D + 1];
+#pragma unroll
+  for (int i = 0; i <= D; ++i) m[i] = B.m[i];
+#pragma unroll
+  for (int k = 1; k <= D; ++k)
+#pragma unroll
+    for (int i = D; i >= k; --i) m[i] += dl * m[i - 1];
+#pragma unroll
+  for (int i = 0; i <= D; ++i) U.m[i] = A.m[i] + m[i];
+  U.e = A.e + B.e;
+  return U;
+}
+
+// Legendre moments lam_j = int_0^1 f(u) P~_j(u) du of the node's field on u = (t - a) / (b - a) and
+// its mean square int_0^1 f^2 du.
+template <int D>
+__device__ __forceinline__ void node_moments(const MergeTables& mt, const Node<D>& n, double* lam, double* ms) {
+  const double inv = 1.0 / (double)((int64_t)n.b - (int64_t)n.a);
+  double mh[D + 1];
+  double p = inv;
+#pragma unroll
+  for (int i = 0; i <= D; ++i) {
+    mh[i] = n.m[i] * p;
+    p *= inv;
   }
 #pragma unroll
   for (int j = 0; j <= D; ++j) {
     double s = 0.0;
 #pragma unroll
-    for (int d = 0; d <= D; ++d) s += mt.pow2leg[j][d] * beta[d];
-    n.g[j] = s;
+    for (int i = 0; i <= j; ++i) s += mt.leg2pow[j][i] * mh[i];
+    lam[j] = s;
   }
-  n.e = mean_square<D>(n.g);
-  return n;
+  *ms = n.e * inv;
 }
 
-// Union of adjacent nodes A = [a, b], B = [b, c]: projection and residual, exact from the parts.
-// The residual added by the union is the squared distance of the parts' projections from the
-// union's projection; by orthogonality it equals la e_A + lb e_B - (la + lb) e_U (lengths times mean
-// squares).  That difference cancels when the parts are nearly one polynomial, so when it lies
-// within its rounding bound of the merge threshold thr2 * length the distance is integrated
-// directly instead (a second Gauss-Legendre sweep, exact for the degree 2D integrand).
+// Merge test: the mean square of F minus its projection, int_0^1 f^2 - sum_j (2j + 1) lam_j^2, plus
+// a bound on the rounding of that difference, is within thr2 = (tol * peak)^2 (units of sigma).  The
+// bound makes every accepted interval valid; near the threshold the test may refuse a union that
+// exact arithmetic would accept.
 template <int D>
-__device__ Node<D> combine(const MergeTables& mt, const Node<D>& A, const Node<D>& B, double tau, double thr2) {
-  Node<D> U;
-  U.a = A.a;
-  U.b = B.b;
-  const double la = (double)((int64_t)A.b - (int64_t)A.a), lb = (double)((int64_t)B.b - (int64_t)B.a);
-  const double lam = la / (la + lb);
-  double g[D + 1];
+__device__ __forceinline__ bool passes(const MergeTables& mt, const Node<D>& n, double thr2) {
+  double lam[D + 1], ms;
+  node_moments<D>(mt, n, lam, &ms);
+  double q = 0.0;
 #pragma unroll
-  for (int j = 0; j <= D; ++j) g[j] = 0.0;
-#pragma unroll
-  for (int i = 0; i <= D; ++i) {
-    double fa = 0.0, fb = 0.0;
-#pragma unroll
-    for (int j = 0; j <= D; ++j) {
-      fa += A.g[j] * mt.leg_at_node[j][i];
-      fb += B.g[j] * mt.leg_at_node[j][i];
-    }
-    double pa[D + 1], pb[D + 1];
-    legendre_at<D>(lam * mt.node[i], pa);
-    legendre_at<D>(lam + (1.0 - lam) * mt.node[i], pb);
-    const double wa = mt.wgt[i] * fa * lam, wb = mt.wgt[i] * fb * (1.0 - lam);
-#pragma unroll
-    for (int j = 0; j <= D; ++j) g[j] += wa * pa[j] + wb * pb[j];
-  }
-#pragma unroll
-  for (int j = 0; j <= D; ++j) U.g[j] = (2.0 * j + 1.0) * g[j];
-  U.e = mean_square<D>(U.g);
-  const double parts = la * A.e + lb * B.e;
-  double rloc = fmax(0.0, (parts - (la + lb) * U.e) * tau);
-  const double rin = A.r + B.r;
-  const double bound = 1e-13 * parts * tau + 1e-13 * rin;
-  if (fabs(rin + rloc - thr2 * ((la + lb) * tau)) <= bound) {
-    double ra = 0.0, rb = 0.0;
-#pragma unroll
-    for (int i = 0; i <= D; ++i) {
-      double fa = 0.0, fb = 0.0;
-#pragma unroll
-      for (int j = 0; j <= D; ++j) {
-        fa += A.g[j] * mt.leg_at_node[j][i];
-        fb += B.g[j] * mt.leg_at_node[j][i];
-      }
-      double pa[D + 1], pb[D + 1];
-      legendre_at<D>(lam * mt.node[i], pa);
-      legendre_at<D>(lam + (1.0 - lam) * mt.node[i], pb);
-      double ua = 0.0, ub = 0.0;
-#pragma unroll
-      for (int j = 0; j <= D; ++j) {
-        ua += U.g[j] * pa[j];
-        ub += U.g[j] * pb[j];
-      }
-      const double da = fa - ua, db = fb - ub;
-      ra += mt.wgt[i] * da * da;
-      rb += mt.wgt[i] * db * db;
-    }
-    rloc = la * tau * ra + lb * tau * rb;
-  }
-  U.r = rin + rloc;
-  return U;
+  for (int j = 0; j <= D; ++j) q += (2.0 * j + 1.0) * lam[j] * lam[j];
+  const double bound = ((double)n.n * (D + 2) + 16.0) * mt.err_c * ms;
+  return (ms - q) + bound <= thr2;
 }
 
+// Replace the node's moments by the power coefficients (world units, sigma applied) of the
+// projection in u = (t - a) / (b - a): c_d = sigma sum_j (2j + 1) lam_j leg2pow[j][d].
 template <int D>
-__device__ __forceinline__ bool passes(const Node<D>& n, double thr2, double tau) {
-  return n.r <= thr2 * ((double)((int64_t)n.b - (int64_t)n.a) * tau);
+__device__ __forceinline__ void finalize_node(const MergeTables& mt, Node<D>& n, double sigma) {
+  double lam[D + 1], ms;
+  node_moments<D>(mt, n, lam, &ms);
+#pragma unroll
+  for (int d = 0; d <= D; ++d) {
+    double s = 0.0;
+#pragma unroll
+    for (int j = d; j <= D; ++j) s += (2.0 * j + 1.0) * lam[j] * mt.leg2pow[j][d];
+    n.m[d] = sigma * s;
+  }
 }
 
 __device__ __forceinline__ uint32_t key_slot(uint64_t key) { return (uint32_t)key >> 3; }
@@ -1124,7 +1114,8 @@ __device__ void process_ray(const FieldArgs& A, Shared<D>& sh, const RayStore& S
   __syncthreads();
   // ---- pass C: exact pieces -> leaves -> greedy merge within chunks -> nodes
   const double tol = A.mc.merge_tol;
-  const double thr2 = (tol * peak) * (tol * peak);
+  const double pk_s = (double)sh.peak;  // the peak in units of sigma
+  const double thr2 = (tol * pk_s) * (tol * pk_s);
   {
     Agg<D> st = carry;
     int64_t ex_pos = ex_first;
@@ -1170,13 +1161,13 @@ __device__ void process_ray(const FieldArgs& A, Shared<D>& sh, const RayStore& S
             }
           }
           ++ex_pos;
-          Node<D> leaf = make_leaf<D>(A.mt, (int32_t)t, tn, st.a, sigma);
+          Node<D> leaf = make_leaf<D>(A.mt, (int32_t)t, tn, st.a);
           if (!have) {
             cur = leaf;
             have = true;
           } else if (tol > 0.0) {
-            Node<D> cand = combine<D>(A.mt, cur, leaf, tau, thr2);
-            if (passes<D>(cand, thr2, tau)) cur = cand;
+            Node<D> cand = combine<D>(cur, leaf);
+            if (passes<D>(A.mt, cand, thr2)) cur = cand;
             else {
               flush(chunk);
               cur = leaf;
@@ -1213,8 +1204,8 @@ __device__ void process_ray(const FieldArgs& A, Shared<D>& sh, const RayStore& S
         int32_t nf = lf >= 0 ? lf : rf;
         int32_t nl = rl >= 0 ? rl : ll;
         if (ll >= 0 && rf >= 0) {
-          Node<D> cand = combine<D>(A.mt, nodes[ll], nodes[rf], tau, thr2);
-          if (passes<D>(cand, thr2, tau)) {
+          Node<D> cand = combine<D>(nodes[ll], nodes[rf]);
+          if (passes<D>(A.mt, cand, thr2)) {
             nodes[ll] = cand;
             const int64_t rc = rf / kChunk;
             S.chead[rc] = S.chead[rc] + 1;
@@ -1234,9 +1225,12 @@ __device__ void process_ray(const FieldArgs& A, Shared<D>& sh, const RayStore& S
       __syncthreads();
     }
   }
-  // ---- live nodes per thread range, in order
+  // ---- live nodes per thread range, in order; their moments become output coefficients
   int64_t mine = 0;
-  for (int64_t c = c_lo; c < c_hi; ++c) mine += S.ccnt[c] - S.chead[c];
+  for (int64_t c = c_lo; c < c_hi; ++c) {
+    mine += S.ccnt[c] - S.chead[c];
+    for (int32_t q = S.chead[c]; q < S.ccnt[c]; ++q) finalize_node<D>(A.mt, nodes[c * kChunk + q], sigma);
+  }
   int64_t n_live = 0;
   const int64_t live_first = block_excl_scan_i64<kFieldThreads>(mine, sh.wtot, tid, &n_live);
   if (!RENDER) {
@@ -1261,12 +1255,7 @@ __device__ void process_ray(const FieldArgs& A, Shared<D>& sh, const RayStore& S
           const double len = (double)((int64_t)nd.b - (int64_t)nd.a) * tau;
           double cu[D + 1];
 #pragma unroll
-          for (int d = 0; d <= D; ++d) {
-            double s = 0.0;
-#pragma unroll
-            for (int j = 0; j <= D; ++j) s += nd.g[j] * A.mt.leg2pow[j][d];
-            cu[d] = s;
-          }
+          for (int d = 0; d <= D; ++d) cu[d] = nd.m[d];
           const double al = ((double)fa - ta) / len;
           const double be = ((double)fb - (double)fa) / len;
           double rc[D + 1];
@@ -1380,11 +1369,7 @@ __device__ void process_ray(const FieldArgs& A, Shared<D>& sh, const RayStore& S
         const int64_t S_n = (int64_t)Sd;
         const double delta = (b - a) / Sd;
         float cf[D + 1];
-        for (int d = 0; d <= D; ++d) {
-          double sacc = 0.0;
-          for (int j = 0; j <= D; ++j) sacc += nd.g[j] * A.mt.leg2pow[j][d];
-          cf[d] = (float)sacc;
-        }
+        for (int d = 0; d <= D; ++d) cf[d] = (float)nd.m[d];
         const float u0 = (float)((a - ta) / (tb - ta)), du = (float)(delta / (tb - ta));
         const float dl = (float)delta;
         const int64_t first = ist[n];
@@ -1588,22 +1573,18 @@ MergeTables make_merge_tables(int D) {
   };
   for (int j = 0; j <= D; ++j)
     for (int k = 0; k <= D; ++k) t.leg2pow[j][k] = (k <= j) ? (((j + k) % 2) ? -1.0 : 1.0) * C(j, k) * C(j + k, k) : 0.0;
-  for (int j = 0; j <= D; ++j)
-    for (int i = 0; i <= D; ++i) {
-      double s = 0.0, p = 1.0;
-      for (int k = 0; k <= D; ++k) {
-        s += t.leg2pow[j][k] * p;
-        p *= t.node[i];
-      }
-      t.leg_at_node[j][i] = s;
-    }
-  // gamma_j = (2j+1) int_0^1 u^d P~_j(u) du = (2j+1) sum_k coef_jk / (d + k + 1)
-  for (int j = 0; j <= D; ++j)
-    for (int d = 0; d <= D; ++d) {
-      double s = 0.0;
-      for (int k = 0; k <= j; ++k) s += t.leg2pow[j][k] / (double)(d + k + 1);
-      t.pow2leg[j][d] = (2.0 * j + 1.0) * s;
-    }
+  // Rounding of the merge test.  With |lam_j| <= |f| / sqrt(2j + 1) (Cauchy-Schwarz) and every
+  // moment off by at most (pieces) eps |f| (sums of the pieces' terms and of the shifts, whose
+  // terms are all bounded by the integral of |F| (t - a)^i), sum_j (2j + 1) lam_j^2 is off by at
+  // most 2 sum_j sqrt(2j + 1) S_j (pieces) eps |f|^2, S_j the absolute row sum of P~_j; a factor 2
+  // covers the quadrature, the reciprocal and the last subtraction.
+  double cd = 0.0;
+  for (int j = 0; j <= D; ++j) {
+    double sj = 0.0;
+    for (int k = 0; k <= j; ++k) sj += std::fabs(t.leg2pow[j][k]);
+    cd += std::sqrt(2.0 * j + 1.0) * sj;
+  }
+  t.err_c = 2.0 * 2.0 * cd * std::ldexp(1.0, -52);
   return t;
 }
 
