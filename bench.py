@@ -42,7 +42,7 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--particles", type=int, default=1_000_000)
     ap.add_argument("--size", type=int, default=512)
     ap.add_argument("--parity-rays", type=int, default=2621,

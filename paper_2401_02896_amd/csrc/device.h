@@ -84,7 +84,7 @@ __device__ int64_t block_excl_scan_i64(int64_t v, int64_t* wtot, int tid, int64_
 // unused slot after every 16 elements (element i at i + i / 16; a and tmp then hold
 // n + n / 16 + 1 elements).  Caller guarantees a barrier before; ends with a barrier.
 template <int NT, bool PAD_OUT>
-__device__ void radix_sort_u64(uint64_t* a, uint64_t* tmp, int n, int lo_bit, int nbits, uint32_t* tab, int tid) {
+__device__ __forceinline__ void radix_sort_u64(uint64_t* a, uint64_t* tmp, int n, int lo_bit, int nbits, uint32_t* tab, int tid) {
   constexpr int W = NT / 64;
   constexpr int E = (16 * W + 63) / 64;  // table entries per lane of the scanning wave
   constexpr int MB = 16;

@@ -119,9 +119,14 @@ struct MethodConsts {
   double tau, sigma, q, merge_tol;
 };
 
-// Online choice of the field kernel's work-groups per CU (1 or 2) per workload signature (degree,
-// mode, log2 of the mean and of the largest hits per ray): each candidate is timed once on a real
-// call (its output is identical), then the faster is kept.
+// Most field work-groups per CU for degree D (render or field output) that the kernel's registers
+// allow without spilling.
+int max_field_wgs(int D, bool render);
+
+// Online choice of the field kernel's work-groups per CU (1 to 4; a ray's layout gets 1 / wgs of
+// the CU's LDS) per workload signature (degree, mode, log2 of the mean and of the largest hits per
+// ray): each candidate is timed once on a real call (its output is identical), then the fastest is
+// kept.
 struct FieldTuner {
   struct Key {
     int D, render, mean_bucket, max_bucket;
@@ -133,8 +138,9 @@ struct FieldTuner {
     }
   };
   struct Entry {
-    double ms_per_pair[2] = {-1.0, -1.0};  // two work-groups per CU, one
+    double ms_per_pair[5] = {-1.0, -1.0, -1.0, -1.0, -1.0};  // by work-groups per CU (1..4)
   };
+  static constexpr int kOrder[4] = {2, 3, 4, 1};  // candidates, in the order they are measured
   std::map<Key, Entry> table;
   bool pending = false;
   Key pend_key{};

@@ -595,8 +595,22 @@ __device__ __forceinline__ void taylor_shift(uint64_t* a, uint32_t delta) {
     for (int j = D - 1; j >= i; --j) a[j] += a[j + 1] * dd;
 }
 
-__host__ __device__ constexpr uint64_t binom_c(int n, int k) {
-  return (k < 0 || k > n) ? 0 : ((k == 0 || k == n) ? 1 : binom_c(n - 1, k - 1) + binom_c(n - 1, k));
+// Binomial coefficients C(n, k), n, k <= kMaxD, from a compile-time table (the loops that use them
+// are unrolled, so every use folds to a constant)
+struct BinomTable {
+  uint64_t v[kMaxD + 1][kMaxD + 1];
+};
+constexpr BinomTable make_binom_table() {
+  BinomTable t{};
+  for (int n = 0; n <= kMaxD; ++n) {
+    t.v[n][0] = 1;
+    for (int k = 1; k <= n; ++k) t.v[n][k] = t.v[n - 1][k - 1] + (k <= n - 1 ? t.v[n - 1][k] : 0);
+  }
+  return t;
+}
+__device__ __forceinline__ uint64_t binom_c(int n, int k) {
+  constexpr BinomTable T = make_binom_table();
+  return T.v[n][k];
 }
 
 // Rows of jump values stored per hit: one row of D orders for each knot pair +-theta_k, plus the
@@ -609,13 +623,15 @@ __host__ __device__ inline int jump_values_per_hit(int P, int even_k, int D) { r
 //   row k-1, k = 1..P: the knot at +theta_k; the knot at -theta_k mirrors it (even orders negated);
 //   odd K: row 0 is the knot at +theta_1, whose odd orders come from the closure;
 //   even K: row P is the middle knot (odd orders from the closure, even orders zero).
-// sr[m][d-1]: the table's projection jump of order d at +theta_{m+1} (s-hat, Sec. 3.1).  The
-// knot pairs are visited one at a time, keeping only the closure sums live.  Computed once per
-// hit, so the scans over the sorted knots only look values up.  Returns false if a quantized
-// coefficient left the int64 range.
+// srow: the hit's table row, s-hat[m][d] (projection jump of order d at +theta_{m+1}, Sec. 3.1) at
+// srow[m (D + 1) + d].  The knot pairs are visited one at a time (their table jumps read from
+// memory as they are needed), keeping only the closure sums live; the closure's polynomial sums
+// in the knot offsets are evaluated by Horner's rule with the 32-bit offset as multiplier.
+// Computed once per hit, so the scans over the sorted knots only look values up.  Returns false if
+// a quantized coefficient left the int64 range.
 template <int D>
-__device__ bool hit_jumps(const MethodConsts& mc, const double (&sr)[kMaxP][D], double base, double u,
-                          const int32_t* off, uint64_t* rows) {
+__device__ bool hit_jumps(const MethodConsts& mc, const double* srow, double base, double u, const int32_t* off,
+                          uint64_t* rows) {
   const int P = mc.P;
   constexpr int ND = (D + 1) / 2;  // odd orders 1, 3, ...
   uint64_t acc[ND];
@@ -629,7 +645,7 @@ __device__ bool hit_jumps(const MethodConsts& mc, const double (&sr)[kMaxP][D], 
     for (int d = 1; d <= D; ++d) {
       p = p * u;
       const double scale = base * p;
-      const double x = sr[m][d - 1] * scale;
+      const double x = srow[m * (D + 1) + d] * scale;
       ok = ok && (fabs(x) < 4.6e18);
       const uint64_t j = (fabs(x) < 4.6e18) ? (uint64_t)(int64_t)rint(x) : 0ull;
       left[d] = (d % 2 == 0) ? (uint64_t)0 - j : j;
@@ -637,21 +653,18 @@ __device__ bool hit_jumps(const MethodConsts& mc, const double (&sr)[kMaxP][D], 
   };
   // knot pairs whose table jumps enter the closure sums directly: all of them for even K
   // (middle knot), m = 1..P-1 for odd K (the pair +-theta_1 is solved for below)
-#pragma unroll
-  for (int m = 0; m < kMaxP; ++m) {
-    if (m >= P || (m == 0 && !mc.even_k)) continue;
+#pragma unroll 1
+  for (int m = 0; m < P; ++m) {
+    if (m == 0 && !mc.even_k) continue;
     uint64_t left[D + 1];
     table_left(m, left);
-    uint64_t pw[D + 1];
-    pw[0] = 1;
-#pragma unroll
-    for (int e = 1; e <= D; ++e) pw[e] = pw[e - 1] * (uint64_t)(uint32_t)off[m];
+    const uint64_t o = (uint64_t)(uint32_t)off[m];
 #pragma unroll
     for (int d = 1; d <= D; d += 2) {
       // even K: sum_{j=d..D} C(j,d) a_{-m,j} o^(j-d); odd K: a_{-m,d} + sum_{j>d} (same terms)
-      uint64_t t = 0;
+      uint64_t t = binom_c(D, d) * left[D];
 #pragma unroll
-      for (int jj = d; jj <= D; ++jj) t += binom_c(jj, d) * left[jj] * pw[jj - d];
+      for (int jj = D - 1; jj >= d; --jj) t = t * o + binom_c(jj, d) * left[jj];
       acc[d / 2] += t;
     }
 #pragma unroll
@@ -668,15 +681,13 @@ __device__ bool hit_jumps(const MethodConsts& mc, const double (&sr)[kMaxP][D], 
   // (for m = 1 only even j come from the table: odd j use the values already solved)
   uint64_t left[D + 1];
   table_left(0, left);
-  uint64_t pw[D + 1];
-  pw[0] = 1;
-#pragma unroll
-  for (int e = 1; e <= D; ++e) pw[e] = pw[e - 1] * (uint64_t)(uint32_t)off[0];
+  const uint64_t o = (uint64_t)(uint32_t)off[0];
 #pragma unroll
   for (int d = (D % 2 == 1 ? D : D - 1); d >= 1; d -= 2) {
-    uint64_t t = acc[d / 2];
+    uint64_t t = 0;
 #pragma unroll
-    for (int jj = d + 1; jj <= D; ++jj) t += binom_c(jj, d) * left[jj] * pw[jj - d];
+    for (int jj = D; jj > d; --jj) t = t * o + binom_c(jj, d) * left[jj];
+    t = t * o + acc[d / 2];
     left[d] = (uint64_t)0 - t;
   }
   // row 0: the knot at +theta_1, a_{1,d} = (-1)^(d+1) a_{-1,d}
@@ -858,6 +869,7 @@ __host__ __device__ inline int64_t align8(int64_t x) { return (x + 7) & ~int64_t
 // kpad(i)), so that threads walking consecutive 16-knot chunks read different LDS banks.
 __host__ __device__ inline int64_t kpad(int64_t i) { return i + (i >> 4); }
 __host__ __device__ inline int64_t kpad_size(int64_t n) { return n + (n >> 4) + 1; }
+__device__ __forceinline__ int kpad32(int i) { return i + (i >> 4); }
 
 // bytes of the per-ray layout for nh hits and nk knots, with or without the jump rows and the
 // sort scratch (those two can live in the work-group's device-memory slab instead)
@@ -912,19 +924,28 @@ __device__ __forceinline__ void jump_of(const MethodConsts& mc, const RayStore& 
   const uint32_t slot = key_slot(key);
   const int k = key_kidx(key) - mc.P;
   const int row = (k == 0) ? mc.P : (k < 0 ? -k : k) - 1;
-  const uint64_t* v = S.jmp + ((int64_t)slot * S.nj + row * D);
+  const uint64_t* v = S.jmp + ((int)slot * S.nj + row * D);
   a[0] = 0;
 #pragma unroll
   for (int d = 1; d <= D; ++d) a[d] = (k < 0 && (d % 2 == 0)) ? (uint64_t)0 - v[d - 1] : v[d - 1];
 }
 
+// The exact-mode knot list's second sort (canonical order).
+__device__ __forceinline__ void sort_canonical(uint64_t* a, uint64_t* tmp, int n, int nbits, uint32_t* tab, int tid) {
+  radix_sort_u64<kFieldThreads, false>(a, tmp, n, 0, nbits, tab, tid);
+}
+
 // Process one ray with all threads of the work-group.
 template <int D, bool RENDER>
-__device__ void process_ray(const FieldArgs& A, Shared<D>& sh, const RayStore& S, Node<D>* nodes, int64_t r,
+__device__ __forceinline__ void process_ray(const FieldArgs& A, Shared<D>& sh, const RayStore& S, Node<D>* nodes,
+                                            int64_t r,
                             int64_t nh) {
-  const int tid = threadIdx.x;
+  // opaque to the optimiser, so that per-thread addresses are not hoisted out of the ray loop and
+  // kept live in registers across every phase
+  int tid = threadIdx.x;
+  asm volatile("" : "+v"(tid));
   const int K = A.mc.K, P = A.mc.P;
-  const int64_t nk = nh * (K + 1);
+  const int nk = (int)nh * (K + 1);  // at most 1023 * 256 (checked on the host)
   const int64_t hoff = A.hit_slots ? r * A.hit_slots : A.hit_off[r];
   double o[3], v[3];
   for (int k = 0; k < 3; ++k) {
@@ -942,10 +963,10 @@ __device__ void process_ray(const FieldArgs& A, Shared<D>& sh, const RayStore& S
   // hit's own key span until the keys replace them.
   const double tau = A.mc.tau, sigma = A.mc.sigma;
   int32_t* park = reinterpret_cast<int32_t*>(S.kkey);
-  const int64_t span32 = 2 * (int64_t)(K + 1);
+  const int span32 = 2 * (K + 1);
   int32_t my_lo = 0x7fffffff, my_hi = (int32_t)0x80000000;
 #pragma unroll 1
-  for (int64_t s = tid; s < nh; s += kFieldThreads) {
+  for (int s = tid; s < (int)nh; s += kFieldThreads) {
     const uint32_t j = A.hits[hoff + s];
     const float4 p = A.pos4[j];
     const float vj = A.val[j];
@@ -959,15 +980,12 @@ __device__ void process_ray(const FieldArgs& A, Shared<D>& sh, const RayStore& S
     const double lam = sqrt(lam2);
     int li = (int)floor(lam * (double)A.mc.n_lut / kSupport);
     li = li < 0 ? 0 : (li > A.mc.n_lut - 1 ? A.mc.n_lut - 1 : li);
-    // the table row (knots and projection jumps) is loaded in one go before it is used
+    // the table row: knots now, projection jumps as hit_jumps needs them
+    const double* trow = A.theta + (int64_t)li * P;
+    const double* srow = A.shat + (int64_t)li * P * (D + 1);
     double th[kMaxP];
-    double sr[kMaxP][D];
 #pragma unroll
-    for (int m = 0; m < kMaxP; ++m) {
-      th[m] = (m < P) ? A.theta[(int64_t)li * P + m] : 0.0;
-#pragma unroll
-      for (int d = 1; d <= D; ++d) sr[m][d - 1] = (m < P) ? A.shat[((int64_t)li * P + m) * (D + 1) + d] : 0.0;
-    }
+    for (int m = 0; m < kMaxP; ++m) th[m] = (m < P) ? trow[m] : 0.0;
     const double t0d = rint(tchi / tau);
     bool bad = !(fabs(t0d) < 2.0e9);
     const int32_t t0 = bad ? 0 : (int32_t)t0d;
@@ -986,7 +1004,7 @@ __device__ void process_ray(const FieldArgs& A, Shared<D>& sh, const RayStore& S
       if (m < P) park[s * span32 + 1 + m] = offs[m];
     const double base = (double)vj / (sigma * (z * z * z));
     const double u = tau / z;
-    if (!hit_jumps<D>(A.mc, sr, base, u, offs, S.jmp + s * S.nj)) atomicOr(A.flags, kFlagCoefRange);
+    if (!hit_jumps<D>(A.mc, srow, base, u, offs, S.jmp + s * S.nj)) atomicOr(A.flags, kFlagCoefRange);
     const int32_t oP = (P == 1) ? offs[0] : ((P == 2) ? offs[1] : offs[2]);
     my_lo = min(my_lo, t0 - oP);
     my_hi = max(my_hi, t0 + oP);
@@ -999,7 +1017,7 @@ __device__ void process_ray(const FieldArgs& A, Shared<D>& sh, const RayStore& S
   // ---- knot keys: (position - t_lo) in the high half, (slot, kidx) in the low half; kidx = k + P
   // for the knot at t0 + sign(k) o_|k|, laid out slot-major so that the stable sort leaves equal
   // positions in (slot, kidx) order.  Each thread rewrites the spans of the hits it parked.
-  for (int64_t s = tid; s < nh; s += kFieldThreads) {
+  for (int s = tid; s < (int)nh; s += kFieldThreads) {
     const int32_t t0 = park[s * span32];
     int32_t o3[kMaxP];
 #pragma unroll
@@ -1024,10 +1042,10 @@ __device__ void process_ray(const FieldArgs& A, Shared<D>& sh, const RayStore& S
     radix_sort_u64<kFieldThreads, true>(S.kkey, S.kkey2, (int)nk, 32, nbits, sh.rtab, tid);
   }
   // ---- thread ranges of chunks
-  const int64_t n_chunks = (nk + kChunk - 1) / kChunk;
-  const int64_t per = (n_chunks + kFieldThreads - 1) / kFieldThreads;
-  const int64_t c_lo = min((int64_t)tid * per, n_chunks), c_hi = min(c_lo + per, n_chunks);
-  const int64_t k_lo = c_lo * kChunk, k_hi = min(c_hi * kChunk, nk);
+  const int n_chunks = (nk + kChunk - 1) / kChunk;
+  const int per = (n_chunks + kFieldThreads - 1) / kFieldThreads;
+  const int c_lo = min(tid * per, n_chunks), c_hi = min(c_lo + per, n_chunks);
+  const int k_lo = c_lo * kChunk, k_hi = min(c_hi * kChunk, nk);
   // ---- pass A: aggregate of this thread's knots
   Agg<D> agg_mine;
   {
@@ -1035,9 +1053,9 @@ __device__ void process_ray(const FieldArgs& A, Shared<D>& sh, const RayStore& S
     g.valid = 0;
     g.t = 0;
     for (int d = 0; d <= D; ++d) g.a[d] = 0;
-    for (int64_t i = k_lo; i < k_hi; ++i) {
-      const uint64_t key = S.kkey[kpad(i)];
-      const int64_t t = key_t(key);
+    for (int i = k_lo; i < k_hi; ++i) {
+      const uint64_t key = S.kkey[kpad32(i)];
+      const int32_t t = key_t(key);
       uint64_t jmp[D + 1];
       jump_of<D>(A.mc, S, key, jmp);
       if (g.valid) taylor_shift<D>(g.a, (uint32_t)(t - g.t));
@@ -1075,9 +1093,9 @@ __device__ void process_ray(const FieldArgs& A, Shared<D>& sh, const RayStore& S
   int64_t npieces = 0;
   {
     Agg<D> st = carry;
-    for (int64_t i = k_lo; i < k_hi; ++i) {
-      const uint64_t key = S.kkey[kpad(i)];
-      const int64_t t = key_t(key);
+    for (int i = k_lo; i < k_hi; ++i) {
+      const uint64_t key = S.kkey[kpad32(i)];
+      const int32_t t = key_t(key);
       uint64_t jmp[D + 1];
       jump_of<D>(A.mc, S, key, jmp);
       if (st.valid) taylor_shift<D>(st.a, (uint32_t)(t - st.t));
@@ -1085,7 +1103,7 @@ __device__ void process_ray(const FieldArgs& A, Shared<D>& sh, const RayStore& S
       st.t = t;
       st.valid = 1;
       const bool last = (i + 1 == nk);
-      if (!last && key_t(S.kkey[kpad(i + 1)]) != t) {
+      if (!last && key_t(S.kkey[kpad32(i + 1)]) != t) {
         const int64_t a0 = (int64_t)st.a[0];
         const unsigned long long m = (unsigned long long)(a0 < 0 ? -a0 : a0);
         pk = pk > m ? pk : m;
@@ -1119,28 +1137,28 @@ __device__ void process_ray(const FieldArgs& A, Shared<D>& sh, const RayStore& S
   {
     Agg<D> st = carry;
     int64_t ex_pos = ex_first;
-    int64_t cur_chunk = -1;
+    int cur_chunk = -1;
     Node<D> cur;
     bool have = false;
     int32_t emitted = 0;
-    auto flush = [&](int64_t chunk) {
+    auto flush = [&](int chunk) {
       if (have) {
         nodes[chunk * kChunk + emitted] = cur;
         ++emitted;
         have = false;
       }
     };
-    for (int64_t c = c_lo; c < c_hi; ++c) S.ccnt[c] = 0;
-    for (int64_t i = k_lo; i < k_hi; ++i) {
-      const uint64_t key = S.kkey[kpad(i)];
-      const int64_t t = key_t(key);
+    for (int c = c_lo; c < c_hi; ++c) S.ccnt[c] = 0;
+    for (int i = k_lo; i < k_hi; ++i) {
+      const uint64_t key = S.kkey[kpad32(i)];
+      const int32_t t = key_t(key);
       uint64_t jmp[D + 1];
       jump_of<D>(A.mc, S, key, jmp);
       if (st.valid) taylor_shift<D>(st.a, (uint32_t)(t - st.t));
       for (int d = 0; d <= D; ++d) st.a[d] += jmp[d];
       st.t = t;
       st.valid = 1;
-      const int64_t chunk = i / kChunk;
+      const int chunk = i / kChunk;
       if (chunk != cur_chunk) {
         if (cur_chunk >= 0) {
           flush(cur_chunk);
@@ -1150,7 +1168,7 @@ __device__ void process_ray(const FieldArgs& A, Shared<D>& sh, const RayStore& S
         emitted = 0;
       }
       if (i + 1 < nk) {
-        const int32_t tn = key_t(S.kkey[kpad(i + 1)]);
+        const int32_t tn = key_t(S.kkey[kpad32(i + 1)]);
         if (tn != (int32_t)t) {
           if (A.exact) {
             const int64_t e = sh.base_ex + ex_pos;
@@ -1188,7 +1206,7 @@ __device__ void process_ray(const FieldArgs& A, Shared<D>& sh, const RayStore& S
   }
   __syncthreads();
   // ---- junction merges across chunk groups (levels 1, 2, 4, ...)
-  for (int64_t c = tid; c < n_chunks; c += kFieldThreads) {
+  for (int c = tid; c < n_chunks; c += kFieldThreads) {
     S.chead[c] = 0;
     const int32_t cn = S.ccnt[c];
     S.gfirst[c] = cn > 0 ? (int32_t)(c * kChunk) : -1;
@@ -1196,9 +1214,9 @@ __device__ void process_ray(const FieldArgs& A, Shared<D>& sh, const RayStore& S
   }
   __syncthreads();
   if (tol > 0.0) {
-    for (int64_t w = 1; w < n_chunks; w <<= 1) {
-      for (int64_t L = (int64_t)tid * 2 * w; L < n_chunks; L += (int64_t)kFieldThreads * 2 * w) {
-        const int64_t R = L + w;
+    for (int w = 1; w < n_chunks; w <<= 1) {
+      for (int L = tid * 2 * w; L < n_chunks; L += kFieldThreads * 2 * w) {
+        const int R = L + w;
         if (R >= n_chunks) continue;
         const int32_t lf = S.gfirst[L], ll = S.glast[L], rf = S.gfirst[R], rl = S.glast[R];
         int32_t nf = lf >= 0 ? lf : rf;
@@ -1207,12 +1225,12 @@ __device__ void process_ray(const FieldArgs& A, Shared<D>& sh, const RayStore& S
           Node<D> cand = combine<D>(nodes[ll], nodes[rf]);
           if (passes<D>(A.mt, cand, thr2)) {
             nodes[ll] = cand;
-            const int64_t rc = rf / kChunk;
+            const int rc = rf / kChunk;
             S.chead[rc] = S.chead[rc] + 1;
             // next live node of group R
             int32_t nxt = -1;
-            const int64_t r_end = min(R + w, n_chunks);
-            for (int64_t c = rc; c < r_end && nxt < 0; ++c) {
+            const int r_end = min(R + w, n_chunks);
+            for (int c = rc; c < r_end && nxt < 0; ++c) {
               if (S.chead[c] < S.ccnt[c]) nxt = (int32_t)(c * kChunk + S.chead[c]);
             }
             if (nxt < 0) nl = ll;  // group R became empty
@@ -1227,7 +1245,7 @@ __device__ void process_ray(const FieldArgs& A, Shared<D>& sh, const RayStore& S
   }
   // ---- live nodes per thread range, in order; their moments become output coefficients
   int64_t mine = 0;
-  for (int64_t c = c_lo; c < c_hi; ++c) {
+  for (int c = c_lo; c < c_hi; ++c) {
     mine += S.ccnt[c] - S.chead[c];
     for (int32_t q = S.chead[c]; q < S.ccnt[c]; ++q) finalize_node<D>(A.mt, nodes[c * kChunk + q], sigma);
   }
@@ -1242,7 +1260,7 @@ __device__ void process_ray(const FieldArgs& A, Shared<D>& sh, const RayStore& S
     }
     __syncthreads();
     int64_t pos = sh.base_out + live_first;
-    for (int64_t c = c_lo; c < c_hi; ++c) {
+    for (int c = c_lo; c < c_hi; ++c) {
       for (int32_t q = S.chead[c]; q < S.ccnt[c]; ++q) {
         const Node<D>& nd = nodes[c * kChunk + q];
         if (pos < A.out_cap) {
@@ -1297,7 +1315,7 @@ __device__ void process_ray(const FieldArgs& A, Shared<D>& sh, const RayStore& S
       const uint32_t range = (uint32_t)sh.t_hi - (uint32_t)t_lo;
       int nbits = 36;
       while (nbits < 64 && (range >> (nbits - 32)) != 0) nbits += 4;
-      radix_sort_u64<kFieldThreads, false>(S.kkey2, S.kkey, (int)nk, 0, nbits, sh.rtab, tid);
+      sort_canonical(S.kkey2, S.kkey, (int)nk, nbits, sh.rtab, tid);
       for (int64_t i = tid; i < nk; i += kFieldThreads) {
         const uint64_t key = S.kkey2[i];
         const int64_t ko = A.knot_off[r] + i;
@@ -1322,16 +1340,17 @@ __device__ void process_ray(const FieldArgs& A, Shared<D>& sh, const RayStore& S
       return (b > a) ? (int64_t)fmax(1.0, ceil((b - a) / A.tf_step)) : 0;
     };
     int64_t my_samples = 0;
-    for (int64_t c = c_lo; c < c_hi; ++c)
+    for (int c = c_lo; c < c_hi; ++c)
       for (int32_t q = S.chead[c]; q < S.ccnt[c]; ++q) my_samples += sample_count(nodes[c * kChunk + q]);
     int64_t n_samp = 0;
     const int64_t samp_first = block_excl_scan_i64<kFieldThreads>(my_samples, sh.wtot, tid, &n_samp);
-    // node index in the sort scratch: first sample number and node slot of each live node
-    int32_t* ist = reinterpret_cast<int32_t*>(S.kkey2);
+    // node index in the key array (free now; at least 8 bytes per exact piece): first sample
+    // number and node slot of each live node
+    int32_t* ist = reinterpret_cast<int32_t*>(S.kkey);
     int32_t* iref = ist + n_live;
     {
       int64_t pos = live_first, sp = samp_first;
-      for (int64_t c = c_lo; c < c_hi; ++c)
+      for (int c = c_lo; c < c_hi; ++c)
         for (int32_t q = S.chead[c]; q < S.ccnt[c]; ++q) {
           ist[pos] = (int32_t)sp;
           iref[pos] = (int32_t)(c * kChunk + q);
@@ -1339,10 +1358,10 @@ __device__ void process_ray(const FieldArgs& A, Shared<D>& sh, const RayStore& S
           ++pos;
         }
     }
-    // the transfer function is read once per sample: stage it in the key array (free now)
+    // the transfer function is read once per sample: stage it in the jump rows (free now) if it fits
     const float* tfp = A.tf;
-    if ((int64_t)ntf * 16 <= 8 * kpad_size(nk)) {
-      float* t = reinterpret_cast<float*>(S.kkey);
+    if ((int64_t)ntf * 16 <= 8 * (int64_t)S.nj * nh) {
+      float* t = reinterpret_cast<float*>(S.jmp);
       for (int i = tid; i < 4 * ntf; i += kFieldThreads) t[i] = A.tf[i];
       tfp = t;
     }
@@ -1602,23 +1621,38 @@ void launch_field(FieldArgs& A, int grid, size_t lds, hipStream_t st) {
   hip_check(hipGetLastError(), "field launch");
 }
 
+constexpr int max_field_wgs_c(int D, bool render) {
+  return render ? (D <= 2 ? 4 : (D <= 5 ? 3 : 2)) : (D <= 1 ? 4 : (D <= 4 ? 3 : 2));
+}
+
+// Only the (degree, work-groups per CU) pairs whose registers fit without spilling are built.
+template <int D, bool RENDER, int WGS>
+void launch_field_checked(FieldArgs& A, int grid, size_t lds, hipStream_t st) {
+  if constexpr (WGS <= max_field_wgs_c(D, RENDER)) launch_field<D, RENDER, WGS>(A, grid, lds, st);
+  else throw Error(SPH_HOA_E_INTERNAL, "work-groups per CU beyond the degree's limit");
+}
+
 template <bool RENDER, int WGS>
 void dispatch_field_wgs(int D, FieldArgs& A, int grid, size_t lds, hipStream_t st) {
   switch (D) {
-    case 1: launch_field<1, RENDER, WGS>(A, grid, lds, st); break;
-    case 2: launch_field<2, RENDER, WGS>(A, grid, lds, st); break;
-    case 3: launch_field<3, RENDER, WGS>(A, grid, lds, st); break;
-    case 4: launch_field<4, RENDER, WGS>(A, grid, lds, st); break;
-    case 5: launch_field<5, RENDER, WGS>(A, grid, lds, st); break;
-    case 6: launch_field<6, RENDER, WGS>(A, grid, lds, st); break;
+    case 1: launch_field_checked<1, RENDER, WGS>(A, grid, lds, st); break;
+    case 2: launch_field_checked<2, RENDER, WGS>(A, grid, lds, st); break;
+    case 3: launch_field_checked<3, RENDER, WGS>(A, grid, lds, st); break;
+    case 4: launch_field_checked<4, RENDER, WGS>(A, grid, lds, st); break;
+    case 5: launch_field_checked<5, RENDER, WGS>(A, grid, lds, st); break;
+    case 6: launch_field_checked<6, RENDER, WGS>(A, grid, lds, st); break;
     default: throw Error(SPH_HOA_E_UNSUPPORTED, "degree");
   }
 }
 
 template <bool RENDER>
 void dispatch_field(int D, int wgs, FieldArgs& A, int grid, size_t lds, hipStream_t st) {
-  if (wgs == 1) dispatch_field_wgs<RENDER, 1>(D, A, grid, lds, st);
-  else dispatch_field_wgs<RENDER, 2>(D, A, grid, lds, st);
+  switch (wgs) {
+    case 1: dispatch_field_wgs<RENDER, 1>(D, A, grid, lds, st); break;
+    case 3: dispatch_field_wgs<RENDER, 3>(D, A, grid, lds, st); break;
+    case 4: dispatch_field_wgs<RENDER, 4>(D, A, grid, lds, st); break;
+    default: dispatch_field_wgs<RENDER, 2>(D, A, grid, lds, st); break;
+  }
 }
 
 size_t node_bytes(int D) { return 8 + 8 * (size_t)(D + 3); }
@@ -1691,22 +1725,34 @@ FieldTuner::Key FieldTuner::key_of(int D, bool render, int64_t pairs, int64_t ra
   return Key{D, render ? 1 : 0, lg(1 + pairs / std::max<int64_t>(1, rays)), lg(1 + max_hits)};
 }
 
+int max_field_wgs(int D, bool render) { return max_field_wgs_c(D, render); }
+
 int FieldTuner::chosen(const Key& k) const {
   const auto it = table.find(k);
-  if (it == table.end() || it->second.ms_per_pair[0] < 0 || it->second.ms_per_pair[1] < 0) return 2;
-  return it->second.ms_per_pair[1] < it->second.ms_per_pair[0] ? 1 : 2;
+  if (it == table.end()) return kOrder[0];
+  int best = kOrder[0];
+  double best_ms = -1.0;
+  for (int w : kOrder) {
+    if (w > max_field_wgs(k.D, k.render != 0)) continue;
+    const double v = it->second.ms_per_pair[w];
+    if (v >= 0 && (best_ms < 0 || v < best_ms)) {
+      best = w;
+      best_ms = v;
+    }
+  }
+  return best;
 }
 
 int FieldTuner::choose(const Key& k) {
   Entry& e = table[k];
-  if (e.ms_per_pair[0] < 0) return 2;  // measure two work-groups per CU first, then one
-  if (e.ms_per_pair[1] < 0) return 1;
-  return e.ms_per_pair[1] < e.ms_per_pair[0] ? 1 : 2;
+  for (int w : kOrder)
+    if (w <= max_field_wgs(k.D, k.render != 0) && e.ms_per_pair[w] < 0) return w;  // measure each candidate once, in order
+  return chosen(k);
 }
 
 void FieldTuner::begin(const Key& k, int wgs, int64_t pairs, hipStream_t st) {
   Entry& e = table[k];
-  const int slot = wgs == 2 ? 0 : 1;
+  const int slot = wgs;
   pending = (e.ms_per_pair[slot] < 0 && pairs > 0);
   if (!pending) return;
   for (auto& v : ev)
@@ -2053,11 +2099,11 @@ void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam,
   A.counters = ctr;
   const int64_t max_knots = std::max<int64_t>(1, (int64_t)mh * (K + 1));
   A.max_knots = max_knots;
-  // Work-groups per CU: two (two waves per SIMD hide the latency of the dependent integer and
-  // float64 chains; registers capped for it, half the CU's LDS per ray) or one (the whole LDS, so
-  // long rays keep more of their layout on chip).  Chosen per workload signature by measuring
-  // both (FieldTuner); a ray's layout gets 1 / wgs of the CU's LDS less the static part, sized
-  // down to the frame's longest ray.
+  // Work-groups per CU, 1 to 4: more ray work-groups per CU (one wave per SIMD each) hide more of
+  // the latency of the dependent integer and float64 chains, fewer give each ray more LDS (long
+  // rays keep more of their layout on chip).  Chosen per workload signature by measuring each
+  // (FieldTuner); a ray's layout gets 1 / wgs of the CU's LDS less the static part, sized down to
+  // the frame's longest ray.
   const int nj = jump_values_per_hit(P, (K % 2 == 0) ? 1 : 0, D);
   A.nj = nj;
   const size_t lds_static = static_lds(D);
@@ -2066,7 +2112,8 @@ void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam,
   const FieldTuner::Key tkey = FieldTuner::key_of(D, render_mode, total_pairs, n_rays, (int64_t)mh);
   // (the static-scratch entry point takes the tuner's choice without timing anything)
   int wgs = ix.no_alloc ? ix.tuner.chosen(tkey) : ix.tuner.choose(tkey);
-  if (const char* f = std::getenv("SPH_HOA_FIELD_WGS")) wgs = (std::atoi(f) == 1) ? 1 : 2;  // test hook
+  if (const char* f = std::getenv("SPH_HOA_FIELD_WGS")) wgs = std::max(1, std::atoi(f));  // test hook
+  wgs = std::min(wgs, max_field_wgs(D, render_mode));
   const int64_t lds_budget = kLdsPerCu / wgs - (int64_t)lds_static - 512;
   int64_t lds = std::min<int64_t>(lds_budget, ray_store_bytes(mh1, max_knots, nj, true));
   // test hook: a smaller LDS capacity (in hits) sends more rays down the device-memory paths
@@ -2142,9 +2189,9 @@ void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam,
                   "copy");
     }
     if (ix.timing) hip_check(hipEventRecord(ix.ev[4], st), "event");
-    ix.tuner.begin(tkey, wgs, total_pairs, st);
+    if (!ix.no_alloc) ix.tuner.begin(tkey, wgs, total_pairs, st);
     dispatch_field<false>(D, wgs, A, grid, (size_t)lds, st);
-    ix.tuner.end(st);
+    if (!ix.no_alloc) ix.tuner.end(st);
     if (ix.timing) {
       hip_check(hipEventRecord(ix.ev[5], st), "event");
       ix.timing_pending = true;
