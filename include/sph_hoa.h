@@ -322,36 +322,46 @@ sph_hoa_status sph_hoa_float_rays(sph_hoa_index idx, const sph_hoa_rays* rays, i
 
 /* ---------------------------------------------------------------- render server
  *
- * A resident request loop: indices stay in device memory, render requests (one camera each) are
- * queued from any host thread, and one worker thread batches them - the oldest request plus the
- * queued requests with the same index and transfer function, in arrival order, while the batch's
- * estimated device memory stays within the budget and its rays within max_batch_rays - into one
- * sph_hoa_render_batch launch chain on the server's own stream.  Each image is bit-identical to
- * sph_hoa_render of its camera alone.  An index added to a server belongs to it until the server
- * is destroyed (no other call may use it meanwhile); the transfer function's device array and the
- * output buffers must stay valid until the request has completed.
+ * A resident request loop with continuous batching: indices stay in device memory, render requests
+ * (one camera each) are queued from any host thread, and the server's lanes (worker threads, each
+ * with its own stream and per-call device state) render them.  A free lane starts the oldest
+ * queued request as soon as its estimated transient device memory fits in what the batches already
+ * in flight leave of the budget (or when nothing is in flight), together with the queued requests
+ * of the same index and transfer function, in arrival order, that still fit (memory and
+ * max_batch_rays), as one sph_hoa_render_batch launch chain.  Requests arriving while batches run
+ * are thus admitted as memory is returned and their work overlaps the running batches on the
+ * device; batches of different indices run side by side on different lanes.  Each image is
+ * bit-identical to sph_hoa_render of its camera alone.  An index added to a server belongs to it
+ * until the server is destroyed (no other call may use it meanwhile); the transfer function's
+ * device array and the output buffers must stay valid until the request has completed.
  */
 typedef struct sph_hoa_server_s* sph_hoa_server;
 
 typedef struct {
   int64_t completed, failed, queued, batches;
   int64_t n_rays, n_pairs;    /* over the completed batches */
-  double busy_s;              /* worker time spent rendering */
+  double busy_s;              /* lane time spent rendering, summed over the lanes */
   double p50_ms, p99_ms, max_ms; /* request latency, submit to completion, over completed requests */
   int64_t rejected;           /* submissions refused by the admission limits */
   int64_t cancelled;          /* requests cancelled while queued */
+  int64_t lanes;              /* worker lanes */
+  int64_t overlapped_batches; /* batches that started while another batch was being rendered */
+  int64_t max_in_flight;      /* most batches rendered at once */
 } sph_hoa_server_stats;
 
-/* hbm_budget_bytes: admission bound on a batch's estimated transient device memory (a single
- * request larger than it still runs alone); max_batch_rays: bound on a batch's rays. */
+/* hbm_budget_bytes: admission bound on the estimated transient device memory of all batches in
+ * flight (a single request larger than it still runs, alone); max_batch_rays: bound on a batch's
+ * rays.  sph_hoa_server_create uses 2 lanes; sph_hoa_server_create_lanes takes 1..16. */
 sph_hoa_status sph_hoa_server_create(int64_t hbm_budget_bytes, int64_t max_batch_rays, sph_hoa_server* out);
+sph_hoa_status sph_hoa_server_create_lanes(int64_t hbm_budget_bytes, int64_t max_batch_rays, int32_t n_lanes,
+                                           sph_hoa_server* out);
 /* Admission limits checked at submission (0: no limit): max_queued - a submission that finds
  * this many requests waiting is refused with E_BUSY; max_request_bytes - a request whose own
  * estimated transient device memory exceeds it is refused with E_OUT_OF_MEMORY (it could never
  * run within that bound).  Refused submissions get no id and count in stats.rejected. */
 sph_hoa_status sph_hoa_server_set_admission(sph_hoa_server server, int64_t max_queued, int64_t max_request_bytes);
-/* paused != 0: the worker starts no new batch (a batch already running completes; submissions
- * still queue); 0: resume.  Destroying a paused server still renders what is queued. */
+/* paused != 0: the lanes start no new batch (batches already running complete; submissions still
+ * queue); 0: resume.  Destroying a paused server still renders what is queued. */
 sph_hoa_status sph_hoa_server_pause(sph_hoa_server server, int32_t paused);
 /* Registers an index; *slot names it in submissions. */
 sph_hoa_status sph_hoa_server_add_index(sph_hoa_server server, sph_hoa_index idx, int32_t* slot);
@@ -364,11 +374,11 @@ sph_hoa_status sph_hoa_server_submit(sph_hoa_server server, int32_t slot, const 
 sph_hoa_status sph_hoa_server_wait(sph_hoa_server server, int64_t request_id, double timeout_s, int32_t* done,
                                    double* latency_ms);
 /* Cancels a request that is still queued: *cancelled = 1, and its wait then reports done with
- * status E_CANCELLED (its output buffer is left untouched).  A request already taken by the worker
- * or completed is not affected (*cancelled = 0).  Unknown id: E_INVALID_ARG. */
+ * status E_CANCELLED (its output buffer is left untouched).  A request already taken by a lane or
+ * completed is not affected (*cancelled = 0).  Unknown id: E_INVALID_ARG. */
 sph_hoa_status sph_hoa_server_cancel(sph_hoa_server server, int64_t request_id, int32_t* cancelled);
 sph_hoa_status sph_hoa_server_get_stats(sph_hoa_server server, sph_hoa_server_stats* stats);
-/* Renders what is still queued, stops the worker and frees the server (not its indices).  No other
+/* Renders what is still queued, stops the lanes and frees the server (not its indices).  No other
  * call on this server may be running or follow (waits included). */
 sph_hoa_status sph_hoa_server_destroy(sph_hoa_server server);
 

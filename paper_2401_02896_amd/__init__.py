@@ -91,7 +91,8 @@ class ServerStats(ctypes.Structure):
     _fields_ = [("completed", ctypes.c_int64), ("failed", ctypes.c_int64), ("queued", ctypes.c_int64),
                 ("batches", ctypes.c_int64), ("n_rays", ctypes.c_int64), ("n_pairs", ctypes.c_int64),
                 ("busy_s", ctypes.c_double), ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double),
-                ("max_ms", ctypes.c_double), ("rejected", ctypes.c_int64), ("cancelled", ctypes.c_int64)]
+                ("max_ms", ctypes.c_double), ("rejected", ctypes.c_int64), ("cancelled", ctypes.c_int64),
+                ("lanes", ctypes.c_int64), ("overlapped_batches", ctypes.c_int64), ("max_in_flight", ctypes.c_int64)]
 
 
 class Stats(ctypes.Structure):
@@ -103,7 +104,7 @@ class Stats(ctypes.Structure):
 
 EXPORTS = ["sph_hoa_build_index", "sph_hoa_approx_rays", "sph_hoa_approx_rays_shared", "sph_hoa_approx_camera",
            "sph_hoa_camera_hits", "sph_hoa_ray_hits", "sph_hoa_render", "sph_hoa_render_static", "sph_hoa_render_batch",
-           "sph_hoa_server_create", "sph_hoa_server_add_index", "sph_hoa_server_submit", "sph_hoa_server_wait",
+           "sph_hoa_server_create", "sph_hoa_server_create_lanes", "sph_hoa_server_add_index", "sph_hoa_server_submit", "sph_hoa_server_wait",
            "sph_hoa_server_get_stats", "sph_hoa_server_destroy", "sph_hoa_server_set_admission",
            "sph_hoa_server_cancel", "sph_hoa_server_pause", "sph_hoa_accumulate_bits", "sph_hoa_float_rays",
            "sph_hoa_index_free",
@@ -139,6 +140,7 @@ def lib():
     L.sph_hoa_device_alloc_count.restype = i64
     L.sph_hoa_render_batch.argtypes = [vp, ctypes.POINTER(Camera), i32, ctypes.POINTER(TF), vp, vp]
     L.sph_hoa_server_create.argtypes = [i64, i64, ctypes.POINTER(vp)]
+    L.sph_hoa_server_create_lanes.argtypes = [i64, i64, i32, ctypes.POINTER(vp)]
     L.sph_hoa_server_add_index.argtypes = [vp, vp, ctypes.POINTER(i32)]
     L.sph_hoa_server_submit.argtypes = [vp, i32, ctypes.POINTER(Camera), ctypes.POINTER(TF), vp,
                                         ctypes.POINTER(i64)]
@@ -565,12 +567,13 @@ def sph_hoa_render_batch(index, cameras, tf_rgba, v_min, v_max, step, out=None):
 
 class Server:
     """Render server (sph_hoa_server_*): resident indices, a request queue and continuous batching
-    by a native worker thread.  submit() returns a request id; wait() blocks until the image is in
-    the output tensor."""
+    by native worker lanes (each with its own stream).  submit() returns a request id; wait() blocks
+    until the image is in the output tensor."""
 
-    def __init__(self, hbm_budget_bytes=8 << 30, max_batch_rays=1 << 24):
+    def __init__(self, hbm_budget_bytes=8 << 30, max_batch_rays=1 << 24, lanes=2):
         h = ctypes.c_void_p()
-        _check(lib().sph_hoa_server_create(int(hbm_budget_bytes), int(max_batch_rays), ctypes.byref(h)))
+        _check(lib().sph_hoa_server_create_lanes(int(hbm_budget_bytes), int(max_batch_rays), int(lanes),
+                                                 ctypes.byref(h)))
         self.handle = h
         self._keep = {}
 

@@ -548,21 +548,21 @@ sph_hoa_status sph_hoa_index_get_stats(sph_hoa_index idx, sph_hoa_stats* stats) 
     require(idx && stats, "NULL argument");
     sph::Index& ix = idx->ix;
     if (ix.last_stream) sph::hip_check(hipStreamSynchronize(ix.last_stream), "sync");
-    ix.collect_timing();
-    ix.tuner.collect();
-    if (ix.render_stats_pending) {
+    ix.ws.collect_timing();
+    ix.ws.tuner.collect();
+    if (ix.ws.render_stats_pending) {
       // a render does not wait for its kernels; its placement counters are read back here
       unsigned long long c[6];
-      sph::hip_check(hipMemcpy(c, ix.counters.p, sizeof(c), hipMemcpyDeviceToHost), "copy");
-      ix.stats.rays_global = (int64_t)c[3];
-      ix.stats.rays_jumps_device = (int64_t)c[4];
-      ix.stats.rays_scratch_device = (int64_t)c[5];
-      ix.render_stats_pending = false;
+      sph::hip_check(hipMemcpy(c, ix.ws.counters.p, sizeof(c), hipMemcpyDeviceToHost), "copy");
+      ix.ws.stats.rays_global = (int64_t)c[3];
+      ix.ws.stats.rays_jumps_device = (int64_t)c[4];
+      ix.ws.stats.rays_scratch_device = (int64_t)c[5];
+      ix.ws.render_stats_pending = false;
     }
-    *stats = ix.stats;
-    stats->timed_calls = idx->ix.timed_calls;
-    stats->ms_gather = idx->ix.ms_gather;
-    stats->ms_field = idx->ix.ms_field;
+    *stats = ix.ws.stats;
+    stats->timed_calls = idx->ix.ws.timed_calls;
+    stats->ms_gather = idx->ix.ws.ms_gather;
+    stats->ms_field = idx->ix.ws.ms_field;
   });
 }
 
@@ -571,13 +571,13 @@ sph_hoa_status sph_hoa_index_set_timing(sph_hoa_index idx, int32_t on) {
     require(idx, "NULL index");
     sph::Index& ix = idx->ix;
     if (ix.last_stream) sph::hip_check(hipStreamSynchronize(ix.last_stream), "sync");
-    ix.collect_timing();
+    ix.ws.collect_timing();
     if (on)
-      for (auto& e : ix.ev)
+      for (auto& e : ix.ws.ev)
         if (!e) sph::hip_check(hipEventCreate(&e), "event create");
-    ix.timing = on != 0;
-    ix.timed_calls = 0;
-    ix.ms_gather = ix.ms_field = 0.0;
+    ix.ws.timing = on != 0;
+    ix.ws.timed_calls = 0;
+    ix.ws.ms_gather = ix.ws.ms_field = 0.0;
   });
 }
 
@@ -641,15 +641,21 @@ sph_hoa_status sph_hoa_accumulate_bits(int32_t bits, int32_t degree, const uint3
 
 }  // extern "C"
 
-sph_hoa_status sph_hoa_server_create(int64_t hbm_budget_bytes, int64_t max_batch_rays, sph_hoa_server* out) {
+sph_hoa_status sph_hoa_server_create_lanes(int64_t hbm_budget_bytes, int64_t max_batch_rays, int32_t n_lanes,
+                                           sph_hoa_server* out) {
   return guarded([&]() {
     require(out != nullptr, "NULL argument");
     require(hbm_budget_bytes > 0 && max_batch_rays > 0, "budget and max_batch_rays must be > 0");
+    require(n_lanes >= 1 && n_lanes <= 16, "n_lanes must be in 1..16");
     *out = nullptr;
     std::unique_ptr<sph_hoa_server_s> h(new sph_hoa_server_s{nullptr});
-    h->s = sph::server_create(hbm_budget_bytes, max_batch_rays);
+    h->s = sph::server_create(hbm_budget_bytes, max_batch_rays, n_lanes);
     *out = h.release();
   });
+}
+
+sph_hoa_status sph_hoa_server_create(int64_t hbm_budget_bytes, int64_t max_batch_rays, sph_hoa_server* out) {
+  return sph_hoa_server_create_lanes(hbm_budget_bytes, max_batch_rays, 2, out);
 }
 
 sph_hoa_status sph_hoa_server_add_index(sph_hoa_server server, sph_hoa_index idx, int32_t* slot) {

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <cstdint>
 #include <stdexcept>
@@ -73,6 +74,11 @@ struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
   Arena* arena = nullptr;
+  // defer = true: growing keeps the old allocation until the buffer is destroyed instead of
+  // freeing it (hipFree waits for all work on the device, which would stall the work of other
+  // streams), and grows by at least half, so that few generations are kept
+  bool defer = false;
+  std::vector<void*> kept;
   void ensure(size_t b) {
     if (b <= bytes) return;
     if (arena) {
@@ -85,7 +91,11 @@ struct DevBuf {
       arena->used = off + b;
       return;
     }
-    if (p) (void)hipFree(p);
+    if (p) {
+      if (defer) kept.push_back(p);
+      else (void)hipFree(p);
+    }
+    if (defer) b = std::max(b, bytes + bytes / 2);
     p = nullptr;
     bytes = 0;
     if (b == 0) return;
@@ -107,6 +117,7 @@ struct DevBuf {
   T* as() const { return static_cast<T*>(p); }
   ~DevBuf() {
     if (p && !arena) (void)hipFree(p);
+    for (void* q : kept) (void)hipFree(q);
   }
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
@@ -159,26 +170,11 @@ struct FieldTuner {
   ~FieldTuner();
 };
 
-struct Index {
-  int64_t n = 0;
-  Kernel kernel = Kernel::Cubic;
-  int K = 4, D = 2, P = 2, n_lut = 4096;
-  double tau = 0, sigma = 0, a_max = 0, h_repr = 0, phi_repr = 0, merge_tol = 0;
-  GridDev grid{};
-  double cell0 = 0;
-  int grid_bits = 1;  // Morton bits per axis in the sort keys
-  Table table;
-  uint32_t lut_flags = 0;  // table storage precision (SPH_HOA_FLAG_LUT_*), 0: float64
-  // device data (Morton order)
-  DevBuf pos4;    // float4 x, y, z, h
-  DevBuf val;     // float amplitude
-  DevBuf orig;    // int32 input index
-  DevBuf morton;  // uint64 key (level << 57 | morton)
-  DevBuf cell_begin, cell_end;  // uint32 per cell, all levels
-  DevBuf lut_theta, lut_shat;   // double
-  DevBuf lut_smid;              // double [n][D+1] jumps at 0 (even K; float variant only)
-  DevBuf float_scratch;         // float variant, per work-group
-  // per-call scratch
+// Per-call device state of the frame path (rays, hit lists, tiles, field-kernel slabs, counters),
+// its statistics, the work-group tuner and optional kernel timing.  Every index owns one; the
+// render server gives each of its lanes its own, so that batches of one index can be in flight on
+// several streams at once.
+struct Workspace {
   DevBuf rays_o, rays_v;        // double [n][3]
   DevBuf hit_count, hit_off;    // int64 [n + 1]
   DevBuf hit_slots;             // uint32 [n][slots]: single-pass gathering of arbitrary rays
@@ -204,7 +200,7 @@ struct Index {
   FieldTuner tuner;
   bool render_stats_pending = false;  // placement counters of the last render not read back yet
   bool no_alloc = false;              // inside sph_hoa_render_static: no allocation, no tuner timing
-  hipStream_t last_stream = nullptr;
+  int time_slices = 1;                // > 1: field kernel launched in about this many slices
   // optional event timing of the kernels (sph_hoa_index_set_timing)
   bool timing = false;
   bool timing_pending = false;
@@ -212,10 +208,45 @@ struct Index {
   int64_t timed_calls = 0;
   double ms_gather = 0.0, ms_field = 0.0;
   void collect_timing();
-  ~Index() {
+  // every per-call device buffer, once
+  template <class F>
+  void for_each_buf(F f) {
+    DevBuf* list[] = {&rays_o,   &rays_v,      &hit_count,   &hit_off,  &hit_slots,  &hits,       &tile_count,
+                      &tile_off, &tile_items,  &tile_masks,  &tile_order, &scan_tmp, &counters,   &slab,
+                      &ray_meta, &out_stage,   &exact_stage, &cams_dev, &ray_tr,     &order_keys, &order,
+                      &sort_hist, &sort_offs};
+    for (DevBuf* b : list) f(*b);
+  }
+  Workspace() = default;
+  Workspace(const Workspace&) = delete;
+  Workspace& operator=(const Workspace&) = delete;
+  ~Workspace() {
     for (auto& e : ev)
       if (e) (void)hipEventDestroy(e);
   }
+};
+
+struct Index {
+  int64_t n = 0;
+  Kernel kernel = Kernel::Cubic;
+  int K = 4, D = 2, P = 2, n_lut = 4096;
+  double tau = 0, sigma = 0, a_max = 0, h_repr = 0, phi_repr = 0, merge_tol = 0;
+  GridDev grid{};
+  double cell0 = 0;
+  int grid_bits = 1;  // Morton bits per axis in the sort keys
+  Table table;
+  uint32_t lut_flags = 0;  // table storage precision (SPH_HOA_FLAG_LUT_*), 0: float64
+  // device data (Morton order)
+  DevBuf pos4;    // float4 x, y, z, h
+  DevBuf val;     // float amplitude
+  DevBuf orig;    // int32 input index
+  DevBuf morton;  // uint64 key (level << 57 | morton)
+  DevBuf cell_begin, cell_end;  // uint32 per cell, all levels
+  DevBuf lut_theta, lut_shat;   // double
+  DevBuf lut_smid;              // double [n][D+1] jumps at 0 (even K; float variant only)
+  DevBuf float_scratch;         // float variant, per work-group
+  Workspace ws;  // the index's own per-call state
+  hipStream_t last_stream = nullptr;
 };
 
 }  // namespace sph
@@ -228,7 +259,7 @@ namespace sph {
 
 // render server (serve.cpp)
 struct Server;
-Server* server_create(int64_t hbm_budget, int64_t max_rays);
+Server* server_create(int64_t hbm_budget, int64_t max_rays, int n_lanes);
 void server_destroy(Server* s);
 int server_add_index(Server* s, sph_hoa_index idx);
 sph_hoa_index server_index(Server* s, int slot);
@@ -292,9 +323,10 @@ void launch_float_field(FloatArgs& F, int64_t max_hits, DevBuf& scratch, int64_t
 // n_batch > 0: render the cameras batch[0..n_batch) together (rays concatenated in camera order)
 // gathered != nullptr (arbitrary rays only): take the hit lists of gathered's previous call on the
 // same rays instead of gathering (the two indices hold the same particles: same_particles)
+// workspace: the per-call state to use (null: the index's own); gathered uses its own index's
 void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam, const sph_hoa_rays* rays,
               FieldOut& out, hipStream_t st, const sph_hoa_camera* batch = nullptr, int n_batch = 0,
-              const Index* gathered = nullptr);
+              const Index* gathered = nullptr, Workspace* workspace = nullptr);
 // true if a and b hold the same particles in the same order (positions, smoothing lengths and
 // input indices bit for bit), so that every ray has the same hit list in both (index.hip)
 bool same_particles(const Index& a, const Index& b, hipStream_t st);

@@ -526,6 +526,7 @@ struct FieldArgs {
   MergeTables mt;
   // scheduling
   unsigned int* queue;
+  int rays_per_wg;      // > 0: each work-group of a launch takes at most this many rays
   int64_t lds_bytes;    // dynamic LDS of the launch (per-ray layouts up to this size live there)
   int nj;               // jump values per hit
   char* slab;           // per-work-group global storage
@@ -1454,7 +1455,11 @@ __global__ void __launch_bounds__(kFieldThreads, WGS) k_field(FieldArgs A) {
   uint64_t* gjmp = (uint64_t*)(slab + A.slab_jmp);
   uint64_t* gscratch = (uint64_t*)(slab + A.slab_scratch);
   char* gstore = slab + A.slab_store;
-  for (;;) {
+  for (int taken = 0;; ++taken) {
+    // a bounded share per work-group (rays_per_wg > 0) ends the launch early, so that the kernels
+    // of other streams get compute units between this stream's launches; the host then launches
+    // again until the queue is drained
+    if (A.rays_per_wg > 0 && taken == A.rays_per_wg) break;
     if (threadIdx.x == 0) {
       const int64_t q = (int64_t)atomicAdd(A.queue, 1u);
       sh.ray = (q < A.n_rays && A.order) ? (int64_t)A.order[q] : q;
@@ -1781,7 +1786,7 @@ FieldTuner::~FieldTuner() {
     if (v) (void)hipEventDestroy(v);
 }
 
-void Index::collect_timing() {
+void Workspace::collect_timing() {
   if (!timing_pending) return;
   timing_pending = false;
   hip_check(hipEventSynchronize(ev[5]), "event sync");
@@ -1795,24 +1800,26 @@ void Index::collect_timing() {
 }
 
 void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam, const sph_hoa_rays* rays,
-              FieldOut& out, hipStream_t st, const sph_hoa_camera* batch, int n_batch, const Index* gathered) {
+              FieldOut& out, hipStream_t st, const sph_hoa_camera* batch, int n_batch, const Index* gathered,
+              Workspace* workspace) {
+  Workspace& ws = workspace ? *workspace : ix.ws;
   const int D = ix.D, K = ix.K, P = ix.P;
-  if (gathered && (camera || n_batch > 0 || gathered->last_hit_rays != n_rays))
+  if (gathered && (camera || n_batch > 0 || gathered->ws.last_hit_rays != n_rays))
     throw Error(SPH_HOA_E_INTERNAL, "shared gathering needs the same arbitrary rays");
-  ix.collect_timing();
-  ix.tuner.collect();
-  ix.render_stats_pending = false;
-  ix.stats = sph_hoa_stats{};
-  ix.stats.n_rays = n_rays;
-  ix.counters.ensure(256);
-  unsigned long long* ctr = ix.counters.as<unsigned long long>();
+  ws.collect_timing();
+  ws.tuner.collect();
+  ws.render_stats_pending = false;
+  ws.stats = sph_hoa_stats{};
+  ws.stats.n_rays = n_rays;
+  ws.counters.ensure(256);
+  unsigned long long* ctr = ws.counters.as<unsigned long long>();
   uint32_t* flags = reinterpret_cast<uint32_t*>(ctr + 16);
   unsigned int* queue = reinterpret_cast<unsigned int*>(ctr + 17);
   unsigned long long* max_hits = ctr + 18;
-  hip_check(hipMemsetAsync(ix.counters.p, 0, 256, st), "memset");
+  hip_check(hipMemsetAsync(ws.counters.p, 0, 256, st), "memset");
   if (n_rays == 0) return;
-  ix.rays_o.ensure(sizeof(double) * 3 * n_rays);
-  ix.rays_v.ensure(sizeof(double) * 3 * n_rays);
+  ws.rays_o.ensure(sizeof(double) * 3 * n_rays);
+  ws.rays_v.ensure(sizeof(double) * 3 * n_rays);
   double t_min = 0.0, t_max = 0.0;
   const float* ray_tr = nullptr;
   const int n_cams = (n_batch > 0) ? n_batch : (camera ? 1 : 0);
@@ -1831,36 +1838,36 @@ void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam,
       tb[c + 1] = tb[c] + (int64_t)((sc.width + kTile - 1) / kTile) * ((sc.height + kTile - 1) / kTile);
     }
     n_tiles = tb[n_cams];
-    ix.cams_dev.ensure(sizeof(CamDev) * n_cams + sizeof(int64_t) * 2 * (n_cams + 1));
-    cdev = ix.cams_dev.as<CamDev>();
+    ws.cams_dev.ensure(sizeof(CamDev) * n_cams + sizeof(int64_t) * 2 * (n_cams + 1));
+    cdev = ws.cams_dev.as<CamDev>();
     ray_base = reinterpret_cast<int64_t*>(cdev + n_cams);
     tile_base = ray_base + (n_cams + 1);
     hip_check(hipMemcpyAsync(cdev, cd.data(), sizeof(CamDev) * n_cams, hipMemcpyHostToDevice, st), "copy");
     hip_check(hipMemcpyAsync(ray_base, rb.data(), sizeof(int64_t) * (n_cams + 1), hipMemcpyHostToDevice, st), "copy");
     hip_check(hipMemcpyAsync(tile_base, tb.data(), sizeof(int64_t) * (n_cams + 1), hipMemcpyHostToDevice, st), "copy");
-    ix.ray_tr.ensure(sizeof(float) * 2 * n_rays);
-    k_camera_rays_batch<<<blocks_for(n_rays, 256), 256, 0, st>>>(cdev, ray_base, n_cams, n_rays, ix.rays_o.as<double>(),
-                                                                 ix.rays_v.as<double>(), ix.ray_tr.as<float>());
-    ray_tr = ix.ray_tr.as<float>();
+    ws.ray_tr.ensure(sizeof(float) * 2 * n_rays);
+    k_camera_rays_batch<<<blocks_for(n_rays, 256), 256, 0, st>>>(cdev, ray_base, n_cams, n_rays, ws.rays_o.as<double>(),
+                                                                 ws.rays_v.as<double>(), ws.ray_tr.as<float>());
+    ray_tr = ws.ray_tr.as<float>();
     t_min = (double)cam_list[0].t_min;
     t_max = (double)cam_list[0].t_max;
     // the staged host vectors must outlive the copies
     hip_check(hipStreamSynchronize(st), "sync");
   } else {
-    k_widen_rays<<<blocks_for(n_rays, 256), 256, 0, st>>>(rays->origin, rays->dir, n_rays, ix.rays_o.as<double>(),
-                                                          ix.rays_v.as<double>(), flags);
+    k_widen_rays<<<blocks_for(n_rays, 256), 256, 0, st>>>(rays->origin, rays->dir, n_rays, ws.rays_o.as<double>(),
+                                                          ws.rays_v.as<double>(), flags);
     t_min = (double)rays->t_min;
     t_max = (double)rays->t_max;
   }
   hip_check(hipGetLastError(), "ray launch");
   // hit counts (another index's, when the gathering is shared)
-  ix.hit_count.ensure(sizeof(int64_t) * (n_rays + 1));
-  ix.hit_off.ensure(sizeof(int64_t) * (n_rays + 1));
-  int64_t* hit_count = gathered ? gathered->hit_count.as<int64_t>() : ix.hit_count.as<int64_t>();
-  int64_t* hit_off = gathered ? gathered->hit_off.as<int64_t>() : ix.hit_off.as<int64_t>();
+  ws.hit_count.ensure(sizeof(int64_t) * (n_rays + 1));
+  ws.hit_off.ensure(sizeof(int64_t) * (n_rays + 1));
+  int64_t* hit_count = gathered ? gathered->ws.hit_count.as<int64_t>() : ws.hit_count.as<int64_t>();
+  int64_t* hit_off = gathered ? gathered->ws.hit_off.as<int64_t>() : ws.hit_off.as<int64_t>();
   GatherArgs G{};
-  G.o = ix.rays_o.as<double>();
-  G.v = ix.rays_v.as<double>();
+  G.o = ws.rays_o.as<double>();
+  G.v = ws.rays_v.as<double>();
   G.n_rays = n_rays;
   G.t_min = t_min;
   G.t_max = t_max;
@@ -1868,7 +1875,7 @@ void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam,
   G.cbeg = ix.cell_begin.as<uint32_t>();
   G.cend = ix.cell_end.as<uint32_t>();
   G.g = ix.grid;
-  G.count = ix.hit_count.as<int64_t>();
+  G.count = ws.hit_count.as<int64_t>();
   G.max_hits = max_hits;
   G.flags = flags;
   G.tr = ray_tr;
@@ -1884,26 +1891,26 @@ void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam,
     B.cams = cdev;
     B.tile_base = tile_base;
     B.n_cams = n_cams;
-    ix.tile_count.ensure(sizeof(unsigned int) * (n_tiles + 1) * 2);
-    ix.tile_off.ensure(sizeof(int64_t) * (n_tiles + 1) * 2);
-    unsigned int* tcount = ix.tile_count.as<unsigned int>();
+    ws.tile_count.ensure(sizeof(unsigned int) * (n_tiles + 1) * 2);
+    ws.tile_off.ensure(sizeof(int64_t) * (n_tiles + 1) * 2);
+    unsigned int* tcount = ws.tile_count.as<unsigned int>();
     unsigned int* tcur = tcount + (n_tiles + 1);
-    int64_t* tcnt64 = ix.tile_off.as<int64_t>() + (n_tiles + 1);
+    int64_t* tcnt64 = ws.tile_off.as<int64_t>() + (n_tiles + 1);
     B.tile_count = tcount;
     B.tile_cursor = tcur;
-    B.tile_off = ix.tile_off.as<int64_t>();
-    if (ix.timing) hip_check(hipEventRecord(ix.ev[0], st), "event");
+    B.tile_off = ws.tile_off.as<int64_t>();
+    if (ws.timing) hip_check(hipEventRecord(ws.ev[0], st), "event");
     hip_check(hipMemsetAsync(tcount, 0, sizeof(unsigned int) * (n_tiles + 1) * 2, st), "memset");
     k_bin<false><<<blocks_for(n_pairs_bin, 256), 256, 0, st>>>(B);
     k_u32_to_i64_n<<<blocks_for(n_tiles, 256), 256, 0, st>>>(tcount, tcnt64, n_tiles);
-    device_exclusive_scan_i64(tcnt64, ix.tile_off.as<int64_t>(), n_tiles, ix.scan_tmp, st);
-    k_set_last<<<1, 1, 0, st>>>(ix.tile_off.as<int64_t>(), tcnt64, n_tiles);
+    device_exclusive_scan_i64(tcnt64, ws.tile_off.as<int64_t>(), n_tiles, ws.scan_tmp, st);
+    k_set_last<<<1, 1, 0, st>>>(ws.tile_off.as<int64_t>(), tcnt64, n_tiles);
     int64_t n_items = 0;
-    hip_check(hipMemcpyAsync(&n_items, ix.tile_off.as<int64_t>() + n_tiles, 8, hipMemcpyDeviceToHost, st), "copy");
+    hip_check(hipMemcpyAsync(&n_items, ws.tile_off.as<int64_t>() + n_tiles, 8, hipMemcpyDeviceToHost, st), "copy");
     hip_check(hipStreamSynchronize(st), "sync");
-    ix.tile_items.ensure(sizeof(uint32_t) * std::max<int64_t>(1, n_items));
-    ix.tile_masks.ensure(sizeof(unsigned long long) * std::max<int64_t>(1, n_items));
-    B.items = ix.tile_items.as<uint32_t>();
+    ws.tile_items.ensure(sizeof(uint32_t) * std::max<int64_t>(1, n_items));
+    ws.tile_masks.ensure(sizeof(unsigned long long) * std::max<int64_t>(1, n_items));
+    B.items = ws.tile_items.as<uint32_t>();
     k_bin<true><<<blocks_for(n_pairs_bin, 256), 256, 0, st>>>(B);
     TH.o = G.o;
     TH.v = G.v;
@@ -1914,49 +1921,49 @@ void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam,
     TH.pos4 = B.pos4;
     TH.tile_off = B.tile_off;
     TH.items = B.items;
-    TH.masks = ix.tile_masks.as<unsigned long long>();
+    TH.masks = ws.tile_masks.as<unsigned long long>();
     {
       // tiles with the longest candidate lists first, so that they do not finish last
-      ix.order_keys.ensure(sizeof(uint64_t) * 2 * n_tiles);
-      uint64_t* k0 = ix.order_keys.as<uint64_t>();
+      ws.order_keys.ensure(sizeof(uint64_t) * 2 * n_tiles);
+      uint64_t* k0 = ws.order_keys.as<uint64_t>();
       uint64_t* k1 = k0 + n_tiles;
       k_order_keys<<<blocks_for(n_tiles, 256), 256, 0, st>>>(tcnt64, n_tiles, k0);
-      const bool alt = device_sort_u64(k0, k1, n_tiles, 64, ix.sort_hist, ix.sort_offs, ix.scan_tmp, st);
-      ix.tile_order.ensure(sizeof(uint32_t) * n_tiles);
-      k_low32<<<blocks_for(n_tiles, 256), 256, 0, st>>>(alt ? k1 : k0, n_tiles, ix.tile_order.as<uint32_t>());
-      TH.order = ix.tile_order.as<uint32_t>();
+      const bool alt = device_sort_u64(k0, k1, n_tiles, 64, ws.sort_hist, ws.sort_offs, ws.scan_tmp, st);
+      ws.tile_order.ensure(sizeof(uint32_t) * n_tiles);
+      k_low32<<<blocks_for(n_tiles, 256), 256, 0, st>>>(alt ? k1 : k0, n_tiles, ws.tile_order.as<uint32_t>());
+      TH.order = ws.tile_order.as<uint32_t>();
     }
     TH.count = G.count;
     TH.max_hits = max_hits;
     k_tile_hits<false><<<(unsigned)n_tiles, 64, 0, st>>>(TH);
-    if (ix.timing) hip_check(hipEventRecord(ix.ev[1], st), "event");
+    if (ws.timing) hip_check(hipEventRecord(ws.ev[1], st), "event");
   } else if (gathered) {
     // the hit lists of the other index's call on these rays: no gathering (zero gathering time)
-    if (ix.timing) {
-      hip_check(hipEventRecord(ix.ev[0], st), "event");
-      hip_check(hipEventRecord(ix.ev[1], st), "event");
+    if (ws.timing) {
+      hip_check(hipEventRecord(ws.ev[0], st), "event");
+      hip_check(hipEventRecord(ws.ev[1], st), "event");
     }
   } else {
     // Single pass when it fits: the counting walk also stores each ray's first n_slots hits in
     // per-ray slots, sized from the previous call's longest ray; the filling walk then runs only
     // if some ray has more hits than slots.
-    int64_t want = ix.last_max_hits > 0 ? ix.last_max_hits : 256;
+    int64_t want = ws.last_max_hits > 0 ? ws.last_max_hits : 256;
     n_slots = 16;
     while (n_slots < want) n_slots <<= 1;
     if (const char* f = std::getenv("SPH_HOA_GATHER_SLOTS")) n_slots = std::max<int64_t>(0, std::atoll(f));  // test hook
     if (n_slots > 0 && n_rays * n_slots > ((int64_t)1 << 30)) n_slots = 0;  // over 4 GiB: two walks
     if (n_slots > 0) {
-      ix.hit_slots.ensure(sizeof(uint32_t) * n_rays * n_slots);
-      G.slots = ix.hit_slots.as<uint32_t>();
+      ws.hit_slots.ensure(sizeof(uint32_t) * n_rays * n_slots);
+      G.slots = ws.hit_slots.as<uint32_t>();
       G.n_slots = n_slots;
     }
-    if (ix.timing) hip_check(hipEventRecord(ix.ev[0], st), "event");
+    if (ws.timing) hip_check(hipEventRecord(ws.ev[0], st), "event");
     k_gather<false><<<gblocks, kGatherThreads, 0, st>>>(G);
-    if (ix.timing) hip_check(hipEventRecord(ix.ev[1], st), "event");
+    if (ws.timing) hip_check(hipEventRecord(ws.ev[1], st), "event");
   }
   hip_check(hipGetLastError(), "gather launch");
   if (!gathered) {
-    device_exclusive_scan_i64(hit_count, hit_off, n_rays, ix.scan_tmp, st);
+    device_exclusive_scan_i64(hit_count, hit_off, n_rays, ws.scan_tmp, st);
     k_set_last<<<1, 1, 0, st>>>(hit_off, hit_count, n_rays);
   }
   int64_t total_pairs = 0;
@@ -1966,31 +1973,31 @@ void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam,
   if (!gathered) hip_check(hipMemcpyAsync(&mh, max_hits, 8, hipMemcpyDeviceToHost, st), "copy");
   hip_check(hipMemcpyAsync(&fl, flags, 4, hipMemcpyDeviceToHost, st), "copy");
   hip_check(hipStreamSynchronize(st), "sync");
-  if (gathered) mh = (unsigned long long)gathered->last_hit_max;
+  if (gathered) mh = (unsigned long long)gathered->ws.last_hit_max;
   if (fl & kFlagBadInput) throw Error(SPH_HOA_E_INVALID_ARG, "ray origin/direction not finite or direction not unit");
   if (fl & kFlagWindow) throw Error(SPH_HOA_E_INTERNAL, "grid enumeration window exceeded");
-  ix.stats.n_pairs = total_pairs;
-  ix.stats.max_hits = (int64_t)mh;
-  ix.stats.n_knots = total_pairs * (K + 1);
+  ws.stats.n_pairs = total_pairs;
+  ws.stats.max_hits = (int64_t)mh;
+  ws.stats.n_knots = total_pairs * (K + 1);
   // the per-ray sort ranks a wave's keys in 16-bit fields: at most 1023 keys per thread
   if ((int64_t)mh * (K + 1) > (int64_t)1023 * kFieldThreads)
     throw Error(SPH_HOA_E_UNSUPPORTED, "more than 1023 * 256 knots on one ray");
-  if (n_cams == 0) ix.last_max_hits = (int64_t)mh;
-  const bool single_pass = gathered ? gathered->last_hit_slots > 0 : (n_slots > 0 && (int64_t)mh <= n_slots);
+  if (n_cams == 0) ws.last_max_hits = (int64_t)mh;
+  const bool single_pass = gathered ? gathered->ws.last_hit_slots > 0 : (n_slots > 0 && (int64_t)mh <= n_slots);
   const uint32_t* hit_lists = nullptr;
   if (gathered) {
-    hit_lists = single_pass ? gathered->hit_slots.as<uint32_t>() : gathered->hits.as<uint32_t>();
-    n_slots = gathered->last_hit_slots;
+    hit_lists = single_pass ? gathered->ws.hit_slots.as<uint32_t>() : gathered->ws.hits.as<uint32_t>();
+    n_slots = gathered->ws.last_hit_slots;
   } else if (single_pass) {
-    hit_lists = ix.hit_slots.as<uint32_t>();
+    hit_lists = ws.hit_slots.as<uint32_t>();
   } else {
-    ix.hits.ensure(sizeof(uint32_t) * std::max<int64_t>(1, total_pairs));
-    hit_lists = ix.hits.as<uint32_t>();
+    ws.hits.ensure(sizeof(uint32_t) * std::max<int64_t>(1, total_pairs));
+    hit_lists = ws.hits.as<uint32_t>();
   }
   G.off = hit_off;
-  G.hits = ix.hits.as<uint32_t>();
+  G.hits = ws.hits.as<uint32_t>();
   G.slots = nullptr;
-  if (ix.timing) hip_check(hipEventRecord(ix.ev[2], st), "event");
+  if (ws.timing) hip_check(hipEventRecord(ws.ev[2], st), "event");
   if (n_cams > 0) {
     TH.off = G.off;
     TH.hits = G.hits;
@@ -2002,13 +2009,13 @@ void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam,
   // the hit lists this index can share with the next call: its own, or none (its buffers may have
   // been resized) when it used another index's
   if (n_cams > 0 || (gathered && gathered != &ix)) {
-    ix.last_hit_rays = -1;
+    ws.last_hit_rays = -1;
   } else if (!gathered) {
-    ix.last_hit_slots = hit_slots;
-    ix.last_hit_rays = n_rays;
-    ix.last_hit_max = (int64_t)mh;
+    ws.last_hit_slots = hit_slots;
+    ws.last_hit_rays = n_rays;
+    ws.last_hit_max = (int64_t)mh;
   }
-  if (ix.timing) hip_check(hipEventRecord(ix.ev[3], st), "event");
+  if (ws.timing) hip_check(hipEventRecord(ws.ev[3], st), "event");
   hip_check(hipGetLastError(), "gather launch");
   if (out.hits) {
     HitsOut* ho = out.hits;
@@ -2074,14 +2081,14 @@ void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam,
   if (n_cams != 1) {
     // arbitrary rays and batches can be heavy-tailed: process the longest rays first so that the
     // persistent work-groups finish together
-    ix.order_keys.ensure(sizeof(uint64_t) * 2 * n_rays);
-    uint64_t* k0 = ix.order_keys.as<uint64_t>();
+    ws.order_keys.ensure(sizeof(uint64_t) * 2 * n_rays);
+    uint64_t* k0 = ws.order_keys.as<uint64_t>();
     uint64_t* k1 = k0 + n_rays;
     k_order_keys<<<blocks_for(n_rays, 256), 256, 0, st>>>(hit_count, n_rays, k0);
-    const bool alt = device_sort_u64(k0, k1, n_rays, 64, ix.sort_hist, ix.sort_offs, ix.scan_tmp, st);
-    ix.order.ensure(sizeof(uint32_t) * n_rays);
-    k_low32<<<blocks_for(n_rays, 256), 256, 0, st>>>(alt ? k1 : k0, n_rays, ix.order.as<uint32_t>());
-    A.order = ix.order.as<uint32_t>();
+    const bool alt = device_sort_u64(k0, k1, n_rays, 64, ws.sort_hist, ws.sort_offs, ws.scan_tmp, st);
+    ws.order.ensure(sizeof(uint32_t) * n_rays);
+    k_low32<<<blocks_for(n_rays, 256), 256, 0, st>>>(alt ? k1 : k0, n_rays, ws.order.as<uint32_t>());
+    A.order = ws.order.as<uint32_t>();
   }
   A.hit_count = hit_count;
   A.hit_off = hit_off;
@@ -2111,7 +2118,7 @@ void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam,
   const bool render_mode = (out.rgba != nullptr);
   const FieldTuner::Key tkey = FieldTuner::key_of(D, render_mode, total_pairs, n_rays, (int64_t)mh);
   // (the static-scratch entry point takes the tuner's choice without timing anything)
-  int wgs = ix.no_alloc ? ix.tuner.chosen(tkey) : ix.tuner.choose(tkey);
+  int wgs = ws.no_alloc ? ws.tuner.chosen(tkey) : ws.tuner.choose(tkey);
   if (const char* f = std::getenv("SPH_HOA_FIELD_WGS")) wgs = std::max(1, std::atoi(f));  // test hook
   wgs = std::min(wgs, max_field_wgs(D, render_mode));
   const int64_t lds_budget = kLdsPerCu / wgs - (int64_t)lds_static - 512;
@@ -2133,14 +2140,27 @@ void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam,
   A.slab_scratch = A.slab_jmp + (max_tier >= 1 ? align8(8 * (int64_t)nj * mh1) : 0);
   A.slab_store = A.slab_scratch + (max_tier >= 2 ? align8(8 * kpad_size(max_knots)) : 0);
   A.slab_stride = A.slab_store + (max_tier >= 3 ? align8(ray_store_bytes(mh1, max_knots, nj, true)) : 0) + 64;
-  if (ix.slab.arena) {
+  if (ws.slab.arena) {
     // fixed scratch: fewer persistent work-groups when their slabs do not all fit (same results)
-    const int64_t fit = (int64_t)(ix.slab.room() / (size_t)A.slab_stride);
+    const int64_t fit = (int64_t)(ws.slab.room() / (size_t)A.slab_stride);
     if (fit < 1) throw Error(SPH_HOA_E_OUT_OF_MEMORY, "the longest ray needs more static scratch memory than is left");
     grid = (int)std::min<int64_t>(grid, fit);
   }
-  ix.slab.ensure((size_t)A.slab_stride * grid);
-  A.slab = ix.slab.as<char>();
+  ws.slab.ensure((size_t)A.slab_stride * grid);
+  // Time slices: a workspace that shares the device with others (render server lanes) launches the
+  // field kernel several times, each work-group taking a bounded share of the rays per launch, so
+  // that the field work of batches on other streams starts within about one slice instead of
+  // waiting for this batch's whole field kernel.  The last launch takes what rounding left over;
+  // launches that find the queue drained end at once.
+  int launches = 1;
+  A.rays_per_wg = 0;
+  int slices = ws.time_slices;
+  if (const char* f = std::getenv("SPH_HOA_TIME_SLICES")) slices = std::max(1, std::atoi(f));  // test hook
+  if (slices > 1 && n_rays > (int64_t)grid * slices) {
+    A.rays_per_wg = (int)std::max<int64_t>(1, n_rays / ((int64_t)grid * slices));
+    launches = (int)((n_rays + (int64_t)grid * A.rays_per_wg - 1) / ((int64_t)grid * A.rays_per_wg));
+  }
+  A.slab = ws.slab.as<char>();
   if (render_mode) {
     A.tf = out.tf->rgba;
     A.tf_n = out.tf->n;
@@ -2148,32 +2168,32 @@ void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam,
     A.tf_vmax = out.tf->v_max;
     A.tf_step = (double)out.tf->step;
     A.rgba = out.rgba;
-    if (ix.timing) hip_check(hipEventRecord(ix.ev[4], st), "event");
-    if (!ix.no_alloc) ix.tuner.begin(tkey, wgs, total_pairs, st);
-    dispatch_field<true>(D, wgs, A, grid, (size_t)lds, st);
-    if (!ix.no_alloc) ix.tuner.end(st);
-    ix.render_stats_pending = true;
-    if (ix.timing) {
-      hip_check(hipEventRecord(ix.ev[5], st), "event");
-      ix.timing_pending = true;
+    if (ws.timing) hip_check(hipEventRecord(ws.ev[4], st), "event");
+    if (!ws.no_alloc) ws.tuner.begin(tkey, wgs, total_pairs, st);
+    for (int l = 0; l < launches; ++l) dispatch_field<true>(D, wgs, A, grid, (size_t)lds, st);
+    if (!ws.no_alloc) ws.tuner.end(st);
+    ws.render_stats_pending = true;
+    if (ws.timing) {
+      hip_check(hipEventRecord(ws.ev[5], st), "event");
+      ws.timing_pending = true;
     }
   } else {
     sph_hoa_field* f = out.field;
     A.out_cap = f->capacity;
-    ix.out_stage.ensure(std::max<size_t>(16, (size_t)f->capacity * sizeof(float) * (D + 3)));
-    A.st_t0 = ix.out_stage.as<float>();
+    ws.out_stage.ensure(std::max<size_t>(16, (size_t)f->capacity * sizeof(float) * (D + 3)));
+    A.st_t0 = ws.out_stage.as<float>();
     A.st_t1 = A.st_t0 + f->capacity;
     A.st_coef = A.st_t1 + f->capacity;
-    ix.ray_meta.ensure(sizeof(int64_t) * (4 * n_rays + 2));
-    A.ray_out = ix.ray_meta.as<int64_t>();
+    ws.ray_meta.ensure(sizeof(int64_t) * (4 * n_rays + 2));
+    A.ray_out = ws.ray_meta.as<int64_t>();
     A.ray_ex = A.ray_out + 2 * n_rays;
     A.ray_peak = f->ray_peak;
     A.exact = out.exact ? 1 : 0;
     DevBuf knot_off;
     if (out.exact) {
       A.exact_cap = f->exact_capacity;
-      ix.exact_stage.ensure(std::max<size_t>(16, (size_t)f->exact_capacity * sizeof(int64_t) * (D + 3)));
-      A.ex_t = ix.exact_stage.as<int64_t>();
+      ws.exact_stage.ensure(std::max<size_t>(16, (size_t)f->exact_capacity * sizeof(int64_t) * (D + 3)));
+      A.ex_t = ws.exact_stage.as<int64_t>();
       A.ex_end = A.ex_t + f->exact_capacity;
       A.ex_coef = A.ex_end + f->exact_capacity;
       knot_off.ensure(sizeof(int64_t) * (n_rays + 1));
@@ -2188,19 +2208,19 @@ void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam,
         hip_check(hipMemcpyAsync(f->knot_offsets, knot_off.p, sizeof(int64_t) * (n_rays + 1), hipMemcpyDeviceToDevice, st),
                   "copy");
     }
-    if (ix.timing) hip_check(hipEventRecord(ix.ev[4], st), "event");
-    if (!ix.no_alloc) ix.tuner.begin(tkey, wgs, total_pairs, st);
-    dispatch_field<false>(D, wgs, A, grid, (size_t)lds, st);
-    if (!ix.no_alloc) ix.tuner.end(st);
-    if (ix.timing) {
-      hip_check(hipEventRecord(ix.ev[5], st), "event");
-      ix.timing_pending = true;
+    if (ws.timing) hip_check(hipEventRecord(ws.ev[4], st), "event");
+    if (!ws.no_alloc) ws.tuner.begin(tkey, wgs, total_pairs, st);
+    for (int l = 0; l < launches; ++l) dispatch_field<false>(D, wgs, A, grid, (size_t)lds, st);
+    if (!ws.no_alloc) ws.tuner.end(st);
+    if (ws.timing) {
+      hip_check(hipEventRecord(ws.ev[5], st), "event");
+      ws.timing_pending = true;
     }
     // counts -> final offsets, then reorder staged pieces by ray
     DevBuf cnt;
     cnt.ensure(sizeof(int64_t) * (n_rays + 1));
     k_ray_counts<<<blocks_for(n_rays, 256), 256, 0, st>>>(A.ray_out, n_rays, cnt.as<int64_t>());
-    device_exclusive_scan_i64(cnt.as<int64_t>(), f->ray_offsets, n_rays, ix.scan_tmp, st);
+    device_exclusive_scan_i64(cnt.as<int64_t>(), f->ray_offsets, n_rays, ws.scan_tmp, st);
     k_set_last<<<1, 1, 0, st>>>(f->ray_offsets, cnt.as<int64_t>(), n_rays);
     unsigned long long c4[6];
     hip_check(hipMemcpyAsync(c4, ctr, sizeof(c4), hipMemcpyDeviceToHost, st), "copy");
@@ -2210,10 +2230,10 @@ void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam,
     f->n_exact_pieces = (int64_t)c4[2];
     f->n_pairs = total_pairs;
     f->n_knots = total_pairs * (K + 1);
-    ix.stats.n_pieces = (int64_t)c4[0];
-    ix.stats.rays_global = (int64_t)c4[3];
-    ix.stats.rays_jumps_device = (int64_t)c4[4];
-    ix.stats.rays_scratch_device = (int64_t)c4[5];
+    ws.stats.n_pieces = (int64_t)c4[0];
+    ws.stats.rays_global = (int64_t)c4[3];
+    ws.stats.rays_jumps_device = (int64_t)c4[4];
+    ws.stats.rays_scratch_device = (int64_t)c4[5];
     if (fl & kFlagPosRange) throw Error(SPH_HOA_E_OVERFLOW, "a quantized knot position left the int32 range");
     if (fl & kFlagCoefRange) throw Error(SPH_HOA_E_OVERFLOW, "a quantized coefficient left the int64 range");
     if (fl & kFlagTail) throw Error(SPH_HOA_E_INTERNAL, "a ray's knots did not cancel exactly");
@@ -2224,7 +2244,7 @@ void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam,
                                                    A.st_coef, f->t_start, f->t_end, f->coef);
     if (out.exact) {
       k_ray_counts<<<blocks_for(n_rays, 256), 256, 0, st>>>(A.ray_ex, n_rays, cnt.as<int64_t>());
-      device_exclusive_scan_i64(cnt.as<int64_t>(), f->exact_offsets, n_rays, ix.scan_tmp, st);
+      device_exclusive_scan_i64(cnt.as<int64_t>(), f->exact_offsets, n_rays, ws.scan_tmp, st);
       k_set_last<<<1, 1, 0, st>>>(f->exact_offsets, cnt.as<int64_t>(), n_rays);
       k_copy_exact<<<(unsigned)n_rays, 64, 0, st>>>(A.ray_ex, f->exact_offsets, n_rays, D + 1, A.ex_t, A.ex_end,
                                                     A.ex_coef, f->exact_t, f->exact_end, f->exact_coef);
@@ -2233,7 +2253,7 @@ void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam,
     hip_check(hipStreamSynchronize(st), "sync");
     return;
   }
-  ix.last_stream = st;
+  if (!workspace) ix.last_stream = st;  // lanes of the render server keep their own streams
 }
 
 }  // namespace sph

@@ -1,13 +1,17 @@
 // Render server: resident indices, a request queue and continuous batching.
 //
 // Requests (one camera each) are queued by any host thread, subject to admission limits (queue
-// length, one request's estimated memory); a queued request can be cancelled.  One worker thread
-// repeatedly takes the oldest request and admits, in arrival order, the queued requests that use
-// the same index and transfer function while the batch's estimated device memory stays within the
-// budget; the batch is rendered by one batched launch chain (run_rays over all its cameras), and
-// each image is copied into its request's output buffer.  Every image is bit-identical to
-// sph_hoa_render of the same camera alone (the batched path computes each ray exactly as the
-// single path does).
+// length, one request's estimated memory); a queued request can be cancelled.  The server runs
+// several lanes, each a worker thread with its own stream and per-call device state.  A free lane
+// takes the oldest request as soon as its estimated transient device memory fits in what the
+// batches already in flight leave of the budget (or nothing is in flight), adds the queued
+// requests with the same index and transfer function in arrival order while the batch stays
+// within the remaining budget and the ray bound, renders the batch with one batched launch chain
+// (run_rays over all its cameras) and copies each image to its request's output.  Requests that
+// arrive while batches run are admitted by the next free lane as memory is returned, so their work
+// overlaps the running batches on the device.  Every image is bit-identical to sph_hoa_render of
+// the same camera alone (each ray is computed exactly as the single path does, whatever batch or
+// lane carries it).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -26,6 +30,11 @@
 
 namespace sph {
 namespace {
+
+// Field-kernel launches per batch on a lane that shares the device with other lanes: a batch that
+// arrives while another lane's field kernel runs gets compute units within about 1/8 of that
+// kernel's time.
+constexpr int kLaneTimeSlices = 8;
 
 double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
@@ -49,6 +58,17 @@ bool same_tf(const sph_hoa_tf& a, const sph_hoa_tf& b) {
 
 }  // namespace
 
+struct Server;
+
+// One worker with its own stream, per-call device state and image staging.
+struct Lane {
+  Server* srv = nullptr;
+  hipStream_t stream = nullptr;
+  Workspace ws;
+  DevBuf staging;
+  std::thread worker;
+};
+
 struct Server {
   int64_t budget = 0, max_rays = 0;
   std::vector<sph_hoa_index> indices;
@@ -59,12 +79,14 @@ struct Server {
   std::unordered_map<int64_t, std::shared_ptr<Request>> live;
   int64_t next_id = 1;
   bool stop = false, paused = false;
-  std::thread worker;
-  hipStream_t stream = nullptr;
-  DevBuf staging;
+  std::vector<std::unique_ptr<Lane>> lanes;
+  int64_t in_flight_bytes = 0;  // estimated device memory of the batches being rendered
+  int in_flight = 0;            // batches being rendered
   // statistics
   std::vector<double> latencies_ms;
   int64_t completed = 0, failed = 0, batches = 0, pairs = 0, rays = 0, rejected = 0, cancelled = 0;
+  int64_t overlapped = 0;  // batches that started while another batch was being rendered
+  int max_in_flight = 0;
   // admission limits (0: none)
   int64_t max_queued = 0, max_request_bytes = 0;
   double busy_s = 0.0;
@@ -78,24 +100,36 @@ struct Server {
     return n * (48 + 8 + 16 + 16) + (int64_t)(n * hpr * 8.0) + tiles * 24;
   }
 
-  void run() {
+  // the oldest request may start: it fits in what the running batches leave of the budget, or
+  // nothing runs (a request larger than the budget then runs alone)
+  bool head_admissible() const {
+    if (queue.empty()) return false;
+    const Request& h = *queue.front();
+    return in_flight == 0 || in_flight_bytes + estimate_bytes(h.slot, h.cam) <= budget;
+  }
+
+  void run(Lane& lane) {
     for (;;) {
       std::vector<std::shared_ptr<Request>> batch;
+      sph_hoa_index index = nullptr;
+      int64_t bytes = 0;
       {
         std::unique_lock<std::mutex> lk(mu);
-        cv_work.wait(lk, [&] { return stop || (!paused && !queue.empty()); });
+        cv_work.wait(lk, [&] { return (stop && queue.empty()) || ((stop || !paused) && head_admissible()); });
         if (queue.empty()) return;  // stop requested and drained (a stop overrides a pause)
-        // oldest request first; then admit compatible requests in arrival order within the budget
+        // oldest request first; then compatible requests in arrival order within what is left
         const std::shared_ptr<Request> head = queue.front();
         queue.pop_front();
         batch.push_back(head);
-        int64_t bytes = estimate_bytes(head->slot, head->cam);
+        index = indices[head->slot];
+        bytes = estimate_bytes(head->slot, head->cam);
+        const int64_t left = std::max<int64_t>(budget - in_flight_bytes, bytes);
         int64_t nr = (int64_t)head->cam.width * head->cam.height;
         for (auto it = queue.begin(); it != queue.end();) {
           const Request& q = **it;
           const int64_t b = estimate_bytes(q.slot, q.cam);
           const int64_t r = (int64_t)q.cam.width * q.cam.height;
-          if (q.slot == head->slot && same_tf(q.tf, head->tf) && bytes + b <= budget && nr + r <= max_rays) {
+          if (q.slot == head->slot && same_tf(q.tf, head->tf) && bytes + b <= left && nr + r <= max_rays) {
             bytes += b;
             nr += r;
             batch.push_back(*it);
@@ -104,12 +138,22 @@ struct Server {
             ++it;
           }
         }
+        if (in_flight > 0) ++overlapped;
+        ++in_flight;
+        max_in_flight = std::max(max_in_flight, in_flight);
+        in_flight_bytes += bytes;
       }
-      render(batch);
+      render(lane, index, batch);
+      {
+        std::lock_guard<std::mutex> lk(mu);
+        --in_flight;
+        in_flight_bytes -= bytes;
+      }
+      cv_work.notify_all();  // memory returned: another lane may admit the next request
     }
   }
 
-  void render(std::vector<std::shared_ptr<Request>>& batch) {
+  void render(Lane& lane, sph_hoa_index index, std::vector<std::shared_ptr<Request>>& batch) {
     const double t0 = now_s();
     sph_hoa_status st = SPH_HOA_OK;
     std::string err;
@@ -120,20 +164,21 @@ struct Server {
         cams.push_back(r->cam);
         n_rays += (int64_t)r->cam.width * r->cam.height;
       }
-      Index& ix = indices[batch[0]->slot]->ix;
-      staging.ensure(sizeof(float) * 4 * (size_t)n_rays);
-      FieldOut fo{nullptr, staging.as<float>(), &batch[0]->tf, false};
-      run_rays(ix, n_rays, false, nullptr, nullptr, fo, stream, cams.data(), (int)cams.size());
+      Index& ix = index->ix;
+      lane.staging.ensure(sizeof(float) * 4 * (size_t)n_rays);
+      FieldOut fo{nullptr, lane.staging.as<float>(), &batch[0]->tf, false};
+      run_rays(ix, n_rays, false, nullptr, nullptr, fo, lane.stream, cams.data(), (int)cams.size(), nullptr,
+               &lane.ws);
       int64_t off = 0;
       for (auto& r : batch) {
         const int64_t n = (int64_t)r->cam.width * r->cam.height;
-        hip_check(hipMemcpyAsync(r->out, staging.as<float>() + 4 * off, sizeof(float) * 4 * (size_t)n,
-                                 hipMemcpyDeviceToDevice, stream),
+        hip_check(hipMemcpyAsync(r->out, lane.staging.as<float>() + 4 * off, sizeof(float) * 4 * (size_t)n,
+                                 hipMemcpyDeviceToDevice, lane.stream),
                   "copy");
         off += n;
       }
-      hip_check(hipStreamSynchronize(stream), "sync");
-      n_pairs = ix.stats.n_pairs;
+      hip_check(hipStreamSynchronize(lane.stream), "sync");
+      n_pairs = lane.ws.stats.n_pairs;
     } catch (const Error& e) {
       st = e.status;
       err = e.what();
@@ -168,13 +213,25 @@ struct Server {
   }
 };
 
-Server* server_create(int64_t hbm_budget, int64_t max_rays) {
+Server* server_create(int64_t hbm_budget, int64_t max_rays, int n_lanes) {
   std::unique_ptr<Server> s(new Server);
   s->budget = hbm_budget;
   s->max_rays = max_rays;
-  hip_check(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking), "stream");
-  Server* raw = s.get();
-  s->worker = std::thread([raw] { raw->run(); });
+  for (int i = 0; i < n_lanes; ++i) {
+    std::unique_ptr<Lane> l(new Lane);
+    l->srv = s.get();
+    hip_check(hipStreamCreateWithFlags(&l->stream, hipStreamNonBlocking), "stream");
+    if (n_lanes > 1) l->ws.time_slices = kLaneTimeSlices;
+    // growing a lane's buffers must not wait for the other lanes' work (hipFree would)
+    l->ws.for_each_buf([](DevBuf& b) { b.defer = true; });
+    l->staging.defer = true;
+    s->lanes.push_back(std::move(l));
+  }
+  for (auto& l : s->lanes) {
+    Lane* lp = l.get();
+    Server* raw = s.get();
+    l->worker = std::thread([raw, lp] { raw->run(*lp); });
+  }
   return s.release();
 }
 
@@ -184,8 +241,8 @@ void server_destroy(Server* s) {
     s->stop = true;
   }
   s->cv_work.notify_all();
-  s->worker.join();  // the worker drains the queue first
-  (void)hipStreamDestroy(s->stream);
+  for (auto& l : s->lanes) l->worker.join();  // the lanes drain the queue first
+  for (auto& l : s->lanes) (void)hipStreamDestroy(l->stream);
   delete s;
 }
 
@@ -294,6 +351,9 @@ void server_stats(Server* s, sph_hoa_server_stats* st) {
   st->n_rays = s->rays;
   st->n_pairs = s->pairs;
   st->busy_s = s->busy_s;
+  st->lanes = (int64_t)s->lanes.size();
+  st->overlapped_batches = s->overlapped;
+  st->max_in_flight = s->max_in_flight;
   std::vector<double> l = s->latencies_ms;
   if (!l.empty()) {
     std::sort(l.begin(), l.end());

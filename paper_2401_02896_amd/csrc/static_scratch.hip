@@ -43,26 +43,21 @@ char* scratch_ptr() {
 // index's own allocations back.
 struct Bind {
   Index& ix;
-  DevBuf* bufs[24];
-  void* saved_p[24];
-  size_t saved_b[24];
+  DevBuf* bufs[32];
+  void* saved_p[32];
+  size_t saved_b[32];
   int n = 0;
   Bind(Index& x, Arena* a) : ix(x) {
-    DevBuf* list[] = {&ix.rays_o,     &ix.rays_v,     &ix.hit_count,  &ix.hit_off,   &ix.hit_slots,
-                      &ix.hits,       &ix.tile_count, &ix.tile_off,   &ix.tile_items, &ix.tile_masks,
-                      &ix.tile_order, &ix.scan_tmp,   &ix.counters,   &ix.slab,      &ix.ray_meta,
-                      &ix.out_stage,  &ix.exact_stage, &ix.cams_dev,  &ix.ray_tr,    &ix.order_keys,
-                      &ix.order,      &ix.sort_hist,  &ix.sort_offs};
-    for (DevBuf* b : list) {
-      bufs[n] = b;
-      saved_p[n] = b->p;
-      saved_b[n] = b->bytes;
-      b->p = nullptr;
-      b->bytes = 0;
-      b->arena = a;
+    ix.ws.for_each_buf([&](DevBuf& b) {
+      bufs[n] = &b;
+      saved_p[n] = b.p;
+      saved_b[n] = b.bytes;
+      b.p = nullptr;
+      b.bytes = 0;
+      b.arena = a;
       ++n;
-    }
-    ix.no_alloc = true;
+    });
+    ix.ws.no_alloc = true;
   }
   ~Bind() {
     for (int i = 0; i < n; ++i) {
@@ -70,8 +65,8 @@ struct Bind {
       bufs[i]->bytes = saved_b[i];
       bufs[i]->arena = nullptr;
     }
-    ix.no_alloc = false;
-    ix.last_hit_rays = -1;  // no hit lists of this call survive in the index's own buffers
+    ix.ws.no_alloc = false;
+    ix.ws.last_hit_rays = -1;  // no hit lists of this call survive in the index's own buffers
   }
   Bind(const Bind&) = delete;
   Bind& operator=(const Bind&) = delete;
@@ -95,14 +90,14 @@ void render_static(Index& ix, const sph_hoa_camera* cam, const sph_hoa_tf* tf, f
     throw;
   }
   hip_check(hipStreamSynchronize(st), "sync");
-  if (ix.render_stats_pending) {
+  if (ix.ws.render_stats_pending) {
     // the placement counters live in the arena: read them before it is released
     unsigned long long c[6];
-    hip_check(hipMemcpy(c, ix.counters.p, sizeof(c), hipMemcpyDeviceToHost), "copy");
-    ix.stats.rays_global = (int64_t)c[3];
-    ix.stats.rays_jumps_device = (int64_t)c[4];
-    ix.stats.rays_scratch_device = (int64_t)c[5];
-    ix.render_stats_pending = false;
+    hip_check(hipMemcpy(c, ix.ws.counters.p, sizeof(c), hipMemcpyDeviceToHost), "copy");
+    ix.ws.stats.rays_global = (int64_t)c[3];
+    ix.ws.stats.rays_jumps_device = (int64_t)c[4];
+    ix.ws.stats.rays_scratch_device = (int64_t)c[5];
+    ix.ws.render_stats_pending = false;
   }
 }
 

@@ -62,9 +62,13 @@ def clustered_particles(seed: int = 2, n: int = 1_000_000, clusters: int = 16, b
     xyz = np.concatenate([pts, bg]).astype(np.float32)
     perm = rng.permutation(n)
     xyz = xyz[perm]
-    tree = cKDTree(xyz.astype(np.float64))
-    dist, _ = tree.query(xyz.astype(np.float64), k=k_neigh + 1, workers=-1)
-    h = (0.5 * dist[:, k_neigh]).astype(np.float32)
+    pts64 = xyz.astype(np.float64)
+    tree = cKDTree(pts64)
+    h = np.empty(n, dtype=np.float32)
+    chunk = 1 << 20  # bounded memory for large sets (the query's k + 1 distances and indices per point)
+    for a in range(0, n, chunk):
+        dist, _ = tree.query(pts64[a:a + chunk], k=k_neigh + 1, workers=-1)
+        h[a:a + chunk] = (0.5 * dist[:, k_neigh]).astype(np.float32)
     val = np.full(n, 1.0 / n, dtype=np.float32)
     return xyz, h, val
 

@@ -200,7 +200,8 @@ def test_device_memory_path_is_identical():
 
 def test_field_kernel_configurations_identical():
     """One to four ray work-groups per CU (the tuner's choices; with four, every tiny ray's layout
-    still fits a quarter of the LDS or moves to device memory) give the same bits."""
+    still fits a quarter of the LDS or moves to device memory), and the field kernel launched in
+    time slices, give the same bits."""
     sc = H.tiny_scene()
     o, v = synth.ortho_rays()
     o, v = o[:700], v[:700]
@@ -216,7 +217,21 @@ def test_field_kernel_configurations_identical():
         finally:
             del os.environ["SPH_HOA_FIELD_WGS"]
         res.append((a, img))
+    # the field kernel launched in time slices (each work-group a bounded share of the rays per
+    # launch, as on render-server lanes)
+    os.environ["SPH_HOA_TIME_SLICES"] = "5"
+    try:
+        a = _approx(sc, o, v, 0.0, 1.4)
+        img = L.sph_hoa_render(sc.index(), synth.tiny_camera(128, 128), tf, 0.0, 4.0e4, 1.4 / 256)
+        big = synth.tiny_camera(128, 128)
+        torch.cuda.synchronize()
+    finally:
+        del os.environ["SPH_HOA_TIME_SLICES"]
+    ref_big = L.sph_hoa_render(sc.index(), big, tf, 0.0, 4.0e4, 1.4 / 256)
+    torch.cuda.synchronize()
+    assert torch.equal(img, ref_big)
     a1, i1 = res[0]
+    res.append((a, i1))
     for a2, i2 in res[1:]:
         for k in ("ray_offsets", "t_start", "t_end", "coef", "ray_peak", "exact_t", "exact_coef", "knot_t", "knot_pid"):
             assert torch.equal(a1[k], a2[k]), k

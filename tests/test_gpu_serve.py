@@ -1,8 +1,9 @@
-"""Render server (sph_hoa_server_*): resident index, request queue, continuous batching.
+"""Render server (sph_hoa_server_*): resident indices, request queue, continuous batching.
 
 Every image served in a mix of concurrent requests must equal, bit for bit, the image
-sph_hoa_render gives for the same camera alone; admission by the memory budget decides how
-requests share batches; errors surface at submission or at the wait.
+sph_hoa_render gives for the same camera alone, whichever batch and lane carried it; admission by
+the memory budget decides how requests share batches and how many batches run at once; requests
+arriving while a batch runs start on a free lane; errors surface at submission or at the wait.
 """
 import threading
 
@@ -55,10 +56,10 @@ def test_served_images_equal_single_renders():
     big = synth.tiny_camera(256, 256)
     big_ref = L.sph_hoa_render(idx, big, tfs[0], 0.0, VMAX, STEP).clone()
     torch.cuda.synchronize()
-    srv = L.Server(hbm_budget_bytes=1 << 30)
+    srv = L.Server(hbm_budget_bytes=1 << 30, lanes=1)
     try:
         slot = srv.add_index(idx)
-        # a large request first keeps the worker busy while the small ones queue up behind it
+        # a large request first keeps the lane busy while the small ones queue up behind it
         big_id, big_out = srv.submit(slot, big, tfs[0], 0.0, VMAX, STEP)
         ids = [None] * len(cams)
         outs = [None] * len(cams)
@@ -83,6 +84,49 @@ def test_served_images_equal_single_renders():
         assert st["completed"] == len(cams) + 1 and st["failed"] == 0 and st["queued"] == 0
         assert st["batches"] < st["completed"]  # requests shared launches
         assert 0 < st["p50_ms"] <= st["p99_ms"] <= st["max_ms"]
+    finally:
+        srv.close()
+
+
+def test_requests_arriving_mid_batch_overlap_running_work():
+    """Continuous batching: a heavy request of one index is being rendered when small requests of
+    two indices arrive; a second lane admits them at once (their work overlaps the running batch on
+    the device, and they complete before it), and every image equals its single render bit for bit."""
+    tiny = H.tiny_scene()
+    ia = tiny.index()
+    xyz, h, val = synth.clustered_particles(seed=12, n=200_000)
+    heavy = H.Scene("wendland", 4, 3, 4096, xyz, h, val, 1e-3)
+    ib = heavy.index()
+    tf = torch.as_tensor(synth.transfer_function(), device="cuda")
+    persp = {"eye": [0.5, 0.5, -1.5], "look_at": [0.5, 0.5, 0.5], "up": [0.0, 1.0, 0.0], "fov_y_deg": 30.0,
+             "ortho": 0, "ortho_half_extent": 0.0, "width": 512, "height": 512, "t_min": 1.0, "t_max": 3.0}
+    big = persp
+    vb, sb = 300.0, 2.0 / 512
+    small_a = _cams()[:5]
+    small_b = [dict(persp, width=32 + 8 * i, height=24, fov_y_deg=5.0 + i) for i in range(4)]
+    big_ref = L.sph_hoa_render(ib, big, tf, 0.0, vb, sb).clone()
+    refs_a = _refs(ia, small_a, [tf])
+    refs_b = [L.sph_hoa_render(ib, c, tf, 0.0, vb, sb).clone() for c in small_b]
+    torch.cuda.synchronize()
+    srv = L.Server(hbm_budget_bytes=1 << 30, lanes=2)
+    try:
+        sa, sb_slot = srv.add_index(ia), srv.add_index(ib)
+        big_id, big_out = srv.submit(sb_slot, big, tf, 0.0, vb, sb)
+        subs_a = [srv.submit(sa, c, tf, 0.0, VMAX, STEP) for c in small_a]
+        subs_b = [srv.submit(sb_slot, c, tf, 0.0, vb, sb) for c in small_b]
+        lat_small = []
+        for (rid, out), ref in zip(subs_a + subs_b, refs_a + refs_b):
+            done, lat = srv.wait(rid, 120.0)
+            assert done
+            assert torch.equal(out, ref)
+            lat_small.append(lat)
+        done, lat_big = srv.wait(big_id, 120.0)
+        assert done
+        assert torch.equal(big_out, big_ref)
+        st = srv.stats()
+        assert st["lanes"] == 2 and st["completed"] == 1 + len(small_a) + len(small_b) and st["failed"] == 0
+        assert st["overlapped_batches"] >= 1 and st["max_in_flight"] == 2, st
+        assert max(lat_small) < lat_big, (lat_small, lat_big)
     finally:
         srv.close()
 
