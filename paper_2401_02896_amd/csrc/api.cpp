@@ -197,6 +197,37 @@ sph_hoa_status sph_hoa_build_index(const float* xyz, const float* h, const float
                                   hipMemcpyHostToDevice, st), "copy");
     sph::hip_check(hipMemcpyAsync(ix.lut_shat.p, ix.table.shat.data(), sizeof(double) * ix.table.shat.size(),
                                   hipMemcpyHostToDevice, st), "copy");
+    if (ix.lut_flags != 0) {
+      // the field kernel reads the rounded table in its own storage format (every value widens
+      // exactly to the rounded float64 kept beside it)
+      ix.lut_fmt = (ix.lut_flags == SPH_HOA_FLAG_LUT_FP32) ? 1 : (ix.lut_flags == SPH_HOA_FLAG_LUT_BF16) ? 2 : 3;
+      auto narrow = [&](const std::vector<double>& src, sph::DevBuf& dst) {
+        const size_t n = src.size();
+        if (ix.lut_fmt == 1) {
+          std::vector<float> v(n);
+          for (size_t i = 0; i < n; ++i) v[i] = (float)src[i];
+          dst.ensure(sizeof(float) * std::max<size_t>(1, n));
+          sph::hip_check(hipMemcpy(dst.p, v.data(), sizeof(float) * n, hipMemcpyHostToDevice), "copy");
+        } else {
+          std::vector<uint16_t> v(n);
+          for (size_t i = 0; i < n; ++i) {
+            const float f = (float)src[i];
+            if (ix.lut_fmt == 2) {
+              uint32_t u;
+              std::memcpy(&u, &f, 4);
+              v[i] = (uint16_t)(u >> 16);  // exact: the value already has 8 significant bits
+            } else {
+              const _Float16 hf = (_Float16)f;  // exact: already a binary16 value
+              std::memcpy(&v[i], &hf, 2);
+            }
+          }
+          dst.ensure(sizeof(uint16_t) * std::max<size_t>(1, n));
+          sph::hip_check(hipMemcpy(dst.p, v.data(), sizeof(uint16_t) * n, hipMemcpyHostToDevice), "copy");
+        }
+      };
+      narrow(ix.table.theta, ix.lut_theta_n);
+      narrow(ix.table.shat, ix.lut_shat_n);
+    }
     ix.lut_smid.ensure(sizeof(double) * std::max<size_t>(1, ix.table.smid.size()));
     if (!ix.table.smid.empty())
       sph::hip_check(hipMemcpyAsync(ix.lut_smid.p, ix.table.smid.data(), sizeof(double) * ix.table.smid.size(),

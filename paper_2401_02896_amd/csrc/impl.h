@@ -74,11 +74,13 @@ struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
   Arena* arena = nullptr;
-  // defer = true: growing keeps the old allocation until the buffer is destroyed instead of
-  // freeing it (hipFree waits for all work on the device, which would stall the work of other
-  // streams), and grows by at least half, so that few generations are kept
+  // defer = true: growing keeps the old allocation instead of freeing it (hipFree waits for all
+  // work on the device, which would stall the work of other streams) and grows by at least half, so
+  // that few generations are kept; they are freed together once they outgrow the new allocation
+  // (one wait for every few growths) and when the buffer is destroyed
   bool defer = false;
   std::vector<void*> kept;
+  size_t kept_bytes = 0;
   void ensure(size_t b) {
     if (b <= bytes) return;
     if (arena) {
@@ -92,10 +94,21 @@ struct DevBuf {
       return;
     }
     if (p) {
-      if (defer) kept.push_back(p);
-      else (void)hipFree(p);
+      if (defer) {
+        kept.push_back(p);
+        kept_bytes += bytes;
+      } else {
+        (void)hipFree(p);
+      }
     }
-    if (defer) b = std::max(b, bytes + bytes / 2);
+    if (defer) {
+      b = std::max(b, bytes + bytes / 2);
+      if (kept_bytes > b) {
+        for (void* q : kept) (void)hipFree(q);
+        kept.clear();
+        kept_bytes = 0;
+      }
+    }
     p = nullptr;
     bytes = 0;
     if (b == 0) return;
@@ -243,6 +256,8 @@ struct Index {
   DevBuf morton;  // uint64 key (level << 57 | morton)
   DevBuf cell_begin, cell_end;  // uint32 per cell, all levels
   DevBuf lut_theta, lut_shat;   // double
+  int lut_fmt = 0;              // field-kernel table format: 0 float64, 1 float32, 2 bfloat16, 3 binary16
+  DevBuf lut_theta_n, lut_shat_n;  // the table in that narrower format (lut_fmt > 0)
   DevBuf lut_smid;              // double [n][D+1] jumps at 0 (even K; float variant only)
   DevBuf float_scratch;         // float variant, per work-group
   Workspace ws;  // the index's own per-call state

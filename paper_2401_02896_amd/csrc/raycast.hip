@@ -520,8 +520,9 @@ struct FieldArgs {
   const float* val;
   const int32_t* orig;
   // table
-  const double* theta;  // [n_lut][P]
-  const double* shat;   // [n_lut][P][D+1]
+  const void* theta;    // [n_lut][P], stored as tab_fmt
+  const void* shat;     // [n_lut][P][D+1], stored as tab_fmt
+  int tab_fmt;          // table storage: 0 float64, 1 float32, 2 bfloat16, 3 binary16
   MethodConsts mc;
   MergeTables mt;
   // scheduling
@@ -618,6 +619,23 @@ __device__ __forceinline__ uint64_t binom_c(int n, int k) {
 // middle knot for even K.
 __host__ __device__ inline int jump_values_per_hit(int P, int even_k, int D) { return (P + even_k) * D; }
 
+// A row of the table of Sec. 3.1 as stored on the device: float64, or narrower (float32, bfloat16,
+// binary16) for the storage-precision study; every stored value widens exactly to float64.
+struct TabRef {
+  const void* base;
+  int fmt;      // 0 float64, 1 float32, 2 bfloat16, 3 binary16
+  int64_t off;  // first element of the row
+  __device__ __forceinline__ double operator[](int i) const {
+    const int64_t k = off + i;
+    switch (fmt) {
+      case 1: return (double)static_cast<const float*>(base)[k];
+      case 2: return (double)__uint_as_float((uint32_t)static_cast<const uint16_t*>(base)[k] << 16);
+      case 3: return (double)(float)static_cast<const _Float16*>(base)[k];
+      default: return static_cast<const double*>(base)[k];
+    }
+  }
+};
+
 // Quantized jump coefficients of all knots of one particle on one ray (Eq. quantized jumps from
 // the table, Sec. 4.3, with the integer closure of App. A.3), written as rows of orders 1..D
 // (order 0 never jumps):
@@ -631,7 +649,7 @@ __host__ __device__ inline int jump_values_per_hit(int P, int even_k, int D) { r
 // Computed once per hit, so the scans over the sorted knots only look values up.  Returns false if
 // a quantized coefficient left the int64 range.
 template <int D>
-__device__ bool hit_jumps(const MethodConsts& mc, const double* srow, double base, double u, const int32_t* off,
+__device__ bool hit_jumps(const MethodConsts& mc, TabRef srow, double base, double u, const int32_t* off,
                           uint64_t* rows) {
   const int P = mc.P;
   constexpr int ND = (D + 1) / 2;  // odd orders 1, 3, ...
@@ -982,8 +1000,8 @@ __device__ __forceinline__ void process_ray(const FieldArgs& A, Shared<D>& sh, c
     int li = (int)floor(lam * (double)A.mc.n_lut / kSupport);
     li = li < 0 ? 0 : (li > A.mc.n_lut - 1 ? A.mc.n_lut - 1 : li);
     // the table row: knots now, projection jumps as hit_jumps needs them
-    const double* trow = A.theta + (int64_t)li * P;
-    const double* srow = A.shat + (int64_t)li * P * (D + 1);
+    const TabRef trow{A.theta, A.tab_fmt, (int64_t)li * P};
+    const TabRef srow{A.shat, A.tab_fmt, (int64_t)li * P * (D + 1)};
     double th[kMaxP];
 #pragma unroll
     for (int m = 0; m < kMaxP; ++m) th[m] = (m < P) ? trow[m] : 0.0;
@@ -2097,8 +2115,10 @@ void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam,
   A.pos4 = ix.pos4.as<float4>();
   A.val = ix.val.as<float>();
   A.orig = ix.orig.as<int32_t>();
-  A.theta = ix.lut_theta.as<double>();
-  A.shat = ix.lut_shat.as<double>();
+  // the table in its storage format: narrow copies when the index stores it narrow
+  A.tab_fmt = ix.lut_fmt;
+  A.theta = ix.lut_fmt ? ix.lut_theta_n.p : ix.lut_theta.p;
+  A.shat = ix.lut_fmt ? ix.lut_shat_n.p : ix.lut_shat.p;
   A.mc = MethodConsts{K, D, P, (K % 2 == 0) ? 1 : 0, ix.n_lut, (int)ix.kernel, ix.tau, ix.sigma, kSupport, ix.merge_tol};
   A.mt = make_merge_tables(D);
   A.queue = queue;

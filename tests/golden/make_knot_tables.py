@@ -35,6 +35,8 @@ TABLES = [
     ("wendland_grad", 4, 3, 4096),
     ("wendland_c4_grad", 3, 2, 64),
     ("wendland_c6_grad", 2, 2, 64),
+    ("wendland", 4, 2, 4096),
+    ("wendland", 4, 4, 4096),
 ]
 
 
