@@ -582,23 +582,23 @@ def camera_rays(cam, torch):
 
 def run_gradient(a, torch, L, synth):
     """Gradient fields (Sec. 6): on the plain frame's pixel-centre rays (1M clustered particles,
-    Wendland C2, K = 4, D = 3, tol 1e-3, 512^2 rays), the value field and the four fields of the
-    transverse kernel -w'/r with particle values c/h^2 and c chi_a/h^2, from which every gradient
-    component along a ray is assembled ((v.e) F' - alpha G_0 - beta.(G_x, G_y, G_z)), all five by one
-    sph_hoa_approx_rays_shared call (the hits gathered once) with merged output.  A step is all five
-    fields of all rays; the same fields by five separate calls are timed after the timed region.
-    value = contributions/s over the five fields."""
+    Wendland C2, K = 4, D = 3, tol 1e-3, 512^2 rays), the value field and the three transverse
+    fields of the kernel -w'/r (particle values c/h, each pair's amplitude carrying its
+    perpendicular offset from the ray along x, y or z), from which every gradient component along a
+    ray is assembled ((v.e) F' - sum_a e_a T_a), all four by one sph_hoa_approx_rays_shared call
+    (the hits gathered once) with merged output.  A step is all four fields of all rays; the same
+    fields by four separate calls are timed after the timed region.  value = contributions/s over
+    the four fields."""
     xyz, h, val = synth.clustered_particles(n=a.particles)
     K, D, tol = 4, 3, 1e-3
     cam = synth.plain_camera(a.size, a.size)
     ro, rv = camera_rays(cam, torch)
-    c = val.astype(np.float64) / (h.astype(np.float64) ** 2)
-    gvals = [c.astype(np.float32)] + [(c * xyz[:, k].astype(np.float64)).astype(np.float32) for k in range(3)]
+    tv = (val.astype(np.float64) / h.astype(np.float64)).astype(np.float32)
     t_idx = time.time()
     idxs = [L.sph_hoa_build_index(xyz, h, val, kernel=L.KERNEL_WENDLAND_C2, degree=D, pieces=K, lut_entries=4096,
                                   merge_tol=tol)]
-    idxs += [L.sph_hoa_build_index(xyz, h, g, kernel=L.KERNEL_WENDLAND_C2_GRAD, degree=D, pieces=K,
-                                   lut_entries=4096, merge_tol=tol) for g in gvals]
+    idxs += [L.sph_hoa_build_index(xyz, h, tv, kernel=L.KERNEL_WENDLAND_C2_GRAD, degree=D, pieces=K,
+                                   lut_entries=4096, merge_tol=tol, transverse=ax) for ax in range(3)]
     build_s = time.time() - t_idx
     warm = L.sph_hoa_approx_rays_shared(idxs, ro, rv, cam["t_min"], cam["t_max"])
     cap = max(int(w["n_pieces"]) for w in warm) + 1024  # outputs sized once
@@ -615,7 +615,7 @@ def run_gradient(a, torch, L, synth):
         lat.append(time.perf_counter() - ts)
         pairs += sum(x["n_pairs"] for x in outs)
         del outs
-    # the same five fields by separate calls (each gathers its own hits), after the timed region
+    # the same four fields by separate calls (each gathers its own hits), after the timed region
     sep = []
     for _ in range(2):
         ts = time.perf_counter()
@@ -623,15 +623,15 @@ def run_gradient(a, torch, L, synth):
             L.sph_hoa_approx_rays(idx, ro, rv, cam["t_min"], cam["t_max"], capacity=cap)
         torch.cuda.synchronize()
         sep.append(time.perf_counter() - ts)
-    names = ["value F", "G_0 (c/h^2)", "G_x (c chi_x/h^2)", "G_y (c chi_y/h^2)", "G_z (c chi_z/h^2)"]
+    names = ["value F", "T_x", "T_y", "T_z"]
     result = {
-        "metric": "particle-ray contributions/s over the value field and the four transverse gradient fields",
+        "metric": "particle-ray contributions/s over the value field and the three transverse gradient fields",
         "value": pairs / sum(lat), "unit": "contributions/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
         "ms_per_step": float(np.median(lat) * 1e3), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "int64", "data": "synthetic",
         "config": {"workload": f"gradient: {a.size}x{a.size} pixel-centre rays of the plain camera, {a.particles} "
                                "clustered particles, Wendland C2 and its transverse kernel -w'/r, K=4, D=3, "
-                               "tol 1e-3, five fields per step through sph_hoa_approx_rays_shared (one gathering)",
+                               "tol 1e-3, four fields per step through sph_hoa_approx_rays_shared (one gathering)",
                    "pieces": {n: pieces[i] for i, n in enumerate(names)},
                    "separate_calls_ms": float(min(sep) * 1e3),
                    "index_build_s": build_s},

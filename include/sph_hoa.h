@@ -72,6 +72,15 @@ typedef enum {
 #define SPH_HOA_FLAG_LUT_FP32 2u
 #define SPH_HOA_FLAG_LUT_BF16 4u
 #define SPH_HOA_FLAG_LUT_FP16 8u
+/* sph_hoa_params.flags: a transverse gradient field (Sec. 6; at most one of the three): every
+ * (particle, ray) pair contributes with amplitude value * m, m = ((o + t_chi v - chi) . e_a) / h the
+ * particle's perpendicular offset from the ray along axis a in units of its smoothing length
+ * (|m| <= Lambda < q), so that with kernel <kernel>_GRAD (g = -w'/r) and values c / h the field T_a
+ * gives the gradient of the value field across the ray: e.grad f = (v.e) F'(t) - sum_a e_a T_a(t).
+ * Quanta derived from the data (a_max <= 0) then bound |value * m| (twice the value bound). */
+#define SPH_HOA_FLAG_TRANSVERSE_X 16u
+#define SPH_HOA_FLAG_TRANSVERSE_Y 32u
+#define SPH_HOA_FLAG_TRANSVERSE_Z 64u
 
 /* Method parameters (Sec. 3.2 K and D, Sec. 4.4 quanta, Sec. 5 bit length). */
 typedef struct {

@@ -58,10 +58,12 @@ from . import geometry, knots as knots_mod, lut as lut_mod
 
 
 
-def ray_knots(o, v, t_min, t_max, xyz, zeta, value, table, quanta, K, D, kind, hits=None):
+def ray_knots(o, v, t_min, t_max, xyz, zeta, value, table, quanta, K, D, kind, hits=None, transverse=None):
     """All knots of one ray, sorted by (t, pid, kidx).
 
     table: dict with 'theta' [n, P] and 'shat' [n, P, D+1]; quanta: (tau, sigma).
+    transverse = a (0, 1, 2): every pair's amplitude is the particle's value times the pair factor
+    m = ((o + t_chi v - chi) . e_a) / zeta of the transverse gradient fields (oracle.gradient).
     Returns (hits, sorted list of (t, pid, kidx, coefs)).
     """
     q = 2.0
@@ -79,7 +81,12 @@ def ray_knots(o, v, t_min, t_max, xyz, zeta, value, table, quanta, K, D, kind, h
         lam2, tchi = geometry.pair_terms(o, v, chi[pid], z[pid])
         lam = math.sqrt(float(lam2))
         li = lut_mod.lut_index(kind, lam, n_lut)
-        for (t, kidx, coefs) in knots_mod.pair_knots(float(tchi), z[pid], val[pid], table["theta"][li],
+        amp = val[pid]
+        if transverse is not None:
+            from .gradient import pair_factor
+
+            amp = np.float64(val[pid]) * np.float64(pair_factor(o, v, chi[pid], z[pid], transverse))
+        for (t, kidx, coefs) in knots_mod.pair_knots(float(tchi), z[pid], amp, table["theta"][li],
                                                    table["shat"][li], tau, sigma, K, D):
             out.append((t, int(pid), kidx, coefs))
     out.sort(key=lambda e: (e[0], e[1], e[2]))
@@ -274,9 +281,10 @@ def check_merged(pieces, merged, tol, tau, sigma, D, coef_tol=1e-5, resid_slack=
     return out
 
 
-def ray_field(o, v, t_min, t_max, xyz, zeta, value, table, quanta, K, D, kind, tol, hits=None):
-    """Everything the oracle knows about one ray (dict)."""
-    hits, sk = ray_knots(o, v, t_min, t_max, xyz, zeta, value, table, quanta, K, D, kind, hits=hits)
+def ray_field(o, v, t_min, t_max, xyz, zeta, value, table, quanta, K, D, kind, tol, hits=None, transverse=None):
+    """Everything the oracle knows about one ray (dict); transverse: as in ray_knots."""
+    hits, sk = ray_knots(o, v, t_min, t_max, xyz, zeta, value, table, quanta, K, D, kind, hits=hits,
+                         transverse=transverse)
     pieces, tail = exact_pieces(sk)
     tau, sigma = quanta
     nodes, M, margin = merge(pieces, tol, tau, sigma, D)

@@ -271,7 +271,8 @@ def optimal_knots(kind: str, lam: float, K: int, D: int, extra_starts=()):
     best = None
     for y0 in list(default_starts(n_pos_knots(K))) + [list(e) for e in extra_starts]:
         y, e2 = _local_opt(kind, lam, K, D, y0, s)
-        if best is None or e2 < best[1]:
+        # a start whose local search leaves the admissible shapes (non-finite E^2) is no optimum
+        if np.isfinite(e2) and np.all(np.isfinite(y)) and (best is None or e2 < best[1]):
             best = (y, e2)
     return s * best[0], best[1]
 
@@ -297,8 +298,10 @@ def _best_from(kind, lam, K, D, starts):
     s = math.sqrt((q - lam) * (q + lam))
     best = None
     for y0 in starts:
+        if not np.all(np.isfinite(y0)):
+            continue
         y, e2 = _local_opt(kind, lam, K, D, list(y0), s)
-        if best is None or e2 < best[1]:
+        if np.isfinite(e2) and np.all(np.isfinite(y)) and (best is None or e2 < best[1]):
             best = (y, e2)
     return best
 

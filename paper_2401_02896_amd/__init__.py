@@ -26,6 +26,9 @@ FLAG_EXACT = 1
 FLAG_LUT_FP32 = 2
 FLAG_LUT_BF16 = 4
 FLAG_LUT_FP16 = 8
+FLAG_TRANSVERSE_X = 16
+FLAG_TRANSVERSE_Y = 32
+FLAG_TRANSVERSE_Z = 64
 
 STATUS = {0: "OK", 1: "E_INVALID_ARG", 2: "E_OUT_OF_MEMORY", 3: "E_OVERFLOW", 4: "E_DEVICE", 5: "E_UNSUPPORTED",
           6: "E_INTERNAL", 7: "E_BUSY", 8: "E_CANCELLED"}
@@ -253,11 +256,12 @@ class Index:
 
 def sph_hoa_build_index(xyz, h, value, kernel=KERNEL_CUBIC, degree=2, pieces=4, lut_entries=4096, merge_tol=1e-3,
                         a_max=0.0, h_repr=0.0, phi_repr=0.0, tau=0.0, knot_table=None, lut_precision="fp64",
-                        jump_table=None, jump_table_mid=None):
+                        jump_table=None, jump_table_mid=None, transverse=None):
     """Build an index (sph_hoa_build_index).  xyz [n,3], h [n], value [n]: tensors or arrays.
     lut_precision: storage precision of the float table, "fp64", "fp32", "bf16" or "fp16".
     jump_table [lut_entries, ceil(K/2), D+1] / jump_table_mid [lut_entries, D+1] (even K): projection
-    jumps replacing the library's own (with knot_table)."""
+    jumps replacing the library's own (with knot_table).  transverse = 0, 1 or 2: a transverse
+    gradient field along that axis (SPH_HOA_FLAG_TRANSVERSE_X/Y/Z)."""
     import numpy as np
 
     x = _dev_f32(xyz)
@@ -269,6 +273,8 @@ def sph_hoa_build_index(xyz, h, value, kernel=KERNEL_CUBIC, degree=2, pieces=4, 
     flags = {"fp64": 0, "fp32": FLAG_LUT_FP32, "bf16": FLAG_LUT_BF16, "fp16": FLAG_LUT_FP16}.get(lut_precision)
     if flags is None:
         raise ValueError(f"lut_precision must be fp64, fp32, bf16 or fp16, got {lut_precision!r}")
+    if transverse is not None:
+        flags |= {0: FLAG_TRANSVERSE_X, 1: FLAG_TRANSVERSE_Y, 2: FLAG_TRANSVERSE_Z}[int(transverse)]
     p = Params(degree, pieces, lut_entries, 64, merge_tol, a_max, h_repr, phi_repr, tau, None, flags)
     kt = None
     if knot_table is not None:

@@ -141,10 +141,16 @@ sph_hoa_status sph_hoa_build_index(const float* xyz, const float* h, const float
     require(std::isfinite(p->a_max) && std::isfinite(p->h_repr) && std::isfinite(p->phi_repr) &&
                 std::isfinite(p->tau), "quanta parameters must be finite");
     const uint32_t lut_bits = SPH_HOA_FLAG_LUT_FP32 | SPH_HOA_FLAG_LUT_BF16 | SPH_HOA_FLAG_LUT_FP16;
-    require((p->flags & ~lut_bits) == 0, "params.flags: only the SPH_HOA_FLAG_LUT_* table precisions");
-    require(p->flags == 0 || p->flags == SPH_HOA_FLAG_LUT_FP32 || p->flags == SPH_HOA_FLAG_LUT_BF16 ||
-                p->flags == SPH_HOA_FLAG_LUT_FP16,
+    const uint32_t trans_bits = SPH_HOA_FLAG_TRANSVERSE_X | SPH_HOA_FLAG_TRANSVERSE_Y | SPH_HOA_FLAG_TRANSVERSE_Z;
+    require((p->flags & ~(lut_bits | trans_bits)) == 0,
+            "params.flags: only the SPH_HOA_FLAG_LUT_* table precisions and SPH_HOA_FLAG_TRANSVERSE_*");
+    const uint32_t lut_flag = p->flags & lut_bits, trans_flag = p->flags & trans_bits;
+    require(lut_flag == 0 || lut_flag == SPH_HOA_FLAG_LUT_FP32 || lut_flag == SPH_HOA_FLAG_LUT_BF16 ||
+                lut_flag == SPH_HOA_FLAG_LUT_FP16,
             "params.flags: one table precision");
+    require(trans_flag == 0 || trans_flag == SPH_HOA_FLAG_TRANSVERSE_X || trans_flag == SPH_HOA_FLAG_TRANSVERSE_Y ||
+                trans_flag == SPH_HOA_FLAG_TRANSVERSE_Z,
+            "params.flags: one transverse axis");
     sph::Index& ix = H->ix;
     ix.n = n;
     ix.kernel = k;
@@ -154,6 +160,10 @@ sph_hoa_status sph_hoa_build_index(const float* xyz, const float* h, const float
     ix.n_lut = n_lut;
     ix.merge_tol = p->merge_tol;
     ix.a_max = p->a_max > 0 ? p->a_max : 0.0;
+    ix.trans_axis = trans_flag == SPH_HOA_FLAG_TRANSVERSE_X ? 0
+                    : trans_flag == SPH_HOA_FLAG_TRANSVERSE_Y ? 1
+                    : trans_flag == SPH_HOA_FLAG_TRANSVERSE_Z ? 2
+                                                              : -1;
     ix.h_repr = p->h_repr > 0 ? p->h_repr : 0.0;
     ix.phi_repr = p->phi_repr > 0 ? p->phi_repr : 0.0;
     if (p->knot_table) {
@@ -181,14 +191,14 @@ sph_hoa_status sph_hoa_build_index(const float* xyz, const float* h, const float
         ix.table.smid.assign(nm, 0.0);
       }
     }
-    if (p->flags != 0) {
-      const Storage fmt = (p->flags == SPH_HOA_FLAG_LUT_BF16)   ? Storage::BF16
-                          : (p->flags == SPH_HOA_FLAG_LUT_FP16) ? Storage::F16
+    if (lut_flag != 0) {
+      const Storage fmt = (lut_flag == SPH_HOA_FLAG_LUT_BF16)   ? Storage::BF16
+                          : (lut_flag == SPH_HOA_FLAG_LUT_FP16) ? Storage::F16
                                                                 : Storage::F32;
       for (double& x : ix.table.theta) x = round_storage(x, fmt);
       for (double& x : ix.table.shat) x = round_storage(x, fmt);
       for (double& x : ix.table.smid) x = round_storage(x, fmt);
-      ix.lut_flags = p->flags;
+      ix.lut_flags = lut_flag;
     }
     hipStream_t st = (hipStream_t)stream;
     ix.lut_theta.ensure(sizeof(double) * ix.table.theta.size());
@@ -232,7 +242,10 @@ sph_hoa_status sph_hoa_build_index(const float* xyz, const float* h, const float
     if (!ix.table.smid.empty())
       sph::hip_check(hipMemcpyAsync(ix.lut_smid.p, ix.table.smid.data(), sizeof(double) * ix.table.smid.size(),
                                     hipMemcpyHostToDevice, st), "copy");
+    const bool derived_amax = !(p->a_max > 0);
     sph::build_index_device(ix, xyz, h, value, st);
+    // a transverse field's amplitudes are value * m with |m| < q = 2: twice the value bound
+    if (ix.trans_axis >= 0 && derived_amax) ix.a_max *= 2.0;
     const double int_max = 9223372036854775807.0;  // 2^63 - 1 (rounds to 2^63 in double)
     if (ix.a_max > 0.0) {
       ix.sigma = ix.a_max / int_max;

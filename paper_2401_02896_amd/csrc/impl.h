@@ -249,6 +249,7 @@ struct Index {
   int grid_bits = 1;  // Morton bits per axis in the sort keys
   Table table;
   uint32_t lut_flags = 0;  // table storage precision (SPH_HOA_FLAG_LUT_*), 0: float64
+  int trans_axis = -1;     // transverse gradient field along this axis (SPH_HOA_FLAG_TRANSVERSE_*), -1: none
   // device data (Morton order)
   DevBuf pos4;    // float4 x, y, z, h
   DevBuf val;     // float amplitude

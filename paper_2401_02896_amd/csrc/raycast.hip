@@ -523,6 +523,7 @@ struct FieldArgs {
   const void* theta;    // [n_lut][P], stored as tab_fmt
   const void* shat;     // [n_lut][P][D+1], stored as tab_fmt
   int tab_fmt;          // table storage: 0 float64, 1 float32, 2 bfloat16, 3 binary16
+  int trans_axis;       // >= 0: pair amplitude value * ((o + t_chi v - chi) . e_axis) / h
   MethodConsts mc;
   MergeTables mt;
   // scheduling
@@ -1021,7 +1022,15 @@ __device__ __forceinline__ void process_ray(const FieldArgs& A, Shared<D>& sh, c
 #pragma unroll
     for (int m = 0; m < kMaxP; ++m)
       if (m < P) park[s * span32 + 1 + m] = offs[m];
-    const double base = (double)vj / (sigma * (z * z * z));
+    // transverse gradient field: the pair's amplitude carries its perpendicular offset along the
+    // axis, m = (t_chi v_a - dx_a) / h
+    double amp = (double)vj;
+    if (A.trans_axis >= 0) {
+      const double va = A.trans_axis == 0 ? v[0] : (A.trans_axis == 1 ? v[1] : v[2]);
+      const double da = A.trans_axis == 0 ? dxx : (A.trans_axis == 1 ? dxy : dxz);
+      amp = amp * ((tchi * va - da) / z);
+    }
+    const double base = amp / (sigma * (z * z * z));
     const double u = tau / z;
     if (!hit_jumps<D>(A.mc, srow, base, u, offs, S.jmp + s * S.nj)) atomicOr(A.flags, kFlagCoefRange);
     const int32_t oP = (P == 1) ? offs[0] : ((P == 2) ? offs[1] : offs[2]);
@@ -2049,6 +2058,7 @@ void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam,
   }
   if (out.flt) {
     // float accumulation variant: same hits, its own sweep
+    if (ix.trans_axis >= 0) throw Error(SPH_HOA_E_UNSUPPORTED, "the float variant has no transverse fields");
     sph_hoa_float_field* ff = out.flt;
     const int64_t need = float_field_capacity(total_pairs, n_rays, K, out.n_reinit);
     ff->n_slots = need;
@@ -2117,6 +2127,7 @@ void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam,
   A.orig = ix.orig.as<int32_t>();
   // the table in its storage format: narrow copies when the index stores it narrow
   A.tab_fmt = ix.lut_fmt;
+  A.trans_axis = ix.trans_axis;
   A.theta = ix.lut_fmt ? ix.lut_theta_n.p : ix.lut_theta.p;
   A.shat = ix.lut_fmt ? ix.lut_shat_n.p : ix.lut_shat.p;
   A.mc = MethodConsts{K, D, P, (K % 2 == 0) ? 1 : 0, ix.n_lut, (int)ix.kernel, ix.tau, ix.sigma, kSupport, ix.merge_tol};

@@ -26,10 +26,12 @@ KIND_ID = {"cubic": 0, "wendland": 1, "wendland_c4": 2, "wendland_c6": 3, "wendl
 class Scene:
     """quanta: (a_max, h_repr, phi_repr, tau, sigma) when already known (skips the data analysis)."""
 
-    def __init__(self, kind, K, D, n_lut, xyz, h, val, tol, tau_scale=1.0, lut_precision="fp64", quanta=None):
+    def __init__(self, kind, K, D, n_lut, xyz, h, val, tol, tau_scale=1.0, lut_precision="fp64", quanta=None,
+                 transverse=None):
         self.kind, self.K, self.D, self.n_lut, self.tol = kind, K, D, n_lut, tol
         self.xyz, self.h, self.val = xyz, h, val
         self.lut_precision = lut_precision
+        self.transverse = transverse  # transverse gradient field along this axis (pair amplitude value * m)
         self.tau_scale = tau_scale
         self.theta = load_knots(kind, K, D, n_lut)
         # the table as stored (precision study): knots and projection rows rounded once
@@ -37,6 +39,8 @@ class Scene:
         self._shat = None
         if quanta is None:
             self.a_max = grid.a_max(kind, xyz, h, val)
+            if transverse is not None:
+                self.a_max *= 2.0  # |value * m| <= 2 |value|
             self.h_repr, self.phi_repr = grid.representatives(h, val)
             self.tau, self.sigma = quanta_mod.choose_quanta(kind, D, self.a_max, self.h_repr, self.phi_repr)
             self.tau *= tau_scale
@@ -47,7 +51,7 @@ class Scene:
     def spec(self):
         """Constructor arguments of an equal scene (for worker processes)."""
         return dict(kind=self.kind, K=self.K, D=self.D, n_lut=self.n_lut, xyz=self.xyz, h=self.h, val=self.val,
-                    tol=self.tol, lut_precision=self.lut_precision,
+                    tol=self.tol, lut_precision=self.lut_precision, transverse=self.transverse,
                     quanta=(self.a_max, self.h_repr, self.phi_repr, self.tau, self.sigma))
 
     @property
@@ -67,13 +71,13 @@ class Scene:
                                                 pieces=self.K, lut_entries=self.n_lut, merge_tol=self.tol,
                                                 a_max=self.a_max, h_repr=self.h_repr, phi_repr=self.phi_repr,
                                                 tau=self.tau, knot_table=self.theta,
-                                                lut_precision=self.lut_precision)
+                                                lut_precision=self.lut_precision, transverse=self.transverse)
         return self._index
 
     def oracle_ray(self, o, v, t_min, t_max, tol=None):
         return field.ray_field(np.asarray(o, np.float64), np.asarray(v, np.float64), t_min, t_max, self.xyz, self.h,
                                self.val, self.table(), (self.tau, self.sigma), self.K, self.D, self.kind,
-                               self.tol if tol is None else tol)
+                               self.tol if tol is None else tol, transverse=self.transverse)
 
 
 class LazyRows:

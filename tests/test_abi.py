@@ -39,8 +39,8 @@ def test_build_rejects_bad_params_before_device_work():
 
     lib = L.lib()
     buf = (ctypes.c_float * 12)()
-    for flags, degree in ((L.FLAG_LUT_FP32 | L.FLAG_LUT_BF16, 2), (L.FLAG_LUT_BF16 | L.FLAG_LUT_FP16, 2), (16, 2),
-                          (0, 9)):
+    for flags, degree in ((L.FLAG_LUT_FP32 | L.FLAG_LUT_BF16, 2), (L.FLAG_LUT_BF16 | L.FLAG_LUT_FP16, 2), (128, 2),
+                          (L.FLAG_TRANSVERSE_X | L.FLAG_TRANSVERSE_Z, 2), (0, 9)):
         p = L.Params(degree, 4, 64, 64, 1e-3, 0.0, 0.0, 0.0, 0.0, None, flags)
         h = ctypes.c_void_p()
         st = lib.sph_hoa_build_index(buf, buf, buf, 4, 0, ctypes.byref(p), None, ctypes.byref(h))
