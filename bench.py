@@ -217,18 +217,41 @@ def run_batch(a, torch, L, synth):
     pairs = st["n_pairs"] - st0["n_pairs"]
     imgs = [o.cpu().numpy().reshape(-1, 4) for o in outs]
     srv.close()
-    # the same bundles as one render_batch call per index, sequentially
+    # the same bundles as one render_batch call per index, sequentially (per-index kernel times and
+    # ray layouts from the library's timing), and as one sph_hoa_render call per bundle (the plain
+    # path on the same work)
     groups = {k: [j for j in range(n_b) if (int(set_of[j]), int(deg_of[j])) == k] for k in keys}
     for k in keys:
         L.sph_hoa_render_batch(idx[k], [cams[j] for j in groups[k]], tf, vmin, vmax, step)
     torch.cuda.synchronize()
     ts = time.perf_counter()
     seq_pairs = 0
+    per_index = {}
     for k in keys:
+        idx[k].set_timing(True)
         L.sph_hoa_render_batch(idx[k], [cams[j] for j in groups[k]], tf, vmin, vmax, step)
-        seq_pairs += idx[k].stats()["n_pairs"]
+        st_k = idx[k].stats()
+        idx[k].set_timing(False)
+        seq_pairs += st_k["n_pairs"]
+        per_index[f"set{k[0]}_D{k[1]}"] = {
+            "bundles": len(groups[k]), "rays": st_k["n_rays"], "pairs": st_k["n_pairs"],
+            "max_hits_per_ray": st_k["max_hits"], "field_ms": st_k["ms_field"], "gather_ms": st_k["ms_gather"],
+            "rays_jump_rows_in_hbm": st_k["rays_jumps_device"],
+            "rays_jump_rows_and_sort_scratch_in_hbm": st_k["rays_scratch_device"],
+            "rays_all_in_hbm": st_k["rays_global"]}
     torch.cuda.synchronize()
     seq_s = time.perf_counter() - ts
+    for j in range(n_b):
+        L.sph_hoa_render(idx[(int(set_of[j]), int(deg_of[j]))], cams[j], tf, vmin, vmax, step)
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    single_pairs = 0
+    for j in range(n_b):
+        ix = idx[(int(set_of[j]), int(deg_of[j]))]
+        L.sph_hoa_render(ix, cams[j], tf, vmin, vmax, step)
+        single_pairs += ix.stats()["n_pairs"]
+    torch.cuda.synchronize()
+    single_s = time.perf_counter() - ts
     n_rays = sum(c["width"] * c["height"] for c in cams)
     step_ms = np.array(step_lat) * 1e3
     result = {
@@ -246,6 +269,9 @@ def run_batch(a, torch, L, synth):
                    "server": _lane_summary(st, st0),
                    "sequential_render_batch_per_index_s": seq_s,
                    "sequential_contributions_per_s": seq_pairs / seq_s,
+                   "single_render_calls_s": single_s,
+                   "single_render_calls_contributions_per_s": single_pairs / single_s,
+                   "per_index": per_index,
                    "generate_s": gen_s, "index_build_s": index_s},
         "cpu_baseline": None,
     }
