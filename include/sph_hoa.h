@@ -33,7 +33,10 @@ typedef enum {
   SPH_HOA_OK = 0,
   SPH_HOA_E_INVALID_ARG = 1,   /* bad argument: NULL, NaN, h <= 0, non-unit direction, bad K/D ... */
   SPH_HOA_E_OUT_OF_MEMORY = 2, /* device allocation failed, or a caller capacity is too small */
-  SPH_HOA_E_OVERFLOW = 3,      /* a quantized position or coefficient leaves its integer range */
+  SPH_HOA_E_OVERFLOW = 3,      /* a quantized position or coefficient leaves its integer range: knot
+                                  positions are int64 quanta (|t| + q h_max < 4e18 tau), and the
+                                  knots of one ray must span fewer than 2^32 quanta (positions are
+                                  handled relative to the ray's first knot in 32 bits) */
   SPH_HOA_E_DEVICE = 4,        /* HIP runtime error */
   SPH_HOA_E_UNSUPPORTED = 5,   /* configuration outside the implemented range */
   SPH_HOA_E_INTERNAL = 6,      /* an internal invariant failed (e.g. a ray's knots did not cancel) */

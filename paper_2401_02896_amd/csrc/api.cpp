@@ -277,6 +277,16 @@ sph_hoa_status sph_hoa_index_free(sph_hoa_index idx) {
 namespace {
 
 // Output arrays of a field call for n rays; returns whether exact mode is on.
+// Knot positions are 64-bit integers (length quanta): the segment, widened by the coarsest cell
+// (at least q h_max), must stay within that range.  Inside a ray the kernel handles positions
+// relative to the ray's first knot in unsigned 32 bits and reports E_OVERFLOW for a ray whose knots
+// span 2^32 quanta or more.
+void check_positions(const sph::Index& ix, double t_min, double t_max) {
+  const double c = ix.grid.lv[ix.grid.n_levels - 1].c;
+  if (!((std::max(std::fabs(t_min), std::fabs(t_max)) + c) / ix.tau < 4.0e18))
+    throw sph::Error(SPH_HOA_E_OVERFLOW, "ray positions beyond the 64-bit range of length quanta");
+}
+
 bool check_field_out(const sph::Index& ix, const sph_hoa_field* out, int64_t n, uint32_t flags) {
   require(out->capacity >= 0, "capacity must be >= 0");
   if (n > 0) {
@@ -306,10 +316,7 @@ void approx_rays_one(sph_hoa_index idx, const sph_hoa_rays* rays, sph_hoa_field*
   if (rays->n > 0) require(rays->origin && rays->dir, "NULL ray arrays");
   const bool exact = check_field_out(idx->ix, out, rays->n, flags);
   sph::Index& ix = idx->ix;
-  const double span = std::max(std::fabs((double)rays->t_min), std::fabs((double)rays->t_max)) +
-                      ix.grid.lv[ix.grid.n_levels - 1].c;
-  if (!(span / ix.tau < 2.1e9))
-    throw sph::Error(SPH_HOA_E_OVERFLOW, "ray segment too long for int32 positions (|t| + q h_max >= 2^31 tau)");
+  check_positions(ix, (double)rays->t_min, (double)rays->t_max);
   sph::FieldOut fo{out, nullptr, nullptr, exact};
   hipStream_t st = (hipStream_t)stream;
   ix.last_stream = st;
@@ -404,10 +411,7 @@ void check_camera(const sph::Index& ix, const sph_hoa_camera* cam, const sph_hoa
   if (tf)
     require(((double)cam->t_max - (double)cam->t_min) / (double)tf->step < 1073741824.0,
             "step too small: more than 2^30 samples per ray");
-  const double span = std::max(std::fabs((double)cam->t_min), std::fabs((double)cam->t_max)) +
-                      ix.grid.lv[ix.grid.n_levels - 1].c;
-  if (!(span / ix.tau < 2.1e9))
-    throw sph::Error(SPH_HOA_E_OVERFLOW, "ray segment too long for int32 positions (|t| + q h_max >= 2^31 tau)");
+  check_positions(ix, (double)cam->t_min, (double)cam->t_max);
 }
 
 void check_tf(const sph_hoa_tf* tf) {

@@ -29,7 +29,7 @@ constexpr double kAmaxMargin = 1.25;
 // error-flag bits raised by kernels
 enum : uint32_t {
   kFlagBadInput = 1u,       // NaN / h <= 0 / non-unit direction
-  kFlagPosRange = 2u,       // a quantized position left the int32 range
+  kFlagPosRange = 2u,       // a ray's knots span 2^32 quanta or more, or a knot offset reached 2^31
   kFlagCoefRange = 4u,      // a quantized coefficient left |x| < 2^62
   kFlagTail = 8u,           // a ray's accumulated coefficients did not return to zero
   kFlagWindow = 16u,        // grid enumeration window too small (internal)

@@ -574,7 +574,7 @@ struct FieldArgs {
 // finalize_node() replaces the moments by the projection's power coefficients in u = (t - a) / (b - a).
 template <int D>
 struct Node {
-  int32_t a, b;     // [a, b] in length quanta
+  uint32_t a, b;    // [a, b] in length quanta, relative to the ray's first knot
   int32_t n;        // exact pieces in it
   int32_t pad;
   double m[D + 1];  // m_i = int_a^b F(t) (t - a)^i dt; after finalize_node: power coefficients (world units)
@@ -720,7 +720,7 @@ __device__ bool hit_jumps(const MethodConsts& mc, TabRef srow, double base, doub
 // integers read as signed).  Moments and energy by (D + 1)-point Gauss-Legendre quadrature, exact
 // for the degree <= 2D integrands.
 template <int D>
-__device__ __forceinline__ Node<D> make_leaf(const MergeTables& mt, int32_t ta, int32_t tb, const uint64_t* coef) {
+__device__ __forceinline__ Node<D> make_leaf(const MergeTables& mt, uint32_t ta, uint32_t tb, const uint64_t* coef) {
   Node<D> n;
   n.a = ta;
   n.b = tb;
@@ -833,7 +833,7 @@ __device__ __forceinline__ int key_kidx(uint64_t key) { return (int)((uint32_t)k
 template <int D>
 struct Agg {
   uint64_t a[D + 1];
-  int32_t t;  // position of the last knot
+  uint32_t t;  // position of the last knot (relative to the ray's first knot)
   int32_t valid;
 };
 
@@ -852,7 +852,7 @@ __device__ __forceinline__ void agg_combine(const Agg<D>& x, const Agg<D>& y, Ag
   uint64_t s[D + 1];
 #pragma unroll
   for (int d = 0; d <= D; ++d) s[d] = x.a[d];
-  taylor_shift<D>(s, (uint32_t)y.t - (uint32_t)x.t);
+  taylor_shift<D>(s, y.t - x.t);
 #pragma unroll
   for (int d = 0; d <= D; ++d) out.a[d] = s[d] + y.a[d];
 }
@@ -868,7 +868,7 @@ struct Shared {
   unsigned long long peak;
   int64_t ray;
   int64_t base_out, base_ex;
-  int32_t t_lo, t_hi;  // range of the ray's knot positions
+  long long t_lo, t_hi;  // range of the ray's knot positions (length quanta)
 };
 
 // Per-ray storage carved from LDS or from the work-group's global slab.
@@ -973,8 +973,8 @@ __device__ __forceinline__ void process_ray(const FieldArgs& A, Shared<D>& sh, c
     v[k] = A.v[3 * r + k];
   }
   if (tid == 0) {
-    sh.t_lo = 0x7fffffff;
-    sh.t_hi = (int32_t)0x80000000;
+    sh.t_lo = 0x7fffffffffffffffll;
+    sh.t_hi = -0x7fffffffffffffffll - 1;
   }
   __syncthreads();
   // ---- per-hit records (Sec. 4.3: quantized positions and jumps); the hit order does not matter:
@@ -984,7 +984,7 @@ __device__ __forceinline__ void process_ray(const FieldArgs& A, Shared<D>& sh, c
   const double tau = A.mc.tau, sigma = A.mc.sigma;
   int32_t* park = reinterpret_cast<int32_t*>(S.kkey);
   const int span32 = 2 * (K + 1);
-  int32_t my_lo = 0x7fffffff, my_hi = (int32_t)0x80000000;
+  long long my_lo = 0x7fffffffffffffffll, my_hi = -0x7fffffffffffffffll - 1;
 #pragma unroll 1
   for (int s = tid; s < (int)nh; s += kFieldThreads) {
     const uint32_t j = A.hits[hoff + s];
@@ -1006,22 +1006,24 @@ __device__ __forceinline__ void process_ray(const FieldArgs& A, Shared<D>& sh, c
     double th[kMaxP];
 #pragma unroll
     for (int m = 0; m < kMaxP; ++m) th[m] = (m < P) ? trow[m] : 0.0;
+    // positions in 64-bit integers, knot offsets (at most q h / tau) in 32 bits
     const double t0d = rint(tchi / tau);
-    bool bad = !(fabs(t0d) < 2.0e9);
-    const int32_t t0 = bad ? 0 : (int32_t)t0d;
+    bool bad = !(fabs(t0d) < 4.0e18);
+    const long long t0 = bad ? 0 : (long long)t0d;
     int32_t offs[kMaxP] = {0, 0, 0};
 #pragma unroll
     for (int m = 0; m < kMaxP; ++m) {
       if (m >= P) continue;
       const double od = rint(z * th[m] / tau);
-      if (!(od < 2.0e9) || !(fabs(t0d) + od < 2147483647.0)) bad = true;
+      if (!(od < 2.0e9)) bad = true;
       offs[m] = bad ? 0 : (int32_t)od;
     }
     if (bad) atomicOr(A.flags, kFlagPosRange);
-    park[s * span32] = t0;
+    park[s * span32] = (int32_t)(uint32_t)(unsigned long long)t0;
+    park[s * span32 + 1] = (int32_t)(uint32_t)((unsigned long long)t0 >> 32);
 #pragma unroll
     for (int m = 0; m < kMaxP; ++m)
-      if (m < P) park[s * span32 + 1 + m] = offs[m];
+      if (m < P) park[s * span32 + 2 + m] = offs[m];
     // transverse gradient field: the pair's amplitude carries its perpendicular offset along the
     // axis, m = (t_chi v_a - dx_a) / h
     double amp = (double)vj;
@@ -1040,31 +1042,35 @@ __device__ __forceinline__ void process_ray(const FieldArgs& A, Shared<D>& sh, c
   atomicMin(&sh.t_lo, my_lo);
   atomicMax(&sh.t_hi, my_hi);
   __syncthreads();
-  const int32_t t_lo = sh.t_lo;
-  auto key_t = [t_lo](uint64_t key) { return (int32_t)((uint32_t)t_lo + (uint32_t)(key >> 32)); };
+  // Inside the ray, positions are relative to its first knot, t_lo: unsigned 32-bit keys, nodes and
+  // differences (the knots of one ray must span less than 2^32 quanta, checked here); absolute
+  // positions t_lo + t only at the outputs.
+  const long long t_lo = sh.t_lo;
+  if (tid == 0 && !(sh.t_hi - t_lo < 4294967295ll)) atomicOr(A.flags, kFlagPosRange);
+  auto key_t = [](uint64_t key) { return (uint32_t)(key >> 32); };
   // ---- knot keys: (position - t_lo) in the high half, (slot, kidx) in the low half; kidx = k + P
   // for the knot at t0 + sign(k) o_|k|, laid out slot-major so that the stable sort leaves equal
   // positions in (slot, kidx) order.  Each thread rewrites the spans of the hits it parked.
   for (int s = tid; s < (int)nh; s += kFieldThreads) {
-    const int32_t t0 = park[s * span32];
+    const long long t0 = (long long)(((unsigned long long)(uint32_t)park[s * span32 + 1] << 32) |
+                                     (unsigned long long)(uint32_t)park[s * span32]);
     int32_t o3[kMaxP];
 #pragma unroll
-    for (int m = 0; m < kMaxP; ++m) o3[m] = (m < P) ? park[s * span32 + 1 + m] : 0;
+    for (int m = 0; m < kMaxP; ++m) o3[m] = (m < P) ? park[s * span32 + 2 + m] : 0;
     for (int kidx = 0; kidx <= 2 * P; ++kidx) {
       const int k = kidx - P;
       if (k == 0 && !A.mc.even_k) continue;
       int32_t om = 0;
 #pragma unroll
       for (int m = 0; m < kMaxP; ++m) om = (m == (k < 0 ? -k : k) - 1) ? o3[m] : om;
-      const int32_t t = t0 + (k < 0 ? -om : om);
+      const long long t = t0 + (k < 0 ? -om : om);
       const int slotk = A.mc.even_k ? kidx : (k < 0 ? kidx : kidx - 1);
-      S.kkey[s * (K + 1) + slotk] =
-          ((uint64_t)((uint32_t)t - (uint32_t)t_lo) << 32) | ((uint64_t)s << 3) | (uint64_t)kidx;
+      S.kkey[s * (K + 1) + slotk] = ((uint64_t)(uint32_t)(t - t_lo) << 32) | ((uint64_t)s << 3) | (uint64_t)kidx;
     }
   }
   __syncthreads();
   {
-    const uint32_t range = (uint32_t)sh.t_hi - (uint32_t)t_lo;
+    const uint32_t range = (uint32_t)(sh.t_hi - t_lo);
     int nbits = 4;
     while (nbits < 32 && (range >> nbits) != 0) nbits += 4;
     radix_sort_u64<kFieldThreads, true>(S.kkey, S.kkey2, (int)nk, 32, nbits, sh.rtab, tid);
@@ -1083,7 +1089,7 @@ __device__ __forceinline__ void process_ray(const FieldArgs& A, Shared<D>& sh, c
     for (int d = 0; d <= D; ++d) g.a[d] = 0;
     for (int i = k_lo; i < k_hi; ++i) {
       const uint64_t key = S.kkey[kpad32(i)];
-      const int32_t t = key_t(key);
+      const uint32_t t = key_t(key);
       uint64_t jmp[D + 1];
       jump_of<D>(A.mc, S, key, jmp);
       if (g.valid) taylor_shift<D>(g.a, (uint32_t)(t - g.t));
@@ -1123,7 +1129,7 @@ __device__ __forceinline__ void process_ray(const FieldArgs& A, Shared<D>& sh, c
     Agg<D> st = carry;
     for (int i = k_lo; i < k_hi; ++i) {
       const uint64_t key = S.kkey[kpad32(i)];
-      const int32_t t = key_t(key);
+      const uint32_t t = key_t(key);
       uint64_t jmp[D + 1];
       jump_of<D>(A.mc, S, key, jmp);
       if (st.valid) taylor_shift<D>(st.a, (uint32_t)(t - st.t));
@@ -1179,7 +1185,7 @@ __device__ __forceinline__ void process_ray(const FieldArgs& A, Shared<D>& sh, c
     for (int c = c_lo; c < c_hi; ++c) S.ccnt[c] = 0;
     for (int i = k_lo; i < k_hi; ++i) {
       const uint64_t key = S.kkey[kpad32(i)];
-      const int32_t t = key_t(key);
+      const uint32_t t = key_t(key);
       uint64_t jmp[D + 1];
       jump_of<D>(A.mc, S, key, jmp);
       if (st.valid) taylor_shift<D>(st.a, (uint32_t)(t - st.t));
@@ -1196,18 +1202,18 @@ __device__ __forceinline__ void process_ray(const FieldArgs& A, Shared<D>& sh, c
         emitted = 0;
       }
       if (i + 1 < nk) {
-        const int32_t tn = key_t(S.kkey[kpad32(i + 1)]);
-        if (tn != (int32_t)t) {
+        const uint32_t tn = key_t(S.kkey[kpad32(i + 1)]);
+        if (tn != t) {
           if (A.exact) {
             const int64_t e = sh.base_ex + ex_pos;
             if (e < A.exact_cap) {
-              A.ex_t[e] = t;
-              A.ex_end[e] = tn;
+              A.ex_t[e] = t_lo + t;
+              A.ex_end[e] = t_lo + tn;
               for (int d = 0; d <= D; ++d) A.ex_coef[e * (D + 1) + d] = (int64_t)st.a[d];
             }
           }
           ++ex_pos;
-          Node<D> leaf = make_leaf<D>(A.mt, (int32_t)t, tn, st.a);
+          Node<D> leaf = make_leaf<D>(A.mt, t, tn, st.a);
           if (!have) {
             cur = leaf;
             have = true;
@@ -1296,7 +1302,7 @@ __device__ __forceinline__ void process_ray(const FieldArgs& A, Shared<D>& sh, c
           // u = (t - ta) / (tb - ta) over the exact ends, is re-expressed in u' = (t - fa) / (fb - fa)
           // by composing it with u = al + be u' (exact in real arithmetic, float64 here), so that a
           // caller evaluating on the stored ends gets the projection itself.
-          const double ta = (double)nd.a * tau, tb = (double)nd.b * tau;
+          const double ta = (double)(t_lo + nd.a) * tau, tb = (double)(t_lo + nd.b) * tau;
           const float fa = (float)ta, fb = (float)tb;
           const double len = (double)((int64_t)nd.b - (int64_t)nd.a) * tau;
           double cu[D + 1];
@@ -1340,7 +1346,7 @@ __device__ __forceinline__ void process_ray(const FieldArgs& A, Shared<D>& sh, c
                      (uint64_t)key_kidx(key);
       }
       __syncthreads();
-      const uint32_t range = (uint32_t)sh.t_hi - (uint32_t)t_lo;
+      const uint32_t range = (uint32_t)(sh.t_hi - t_lo);
       int nbits = 36;
       while (nbits < 64 && (range >> (nbits - 32)) != 0) nbits += 4;
       sort_canonical(S.kkey2, S.kkey, (int)nk, nbits, sh.rtab, tid);
@@ -1348,7 +1354,7 @@ __device__ __forceinline__ void process_ray(const FieldArgs& A, Shared<D>& sh, c
         const uint64_t key = S.kkey2[i];
         const int64_t ko = A.knot_off[r] + i;
         if (ko < A.knot_cap) {
-          A.kn_t[ko] = key_t(key);
+          A.kn_t[ko] = t_lo + key_t(key);
           A.kn_pid[ko] = (int32_t)((uint32_t)key >> 3);
           A.kn_kidx[ko] = (int32_t)(key & 7u);
         }
@@ -1363,7 +1369,7 @@ __device__ __forceinline__ void process_ray(const FieldArgs& A, Shared<D>& sh, c
     const int ntf = A.tf_n;
     const double ray_tmin = A.tr ? (double)A.tr[2 * r] : A.t_min, ray_tmax = A.tr ? (double)A.tr[2 * r + 1] : A.t_max;
     auto sample_count = [&](const Node<D>& nd) -> int64_t {
-      const double ta = (double)nd.a * tau, tb = (double)nd.b * tau;
+      const double ta = (double)(t_lo + nd.a) * tau, tb = (double)(t_lo + nd.b) * tau;
       const double a = fmax(ta, ray_tmin), b = fmin(tb, ray_tmax);
       return (b > a) ? (int64_t)fmax(1.0, ceil((b - a) / A.tf_step)) : 0;
     };
@@ -1409,7 +1415,7 @@ __device__ __forceinline__ void process_ray(const FieldArgs& A, Shared<D>& sh, c
       int64_t g = g0;
       for (int64_t n = lo; g < g1; ++n) {
         const Node<D>& nd = nodes[iref[n]];
-        const double ta = (double)nd.a * tau, tb = (double)nd.b * tau;
+        const double ta = (double)(t_lo + nd.a) * tau, tb = (double)(t_lo + nd.b) * tau;
         const double a = fmax(ta, ray_tmin), b = fmin(tb, ray_tmax);
         if (!(b > a)) continue;
         const double Sd = fmax(1.0, ceil((b - a) / A.tf_step));
@@ -2265,7 +2271,9 @@ void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam,
     ws.stats.rays_global = (int64_t)c4[3];
     ws.stats.rays_jumps_device = (int64_t)c4[4];
     ws.stats.rays_scratch_device = (int64_t)c4[5];
-    if (fl & kFlagPosRange) throw Error(SPH_HOA_E_OVERFLOW, "a quantized knot position left the int32 range");
+    if (fl & kFlagPosRange)
+      throw Error(SPH_HOA_E_OVERFLOW, "a ray's knots span 2^32 length quanta or more, or a knot offset q h / tau "
+                                      "reached 2^31");
     if (fl & kFlagCoefRange) throw Error(SPH_HOA_E_OVERFLOW, "a quantized coefficient left the int64 range");
     if (fl & kFlagTail) throw Error(SPH_HOA_E_INTERNAL, "a ray's knots did not cancel exactly");
     bool short_cap = f->n_pieces > f->capacity;

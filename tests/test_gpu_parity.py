@@ -146,9 +146,9 @@ def test_configurations(kind, K, D, n_lut):
     spline, the Wendland C2, C4 and C6 kernels and the transverse gradient kernels -w'/r of the
     Wendland kernels (gradient fields)."""
     xyz, h, val = synth.random_scene(21 + K + 10 * D, 500, h_lo=0.03, h_hi=0.1, signed=True)
-    # D = 1: the optimal length quantum is ~1e-9, too fine for int32 positions on these rays
-    # (the library reports E_OVERFLOW then); a 100x coarser quantum is given explicitly instead
-    sc = H.Scene(kind, K, D, n_lut, xyz, h, val, 1e-3, tau_scale=100.0 if D == 1 else 1.0)
+    # D = 1 runs at its optimal length quantum too (~8e-10: up to ~2.6e9 quanta along a ray through
+    # the unit cube), with 64-bit positions and unsigned 32-bit offsets from each ray's first knot
+    sc = H.Scene(kind, K, D, n_lut, xyz, h, val, 1e-3)
     o, v = synth.random_rays(7 + K, 37)
     out = _approx(sc, o, v, -0.5, 3.5)
     # transverse gradient kernels: for small Lambda the outer optimal knot sits at or beyond the
@@ -163,6 +163,46 @@ def test_configurations(kind, K, D, n_lut):
     for r in range(37):
         f = sc.oracle_ray(o[r], v[r], -0.5, 3.5)
         _check_ray(sc, h, r, f, vtol=vtol, hits=hits[r])
+
+
+def test_far_rays_64bit_positions():
+    """Knot positions are 64-bit quanta: with D = 1 (quantum ~7.5e-10) and ray origins 20 units from
+    the scene, every knot lies near 2.7e10 quanta, beyond 32 bits; knots, exact pieces and merged
+    pieces match the oracle as for near rays (the oracle's positions are Python integers)."""
+    xyz, h, val = synth.random_scene(77, 400, h_lo=0.03, h_hi=0.1)
+    sc = H.Scene("wendland", 4, 1, 256, xyz, h, val, 1e-3)
+    o, v = synth.random_rays(5, 29)
+    o = (0.5 - 20.0 * v.astype(np.float64)).astype(np.float32)
+    out = _approx(sc, o, v, 18.5, 21.5)
+    h = H.host_out(out)
+    assert h["knot_t"].min() > 2 ** 33
+    for r in range(29):
+        f = sc.oracle_ray(o[r], v[r], 18.5, 21.5)
+        _check_ray(sc, h, r, f)
+
+
+def test_position_range_errors():
+    """E_OVERFLOW from the host (a segment beyond the 64-bit range of quanta) and from the kernel (a
+    ray whose knots span 2^32 quanta or more); the index stays usable."""
+    xyz, h, val = synth.random_scene(77, 400, h_lo=0.03, h_hi=0.1)
+    base = H.Scene("wendland", 4, 1, 256, xyz, h, val, 1e-3)
+    q = (base.a_max, base.h_repr, base.phi_repr, 2.0e-10, base.sigma)
+    sc = H.Scene("wendland", 4, 1, 256, xyz, h, val, 1e-3, quanta=q)
+    o, v = synth.random_rays(5, 29)
+    with pytest.raises(L.SphHoaError) as e:
+        _approx(sc, o, v, 0.0, 1.0e9)
+    assert e.value.status == 3
+    # rays through the cube cross up to ~1.7 units = 8.5e9 quanta
+    with pytest.raises(L.SphHoaError) as e:
+        _approx(sc, o, v, -0.5, 3.5)
+    assert e.value.status == 3 and "2^32" in str(e.value)
+    # the same index on short pieces of the rays (knots within 0.2 + 2 q h_max = 0.6 units of each
+    # other: 3e9 quanta, below 2^32)
+    out = _approx(sc, o, v, 1.4, 1.6)
+    h = H.host_out(out)
+    for r in range(29):
+        f = sc.oracle_ray(o[r], v[r], 1.4, 1.6)
+        _check_ray(sc, h, r, f)
 
 
 def test_no_merge_outputs_exact_pieces():
