@@ -450,6 +450,17 @@ sph_hoa_status sph_hoa_knot_table(sph_hoa_kernel kernel, int32_t pieces, int32_t
 sph_hoa_status sph_hoa_lut_coefficients(sph_hoa_kernel kernel, int32_t pieces, int32_t degree, int32_t n,
                                         const double* theta, double* shat_out, double* smid_out, double* err2_out);
 
+/* The same projection on the device (Sec. 3.3, App. A.1/A.2; the table of Sec. 3.1), as used by
+ * sph_hoa_build_index: one wave per entry Lambda_i = (i + 1/2) q / n forms the normal equations of
+ * the candidate basis by Gauss-Legendre quadrature and solves them in float64.  All four arrays are
+ * device memory owned by the caller: theta [n][ceil(K/2)] (input, positive and increasing per row),
+ * shat_out [n][ceil(K/2)][D+1], smid_out [n][D+1] (zero for odd K), err2_out [n].  Runs on `stream`
+ * and synchronises it.  E_INVALID_ARG for a row that is not positive and increasing or whose
+ * projection is singular. */
+sph_hoa_status sph_hoa_lut_project(sph_hoa_kernel kernel, int32_t pieces, int32_t degree, int32_t n,
+                                   const double* theta, double* shat_out, double* smid_out, double* err2_out,
+                                   void* stream);
+
 /* Host-only: the length quantum minimising Q_D(tau / h_repr, sigma / phi_repr) (Sec. 4.4, App. A.5). */
 sph_hoa_status sph_hoa_optimal_tau(sph_hoa_kernel kernel, int32_t degree, double sigma, double h_repr,
                                    double phi_repr, double* tau_out);

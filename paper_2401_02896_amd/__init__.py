@@ -113,7 +113,7 @@ EXPORTS = ["sph_hoa_build_index", "sph_hoa_approx_rays", "sph_hoa_approx_rays_sh
            "sph_hoa_index_free",
            "sph_hoa_index_get_info", "sph_hoa_index_get_lut", "sph_hoa_index_get_grid", "sph_hoa_index_get_stats",
            "sph_hoa_index_set_timing",
-           "sph_hoa_optimal_knots", "sph_hoa_knot_table", "sph_hoa_lut_coefficients",
+           "sph_hoa_optimal_knots", "sph_hoa_knot_table", "sph_hoa_lut_coefficients", "sph_hoa_lut_project",
            "sph_hoa_optimal_tau", "sph_hoa_status_string", "sph_hoa_last_error"]
 
 _lib = None
@@ -164,6 +164,7 @@ def lib():
     L.sph_hoa_optimal_knots.argtypes = [ctypes.c_int, i32, i32, dbl, ctypes.POINTER(dbl), ctypes.POINTER(dbl)]
     L.sph_hoa_knot_table.argtypes = [ctypes.c_int, i32, i32, i32, vp, vp]
     L.sph_hoa_lut_coefficients.argtypes = [ctypes.c_int, i32, i32, i32, vp, vp, vp, vp]
+    L.sph_hoa_lut_project.argtypes = [ctypes.c_int, i32, i32, i32, vp, vp, vp, vp, vp]
     L.sph_hoa_optimal_tau.argtypes = [ctypes.c_int, i32, dbl, dbl, dbl, ctypes.POINTER(dbl)]
     L.sph_hoa_status_string.argtypes = [ctypes.c_int]
     L.sph_hoa_status_string.restype = ctypes.c_char_p
@@ -679,6 +680,22 @@ def sph_hoa_lut_coefficients(kernel, pieces, degree, theta):
     _check(lib().sph_hoa_lut_coefficients(kernel, pieces, degree, n, th.ctypes.data_as(ctypes.c_void_p),
                                           shat.ctypes.data_as(ctypes.c_void_p), smid.ctypes.data_as(ctypes.c_void_p),
                                           e2.ctypes.data_as(ctypes.c_void_p)))
+    return shat, smid, e2
+
+
+def sph_hoa_lut_project(kernel, pieces, degree, theta):
+    """Projection jumps for the given knot table on the device (sph_hoa_lut_project): theta
+    [n, ceil(K/2)] (tensor or array) -> device float64 tensors (shat [n, P, D+1], smid [n, D+1],
+    err2 [n])."""
+    import torch
+
+    th = torch.as_tensor(theta, dtype=torch.float64).to("cuda").contiguous()
+    n, P = th.shape
+    shat = torch.empty((n, P, degree + 1), dtype=torch.float64, device=th.device)
+    smid = torch.empty((n, degree + 1), dtype=torch.float64, device=th.device)
+    e2 = torch.empty(n, dtype=torch.float64, device=th.device)
+    _check(lib().sph_hoa_lut_project(kernel, pieces, degree, n, _ptr(th), _ptr(shat), _ptr(smid), _ptr(e2),
+                                     _stream()))
     return shat, smid, e2
 
 

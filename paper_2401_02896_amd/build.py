@@ -16,7 +16,7 @@ OUT_DIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libsph_hoa.so")
 
 SOURCES = ["tables.cpp", "util.hip", "index.hip", "raycast.hip", "serve.cpp", "bitlength.hip", "floatpath.hip",
-           "static_scratch.hip", "api.cpp"]
+           "static_scratch.hip", "lutproj.hip", "api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("SPH_HOA_ARCH", "gfx950")

@@ -172,10 +172,12 @@ sph_hoa_status sph_hoa_build_index(const float* xyz, const float* h, const float
       for (int i = 0; i < n_lut; ++i)
         for (int m = 1; m < ix.P; ++m)
           require(p->knot_table[i * ix.P + m] > p->knot_table[i * ix.P + m - 1], "knot_table rows must increase");
-      ix.table = sph::build_table(k, ix.K, ix.D, n_lut, p->knot_table, host_threads());
+      ix.table = sph::build_table(k, ix.K, ix.D, n_lut, p->knot_table, host_threads(), false);
     } else {
       ix.table = *cached_table(k, ix.K, ix.D, n_lut);
     }
+    // the projection of every entry onto its knots' candidate space, on the device (Sec. 3.3)
+    sph::project_table_device(ix.table, (hipStream_t)stream);
     if (p->jump_table) {
       require(p->knot_table != nullptr, "jump_table needs the knot_table it belongs to");
       const int64_t ns = (int64_t)n_lut * ix.P * (ix.D + 1);
@@ -664,6 +666,18 @@ sph_hoa_status sph_hoa_lut_coefficients(sph_hoa_kernel kernel, int32_t pieces, i
     std::memcpy(shat_out, t.shat.data(), sizeof(double) * t.shat.size());
     if (smid_out) std::memcpy(smid_out, t.smid.data(), sizeof(double) * t.smid.size());
     if (err2_out) std::memcpy(err2_out, t.err2.data(), sizeof(double) * t.err2.size());
+  });
+}
+
+sph_hoa_status sph_hoa_lut_project(sph_hoa_kernel kernel, int32_t pieces, int32_t degree, int32_t n,
+                                   const double* theta, double* shat_out, double* smid_out, double* err2_out,
+                                   void* stream) {
+  return guarded([&]() {
+    require(theta && shat_out && smid_out && err2_out, "NULL argument");
+    check_method(pieces, degree);
+    require(n >= 2 && n <= 65536, "n must be in 2..65536");
+    sph::lut_project_device(kernel_of(kernel), pieces, degree, n, theta, shat_out, smid_out, err2_out,
+                            static_cast<hipStream_t>(stream));
   });
 }
 

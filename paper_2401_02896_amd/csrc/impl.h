@@ -291,6 +291,12 @@ void server_pause(Server* s, bool paused);
 void render_static(Index& ix, const sph_hoa_camera* cam, const sph_hoa_tf* tf, float* rgba, hipStream_t st);
 int64_t static_scratch_bytes();
 
+// table projection on the device (lutproj.hip): theta, shat, smid, err2 device arrays of a table of
+// n entries; project_table_device fills T.shat / smid / err2 from T.theta
+void lut_project_device(Kernel k, int K, int D, int n, const double* theta, double* shat, double* smid, double* err2,
+                        hipStream_t st);
+void project_table_device(Table& T, hipStream_t st);
+
 // build (index.hip)
 void build_index_device(Index& ix, const float* xyz, const float* h, const float* value, hipStream_t st);
 void get_grid_device(Index& ix, uint64_t* morton, int32_t* level, int32_t* order, hipStream_t st);

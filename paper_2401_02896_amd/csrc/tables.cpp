@@ -12,6 +12,8 @@
 // the best optimum and then retries each entry from its neighbours' optima.
 #include "tables.h"
 
+#include "lutmath.h"
+
 #include <algorithm>
 #include <atomic>
 #include <cmath>
@@ -33,59 +35,13 @@ GL make_gl(int n) {
   GL g;
   g.x.resize(n);
   g.w.resize(n);
-  for (int i = 0; i < n; ++i) {
-    double z = std::cos(kPi * (i + 0.75) / (n + 0.5));
-    for (int it = 0; it < 100; ++it) {
-      double p0 = 1.0, p1 = z;
-      for (int k = 2; k <= n; ++k) {
-        double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
-        p0 = p1;
-        p1 = p2;
-      }
-      double dp = n * (z * p1 - p0) / (z * z - 1.0);
-      double dz = p1 / dp;
-      z -= dz;
-      if (std::fabs(dz) < 1e-16) {
-        p0 = 1.0;
-        p1 = z;
-        for (int k = 2; k <= n; ++k) {
-          double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
-          p0 = p1;
-          p1 = p2;
-        }
-        dp = n * (z * p1 - p0) / (z * z - 1.0);
-        g.x[i] = z;
-        g.w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
-        break;
-      }
-    }
-  }
+  gauss_legendre(n, g.x.data(), g.w.data());
   return g;
 }
 
 const GL& gl16() {
   static const GL g = make_gl(16);
   return g;
-}
-
-// w with q - r supplied separately for the outermost polynomial piece.
-double kernel_w_edge(Kernel k, double r, double e) {
-  if (e <= 0.0) return 0.0;
-  if (k == Kernel::Cubic) {
-    if (r < 1.0) return (4.0 - 6.0 * r * r + 3.0 * r * r * r) / (4.0 * kPi);
-    return e * e * e / (4.0 * kPi);
-  }
-  const double h = 0.5 * e;  // 1 - r / 2
-  const double h2 = h * h, h4 = h2 * h2;
-  // g = -w'/r of the Wendland kernels, (1 - r/2)^(n-1) times a polynomial
-  if (k == Kernel::WendlandGrad) return 21.0 / (16.0 * kPi) * 5.0 * h2 * h;
-  if (k == Kernel::WendlandC4Grad) return 495.0 / (256.0 * kPi) * (14.0 / 3.0) * h4 * h * (1.0 + 2.5 * r);
-  if (k == Kernel::WendlandC6Grad)
-    return 1365.0 / (512.0 * kPi) * 5.5 * h4 * h2 * h * (1.0 + r * (3.5 + 4.0 * r));
-  if (k == Kernel::WendlandC4) return 495.0 / (256.0 * kPi) * h4 * h2 * (1.0 + r * (3.0 + r * (35.0 / 12.0)));
-  if (k == Kernel::WendlandC6)
-    return 1365.0 / (512.0 * kPi) * h4 * h4 * (1.0 + r * (4.0 + r * (25.0 / 4.0 + r * 4.0)));
-  return 21.0 / (16.0 * kPi) * h4 * (1.0 + 2.0 * r);
 }
 
 double kernel_dw(Kernel k, double r) {
@@ -109,54 +65,16 @@ struct Quad {
   std::vector<double> t, w, B;
 };
 
-// Nodes on [0, max(theta_P, s)] split at 0, s, the knots and the kernel breakpoint.
+// Quadrature nodes of the inner products (lutmath.h: quad_plan, quad_node).
 void build_quad(Kernel k, double lam, const double* theta, int P, Quad& Q) {
   const GL& g = gl16();
-  const double s = std::sqrt((kSupport - lam) * (kSupport + lam));
-  double cuts[8];
-  int nc = 0;
-  cuts[nc++] = 0.0;
-  cuts[nc++] = s;
-  for (int i = 0; i < P; ++i) cuts[nc++] = theta[i];
-  if (k == Kernel::Cubic && lam < 1.0) cuts[nc++] = std::sqrt((1.0 - lam) * (1.0 + lam));
-  std::sort(cuts, cuts + nc);
-  Q.t.clear();
-  Q.w.clear();
-  Q.B.clear();
-  for (int c = 0; c + 1 < nc; ++c) {
-    const double a = cuts[c], b = cuts[c + 1];
-    if (!(b > a)) continue;
-    if (b <= s && lam > 0.0) {
-      const double ua = std::asinh(a / lam), ub = std::asinh(b / lam);
-      const int m = std::max(1, (int)std::ceil((ub - ua) / 0.5));
-      for (int j = 0; j < m; ++j) {
-        const double u0 = ua + (ub - ua) * j / m, u1 = ua + (ub - ua) * (j + 1) / m;
-        const double hw = 0.5 * (u1 - u0), mid = 0.5 * (u1 + u0);
-        for (size_t i = 0; i < g.x.size(); ++i) {
-          const double u = hw * g.x[i] + mid;
-          Q.t.push_back(lam * std::sinh(u));
-          Q.w.push_back(hw * g.w[i] * lam * std::cosh(u));
-        }
-      }
-    } else {
-      const double hw = 0.5 * (b - a), mid = 0.5 * (b + a);
-      for (size_t i = 0; i < g.x.size(); ++i) {
-        Q.t.push_back(hw * g.x[i] + mid);
-        Q.w.push_back(hw * g.w[i]);
-      }
-    }
-  }
-  Q.B.resize(Q.t.size());
-  for (size_t i = 0; i < Q.t.size(); ++i) {
-    const double t = Q.t[i];
-    if (t < s) {
-      const double r = std::sqrt(lam * lam + t * t);
-      const double e = (s - t) * (s + t) / (kSupport + r);
-      Q.B[i] = kernel_w_edge(k, r, e);
-    } else {
-      Q.B[i] = 0.0;
-    }
-  }
+  QuadPlan plan;
+  quad_plan(k, lam, theta, P, plan);
+  const int m = plan.first[plan.nseg];
+  Q.t.resize(m);
+  Q.w.resize(m);
+  Q.B.resize(m);
+  for (int i = 0; i < m; ++i) quad_node(k, plan, g.x.data(), g.w.data(), i, &Q.t[i], &Q.w[i], &Q.B[i]);
 }
 
 struct Basis {
@@ -169,55 +87,17 @@ Basis make_basis(int K, int D) {
   b.K = K;
   b.D = D;
   b.P = (K + 1) / 2;
-  for (int k = 1; k <= b.P; ++k)
-    for (int d = 1; d <= D; ++d)
-      if (!(K % 2 == 1 && k == 1 && d % 2 == 1)) {
-        b.bk.push_back(k);
-        b.bd.push_back(d);
-      }
+  int bk[64], bd[64];
+  const int n = lut_basis(K, D, bk, bd);
+  b.bk.assign(bk, bk + n);
+  b.bd.assign(bd, bd + n);
   return b;
 }
 
-inline double ipow(double x, int n) {
-  double r = 1.0;
-  for (int i = 0; i < n; ++i) r *= x;
-  return r;
-}
-
-// A~_kd(t) for t >= 0 with th[0] = 0.
-inline double basis_val(const double* th, int k, int d, double t) {
-  const double a = th[k - 1], b = th[k];
-  if (t <= a) return 1.0;
-  if (t >= b) return 0.0;
-  return 1.0 - ipow((t - a) / (b - a), d);
-}
+inline double ipow(double x, int n) { return lut_ipow(x, n); }
 
 // Cholesky solve of the small SPD system; false if not positive definite.
-bool chol_solve(std::vector<double>& G, std::vector<double>& x, int n) {
-  for (int j = 0; j < n; ++j) {
-    double s = G[j * n + j];
-    for (int k = 0; k < j; ++k) s -= G[j * n + k] * G[j * n + k];
-    if (!(s > 0.0)) return false;
-    const double l = std::sqrt(s);
-    G[j * n + j] = l;
-    for (int i = j + 1; i < n; ++i) {
-      double v = G[i * n + j];
-      for (int k = 0; k < j; ++k) v -= G[i * n + k] * G[j * n + k];
-      G[i * n + j] = v / l;
-    }
-  }
-  for (int i = 0; i < n; ++i) {
-    double v = x[i];
-    for (int k = 0; k < i; ++k) v -= G[i * n + k] * x[k];
-    x[i] = v / G[i * n + i];
-  }
-  for (int i = n - 1; i >= 0; --i) {
-    double v = x[i];
-    for (int k = i + 1; k < n; ++k) v -= G[k * n + i] * x[k];
-    x[i] = v / G[i * n + i];
-  }
-  return true;
-}
+bool chol_solve(std::vector<double>& G, std::vector<double>& x, int n) { return lut_chol_solve(G.data(), x.data(), n); }
 
 struct Proj {
   std::vector<double> c;
@@ -476,43 +356,9 @@ void local_opt(Kernel k, const Basis& bs, double lam, const double* y0, double* 
   *e2_out = fe;
 }
 
-// Jump coefficients of the projection with coefficients c over the index set:
-//   at +theta_k (k = 1..P): s_kd = sum_{i in J: k_i = k, d_i >= d} c_i C(d_i, d) / Delta_k^d
-//                                  - sum_{i in J: k_i = k + 1, d_i = d} c_i / Delta_{k+1}^d
-//   at 0 (even K, odd d):   s_0d = -2 sum_{i in J: k_i = 1, d_i = d} c_i / theta_1^d
-// (the piece on [theta_{k-1}, theta_k] is sum_{k_i > k} c_i + sum_{k_i = k} c_i (1 - z^{d_i})).
 void jumps_from_coeffs(const Basis& bs, const double* theta, const std::vector<double>& c, double* shat,
                        double* smid) {
-  const int P = bs.P, D = bs.D;
-  double th[8];
-  th[0] = 0.0;
-  for (int i = 0; i < P; ++i) th[i + 1] = theta[i];
-  auto binom = [](int n, int r) {
-    double v = 1.0;
-    for (int i = 1; i <= r; ++i) v = v * (n - r + i) / i;
-    return v;
-  };
-  for (int k = 1; k <= P; ++k) {
-    const double dk = th[k] - th[k - 1];
-    const double dk1 = (k < P) ? th[k + 1] - th[k] : 1.0;
-    for (int d = 0; d <= D; ++d) {
-      double v = 0.0;
-      if (d >= 1) {
-        for (size_t i = 0; i < c.size(); ++i) {
-          if (bs.bk[i] == k && bs.bd[i] >= d) v += c[i] * binom(bs.bd[i], d) / ipow(dk, d);
-          if (k < P && bs.bk[i] == k + 1 && bs.bd[i] == d) v -= c[i] / ipow(dk1, d);
-        }
-      }
-      shat[(k - 1) * (D + 1) + d] = v;
-    }
-  }
-  for (int d = 0; d <= D; ++d) {
-    double v = 0.0;
-    if (bs.K % 2 == 0 && d % 2 == 1)
-      for (size_t i = 0; i < c.size(); ++i)
-        if (bs.bk[i] == 1 && bs.bd[i] == d) v += -2.0 * c[i] / ipow(th[1], d);
-    smid[d] = v;
-  }
+  lut_jumps(bs.K, bs.D, bs.bk.data(), bs.bd.data(), (int)c.size(), theta, c.data(), shat, smid);
 }
 
 }  // namespace
@@ -613,7 +459,7 @@ double project_jumps(Kernel k, int K, int D, double lambda, const double* theta,
   return pr.E2;
 }
 
-Table build_table(Kernel k, int K, int D, int n, const double* given_theta, int n_threads) {
+Table build_table(Kernel k, int K, int D, int n, const double* given_theta, int n_threads, bool project) {
   Table T;
   T.K = K;
   T.D = D;
@@ -668,6 +514,7 @@ Table build_table(Kernel k, int K, int D, int n, const double* given_theta, int 
       }
     });
   }
+  if (!project) return T;
   parallel([&](int i) {
     T.err2[i] = project_jumps(k, K, D, lam_of(i), &T.theta[(size_t)i * P], &T.shat[(size_t)i * P * (D + 1)],
                               &T.smid[(size_t)i * (D + 1)]);

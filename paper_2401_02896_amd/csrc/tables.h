@@ -54,8 +54,9 @@ std::vector<double> default_starts(int P);
 double project_jumps(Kernel k, int K, int D, double lambda, const double* theta, double* shat_rows,
                      double* smid_row);
 
-// Full table (optimisation unless `given_theta` is non-null).
-Table build_table(Kernel k, int K, int D, int n, const double* given_theta, int n_threads);
+// Full table (optimisation unless `given_theta` is non-null); with project = false the jump
+// coefficients and errors are left for the device projection (project_table_device).
+Table build_table(Kernel k, int K, int D, int n, const double* given_theta, int n_threads, bool project = true);
 
 // Length quantum minimising Q_D(tau / h_repr, sigma / phi_repr).
 double optimal_tau(Kernel k, int D, double sigma, double h_repr, double phi_repr);

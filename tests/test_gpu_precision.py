@@ -56,8 +56,8 @@ def test_stored_table_is_the_rounded_table(fmt):
     for i in rows:
         assert _row_in_band(shat[i], sc, i), i
     # the rounding itself: the stored values are exactly the oracle's rounding of the library's
-    # own float64 projection of the same knots (host routine, no rounding)
-    raw, _, _ = L.sph_hoa_lut_coefficients(0, sc.K, sc.D, sc.theta)
+    # own float64 projection of the same knots (the device projection the index is built with)
+    raw = L.sph_hoa_lut_project(0, sc.K, sc.D, sc.theta)[0].cpu().numpy()
     assert np.array_equal(shat, lut.round_storage(raw, fmt))
 
 
