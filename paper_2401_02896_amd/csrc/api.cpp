@@ -126,6 +126,7 @@ const char* sph_hoa_last_error(void) { return g_last_error.c_str(); }
 sph_hoa_status sph_hoa_build_index(const float* xyz, const float* h, const float* value, int64_t n,
                                    sph_hoa_kernel kernel, const sph_hoa_params* p, void* stream,
                                    sph_hoa_index* out) {
+  sph::TraceRange trace_range("sph_hoa_build_index");
   if (!out) return fail(SPH_HOA_E_INVALID_ARG, "out is NULL");
   *out = nullptr;
   std::unique_ptr<sph_hoa_index_s> H(new sph_hoa_index_s());
@@ -338,11 +339,13 @@ void approx_rays_one(sph_hoa_index idx, const sph_hoa_rays* rays, sph_hoa_field*
 
 sph_hoa_status sph_hoa_approx_rays(sph_hoa_index idx, const sph_hoa_rays* rays, sph_hoa_field* out, uint32_t flags,
                                    void* stream) {
+  sph::TraceRange trace_range("sph_hoa_approx_rays");
   return guarded([&]() { approx_rays_one(idx, rays, out, flags, stream, nullptr); });
 }
 
 sph_hoa_status sph_hoa_approx_rays_shared(const sph_hoa_index* idx, int32_t n_idx, const sph_hoa_rays* rays,
                                           sph_hoa_field* out, uint32_t flags, void* stream) {
+  sph::TraceRange trace_range("sph_hoa_approx_rays_shared");
   return guarded([&]() {
     require(idx && out && rays, "NULL argument");
     require(n_idx >= 1, "need at least one index");
@@ -359,6 +362,7 @@ sph_hoa_status sph_hoa_approx_rays_shared(const sph_hoa_index* idx, int32_t n_id
 
 sph_hoa_status sph_hoa_float_rays(sph_hoa_index idx, const sph_hoa_rays* rays, int32_t n_reinit,
                                   sph_hoa_float_field* out, void* stream) {
+  sph::TraceRange trace_range("sph_hoa_float_rays");
   return guarded([&]() {
     require(idx && rays && out, "NULL argument");
     require(rays->n >= 0 && rays->n < (int64_t(1) << 31), "ray count must be in 0..2^31-1");
@@ -426,6 +430,7 @@ void check_tf(const sph_hoa_tf* tf) {
 
 sph_hoa_status sph_hoa_render(sph_hoa_index idx, const sph_hoa_camera* cam, const sph_hoa_tf* tf, float* rgba_out,
                               void* stream) {
+  sph::TraceRange trace_range("sph_hoa_render");
   return guarded([&]() {
     require(idx && cam && tf && rgba_out, "NULL argument");
     sph::Index& ix = idx->ix;
@@ -440,6 +445,7 @@ sph_hoa_status sph_hoa_render(sph_hoa_index idx, const sph_hoa_camera* cam, cons
 
 sph_hoa_status sph_hoa_render_static(sph_hoa_index idx, const sph_hoa_camera* cam, const sph_hoa_tf* tf,
                                      float* rgba_out, void* stream) {
+  sph::TraceRange trace_range("sph_hoa_render_static");
   return guarded([&]() {
     require(idx && cam && tf && rgba_out, "NULL argument");
     sph::Index& ix = idx->ix;
@@ -457,6 +463,7 @@ int64_t sph_hoa_device_alloc_count(void) { return sph::g_device_allocs.load(); }
 
 sph_hoa_status sph_hoa_approx_camera(sph_hoa_index idx, const sph_hoa_camera* cam, sph_hoa_field* out, uint32_t flags,
                                      void* stream) {
+  sph::TraceRange trace_range("sph_hoa_approx_camera");
   return guarded([&]() {
     require(idx && cam && out, "NULL argument");
     require(flags == 0 || flags == SPH_HOA_FLAG_EXACT, "unknown flags");
@@ -482,6 +489,7 @@ void check_hits_out(int64_t n, const int64_t* offsets, const int32_t* ids, int64
 
 sph_hoa_status sph_hoa_camera_hits(sph_hoa_index idx, const sph_hoa_camera* cam, int64_t* hit_offsets,
                                    int32_t* hit_ids, int64_t capacity, int64_t* n_pairs, void* stream) {
+  sph::TraceRange trace_range("sph_hoa_camera_hits");
   if (n_pairs) *n_pairs = 0;
   sph::HitsOut ho{hit_offsets, hit_ids, capacity, 0};
   const sph_hoa_status s = guarded([&]() {
@@ -502,6 +510,7 @@ sph_hoa_status sph_hoa_camera_hits(sph_hoa_index idx, const sph_hoa_camera* cam,
 
 sph_hoa_status sph_hoa_ray_hits(sph_hoa_index idx, const sph_hoa_rays* rays, int64_t* hit_offsets, int32_t* hit_ids,
                                 int64_t capacity, int64_t* n_pairs, void* stream) {
+  sph::TraceRange trace_range("sph_hoa_ray_hits");
   if (n_pairs) *n_pairs = 0;
   sph::HitsOut ho{hit_offsets, hit_ids, capacity, 0};
   const sph_hoa_status s = guarded([&]() {
@@ -532,6 +541,7 @@ sph_hoa_status sph_hoa_ray_hits(sph_hoa_index idx, const sph_hoa_rays* rays, int
 
 sph_hoa_status sph_hoa_render_batch(sph_hoa_index idx, const sph_hoa_camera* cams, int32_t n_cams,
                                     const sph_hoa_tf* tf, float* rgba_out, void* stream) {
+  sph::TraceRange trace_range("sph_hoa_render_batch");
   return guarded([&]() {
     require(idx && tf && (n_cams == 0 || (cams && rgba_out)), "NULL argument");
     require(n_cams >= 0 && n_cams <= (1 << 20), "n_cams must be in [0, 2^20]");
@@ -644,6 +654,7 @@ sph_hoa_status sph_hoa_optimal_knots(sph_hoa_kernel kernel, int32_t pieces, int3
 
 sph_hoa_status sph_hoa_knot_table(sph_hoa_kernel kernel, int32_t pieces, int32_t degree, int32_t n,
                                   double* theta_out, double* err2_out) {
+  sph::TraceRange trace_range("sph_hoa_knot_table");
   return guarded([&]() {
     require(theta_out, "NULL argument");
     check_method(pieces, degree);
@@ -656,6 +667,7 @@ sph_hoa_status sph_hoa_knot_table(sph_hoa_kernel kernel, int32_t pieces, int32_t
 
 sph_hoa_status sph_hoa_lut_coefficients(sph_hoa_kernel kernel, int32_t pieces, int32_t degree, int32_t n,
                                         const double* theta, double* shat_out, double* smid_out, double* err2_out) {
+  sph::TraceRange trace_range("sph_hoa_lut_coefficients");
   return guarded([&]() {
     require(theta && shat_out, "NULL argument");
     check_method(pieces, degree);
@@ -672,6 +684,7 @@ sph_hoa_status sph_hoa_lut_coefficients(sph_hoa_kernel kernel, int32_t pieces, i
 sph_hoa_status sph_hoa_lut_project(sph_hoa_kernel kernel, int32_t pieces, int32_t degree, int32_t n,
                                    const double* theta, double* shat_out, double* smid_out, double* err2_out,
                                    void* stream) {
+  sph::TraceRange trace_range("sph_hoa_lut_project");
   return guarded([&]() {
     require(theta && shat_out && smid_out && err2_out, "NULL argument");
     check_method(pieces, degree);
@@ -694,6 +707,7 @@ sph_hoa_status sph_hoa_optimal_tau(sph_hoa_kernel kernel, int32_t degree, double
 sph_hoa_status sph_hoa_accumulate_bits(int32_t bits, int32_t degree, const uint32_t* dist, const uint32_t* jumps,
                                        int32_t n_table, int64_t n_threads, int32_t steps, uint32_t* out_host,
                                        float* ms_out, void* stream) {
+  sph::TraceRange trace_range("sph_hoa_accumulate_bits");
   return guarded([&]() {
     require(dist && jumps, "NULL argument");
     sph::accumulate_bits(bits, degree, dist, jumps, n_table, n_threads, steps, out_host, ms_out,

@@ -1,6 +1,7 @@
 // Internal declarations shared by the library's translation units.
 #pragma once
 
+#include <rocprofiler-sdk-roctx/roctx.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -39,6 +40,16 @@ enum : uint32_t {
 struct Error : std::runtime_error {
   sph_hoa_status status;
   Error(sph_hoa_status s, const std::string& m) : std::runtime_error(m), status(s) {}
+};
+
+// A named range on the host timeline (roctx): rocprofv3 --marker-trace shows each ABI call and
+// each phase of a frame as a range; without a profiler attached a push/pop pair costs a few
+// nanoseconds.
+struct TraceRange {
+  explicit TraceRange(const char* name) { roctxRangePushA(name); }
+  ~TraceRange() { roctxRangePop(); }
+  TraceRange(const TraceRange&) = delete;
+  TraceRange& operator=(const TraceRange&) = delete;
 };
 
 inline void hip_check(hipError_t e, const char* what) {

@@ -10,6 +10,8 @@
 // composites them - all for one ray per work-group, in LDS.
 #include <hip/hip_runtime.h>
 
+#include <memory>
+
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
@@ -1837,6 +1839,7 @@ void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam,
               Workspace* workspace) {
   Workspace& ws = workspace ? *workspace : ix.ws;
   const int D = ix.D, K = ix.K, P = ix.P;
+  auto gather_range = std::make_unique<TraceRange>(camera ? "hit gathering (screen tiles)" : "hit gathering (grid walk)");
   if (gathered && (camera || n_batch > 0 || gathered->ws.last_hit_rays != n_rays))
     throw Error(SPH_HOA_E_INTERNAL, "shared gathering needs the same arbitrary rays");
   ws.collect_timing();
@@ -2103,6 +2106,8 @@ void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam,
     if (fl2 & kFlagCapacity) throw Error(SPH_HOA_E_INTERNAL, "float field wrote past its slots");
     return;
   }
+  gather_range.reset();
+  TraceRange field_range(out.rgba ? "field kernel (render)" : "field kernel (fields)");
   // ---- field kernel
   FieldArgs A{};
   A.o = G.o;
