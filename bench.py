@@ -195,12 +195,14 @@ def run_batch(a, torch, L, synth):
             idx[key] = _build(L, xyz, h, val, key[1], tables)
     torch.cuda.synchronize()
     index_s = time.time() - t_idx
+    print(f"batch: {len(idx)} indices built ({time.time() - t_gen:.0f} s)", file=sys.stderr, flush=True)
     keys = sorted(idx)
     srv = L.Server(hbm_budget_bytes=a.budget_gib << 30, max_batch_rays=1 << 24, lanes=a.lanes)
     slots = {k: srv.add_index(idx[k]) for k in keys}
     reqs = [(slots[(int(set_of[j]), int(deg_of[j]))], cams[j], tf, vmin, vmax, step) for j in range(n_b)]
     for _ in range(a.warmup):
         _served(srv, reqs)
+        print(f"batch: warm-up step done ({time.time() - t_gen:.0f} s)", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     st0 = srv.stats()
     lat_steps, step_lat = [], []
@@ -212,6 +214,7 @@ def run_batch(a, torch, L, synth):
         torch.cuda.synchronize()
         step_lat.append(time.perf_counter() - ts)
         lat_steps.extend(lat)
+        print(f"batch: timed step done ({time.time() - t_gen:.0f} s)", file=sys.stderr, flush=True)
     elapsed = time.perf_counter() - t0
     st = srv.stats()
     pairs = st["n_pairs"] - st0["n_pairs"]
@@ -231,6 +234,8 @@ def run_batch(a, torch, L, synth):
         idx[k].set_timing(True)
         L.sph_hoa_render_batch(idx[k], [cams[j] for j in groups[k]], tf, vmin, vmax, step)
         st_k = idx[k].stats()
+        print(f"batch: set {k[0]} D={k[1]} by one render_batch call ({time.time() - t_gen:.0f} s)", file=sys.stderr,
+              flush=True)
         idx[k].set_timing(False)
         seq_pairs += st_k["n_pairs"]
         per_index[f"set{k[0]}_D{k[1]}"] = {
@@ -243,6 +248,8 @@ def run_batch(a, torch, L, synth):
     seq_s = time.perf_counter() - ts
     for j in range(n_b):
         L.sph_hoa_render(idx[(int(set_of[j]), int(deg_of[j]))], cams[j], tf, vmin, vmax, step)
+        if j % 32 == 31:
+            print(f"batch: single-call warm-up {j + 1}/{n_b} ({time.time() - t_gen:.0f} s)", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     ts = time.perf_counter()
     single_pairs = 0
@@ -250,6 +257,8 @@ def run_batch(a, torch, L, synth):
         ix = idx[(int(set_of[j]), int(deg_of[j]))]
         L.sph_hoa_render(ix, cams[j], tf, vmin, vmax, step)
         single_pairs += ix.stats()["n_pairs"]
+        if j % 32 == 31:
+            print(f"batch: single calls {j + 1}/{n_b} ({time.time() - t_gen:.0f} s)", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     single_s = time.perf_counter() - ts
     n_rays = sum(c["width"] * c["height"] for c in cams)
