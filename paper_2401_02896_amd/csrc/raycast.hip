@@ -146,6 +146,7 @@ template <bool FILL>
 __global__ void __launch_bounds__(kGatherThreads) k_gather(GatherArgs A) {
   __shared__ int64_t s_excl[kGatherThreads];
   __shared__ uint32_t s_beg[kGatherThreads];
+  __shared__ int32_t s_cfirst[kGatherThreads], s_cb0[kGatherThreads], s_ce0[kGatherThreads], s_cne[kGatherThreads];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int64_t r = (int64_t)blockIdx.x * (kGatherThreads / 64) + w;
   if (r >= A.n_rays) return;  // whole wave leaves together
@@ -157,6 +158,7 @@ __global__ void __launch_bounds__(kGatherThreads) k_gather(GatherArgs A) {
   const double t_min = A.tr ? (double)A.tr[2 * r] : A.t_min, t_max = A.tr ? (double)A.tr[2 * r + 1] : A.t_max;
   int64_t* ex = s_excl + w * 64;
   uint32_t* bg = s_beg + w * 64;
+  int32_t *sx = s_cfirst + w * 64, *sb = s_cb0 + w * 64, *se = s_ce0 + w * 64, *sn = s_cne + w * 64;
   int64_t found = 0;
   const int64_t out0 = FILL ? A.off[r] : 0;
   // dominant axis
@@ -193,14 +195,15 @@ __global__ void __launch_bounds__(kGatherThreads) k_gather(GatherArgs A) {
     s_lo = max(s_lo, (int64_t)0);
     s_hi = min(s_hi, (int64_t)L.n[ax] - 1);
     if (s_hi < s_lo) continue;
-    const int64_t total = (s_hi - s_lo + 1) * 49;
-    for (int64_t base = 0; base < total; base += 64) {
-      const int64_t idx = base + lane;
-      int64_t cnt = 0;
-      uint32_t cb = 0;
-      if (idx < total) {
-        const int64_t s = s_lo + idx / 49;
-        const int wi = (int)(idx % 49), wb = wi / 7, we = wi % 7;
+    // The slabs of this level 64 at a time, one lane per slab: each lane finds its slab's window
+    // of cells in the two other axes (the segment's crossing of the slab and its two neighbours,
+    // widened by one cell; at most 7 x 7), then the chunk's cells are visited 64 at a time in
+    // (slab, b, e) order, so every lane of a batch holds a real cell.
+    for (int64_t s_base = s_lo; s_base <= s_hi; s_base += 64) {
+      const int64_t s = s_base + lane;
+      int nb = 0, ne = 0;
+      int64_t cb0 = 0, ce0 = 0;
+      if (s <= s_hi) {
         double t1 = (A.g.lo[ax] + (double)(s - 1) * c - eps - o[ax]) / v[ax];
         double t2 = (A.g.lo[ax] + (double)(s + 2) * c + eps - o[ax]) / v[ax];
         if (t1 > t2) {
@@ -220,48 +223,76 @@ __global__ void __launch_bounds__(kGatherThreads) k_gather(GatherArgs A) {
           if (cb_hi - cb_lo > 6 || ce_hi - ce_lo > 6) atomicOr(A.flags, kFlagWindow);
           cb_lo = max(cb_lo, (int64_t)0);
           ce_lo = max(ce_lo, (int64_t)0);
-          cb_hi = min(cb_hi, (int64_t)L.n[bx] - 1);
-          ce_hi = min(ce_hi, (int64_t)L.n[ex_ax] - 1);
-          const int64_t ib = cb_lo + wb, ie = ce_lo + we;
-          if (ib <= cb_hi && ie <= ce_hi) {
-            int64_t cc[3];
-            cc[ax] = s;
-            cc[bx] = ib;
-            cc[ex_ax] = ie;
-            const int64_t cell = L.cell_off + cc[0] + (int64_t)L.n[0] * (cc[1] + (int64_t)L.n[1] * cc[2]);
-            cb = A.cbeg[cell];
-            cnt = (int64_t)A.cend[cell] - (int64_t)cb;
+          cb_hi = min(min(cb_hi, (int64_t)L.n[bx] - 1), cb_lo + 6);
+          ce_hi = min(min(ce_hi, (int64_t)L.n[ex_ax] - 1), ce_lo + 6);
+          if (cb_hi >= cb_lo && ce_hi >= ce_lo) {
+            nb = (int)(cb_hi - cb_lo + 1);
+            ne = (int)(ce_hi - ce_lo + 1);
+            cb0 = cb_lo;
+            ce0 = ce_lo;
           }
         }
       }
-      const int64_t incl = wave_incl_scan(cnt);
-      const int64_t tot = __shfl(incl, 63, 64);
-      ex[lane] = incl - cnt;
-      bg[lane] = cb;
+      const int ncell = nb * ne;
+      const int cincl = (int)wave_incl_scan((int64_t)ncell);
+      const int ctot = __shfl(cincl, 63, 64);
+      sx[lane] = cincl - ncell;
+      sb[lane] = (int32_t)cb0;
+      se[lane] = (int32_t)ce0;
+      sn[lane] = ne;
       __builtin_amdgcn_wave_barrier();
-      for (int64_t k = 0; k < tot; k += 64) {
-        const int64_t ci = k + lane;
-        bool hit = false;
-        uint32_t j = 0;
-        if (ci < tot) {
-          // owner lane: last lane with ex <= ci
+      for (int cbase = 0; cbase < ctot; cbase += 64) {
+        const int ci0 = cbase + lane;
+        int64_t cnt = 0;
+        uint32_t cb = 0;
+        if (ci0 < ctot) {
+          // owner lane: last lane whose first cell is <= ci0 (lanes without cells share the next
+          // lane's first cell, so the search ends on a lane with cells)
           int lo = 0, hi = 63;
           while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
-            if (ex[mid] <= ci) lo = mid;
+            if (sx[mid] <= ci0) lo = mid;
             else hi = mid - 1;
           }
-          j = bg[lo] + (uint32_t)(ci - ex[lo]);
-          hit = pair_hit(o, v, A.pos4[j], t_min, t_max);
+          const int li = ci0 - sx[lo], nel = sn[lo];
+          int64_t cc[3];
+          cc[ax] = s_base + lo;
+          cc[bx] = (int64_t)sb[lo] + li / nel;
+          cc[ex_ax] = (int64_t)se[lo] + li % nel;
+          const int64_t cell = L.cell_off + cc[0] + (int64_t)L.n[0] * (cc[1] + (int64_t)L.n[1] * cc[2]);
+          cb = A.cbeg[cell];
+          cnt = (int64_t)A.cend[cell] - (int64_t)cb;
         }
-        const uint64_t m = __ballot(hit);
-        if (hit) {
-          const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-          const int64_t pos = found + __popcll(m & lt);
-          if (FILL) A.hits[out0 + pos] = j;
-          else if (A.slots && pos < A.n_slots) A.slots[r * A.n_slots + pos] = j;
+        const int64_t incl = wave_incl_scan(cnt);
+        const int64_t tot = __shfl(incl, 63, 64);
+        ex[lane] = incl - cnt;
+        bg[lane] = cb;
+        __builtin_amdgcn_wave_barrier();
+        for (int64_t k = 0; k < tot; k += 64) {
+          const int64_t ci = k + lane;
+          bool hit = false;
+          uint32_t j = 0;
+          if (ci < tot) {
+            // owner lane: last lane with ex <= ci
+            int lo = 0, hi = 63;
+            while (lo < hi) {
+              const int mid = (lo + hi + 1) >> 1;
+              if (ex[mid] <= ci) lo = mid;
+              else hi = mid - 1;
+            }
+            j = bg[lo] + (uint32_t)(ci - ex[lo]);
+            hit = pair_hit(o, v, A.pos4[j], t_min, t_max);
+          }
+          const uint64_t m = __ballot(hit);
+          if (hit) {
+            const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+            const int64_t pos = found + __popcll(m & lt);
+            if (FILL) A.hits[out0 + pos] = j;
+            else if (A.slots && pos < A.n_slots) A.slots[r * A.n_slots + pos] = j;
+          }
+          found += __popcll(m);
         }
-        found += __popcll(m);
+        __builtin_amdgcn_wave_barrier();
       }
       __builtin_amdgcn_wave_barrier();
     }
