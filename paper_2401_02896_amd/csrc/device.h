@@ -180,4 +180,98 @@ __device__ __forceinline__ void radix_sort_u64(uint64_t* a, uint64_t* tmp, int n
   }
 }
 
+// Stable LSD radix sort of a[0..n) by bits [lo_bit, lo_bit + nbits) with 8-bit digits (the last
+// one narrower when nbits is not a multiple of 8), by the NT threads of the work-group.  Wave w
+// owns the contiguous segment [w s, (w + 1) s) of each pass's source, s = ceil(n / W).  The digit
+// counts of a pass are kept per (wave, digit): the first pass counts them directly, every pass
+// counts the next pass's while it moves the keys (a key written to slot p belongs to wave p / s
+// next time).  Per pass one wave turns the W x 256 counts into first output slots by an exclusive
+// scan in digit-major order (all keys of smaller digits, then this digit's keys of earlier waves);
+// each wave then moves its segment in rounds of 64 keys, a key's rank among the round's equal
+// digits coming from a match over the digit's bits (one ballot per bit) and the digit's slot
+// advancing by the round's count, so no work-group barrier is needed inside the pass and equal
+// digits keep their order.  tab: 2 * 256 * W uint32 of LDS.  The result ends in `a`; with PAD_OUT
+// it is stored with one unused slot after every 16 elements (element i at i + i / 16; a and tmp
+// then hold n + n / 16 + 1 elements).  Caller guarantees a barrier before; ends with a barrier.
+template <int NT, bool PAD_OUT>
+__device__ __forceinline__ void radix_sort_u64_d8(uint64_t* a, uint64_t* tmp, int n, int lo_bit, int nbits,
+                                                  uint32_t* tab, int tid) {
+  constexpr int W = NT / 64;
+  constexpr int E = 256 * W / 64;  // scan entries per lane
+  const int w = tid >> 6, lane = tid & 63;
+  const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  const int seg = (n + W - 1) / W;
+  const int s0 = min(w * seg, n), s1 = min(s0 + seg, n);
+  uint32_t* cur = tab;             // [W][256] this pass: counts, then slots
+  uint32_t* nxt = tab + 256 * W;   // [W][256] next pass's counts
+  uint64_t* src = a;
+  uint64_t* dst = tmp;
+  for (int i = tid; i < 256 * W; i += NT) cur[i] = 0u;
+  __syncthreads();
+  {
+    const uint32_t mask = (1u << min(8, nbits)) - 1u;
+    for (int i = s0 + lane; i < s1; i += 64) atomicAdd(&cur[w * 256 + ((uint32_t)(src[i] >> lo_bit) & mask)], 1u);
+  }
+  for (int shift = lo_bit; shift < lo_bit + nbits; shift += 8) {
+    const int bits = min(8, lo_bit + nbits - shift);
+    const uint32_t mask = (1u << bits) - 1u;
+    const bool last = shift + 8 >= lo_bit + nbits;
+    const uint32_t mask_n = last ? 0u : (1u << min(8, lo_bit + nbits - shift - 8)) - 1u;
+    __syncthreads();
+    if (w == 0) {
+      // entry e = d * W + ww (digit-major), E consecutive entries per lane
+      uint32_t x[E], sum = 0;
+#pragma unroll
+      for (int j = 0; j < E; ++j) {
+        const int e = lane * E + j, d = e / W, ww = e % W;
+        x[j] = cur[ww * 256 + d];
+        sum += x[j];
+      }
+      uint32_t run = wave_incl_scan_u32(sum) - sum;
+#pragma unroll
+      for (int j = 0; j < E; ++j) {
+        const int e = lane * E + j, d = e / W, ww = e % W;
+        cur[ww * 256 + d] = run;
+        run += x[j];
+      }
+    }
+    for (int i = tid; i < 256 * W; i += NT) nxt[i] = 0u;
+    __syncthreads();
+    uint32_t* mine = cur + w * 256;
+    for (int i0 = s0; i0 < s1; i0 += 64) {
+      const int i = i0 + lane;
+      const bool valid = i < s1;
+      const uint64_t k = valid ? src[i] : 0ull;
+      const uint32_t d = (uint32_t)(k >> shift) & mask;
+      uint64_t m = __ballot(valid);
+      for (int b = 0; b < bits; ++b) {
+        const uint64_t bal = __ballot((d >> b) & 1u);
+        m &= ((d >> b) & 1u) ? bal : ~bal;
+      }
+      const uint32_t rank = (uint32_t)__popcll(m & lt);
+      const uint32_t c = valid ? mine[d] : 0u;
+      __builtin_amdgcn_wave_barrier();
+      if (valid) {
+        const uint32_t p = min(c + rank, (uint32_t)(n - 1));  // (always below n; kept in bounds regardless)
+        dst[(PAD_OUT && last) ? p + (p >> 4) : p] = k;
+        if (rank == 0) mine[d] = c + (uint32_t)__popcll(m);
+        if (!last) atomicAdd(&nxt[(p / (uint32_t)seg) * 256 + ((uint32_t)(k >> (shift + 8)) & mask_n)], 1u);
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
+    uint32_t* t32 = cur;
+    cur = nxt;
+    nxt = t32;
+    uint64_t* t = src;
+    src = dst;
+    dst = t;
+  }
+  __syncthreads();
+  if (src != a) {
+    const int np = PAD_OUT ? n + (n >> 4) : n;
+    for (int i = tid; i < np; i += NT) a[i] = src[i];
+    __syncthreads();
+  }
+}
+
 }  // namespace sph

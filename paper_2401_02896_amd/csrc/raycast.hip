@@ -895,6 +895,7 @@ struct Shared {
   union {                          // never live together: LDS is the ray layout's capacity
     Agg<D> hs[kFieldThreads];      // scan of the thread aggregates (passes A and B)
     float part[kFieldThreads][4];  // compositing partials (render, at the end)
+    uint32_t sort_tab[2 * 256 * (kFieldThreads / 64)];  // digit counts of the knot sort
   };
   uint32_t rtab[32 * (kFieldThreads / 64)];  // radix sort tables
   int64_t wtot[kFieldThreads / 64];
@@ -1103,10 +1104,10 @@ __device__ __forceinline__ void process_ray(const FieldArgs& A, Shared<D>& sh, c
   }
   __syncthreads();
   {
+    // the position bits of the ray's range (at least one), 8 per pass
     const uint32_t range = (uint32_t)(sh.t_hi - t_lo);
-    int nbits = 4;
-    while (nbits < 32 && (range >> nbits) != 0) nbits += 4;
-    radix_sort_u64<kFieldThreads, true>(S.kkey, S.kkey2, (int)nk, 32, nbits, sh.rtab, tid);
+    const int nbits = range ? 32 - __clz(range) : 1;
+    radix_sort_u64_d8<kFieldThreads, true>(S.kkey, S.kkey2, (int)nk, 32, nbits, sh.sort_tab, tid);
   }
   // ---- thread ranges of chunks
   const int n_chunks = (nk + kChunk - 1) / kChunk;
