@@ -1198,7 +1198,15 @@ __device__ __forceinline__ void process_ray(const FieldArgs& A, Shared<D>& sh, c
     atomicAdd(&A.counters[2], (unsigned long long)run);
   }
   __syncthreads();
-  // ---- pass C: exact pieces -> leaves -> greedy merge within chunks -> nodes
+  // ---- pass C: exact pieces -> leaves -> greedy merge within chunks -> nodes.  A chunk's first
+  // node lives in the sort scratch (free from here to the end; most chunks keep at most one node
+  // after the merge, and for rays laid out in LDS the junction tree and the output then read them
+  // from LDS), the others in the work-group's slab.
+  const bool first_in_scratch = (int64_t)sizeof(Node<D>) * n_chunks <= 8 * kpad_size(nk);
+  Node<D>* const first_nodes = reinterpret_cast<Node<D>*>(S.kkey2);
+  auto node = [&](int32_t id) -> Node<D>& {
+    return (first_in_scratch && id % kChunk == 0) ? first_nodes[id / kChunk] : nodes[id];
+  };
   const double tol = A.mc.merge_tol;
   const double pk_s = (double)sh.peak;  // the peak in units of sigma
   const double thr2 = (tol * pk_s) * (tol * pk_s);
@@ -1211,7 +1219,7 @@ __device__ __forceinline__ void process_ray(const FieldArgs& A, Shared<D>& sh, c
     int32_t emitted = 0;
     auto flush = [&](int chunk) {
       if (have) {
-        nodes[chunk * kChunk + emitted] = cur;
+        node(chunk * kChunk + emitted) = cur;
         ++emitted;
         have = false;
       }
@@ -1290,9 +1298,9 @@ __device__ __forceinline__ void process_ray(const FieldArgs& A, Shared<D>& sh, c
         int32_t nf = lf >= 0 ? lf : rf;
         int32_t nl = rl >= 0 ? rl : ll;
         if (ll >= 0 && rf >= 0) {
-          Node<D> cand = combine<D>(nodes[ll], nodes[rf]);
+          Node<D> cand = combine<D>(node(ll), node(rf));
           if (passes<D>(A.mt, cand, thr2)) {
-            nodes[ll] = cand;
+            node(ll) = cand;
             const int rc = rf / kChunk;
             S.chead[rc] = S.chead[rc] + 1;
             // next live node of group R
@@ -1315,7 +1323,7 @@ __device__ __forceinline__ void process_ray(const FieldArgs& A, Shared<D>& sh, c
   int64_t mine = 0;
   for (int c = c_lo; c < c_hi; ++c) {
     mine += S.ccnt[c] - S.chead[c];
-    for (int32_t q = S.chead[c]; q < S.ccnt[c]; ++q) finalize_node<D>(A.mt, nodes[c * kChunk + q], sigma);
+    for (int32_t q = S.chead[c]; q < S.ccnt[c]; ++q) finalize_node<D>(A.mt, node(c * kChunk + q), sigma);
   }
   int64_t n_live = 0;
   const int64_t live_first = block_excl_scan_i64<kFieldThreads>(mine, sh.wtot, tid, &n_live);
@@ -1330,7 +1338,7 @@ __device__ __forceinline__ void process_ray(const FieldArgs& A, Shared<D>& sh, c
     int64_t pos = sh.base_out + live_first;
     for (int c = c_lo; c < c_hi; ++c) {
       for (int32_t q = S.chead[c]; q < S.ccnt[c]; ++q) {
-        const Node<D>& nd = nodes[c * kChunk + q];
+        const Node<D>& nd = node(c * kChunk + q);
         if (pos < A.out_cap) {
           // The piece is delivered on its float32 ends fa, fb: the projection, a polynomial in
           // u = (t - ta) / (tb - ta) over the exact ends, is re-expressed in u' = (t - fa) / (fb - fa)
@@ -1409,7 +1417,7 @@ __device__ __forceinline__ void process_ray(const FieldArgs& A, Shared<D>& sh, c
     };
     int64_t my_samples = 0;
     for (int c = c_lo; c < c_hi; ++c)
-      for (int32_t q = S.chead[c]; q < S.ccnt[c]; ++q) my_samples += sample_count(nodes[c * kChunk + q]);
+      for (int32_t q = S.chead[c]; q < S.ccnt[c]; ++q) my_samples += sample_count(node(c * kChunk + q));
     int64_t n_samp = 0;
     const int64_t samp_first = block_excl_scan_i64<kFieldThreads>(my_samples, sh.wtot, tid, &n_samp);
     // node index in the key array (free now; at least 8 bytes per exact piece): first sample
@@ -1422,7 +1430,7 @@ __device__ __forceinline__ void process_ray(const FieldArgs& A, Shared<D>& sh, c
         for (int32_t q = S.chead[c]; q < S.ccnt[c]; ++q) {
           ist[pos] = (int32_t)sp;
           iref[pos] = (int32_t)(c * kChunk + q);
-          sp += sample_count(nodes[c * kChunk + q]);
+          sp += sample_count(node(c * kChunk + q));
           ++pos;
         }
     }
@@ -1448,7 +1456,7 @@ __device__ __forceinline__ void process_ray(const FieldArgs& A, Shared<D>& sh, c
       }
       int64_t g = g0;
       for (int64_t n = lo; g < g1; ++n) {
-        const Node<D>& nd = nodes[iref[n]];
+        const Node<D>& nd = node(iref[n]);
         const double ta = (double)(t_lo + nd.a) * tau, tb = (double)(t_lo + nd.b) * tau;
         const double a = fmax(ta, ray_tmin), b = fmin(tb, ray_tmax);
         if (!(b > a)) continue;
