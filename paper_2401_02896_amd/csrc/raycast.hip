@@ -1133,26 +1133,45 @@ __device__ __forceinline__ void process_ray(const FieldArgs& A, Shared<D>& sh, c
     }
     agg_mine = g;
   }
-  // inclusive Hillis-Steele scan of the thread aggregates in thread order
-  sh.hs[tid] = agg_mine;
-  __syncthreads();
-  for (int ofs = 1; ofs < kFieldThreads; ofs <<= 1) {
-    Agg<D> mine = sh.hs[tid];
-    Agg<D> res = mine;
-    if (tid >= ofs) {
-      Agg<D> prev = sh.hs[tid - ofs];
-      agg_combine<D>(prev, mine, res);
-    }
-    __syncthreads();
-    sh.hs[tid] = res;
-    __syncthreads();
-  }
+  // scan of the thread aggregates in thread order (exact integers: any grouping gives the same
+  // states): inclusive within each wave by lane shuffles, then the totals of the earlier waves
+  // through LDS; a thread's carry is the inclusive aggregate of the thread before it
   Agg<D> carry;
-  if (tid > 0) carry = sh.hs[tid - 1];
-  else {
-    carry.valid = 0;
-    carry.t = 0;
-    for (int d = 0; d <= D; ++d) carry.a[d] = 0;
+  {
+    const int lane = tid & 63, wv = tid >> 6;
+    Agg<D> x = agg_mine;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      Agg<D> y;
+#pragma unroll
+      for (int d = 0; d <= D; ++d) y.a[d] = __shfl_up(x.a[d], o, 64);
+      y.t = __shfl_up(x.t, o, 64);
+      y.valid = __shfl_up(x.valid, o, 64);
+      if (lane >= o) {
+        Agg<D> res;
+        agg_combine<D>(y, x, res);
+        x = res;
+      }
+    }
+    if (lane == 63) sh.hs[wv] = x;
+    __syncthreads();
+    Agg<D> pre;
+    pre.valid = 0;
+    pre.t = 0;
+#pragma unroll
+    for (int d = 0; d <= D; ++d) pre.a[d] = 0;
+    for (int ww = 0; ww < wv; ++ww) {
+      Agg<D> res;
+      agg_combine<D>(pre, sh.hs[ww], res);
+      pre = res;
+    }
+    Agg<D> below;  // inclusive aggregate of the previous lane of this wave
+#pragma unroll
+    for (int d = 0; d <= D; ++d) below.a[d] = __shfl_up(x.a[d], 1, 64);
+    below.t = __shfl_up(x.t, 1, 64);
+    below.valid = __shfl_up(x.valid, 1, 64);
+    if (lane == 0) carry = pre;
+    else agg_combine<D>(pre, below, carry);
   }
   // ---- pass B: peak over piece starts, tail check, piece counts
   if (tid == 0) sh.peak = 0;
