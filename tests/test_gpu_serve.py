@@ -100,7 +100,9 @@ def test_requests_arriving_mid_batch_overlap_running_work():
     tf = torch.as_tensor(synth.transfer_function(), device="cuda")
     persp = {"eye": [0.5, 0.5, -1.5], "look_at": [0.5, 0.5, 0.5], "up": [0.0, 1.0, 0.0], "fov_y_deg": 30.0,
              "ortho": 0, "ortho_half_extent": 0.0, "width": 512, "height": 512, "t_min": 1.0, "t_max": 3.0}
-    big = persp
+    # the heavy request: 1024^2 rays through the 200k clustered set, several times the small
+    # requests' work even when their kernels wait for a slice of it to end
+    big = dict(persp, width=1024, height=1024)
     vb, sb = 300.0, 2.0 / 512
     small_a = _cams()[:5]
     small_b = [dict(persp, width=32 + 8 * i, height=24, fov_y_deg=5.0 + i) for i in range(4)]
@@ -126,6 +128,7 @@ def test_requests_arriving_mid_batch_overlap_running_work():
         st = srv.stats()
         assert st["lanes"] == 2 and st["completed"] == 1 + len(small_a) + len(small_b) and st["failed"] == 0
         assert st["overlapped_batches"] >= 1 and st["max_in_flight"] == 2, st
+        print(f"small requests: max latency {max(lat_small):.1f} ms; heavy request: {lat_big:.1f} ms", flush=True)
         assert max(lat_small) < lat_big, (lat_small, lat_big)
     finally:
         srv.close()
