@@ -754,6 +754,7 @@ __device__ bool hit_jumps(const MethodConsts& mc, TabRef srow, double base, doub
 // for the degree <= 2D integrands.
 template <int D>
 __device__ __forceinline__ Node<D> make_leaf(const MergeTables& mt, uint32_t ta, uint32_t tb, const uint64_t* coef) {
+  #pragma clang fp contract(fast)  // merge arithmetic: fused multiply-adds (no exact key depends on it)
   Node<D> n;
   n.a = ta;
   n.b = tb;
@@ -788,6 +789,7 @@ __device__ __forceinline__ Node<D> make_leaf(const MergeTables& mt, uint32_t ta,
 // (m_i <- sum_j C(i, j) (b - a)^(i - j) m_j, as repeated synthetic steps) plus A's.
 template <int D>
 __device__ __forceinline__ Node<D> combine(const Node<D>& A, const Node<D>& B) {
+  #pragma clang fp contract(fast)  // merge arithmetic: fused multiply-adds (no exact key depends on it)
   Node<D> U;
   U.a = A.a;
   U.b = B.b;
@@ -811,6 +813,7 @@ __device__ __forceinline__ Node<D> combine(const Node<D>& A, const Node<D>& B) {
 // its mean square int_0^1 f^2 du.
 template <int D>
 __device__ __forceinline__ void node_moments(const MergeTables& mt, const Node<D>& n, double* lam, double* ms) {
+  #pragma clang fp contract(fast)  // merge arithmetic: fused multiply-adds (no exact key depends on it)
   const double inv = 1.0 / (double)((int64_t)n.b - (int64_t)n.a);
   double mh[D + 1];
   double p = inv;
@@ -835,6 +838,7 @@ __device__ __forceinline__ void node_moments(const MergeTables& mt, const Node<D
 // exact arithmetic would accept.
 template <int D>
 __device__ __forceinline__ bool passes(const MergeTables& mt, const Node<D>& n, double thr2) {
+  #pragma clang fp contract(fast)  // merge arithmetic: fused multiply-adds (no exact key depends on it)
   double lam[D + 1], ms;
   node_moments<D>(mt, n, lam, &ms);
   double q = 0.0;
@@ -848,6 +852,7 @@ __device__ __forceinline__ bool passes(const MergeTables& mt, const Node<D>& n, 
 // projection in u = (t - a) / (b - a): c_d = sigma sum_j (2j + 1) lam_j leg2pow[j][d].
 template <int D>
 __device__ __forceinline__ void finalize_node(const MergeTables& mt, Node<D>& n, double sigma) {
+  #pragma clang fp contract(fast)  // merge arithmetic: fused multiply-adds (no exact key depends on it)
   double lam[D + 1], ms;
   node_moments<D>(mt, n, lam, &ms);
 #pragma unroll
@@ -1347,6 +1352,7 @@ __device__ __forceinline__ void process_ray(const FieldArgs& A, Shared<D>& sh, c
   int64_t n_live = 0;
   const int64_t live_first = block_excl_scan_i64<kFieldThreads>(mine, sh.wtot, tid, &n_live);
   if (!RENDER) {
+    #pragma clang fp contract(fast)  // output arithmetic: fused multiply-adds
     if (tid == 0) {
       sh.base_out = (int64_t)atomicAdd(&A.counters[0], (unsigned long long)n_live);
       A.ray_out[2 * r] = sh.base_out;
@@ -1422,6 +1428,7 @@ __device__ __forceinline__ void process_ray(const FieldArgs& A, Shared<D>& sh, c
       }
     }
   } else {
+    #pragma clang fp contract(fast)  // compositing arithmetic: fused multiply-adds
     // classification and front-to-back compositing.  The samples of the ray's live nodes are
     // numbered in order and split evenly over the threads (merged nodes can be long, so per-node
     // work is uneven); a thread finds its first node by binary search in an index of the nodes'
