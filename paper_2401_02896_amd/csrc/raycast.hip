@@ -898,7 +898,7 @@ __device__ __forceinline__ void agg_combine(const Agg<D>& x, const Agg<D>& y, Ag
 template <int D>
 struct Shared {
   union {                          // never live together: LDS is the ray layout's capacity
-    Agg<D> hs[kFieldThreads];      // scan of the thread aggregates (passes A and B)
+    Agg<D> hs[kFieldThreads / 64];  // the waves' totals in the scan of the thread aggregates
     float part[kFieldThreads][4];  // compositing partials (render, at the end)
     uint32_t sort_tab[2 * 256 * (kFieldThreads / 64)];  // digit counts of the knot sort
   };
