@@ -21,7 +21,10 @@ constexpr int kMaxLevels = 32;
 constexpr int kMaxD = 6;
 constexpr int kMaxP = 3;
 constexpr int kChunk = 16;          // knots per merge chunk
-constexpr int kFieldThreads = 256;  // threads per ray work-group
+// threads per ray work-group of the field kernel: 512 for D <= 3; 256 above, where the registers
+// of the higher degrees leave room for only four waves per SIMD at two work-groups of 256
+constexpr int field_threads(int D) { return D <= 3 ? 512 : 256; }
+constexpr int kFieldThreadsMin = 256;
 constexpr int64_t kLdsPerCu = 160 * 1024;
 constexpr int64_t kMaxAxisCells = int64_t(1) << 19;
 constexpr int64_t kMaxLevel0Cells = int64_t(1) << 24;

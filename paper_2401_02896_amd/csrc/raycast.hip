@@ -897,13 +897,14 @@ __device__ __forceinline__ void agg_combine(const Agg<D>& x, const Agg<D>& y, Ag
 
 template <int D>
 struct Shared {
+  static constexpr int NT = field_threads(D);
   union {                          // never live together: LDS is the ray layout's capacity
-    Agg<D> hs[kFieldThreads / 64];  // the waves' totals in the scan of the thread aggregates
-    float part[kFieldThreads][4];  // compositing partials (render, at the end)
-    uint32_t sort_tab[2 * 256 * (kFieldThreads / 64)];  // digit counts of the knot sort
+    Agg<D> hs[NT / 64];  // the waves' totals in the scan of the thread aggregates
+    float part[NT][4];  // compositing partials (render, at the end)
+    uint32_t sort_tab[2 * 256 * (NT / 64)];  // digit counts of the knot sort
   };
-  uint32_t rtab[32 * (kFieldThreads / 64)];  // radix sort tables
-  int64_t wtot[kFieldThreads / 64];
+  uint32_t rtab[32 * (NT / 64)];  // radix sort tables
+  int64_t wtot[NT / 64];
   unsigned long long peak;
   int64_t ray;
   int64_t base_out, base_ex;
@@ -990,8 +991,9 @@ __device__ __forceinline__ void jump_of(const MethodConsts& mc, const RayStore& 
 }
 
 // The exact-mode knot list's second sort (canonical order).
+template <int NT>
 __device__ __forceinline__ void sort_canonical(uint64_t* a, uint64_t* tmp, int n, int nbits, uint32_t* tab, int tid) {
-  radix_sort_u64<kFieldThreads, false>(a, tmp, n, 0, nbits, tab, tid);
+  radix_sort_u64<NT, false>(a, tmp, n, 0, nbits, tab, tid);
 }
 
 // Process one ray with all threads of the work-group.
@@ -999,6 +1001,7 @@ template <int D, bool RENDER>
 __device__ __forceinline__ void process_ray(const FieldArgs& A, Shared<D>& sh, const RayStore& S, Node<D>* nodes,
                                             int64_t r,
                             int64_t nh) {
+  constexpr int NT = field_threads(D);
   // opaque to the optimiser, so that per-thread addresses are not hoisted out of the ray loop and
   // kept live in registers across every phase
   int tid = threadIdx.x;
@@ -1025,7 +1028,7 @@ __device__ __forceinline__ void process_ray(const FieldArgs& A, Shared<D>& sh, c
   const int span32 = 2 * (K + 1);
   long long my_lo = 0x7fffffffffffffffll, my_hi = -0x7fffffffffffffffll - 1;
 #pragma unroll 1
-  for (int s = tid; s < (int)nh; s += kFieldThreads) {
+  for (int s = tid; s < (int)nh; s += NT) {
     const uint32_t j = A.hits[hoff + s];
     const float4 p = A.pos4[j];
     const float vj = A.val[j];
@@ -1090,7 +1093,7 @@ __device__ __forceinline__ void process_ray(const FieldArgs& A, Shared<D>& sh, c
   // ---- knot keys: (position - t_lo) in the high half, (slot, kidx) in the low half; kidx = k + P
   // for the knot at t0 + sign(k) o_|k|, laid out slot-major so that the stable sort leaves equal
   // positions in (slot, kidx) order.  Each thread rewrites the spans of the hits it parked.
-  for (int s = tid; s < (int)nh; s += kFieldThreads) {
+  for (int s = tid; s < (int)nh; s += NT) {
     const long long t0 = (long long)(((unsigned long long)(uint32_t)park[s * span32 + 1] << 32) |
                                      (unsigned long long)(uint32_t)park[s * span32]);
     int32_t o3[kMaxP];
@@ -1112,11 +1115,11 @@ __device__ __forceinline__ void process_ray(const FieldArgs& A, Shared<D>& sh, c
     // the position bits of the ray's range (at least one), 8 per pass
     const uint32_t range = (uint32_t)(sh.t_hi - t_lo);
     const int nbits = range ? 32 - __clz(range) : 1;
-    radix_sort_u64_d8<kFieldThreads, true>(S.kkey, S.kkey2, (int)nk, 32, nbits, sh.sort_tab, tid);
+    radix_sort_u64_d8<NT, true>(S.kkey, S.kkey2, (int)nk, 32, nbits, sh.sort_tab, tid);
   }
   // ---- thread ranges of chunks
   const int n_chunks = (nk + kChunk - 1) / kChunk;
-  const int per = (n_chunks + kFieldThreads - 1) / kFieldThreads;
+  const int per = (n_chunks + NT - 1) / NT;
   const int c_lo = min(tid * per, n_chunks), c_hi = min(c_lo + per, n_chunks);
   const int k_lo = c_lo * kChunk, k_hi = min(c_hi * kChunk, nk);
   // ---- pass A: aggregate of this thread's knots
@@ -1211,7 +1214,7 @@ __device__ __forceinline__ void process_ray(const FieldArgs& A, Shared<D>& sh, c
   atomicMax(&sh.peak, pk);
   // exclusive scan of piece counts (exact-mode positions)
   int64_t run = 0;
-  const int64_t ex_first = block_excl_scan_i64<kFieldThreads>(npieces, sh.wtot, tid, &run);
+  const int64_t ex_first = block_excl_scan_i64<NT>(npieces, sh.wtot, tid, &run);
   const double peak = sigma * (double)(int64_t)sh.peak;
   if (tid == 0) {
     if (A.exact) {
@@ -1306,7 +1309,7 @@ __device__ __forceinline__ void process_ray(const FieldArgs& A, Shared<D>& sh, c
   }
   __syncthreads();
   // ---- junction merges across chunk groups (levels 1, 2, 4, ...)
-  for (int c = tid; c < n_chunks; c += kFieldThreads) {
+  for (int c = tid; c < n_chunks; c += NT) {
     S.chead[c] = 0;
     const int32_t cn = S.ccnt[c];
     S.gfirst[c] = cn > 0 ? (int32_t)(c * kChunk) : -1;
@@ -1315,7 +1318,7 @@ __device__ __forceinline__ void process_ray(const FieldArgs& A, Shared<D>& sh, c
   __syncthreads();
   if (tol > 0.0) {
     for (int w = 1; w < n_chunks; w <<= 1) {
-      for (int L = tid * 2 * w; L < n_chunks; L += kFieldThreads * 2 * w) {
+      for (int L = tid * 2 * w; L < n_chunks; L += NT * 2 * w) {
         const int R = L + w;
         if (R >= n_chunks) continue;
         const int32_t lf = S.gfirst[L], ll = S.glast[L], rf = S.gfirst[R], rl = S.glast[R];
@@ -1350,7 +1353,7 @@ __device__ __forceinline__ void process_ray(const FieldArgs& A, Shared<D>& sh, c
     for (int32_t q = S.chead[c]; q < S.ccnt[c]; ++q) finalize_node<D>(A.mt, node(c * kChunk + q), sigma);
   }
   int64_t n_live = 0;
-  const int64_t live_first = block_excl_scan_i64<kFieldThreads>(mine, sh.wtot, tid, &n_live);
+  const int64_t live_first = block_excl_scan_i64<NT>(mine, sh.wtot, tid, &n_live);
   if (!RENDER) {
     #pragma clang fp contract(fast)  // output arithmetic: fused multiply-adds
     if (tid == 0) {
@@ -1407,7 +1410,7 @@ __device__ __forceinline__ void process_ray(const FieldArgs& A, Shared<D>& sh, c
     if (A.exact) {
       // sorted knot list in the canonical order (position, particle input index, kidx)
       __syncthreads();
-      for (int64_t i = tid; i < nk; i += kFieldThreads) {
+      for (int64_t i = tid; i < nk; i += NT) {
         const uint64_t key = S.kkey[kpad(i)];
         S.kkey2[i] = (key & 0xffffffff00000000ull) | ((uint64_t)(uint32_t)A.orig[A.hits[hoff + key_slot(key)]] << 3) |
                      (uint64_t)key_kidx(key);
@@ -1416,8 +1419,8 @@ __device__ __forceinline__ void process_ray(const FieldArgs& A, Shared<D>& sh, c
       const uint32_t range = (uint32_t)(sh.t_hi - t_lo);
       int nbits = 36;
       while (nbits < 64 && (range >> (nbits - 32)) != 0) nbits += 4;
-      sort_canonical(S.kkey2, S.kkey, (int)nk, nbits, sh.rtab, tid);
-      for (int64_t i = tid; i < nk; i += kFieldThreads) {
+      sort_canonical<NT>(S.kkey2, S.kkey, (int)nk, nbits, sh.rtab, tid);
+      for (int64_t i = tid; i < nk; i += NT) {
         const uint64_t key = S.kkey2[i];
         const int64_t ko = A.knot_off[r] + i;
         if (ko < A.knot_cap) {
@@ -1445,7 +1448,7 @@ __device__ __forceinline__ void process_ray(const FieldArgs& A, Shared<D>& sh, c
     for (int c = c_lo; c < c_hi; ++c)
       for (int32_t q = S.chead[c]; q < S.ccnt[c]; ++q) my_samples += sample_count(node(c * kChunk + q));
     int64_t n_samp = 0;
-    const int64_t samp_first = block_excl_scan_i64<kFieldThreads>(my_samples, sh.wtot, tid, &n_samp);
+    const int64_t samp_first = block_excl_scan_i64<NT>(my_samples, sh.wtot, tid, &n_samp);
     // node index in the key array (free now; at least 8 bytes per exact piece): first sample
     // number and node slot of each live node
     int32_t* ist = reinterpret_cast<int32_t*>(S.kkey);
@@ -1464,12 +1467,12 @@ __device__ __forceinline__ void process_ray(const FieldArgs& A, Shared<D>& sh, c
     const float* tfp = A.tf;
     if ((int64_t)ntf * 16 <= 8 * (int64_t)S.nj * nh) {
       float* t = reinterpret_cast<float*>(S.jmp);
-      for (int i = tid; i < 4 * ntf; i += kFieldThreads) t[i] = A.tf[i];
+      for (int i = tid; i < 4 * ntf; i += NT) t[i] = A.tf[i];
       tfp = t;
     }
     __syncthreads();
     float C0 = 0.f, C1 = 0.f, C2 = 0.f, T = 1.f;
-    const int64_t share = (n_samp + kFieldThreads - 1) / kFieldThreads;
+    const int64_t share = (n_samp + NT - 1) / NT;
     const int64_t g0 = min((int64_t)tid * share, n_samp), g1 = min(g0 + share, n_samp);
     if (g0 < g1) {
       // last node whose first sample number is <= g0 (nodes without samples share the number of
@@ -1526,8 +1529,8 @@ __device__ __forceinline__ void process_ray(const FieldArgs& A, Shared<D>& sh, c
     sh.part[tid][3] = T;
     __syncthreads();
     // ordered tree reduction: (C1, T1) then (C2, T2) = (C1 + T1 C2, T1 T2)
-    for (int s = 1; s < kFieldThreads; s <<= 1) {
-      if ((tid % (2 * s)) == 0 && tid + s < kFieldThreads) {
+    for (int s = 1; s < NT; s <<= 1) {
+      if ((tid % (2 * s)) == 0 && tid + s < NT) {
         const float t1 = sh.part[tid][3];
         sh.part[tid][0] += t1 * sh.part[tid + s][0];
         sh.part[tid][1] += t1 * sh.part[tid + s][1];
@@ -1548,7 +1551,7 @@ __device__ __forceinline__ void process_ray(const FieldArgs& A, Shared<D>& sh, c
 // WGS: ray work-groups meant to share a CU (registers capped accordingly; the host sizes the
 // dynamic LDS to 1 / WGS of the CU)
 template <int D, bool RENDER, int WGS>
-__global__ void __launch_bounds__(kFieldThreads, WGS) k_field(FieldArgs A) {
+__global__ void __launch_bounds__(field_threads(D), WGS) k_field(FieldArgs A) {
   extern __shared__ __align__(16) char lds[];
   __shared__ Shared<D> sh;
   char* slab = A.slab + (int64_t)blockIdx.x * A.slab_stride;
@@ -1723,12 +1726,12 @@ void launch_field(FieldArgs& A, int grid, size_t lds, hipStream_t st) {
   hip_check(hipFuncSetAttribute((const void*)k_field<D, RENDER, WGS>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)lds),
             "set lds");
-  k_field<D, RENDER, WGS><<<grid, kFieldThreads, lds, st>>>(A);
+  k_field<D, RENDER, WGS><<<grid, field_threads(D), lds, st>>>(A);
   hip_check(hipGetLastError(), "field launch");
 }
 
 constexpr int max_field_wgs_c(int D, bool render) {
-  return render ? (D <= 2 ? 4 : (D <= 5 ? 3 : 2)) : (D <= 1 ? 4 : (D <= 4 ? 3 : 2));
+  return (field_threads(D) == 512) ? 2 : (render ? (D <= 5 ? 3 : 2) : (D <= 4 ? 3 : 2));
 }
 
 // Only the (degree, work-groups per CU) pairs whose registers fit without spilling are built.
@@ -2082,7 +2085,7 @@ void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam,
   ws.stats.max_hits = (int64_t)mh;
   ws.stats.n_knots = total_pairs * (K + 1);
   // the per-ray sort ranks a wave's keys in 16-bit fields: at most 1023 keys per thread
-  if ((int64_t)mh * (K + 1) > (int64_t)1023 * kFieldThreads)
+  if ((int64_t)mh * (K + 1) > (int64_t)1023 * kFieldThreadsMin)
     throw Error(SPH_HOA_E_UNSUPPORTED, "more than 1023 * 256 knots on one ray");
   if (n_cams == 0) ws.last_max_hits = (int64_t)mh;
   const bool single_pass = gathered ? gathered->ws.last_hit_slots > 0 : (n_slots > 0 && (int64_t)mh <= n_slots);

@@ -239,9 +239,9 @@ def test_device_memory_path_is_identical():
 
 
 def test_field_kernel_configurations_identical():
-    """One to four ray work-groups per CU (the tuner's choices; with four, every tiny ray's layout
-    still fits a quarter of the LDS or moves to device memory), and the field kernel launched in
-    time slices, give the same bits."""
+    """One to four ray work-groups per CU, as far as the degree allows (the tuner's choices: D <= 3
+    runs work-groups of 512 threads, at most two per CU; D >= 4 of 256, up to three), and the field
+    kernel launched in time slices, give the same bits."""
     sc = H.tiny_scene()
     o, v = synth.ortho_rays()
     o, v = o[:700], v[:700]
