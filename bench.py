@@ -817,6 +817,9 @@ def main():
     warm = L.sph_hoa_approx_rays(idx, ro, rv, cam["t_min"], cam["t_max"])
     cap = int(warm["n_pieces"]) + 1024  # output sized once, as a caller reusing buffers would
     del warm
+    # warm-up calls while the library's tuner times its field kernel configurations (one call each)
+    for _ in range(6):
+        L.sph_hoa_approx_rays(idx, ro, rv, cam["t_min"], cam["t_max"], capacity=cap)
     torch.cuda.synchronize()
     alat = []
     for _ in range(3):

@@ -21,9 +21,23 @@ constexpr int kMaxLevels = 32;
 constexpr int kMaxD = 6;
 constexpr int kMaxP = 3;
 constexpr int kChunk = 16;          // knots per merge chunk
-// threads per ray work-group of the field kernel: 512 for D <= 3; 256 above, where the registers
-// of the higher degrees leave room for only four waves per SIMD at two work-groups of 256
-constexpr int field_threads(int D) { return D <= 3 ? 512 : 256; }
+// Field kernel configurations: threads per ray work-group (256 or 512) and work-groups per CU
+// (which also splits the CU's LDS between the rays), numbered 1..4 (256 threads, 1..4 per CU) and
+// 5..6 (512 threads, 1..2 per CU).  field_cfg_valid: the ones a degree can run without spilling
+// registers; rendering keeps one thread count per degree (512 for D <= 3, 256 above), because the
+// compositing partials are combined over the work-group's threads and a pixel must not depend on
+// the configuration, while the fields (integer sums, chunked merge) are the same bits under every
+// configuration.  The tuner picks among the valid ones per workload signature.
+constexpr int kFieldCfgs = 6;
+constexpr int field_cfg_threads(int cfg) { return cfg > 4 ? 512 : 256; }
+constexpr int field_cfg_wgs(int cfg) { return cfg > 4 ? cfg - 4 : cfg; }
+constexpr bool field_cfg_valid(int D, bool render, int cfg) {
+  return cfg < 1 || cfg > kFieldCfgs ? false
+         : field_cfg_threads(cfg) == 512
+             ? (D <= 3 && field_cfg_wgs(cfg) <= 2)
+             : (!(render && D <= 3) &&
+                field_cfg_wgs(cfg) <= (render ? (D <= 5 ? 3 : 2) : (D <= 1 ? 4 : (D <= 4 ? 3 : 2))));
+}
 constexpr int kFieldThreadsMin = 256;
 constexpr int64_t kLdsPerCu = 160 * 1024;
 constexpr int64_t kMaxAxisCells = int64_t(1) << 19;
@@ -159,7 +173,6 @@ struct MethodConsts {
 
 // Most field work-groups per CU for degree D (render or field output) that the kernel's registers
 // allow without spilling.
-int max_field_wgs(int D, bool render);
 
 // Online choice of the field kernel's work-groups per CU (1 to 4; a ray's layout gets 1 / wgs of
 // the CU's LDS) per workload signature (degree, mode, log2 of the mean and of the largest hits per
@@ -176,9 +189,10 @@ struct FieldTuner {
     }
   };
   struct Entry {
-    double ms_per_pair[5] = {-1.0, -1.0, -1.0, -1.0, -1.0};  // by work-groups per CU (1..4)
+    double ms_per_pair[kFieldCfgs + 1] = {-1.0, -1.0, -1.0, -1.0, -1.0, -1.0, -1.0};  // by configuration
   };
-  static constexpr int kOrder[4] = {2, 3, 4, 1};  // candidates, in the order they are measured
+  // candidates (field kernel configurations), in the order they are measured
+  static constexpr int kOrder[kFieldCfgs] = {6, 2, 3, 4, 5, 1};
   std::map<Key, Entry> table;
   bool pending = false;
   Key pend_key{};
@@ -187,8 +201,8 @@ struct FieldTuner {
   hipEvent_t ev[2] = {};
   static Key key_of(int D, bool render, int64_t pairs, int64_t rays, int64_t max_hits);
   int choose(const Key& k);
-  int chosen(const Key& k) const;  // the measured choice, 2 while not both measured; times nothing
-  void begin(const Key& k, int wgs, int64_t pairs, hipStream_t st);
+  int chosen(const Key& k) const;  // the best measured configuration (the first valid candidate while none is); times nothing
+  void begin(const Key& k, int cfg, int64_t pairs, hipStream_t st);
   void end(hipStream_t st);
   void collect();
   FieldTuner() = default;

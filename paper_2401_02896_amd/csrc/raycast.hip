@@ -895,9 +895,8 @@ __device__ __forceinline__ void agg_combine(const Agg<D>& x, const Agg<D>& y, Ag
   for (int d = 0; d <= D; ++d) out.a[d] = s[d] + y.a[d];
 }
 
-template <int D>
+template <int D, int NT>
 struct Shared {
-  static constexpr int NT = field_threads(D);
   union {                          // never live together: LDS is the ray layout's capacity
     Agg<D> hs[NT / 64];  // the waves' totals in the scan of the thread aggregates
     float part[NT][4];  // compositing partials (render, at the end)
@@ -997,11 +996,10 @@ __device__ __forceinline__ void sort_canonical(uint64_t* a, uint64_t* tmp, int n
 }
 
 // Process one ray with all threads of the work-group.
-template <int D, bool RENDER>
-__device__ __forceinline__ void process_ray(const FieldArgs& A, Shared<D>& sh, const RayStore& S, Node<D>* nodes,
+template <int D, bool RENDER, int NT>
+__device__ __forceinline__ void process_ray(const FieldArgs& A, Shared<D, NT>& sh, const RayStore& S, Node<D>* nodes,
                                             int64_t r,
                             int64_t nh) {
-  constexpr int NT = field_threads(D);
   // opaque to the optimiser, so that per-thread addresses are not hoisted out of the ray loop and
   // kept live in registers across every phase
   int tid = threadIdx.x;
@@ -1550,10 +1548,10 @@ __device__ __forceinline__ void process_ray(const FieldArgs& A, Shared<D>& sh, c
 
 // WGS: ray work-groups meant to share a CU (registers capped accordingly; the host sizes the
 // dynamic LDS to 1 / WGS of the CU)
-template <int D, bool RENDER, int WGS>
-__global__ void __launch_bounds__(field_threads(D), WGS) k_field(FieldArgs A) {
+template <int D, bool RENDER, int WGS, int NT>
+__global__ void __launch_bounds__(NT, WGS) k_field(FieldArgs A) {
   extern __shared__ __align__(16) char lds[];
-  __shared__ Shared<D> sh;
+  __shared__ Shared<D, NT> sh;
   char* slab = A.slab + (int64_t)blockIdx.x * A.slab_stride;
   Node<D>* nodes = (Node<D>*)slab;
   uint64_t* gjmp = (uint64_t*)(slab + A.slab_jmp);
@@ -1594,12 +1592,12 @@ __global__ void __launch_bounds__(field_threads(D), WGS) k_field(FieldArgs A) {
       if (tier == 0) {
         // common case, its own inlined copy so that every access compiles to LDS instructions
         const RayStore S = carve(lds, nh, nk, A.nj, nullptr);
-        process_ray<D, RENDER>(A, sh, S, nodes, r, nh);
+        process_ray<D, RENDER, NT>(A, sh, S, nodes, r, nh);
       } else {
         if (threadIdx.x == 0) atomicAdd(&A.counters[tier == 1 ? 4 : (tier == 2 ? 5 : 3)], 1ull);
         const RayStore S = carve(tier < 3 ? lds : gstore, nh, nk, A.nj, tier < 3 ? gjmp : nullptr,
                                  tier == 2 ? gscratch : nullptr);
-        process_ray<D, RENDER>(A, sh, S, nodes, r, nh);
+        process_ray<D, RENDER, NT>(A, sh, S, nodes, r, nh);
       }
     }
     __syncthreads();
@@ -1716,66 +1714,69 @@ MergeTables make_merge_tables(int D) {
   return t;
 }
 
-template <int D>
+template <int D, int NT>
 size_t shared_static_bytes() {
-  return sizeof(Shared<D>);
+  return sizeof(Shared<D, NT>);
 }
 
-template <int D, bool RENDER, int WGS>
+template <int D, bool RENDER, int WGS, int NT>
 void launch_field(FieldArgs& A, int grid, size_t lds, hipStream_t st) {
-  hip_check(hipFuncSetAttribute((const void*)k_field<D, RENDER, WGS>, hipFuncAttributeMaxDynamicSharedMemorySize,
+  hip_check(hipFuncSetAttribute((const void*)k_field<D, RENDER, WGS, NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)lds),
             "set lds");
-  k_field<D, RENDER, WGS><<<grid, field_threads(D), lds, st>>>(A);
+  k_field<D, RENDER, WGS, NT><<<grid, NT, lds, st>>>(A);
   hip_check(hipGetLastError(), "field launch");
 }
 
-constexpr int max_field_wgs_c(int D, bool render) {
-  return (field_threads(D) == 512) ? 2 : (render ? (D <= 5 ? 3 : 2) : (D <= 4 ? 3 : 2));
-}
-
-// Only the (degree, work-groups per CU) pairs whose registers fit without spilling are built.
-template <int D, bool RENDER, int WGS>
+// Only the configurations whose registers fit without spilling are built (field_cfg_valid).
+template <int D, bool RENDER, int CFG>
 void launch_field_checked(FieldArgs& A, int grid, size_t lds, hipStream_t st) {
-  if constexpr (WGS <= max_field_wgs_c(D, RENDER)) launch_field<D, RENDER, WGS>(A, grid, lds, st);
-  else throw Error(SPH_HOA_E_INTERNAL, "work-groups per CU beyond the degree's limit");
+  if constexpr (field_cfg_valid(D, RENDER, CFG))
+    launch_field<D, RENDER, field_cfg_wgs(CFG), field_cfg_threads(CFG)>(A, grid, lds, st);
+  else
+    throw Error(SPH_HOA_E_INTERNAL, "field kernel configuration beyond the degree's limit");
 }
 
-template <bool RENDER, int WGS>
-void dispatch_field_wgs(int D, FieldArgs& A, int grid, size_t lds, hipStream_t st) {
+template <bool RENDER, int CFG>
+void dispatch_field_cfg(int D, FieldArgs& A, int grid, size_t lds, hipStream_t st) {
   switch (D) {
-    case 1: launch_field_checked<1, RENDER, WGS>(A, grid, lds, st); break;
-    case 2: launch_field_checked<2, RENDER, WGS>(A, grid, lds, st); break;
-    case 3: launch_field_checked<3, RENDER, WGS>(A, grid, lds, st); break;
-    case 4: launch_field_checked<4, RENDER, WGS>(A, grid, lds, st); break;
-    case 5: launch_field_checked<5, RENDER, WGS>(A, grid, lds, st); break;
-    case 6: launch_field_checked<6, RENDER, WGS>(A, grid, lds, st); break;
+    case 1: launch_field_checked<1, RENDER, CFG>(A, grid, lds, st); break;
+    case 2: launch_field_checked<2, RENDER, CFG>(A, grid, lds, st); break;
+    case 3: launch_field_checked<3, RENDER, CFG>(A, grid, lds, st); break;
+    case 4: launch_field_checked<4, RENDER, CFG>(A, grid, lds, st); break;
+    case 5: launch_field_checked<5, RENDER, CFG>(A, grid, lds, st); break;
+    case 6: launch_field_checked<6, RENDER, CFG>(A, grid, lds, st); break;
     default: throw Error(SPH_HOA_E_UNSUPPORTED, "degree");
   }
 }
 
 template <bool RENDER>
-void dispatch_field(int D, int wgs, FieldArgs& A, int grid, size_t lds, hipStream_t st) {
-  switch (wgs) {
-    case 1: dispatch_field_wgs<RENDER, 1>(D, A, grid, lds, st); break;
-    case 3: dispatch_field_wgs<RENDER, 3>(D, A, grid, lds, st); break;
-    case 4: dispatch_field_wgs<RENDER, 4>(D, A, grid, lds, st); break;
-    default: dispatch_field_wgs<RENDER, 2>(D, A, grid, lds, st); break;
+void dispatch_field(int D, int cfg, FieldArgs& A, int grid, size_t lds, hipStream_t st) {
+  switch (cfg) {
+    case 1: dispatch_field_cfg<RENDER, 1>(D, A, grid, lds, st); break;
+    case 2: dispatch_field_cfg<RENDER, 2>(D, A, grid, lds, st); break;
+    case 3: dispatch_field_cfg<RENDER, 3>(D, A, grid, lds, st); break;
+    case 4: dispatch_field_cfg<RENDER, 4>(D, A, grid, lds, st); break;
+    case 5: dispatch_field_cfg<RENDER, 5>(D, A, grid, lds, st); break;
+    default: dispatch_field_cfg<RENDER, 6>(D, A, grid, lds, st); break;
   }
 }
 
 size_t node_bytes(int D) { return 8 + 8 * (size_t)(D + 3); }
 
-size_t static_lds(int D) {
+template <int NT>
+size_t static_lds_nt(int D) {
   switch (D) {
-    case 1: return shared_static_bytes<1>();
-    case 2: return shared_static_bytes<2>();
-    case 3: return shared_static_bytes<3>();
-    case 4: return shared_static_bytes<4>();
-    case 5: return shared_static_bytes<5>();
-    default: return shared_static_bytes<6>();
+    case 1: return shared_static_bytes<1, NT>();
+    case 2: return shared_static_bytes<2, NT>();
+    case 3: return shared_static_bytes<3, NT>();
+    case 4: return shared_static_bytes<4, NT>();
+    case 5: return shared_static_bytes<5, NT>();
+    default: return shared_static_bytes<6, NT>();
   }
 }
+
+size_t static_lds(int D, int nt) { return nt == 512 ? static_lds_nt<512>(D) : static_lds_nt<256>(D); }
 
 unsigned blocks_for(int64_t n, int t) {
   return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + t - 1) / t, 65536));
@@ -1834,18 +1835,21 @@ FieldTuner::Key FieldTuner::key_of(int D, bool render, int64_t pairs, int64_t ra
   return Key{D, render ? 1 : 0, lg(1 + pairs / std::max<int64_t>(1, rays)), lg(1 + max_hits)};
 }
 
-int max_field_wgs(int D, bool render) { return max_field_wgs_c(D, render); }
-
 int FieldTuner::chosen(const Key& k) const {
+  int best = -1;
+  for (int c : kOrder)
+    if (field_cfg_valid(k.D, k.render != 0, c)) {
+      best = c;  // the first valid candidate while nothing is measured
+      break;
+    }
   const auto it = table.find(k);
-  if (it == table.end()) return kOrder[0];
-  int best = kOrder[0];
+  if (it == table.end()) return best;
   double best_ms = -1.0;
-  for (int w : kOrder) {
-    if (w > max_field_wgs(k.D, k.render != 0)) continue;
-    const double v = it->second.ms_per_pair[w];
+  for (int c : kOrder) {
+    if (!field_cfg_valid(k.D, k.render != 0, c)) continue;
+    const double v = it->second.ms_per_pair[c];
     if (v >= 0 && (best_ms < 0 || v < best_ms)) {
-      best = w;
+      best = c;
       best_ms = v;
     }
   }
@@ -1854,14 +1858,14 @@ int FieldTuner::chosen(const Key& k) const {
 
 int FieldTuner::choose(const Key& k) {
   Entry& e = table[k];
-  for (int w : kOrder)
-    if (w <= max_field_wgs(k.D, k.render != 0) && e.ms_per_pair[w] < 0) return w;  // measure each candidate once, in order
+  for (int c : kOrder)
+    if (field_cfg_valid(k.D, k.render != 0, c) && e.ms_per_pair[c] < 0) return c;  // measure each candidate once, in order
   return chosen(k);
 }
 
-void FieldTuner::begin(const Key& k, int wgs, int64_t pairs, hipStream_t st) {
+void FieldTuner::begin(const Key& k, int cfg, int64_t pairs, hipStream_t st) {
   Entry& e = table[k];
-  const int slot = wgs;
+  const int slot = cfg;
   pending = (e.ms_per_pair[slot] < 0 && pairs > 0);
   if (!pending) return;
   for (auto& v : ev)
@@ -2224,14 +2228,26 @@ void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam,
   // the frame's longest ray.
   const int nj = jump_values_per_hit(P, (K % 2 == 0) ? 1 : 0, D);
   A.nj = nj;
-  const size_t lds_static = static_lds(D);
   const int64_t mh1 = std::max<int64_t>(1, (int64_t)mh);
   const bool render_mode = (out.rgba != nullptr);
   const FieldTuner::Key tkey = FieldTuner::key_of(D, render_mode, total_pairs, n_rays, (int64_t)mh);
   // (the static-scratch entry point takes the tuner's choice without timing anything)
-  int wgs = ws.no_alloc ? ws.tuner.chosen(tkey) : ws.tuner.choose(tkey);
-  if (const char* f = std::getenv("SPH_HOA_FIELD_WGS")) wgs = std::max(1, std::atoi(f));  // test hook
-  wgs = std::min(wgs, max_field_wgs(D, render_mode));
+  int cfg = ws.no_alloc ? ws.tuner.chosen(tkey) : ws.tuner.choose(tkey);
+  {
+    // test hooks: a given number of work-groups per CU and of threads per work-group (the nearest
+    // valid configuration)
+    int w = field_cfg_wgs(cfg), t = field_cfg_threads(cfg);
+    if (const char* f = std::getenv("SPH_HOA_FIELD_WGS")) w = std::min(4, std::max(1, std::atoi(f)));
+    if (const char* f = std::getenv("SPH_HOA_FIELD_THREADS")) t = std::atoi(f) >= 512 ? 512 : 256;
+    const int base = (t == 512 ? 4 : 0);
+    if (!field_cfg_valid(D, render_mode, base + 1)) t = (t == 512 ? 256 : 512);  // the other thread count
+    const int b = (t == 512 ? 4 : 0);
+    if (t == 512) w = std::min(w, 2);
+    while (w > 1 && !field_cfg_valid(D, render_mode, b + w)) --w;
+    cfg = b + w;
+  }
+  const int wgs = field_cfg_wgs(cfg);
+  const size_t lds_static = static_lds(D, field_cfg_threads(cfg));
   const int64_t lds_budget = kLdsPerCu / wgs - (int64_t)lds_static - 512;
   int64_t lds = std::min<int64_t>(lds_budget, ray_store_bytes(mh1, max_knots, nj, true));
   // test hook: a smaller LDS capacity (in hits) sends more rays down the device-memory paths
@@ -2280,8 +2296,8 @@ void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam,
     A.tf_step = (double)out.tf->step;
     A.rgba = out.rgba;
     if (ws.timing) hip_check(hipEventRecord(ws.ev[4], st), "event");
-    if (!ws.no_alloc) ws.tuner.begin(tkey, wgs, total_pairs, st);
-    for (int l = 0; l < launches; ++l) dispatch_field<true>(D, wgs, A, grid, (size_t)lds, st);
+    if (!ws.no_alloc) ws.tuner.begin(tkey, cfg, total_pairs, st);
+    for (int l = 0; l < launches; ++l) dispatch_field<true>(D, cfg, A, grid, (size_t)lds, st);
     if (!ws.no_alloc) ws.tuner.end(st);
     ws.render_stats_pending = true;
     if (ws.timing) {
@@ -2320,8 +2336,8 @@ void run_rays(Index& ix, int64_t n_rays, bool camera, const sph_hoa_camera* cam,
                   "copy");
     }
     if (ws.timing) hip_check(hipEventRecord(ws.ev[4], st), "event");
-    if (!ws.no_alloc) ws.tuner.begin(tkey, wgs, total_pairs, st);
-    for (int l = 0; l < launches; ++l) dispatch_field<false>(D, wgs, A, grid, (size_t)lds, st);
+    if (!ws.no_alloc) ws.tuner.begin(tkey, cfg, total_pairs, st);
+    for (int l = 0; l < launches; ++l) dispatch_field<false>(D, cfg, A, grid, (size_t)lds, st);
     if (!ws.no_alloc) ws.tuner.end(st);
     if (ws.timing) {
       hip_check(hipEventRecord(ws.ev[5], st), "event");

@@ -239,24 +239,27 @@ def test_device_memory_path_is_identical():
 
 
 def test_field_kernel_configurations_identical():
-    """One to four ray work-groups per CU, as far as the degree allows (the tuner's choices: D <= 3
-    runs work-groups of 512 threads, at most two per CU; D >= 4 of 256, up to three), and the field
-    kernel launched in time slices, give the same bits."""
+    """Every field kernel configuration the tuner can choose (work-groups of 256 threads, one to
+    four per CU as far as the degree allows; of 512 threads, one or two per CU for D <= 3) and the
+    field kernel launched in time slices give the same fields and images bit for bit."""
     sc = H.tiny_scene()
     o, v = synth.ortho_rays()
     o, v = o[:700], v[:700]
     cam = synth.tiny_camera(48, 40)
     tf = synth.transfer_function()
     res = []
-    for wgs in ("1", "2", "3", "4"):
-        os.environ["SPH_HOA_FIELD_WGS"] = wgs
-        try:
-            a = _approx(sc, o, v, 0.0, 1.4)
-            img = L.sph_hoa_render(sc.index(), cam, tf, 0.0, 4.0e4, 1.4 / 256)
-            torch.cuda.synchronize()
-        finally:
-            del os.environ["SPH_HOA_FIELD_WGS"]
-        res.append((a, img))
+    for threads in ("256", "512"):
+        for wgs in ("1", "2", "3", "4"):
+            os.environ["SPH_HOA_FIELD_WGS"] = wgs
+            os.environ["SPH_HOA_FIELD_THREADS"] = threads
+            try:
+                a = _approx(sc, o, v, 0.0, 1.4)
+                img = L.sph_hoa_render(sc.index(), cam, tf, 0.0, 4.0e4, 1.4 / 256)
+                torch.cuda.synchronize()
+            finally:
+                del os.environ["SPH_HOA_FIELD_WGS"]
+                del os.environ["SPH_HOA_FIELD_THREADS"]
+            res.append((a, img, threads))
     # the field kernel launched in time slices (each work-group a bounded share of the rays per
     # launch, as on render-server lanes)
     os.environ["SPH_HOA_TIME_SLICES"] = "5"
@@ -270,9 +273,10 @@ def test_field_kernel_configurations_identical():
     ref_big = L.sph_hoa_render(sc.index(), big, tf, 0.0, 4.0e4, 1.4 / 256)
     torch.cuda.synchronize()
     assert torch.equal(img, ref_big)
-    a1, i1 = res[0]
-    res.append((a, i1))
-    for a2, i2 in res[1:]:
+    # fields: the same bits in every configuration; images too (rendering keeps one thread count
+    # per degree, so the requested 256-thread work-groups render with 512 here)
+    a1, i1, _ = res[0]
+    for a2, i2, _ in res[1:] + [(a, i1, None)]:
         for k in ("ray_offsets", "t_start", "t_end", "coef", "ray_peak", "exact_t", "exact_coef", "knot_t", "knot_pid"):
             assert torch.equal(a1[k], a2[k]), k
         assert torch.equal(i1, i2)
