@@ -190,7 +190,8 @@ __device__ __forceinline__ void radix_sort_u64(uint64_t* a, uint64_t* tmp, int n
 // each wave then moves its segment in rounds of 64 keys, a key's rank among the round's equal
 // digits coming from a match over the digit's bits (one ballot per bit) and the digit's slot
 // advancing by the round's count, so no work-group barrier is needed inside the pass and equal
-// digits keep their order.  tab: 2 * 256 * W uint32 of LDS.  The result ends in `a`; with PAD_OUT
+// digits keep their order; n <= 2^16 W - W (a wave's segment of counts fits 16 bits).  tab: 384 * W
+// uint32 of LDS.  The result ends in `a`; with PAD_OUT
 // it is stored with one unused slot after every 16 elements (element i at i + i / 16; a and tmp
 // then hold n + n / 16 + 1 elements).  Caller guarantees a barrier before; ends with a barrier.
 template <int NT, bool PAD_OUT>
@@ -202,15 +203,19 @@ __device__ __forceinline__ void radix_sort_u64_d8(uint64_t* a, uint64_t* tmp, in
   const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
   const int seg = (n + W - 1) / W;
   const int s0 = min(w * seg, n), s1 = min(s0 + seg, n);
-  uint32_t* cur = tab;             // [W][256] this pass: counts, then slots
-  uint32_t* nxt = tab + 256 * W;   // [W][256] next pass's counts
+  uint32_t* cur = tab;             // [W][256] this pass's first output slots
+  uint32_t* cnt = tab + 256 * W;   // [W][128] digit counts, two 16-bit fields per word (a wave's
+                                   // segment holds fewer than 2^16 keys)
   uint64_t* src = a;
   uint64_t* dst = tmp;
-  for (int i = tid; i < 256 * W; i += NT) cur[i] = 0u;
+  for (int i = tid; i < 128 * W; i += NT) cnt[i] = 0u;
   __syncthreads();
   {
     const uint32_t mask = (1u << min(8, nbits)) - 1u;
-    for (int i = s0 + lane; i < s1; i += 64) atomicAdd(&cur[w * 256 + ((uint32_t)(src[i] >> lo_bit) & mask)], 1u);
+    for (int i = s0 + lane; i < s1; i += 64) {
+      const uint32_t d = (uint32_t)(src[i] >> lo_bit) & mask;
+      atomicAdd(&cnt[w * 128 + (d >> 1)], 1u << (16 * (d & 1u)));
+    }
   }
   for (int shift = lo_bit; shift < lo_bit + nbits; shift += 8) {
     const int bits = min(8, lo_bit + nbits - shift);
@@ -219,13 +224,19 @@ __device__ __forceinline__ void radix_sort_u64_d8(uint64_t* a, uint64_t* tmp, in
     const uint32_t mask_n = last ? 0u : (1u << min(8, lo_bit + nbits - shift - 8)) - 1u;
     __syncthreads();
     if (w == 0) {
-      // entry e = d * W + ww (digit-major), E consecutive entries per lane
+      // entry e = d * W + ww (digit-major), E consecutive entries per lane; the counts are read,
+      // then cleared for the counts of the next pass, then turned into slots
       uint32_t x[E], sum = 0;
 #pragma unroll
       for (int j = 0; j < E; ++j) {
         const int e = lane * E + j, d = e / W, ww = e % W;
-        x[j] = cur[ww * 256 + d];
+        x[j] = (cnt[ww * 128 + (d >> 1)] >> (16 * (d & 1))) & 0xffffu;
         sum += x[j];
+      }
+#pragma unroll
+      for (int j = 0; j < E; ++j) {
+        const int e = lane * E + j, d = e / W, ww = e % W;
+        cnt[ww * 128 + (d >> 1)] = 0u;
       }
       uint32_t run = wave_incl_scan_u32(sum) - sum;
 #pragma unroll
@@ -235,7 +246,6 @@ __device__ __forceinline__ void radix_sort_u64_d8(uint64_t* a, uint64_t* tmp, in
         run += x[j];
       }
     }
-    for (int i = tid; i < 256 * W; i += NT) nxt[i] = 0u;
     __syncthreads();
     uint32_t* mine = cur + w * 256;
     for (int i0 = s0; i0 < s1; i0 += 64) {
@@ -255,13 +265,13 @@ __device__ __forceinline__ void radix_sort_u64_d8(uint64_t* a, uint64_t* tmp, in
         const uint32_t p = min(c + rank, (uint32_t)(n - 1));  // (always below n; kept in bounds regardless)
         dst[(PAD_OUT && last) ? p + (p >> 4) : p] = k;
         if (rank == 0) mine[d] = c + (uint32_t)__popcll(m);
-        if (!last) atomicAdd(&nxt[(p / (uint32_t)seg) * 256 + ((uint32_t)(k >> (shift + 8)) & mask_n)], 1u);
+        if (!last) {
+          const uint32_t dn = (uint32_t)(k >> (shift + 8)) & mask_n;
+          atomicAdd(&cnt[(p / (uint32_t)seg) * 128 + (dn >> 1)], 1u << (16 * (dn & 1u)));
+        }
       }
       __builtin_amdgcn_wave_barrier();
     }
-    uint32_t* t32 = cur;
-    cur = nxt;
-    nxt = t32;
     uint64_t* t = src;
     src = dst;
     dst = t;

@@ -900,7 +900,7 @@ struct Shared {
   union {                          // never live together: LDS is the ray layout's capacity
     Agg<D> hs[NT / 64];  // the waves' totals in the scan of the thread aggregates
     float part[NT][4];  // compositing partials (render, at the end)
-    uint32_t sort_tab[2 * 256 * (NT / 64)];  // digit counts of the knot sort
+    uint32_t sort_tab[384 * (NT / 64)];  // slots and digit counts of the knot sort
   };
   uint32_t rtab[32 * (NT / 64)];  // radix sort tables
   int64_t wtot[NT / 64];
