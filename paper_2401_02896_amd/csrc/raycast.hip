@@ -137,6 +137,10 @@ __device__ __forceinline__ bool pair_hit(const double o[3], const double v[3], f
   const double lam2 = (cx * cx + cy * cy + cz * cz) / (z * z);
   if (!(lam2 < kSupport * kSupport)) return false;
   const double tchi = dxx * v[0] + dxy * v[1] + dxz * v[2];
+  // s z >= 0 and rounding is monotone, so fl(tchi + s z) >= tchi and fl(tchi - s z) <= tchi: a
+  // centre strictly inside (t_min, t_max) passes both end tests whatever s is, and the square
+  // root is only needed for the others (same decisions as evaluating both tests).
+  if (tchi > t_min && tchi < t_max) return true;
   const double s = sqrt(kSupport * kSupport - lam2);
   const double sz = s * z;
   return (tchi + sz > t_min) && (tchi - sz < t_max);
