@@ -32,6 +32,10 @@ integral of the approximation against the closed-form kernel column integral.
 The storage rounding of the table precision study (round_storage) is pinned by
 hand-worked ties, torch's float32 -> bfloat16 and numpy's float32 -> float16
 conversions.
+
+Parity unpinned: the knot positions themselves.  The paper prints only the errors E_{K,D} they
+reach (Fig. 4), so the positions are pinned through those errors and local optimality, not
+against printed values.
 """
 from __future__ import annotations
 
